@@ -1,0 +1,93 @@
+"""Independent constructions that pin the oracle (test code, not part of the oracle).
+
+* ``maxcut_p1``: closed-form p=1 MaxCut expectation of Wang, Hadfield, Jiang and Rieffel
+  (Phys. Rev. A 97, 022304, 2018), for H_M = sum X_q, phase e^{-i gamma C}, C = number of cut
+  edges, and its analytic derivative in (beta, gamma).
+* ``dense_*``: brute-force 2^n x 2^n constructions from Pauli matrices with
+  ``scipy.linalg.expm`` (matrix exponential of the full Hamiltonian, not the oracle's
+  per-qubit loop or Taylor series).
+* ``johnson_spectrum``: closed-form eigenvalues of the clique mixer on weight-k strings
+  (Johnson-scheme adjacency times 2).
+"""
+from __future__ import annotations
+
+from math import comb
+
+import numpy as np
+import scipy.linalg
+
+X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+I2 = np.eye(2, dtype=np.complex128)
+
+
+def _op_on(n, ops):
+    """Kronecker product with ops[q] on qubit q (qubit q = bit q of the basis index)."""
+    m = np.array([[1.0 + 0j]])
+    for q in range(n - 1, -1, -1):        # most significant qubit leftmost
+        m = np.kron(m, ops.get(q, I2))
+    return m
+
+
+def dense_x_mixer_hamiltonian(n):
+    return sum(_op_on(n, {q: X}) for q in range(n))
+
+
+def dense_clique_hamiltonian(n):
+    H = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    for i in range(n):
+        for j in range(i + 1, n):
+            H += _op_on(n, {i: X, j: X}) + _op_on(n, {i: Y, j: Y})
+    return H
+
+
+def dense_evolve(H_M, table, angles, psi0):
+    """Eq. (1) by dense matrix exponentials: psi <- expm(-i b H_M) diag(e^{-i g C}) psi."""
+    p = len(angles) // 2
+    psi = np.array(psi0, dtype=np.complex128)
+    for r in range(p):
+        psi = np.exp(-1j * angles[p + r] * np.asarray(table, dtype=np.float64)) * psi
+        psi = scipy.linalg.expm(-1j * angles[r] * H_M) @ psi
+    return psi
+
+
+def maxcut_p1(n, edges, beta, gamma):
+    """Closed-form p=1 <C> for unweighted MaxCut, and (d/dbeta, d/dgamma)."""
+    nbrs = [set() for _ in range(n)]
+    for a, b in edges:
+        nbrs[a].add(b)
+        nbrs[b].add(a)
+    s4b, c4b = np.sin(4 * beta), np.cos(4 * beta)
+    s2b2, ds2b2 = np.sin(2 * beta) ** 2, 2 * np.sin(4 * beta)
+    sg, cg = np.sin(gamma), np.cos(gamma)
+    c2g, s2g = np.cos(2 * gamma), np.sin(2 * gamma)
+
+    def pw(x, k):
+        return x ** k
+
+    def dpw(x, k, dx):          # d/dgamma x^k where dx = dx/dgamma
+        return k * x ** (k - 1) * dx if k > 0 else 0.0
+
+    E = dEb = dEg = 0.0
+    for a, b in edges:
+        du, dv = len(nbrs[a]) - 1, len(nbrs[b]) - 1
+        f = len(nbrs[a] & nbrs[b])
+        S = sg * (pw(cg, du) + pw(cg, dv))
+        dS = cg * (pw(cg, du) + pw(cg, dv)) + sg * (dpw(cg, du, -sg) + dpw(cg, dv, -sg))
+        ex = du + dv - 2 * f
+        T = pw(cg, ex) * (1 - pw(c2g, f))
+        dT = dpw(cg, ex, -sg) * (1 - pw(c2g, f)) - pw(cg, ex) * dpw(c2g, f, -2 * s2g)
+        E += 0.5 + 0.25 * s4b * S - 0.25 * s2b2 * T
+        dEb += 0.25 * 4 * c4b * S - 0.25 * ds2b2 * T
+        dEg += 0.25 * s4b * dS - 0.25 * s2b2 * dT
+    return E, dEb, dEg
+
+
+def johnson_spectrum(n, k):
+    """Eigenvalues of sum_{i<j} X_iX_j + Y_iY_j on weight k, with multiplicities."""
+    out = []
+    for j in range(min(k, n - k) + 1):
+        lam = 2 * ((k - j) * (n - k - j) - j)
+        mult = comb(n, j) - (comb(n, j - 1) if j > 0 else 0)
+        out += [lam] * mult
+    return np.sort(np.array(out, dtype=np.float64))

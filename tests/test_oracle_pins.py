@@ -1,0 +1,286 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix (CPU only).
+
+Each test would fail for a plausible slip in the oracle: a wrong bit index or XOR in the
+table (sum identity, complete-graph closed form), a wrong sign or a missing factor in the
+mixer (dense expm, Eq. (2) form, closed form), a swapped round order (dense brute force at
+p >= 2), or a wrong inner product in the adjoint (closed-form derivative, finite
+differences, zero-gradient identities).
+"""
+from math import comb
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import workloads
+from tests import pins
+
+
+def _er(n, seed, weights=None):
+    return workloads.erdos_renyi(n, seed, 0.5, weights)
+
+
+# ---------------------------------------------------------------- cost table (step a)
+
+@pytest.mark.parametrize("g", [workloads.random_regular_graph(10, 3, 7), _er(12, 3, (1, 4)),
+                               workloads.random_regular_graph(16, 3, 11)])
+def test_table_sum_identity(g):
+    # every edge is cut in exactly half of all 2^n strings: sum_x C(x) = W 2^(n-1)
+    t = oracle.graph_table(g)
+    assert t.sum() == g.total_weight * 2 ** (g.n - 1)
+
+
+def test_table_complement_symmetry():
+    g = _er(11, 5, (1, 4))
+    t = oracle.graph_table(g)
+    x = np.arange(1 << g.n)
+    assert np.array_equal(t, t[x ^ ((1 << g.n) - 1)])
+
+
+def test_table_complete_graph_closed_form():
+    # K_n: a string with h ones cuts exactly h (n - h) edges
+    n = 9
+    iu, ju = np.triu_indices(n, 1)
+    t = oracle.cost_table(n, iu, ju)
+    h = np.array([bin(x).count("1") for x in range(1 << n)])
+    assert np.array_equal(t, h * (n - h))
+
+
+def test_table_single_edge_is_bit_xor():
+    n = 7
+    for a, b in [(0, 6), (3, 4), (5, 1)]:
+        t = oracle.cost_table(n, [a], [b])
+        x = np.arange(1 << n)
+        assert np.array_equal(t, ((x >> a) ^ (x >> b)) & 1)
+
+
+def test_table_hamming_weight_subspace():
+    g = _er(12, 9, (1, 3))
+    for k in (1, 5, 6):
+        st = oracle.states(g.n, k)
+        assert st.size == comb(g.n, k)
+        assert np.all(np.diff(st.astype(np.int64)) > 0)              # increasing order
+        assert all(bin(int(x)).count("1") == k for x in st[:50])
+        tk = oracle.cost_table(g.n, g.u, g.v, g.w, k)
+        # an edge is cut by exactly 2 C(n-2, k-1) weight-k strings
+        assert tk.sum() == g.total_weight * 2 * comb(g.n - 2, k - 1)
+        assert np.array_equal(tk, oracle.graph_table(g)[st.astype(np.int64)])
+
+
+# ---------------------------------------------------------------- X mixer (step c)
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_x_mixer_matches_dense_expm(n):
+    rng = np.random.default_rng(n)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    beta = 0.7312
+    want = scipy.linalg.expm(-1j * beta * pins.dense_x_mixer_hamiltonian(n)) @ psi
+    got = psi.copy()
+    oracle.apply_x_mixer(n, beta, got)
+    assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
+
+
+def test_x_mixer_equation_2_hadamard_form():
+    # Eq. (2): e^{-i b sum X} = H^n diag(e^{-i b (n - 2|y|)}) H^n
+    n = 7
+    Hd = scipy.linalg.hadamard(1 << n) / 2 ** (n / 2)
+    pop = np.array([bin(y).count("1") for y in range(1 << n)])
+    beta = 2.2
+    rng = np.random.default_rng(3)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    want = Hd @ (np.exp(-1j * beta * (n - 2 * pop)) * (Hd @ psi))
+    got = psi.copy()
+    oracle.apply_x_mixer(n, beta, got)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_x_sum_is_sum_of_flips():
+    n = 6
+    rng = np.random.default_rng(4)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    want = pins.dense_x_mixer_hamiltonian(n) @ psi
+    assert np.max(np.abs(oracle.apply_x_sum(n, psi) - want)) < 1e-12
+
+
+def test_norm_preserved():
+    W = workloads.workload("maxcut3reg_n10_p3")
+    g = W.graphs[0]
+    t = oracle.graph_table(g)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        a = rng.uniform(-np.pi, np.pi, 10)
+        E, N = oracle.expect(g.n, t, a)
+        assert abs(N - 1) < 1e-13
+
+
+# ---------------------------------------------------------------- <C> (step d), Eq. (1)
+
+P1_GRAPHS = [workloads.random_regular_graph(10, 3, 1), workloads.random_regular_graph(12, 3, 2),
+             _er(8, 17), _er(9, 18), workloads.random_regular_graph(8, 5, 3)]
+
+
+@pytest.mark.parametrize("g", P1_GRAPHS)
+def test_p1_closed_form_expectation_and_gradient(g):
+    t = oracle.graph_table(g)
+    edges = list(zip(g.u.tolist(), g.v.tolist()))
+    rng = np.random.default_rng(g.n)
+    for _ in range(4):
+        beta, gamma = rng.uniform(0, np.pi, 2)
+        Ecf, dbeta, dgamma = pins.maxcut_p1(g.n, edges, beta, gamma)
+        E, N, gr = oracle.grad(g.n, t, [beta, gamma])
+        assert abs(E - Ecf) < 1e-12 * max(1, abs(Ecf))
+        assert abs(gr[0] - dbeta) < 1e-11 * max(1, abs(dbeta))
+        assert abs(gr[1] - dgamma) < 1e-11 * max(1, abs(dgamma))
+
+
+def test_zero_angles_give_uniform_mean():
+    g = _er(10, 21, (1, 4))
+    t = oracle.graph_table(g)
+    rng = np.random.default_rng(1)
+    p = 3
+    for which in ("beta", "gamma"):
+        a = rng.uniform(0, np.pi, 2 * p)
+        if which == "beta":
+            a[:p] = 0
+        else:
+            a[p:] = 0
+        E, N, gr = oracle.grad(g.n, t, a)
+        assert abs(E - g.total_weight / 2) < 1e-12 * g.total_weight
+        # at beta = 0 nothing depends on gamma; at gamma = 0 nothing depends on beta
+        zero = gr[p:] if which == "beta" else gr[:p]
+        assert np.max(np.abs(zero)) < 1e-12 * g.total_weight
+
+
+def test_symmetries():
+    g = workloads.random_regular_graph(10, 3, 5)
+    t = oracle.graph_table(g)
+    rng = np.random.default_rng(2)
+    p = 3
+    a = rng.uniform(0, np.pi, 2 * p)
+    E, N, gr = oracle.grad(g.n, t, a)
+    # beta_k -> beta_k + pi/2 multiplies the state by a product of X's (C(x) = C(~x))
+    b = a.copy(); b[1] += np.pi / 2
+    assert abs(oracle.expect(g.n, t, b)[0] - E) < 1e-12
+    # gamma_k -> gamma_k + 2 pi (integer C)
+    b = a.copy(); b[p + 2] += 2 * np.pi
+    assert abs(oracle.expect(g.n, t, b)[0] - E) < 1e-12
+    # (beta, gamma) -> (-beta, -gamma) is complex conjugation: same <C>, gradient flips sign
+    E2, N2, gr2 = oracle.grad(g.n, t, -a)
+    assert abs(E2 - E) < 1e-12
+    assert np.max(np.abs(gr2 + gr)) < 1e-11
+
+
+@pytest.mark.parametrize("n,p", [(5, 2), (7, 3), (8, 2)])
+def test_state_matches_dense_bruteforce(n, p):
+    g = _er(n, 100 + n, (1, 3))
+    t = oracle.graph_table(g)
+    a = workloads.random_angles(p, 1, 7 + n)[0]
+    psi0 = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    want = pins.dense_evolve(pins.dense_x_mixer_hamiltonian(n), t, a, psi0)
+    got = oracle.state(n, t, a)
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_custom_initial_state():
+    n, p = 6, 2
+    g = _er(n, 55)
+    t = oracle.graph_table(g)
+    rng = np.random.default_rng(8)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    a = rng.uniform(0, np.pi, 2 * p)
+    want = pins.dense_evolve(pins.dense_x_mixer_hamiltonian(n), t, a, psi0)
+    assert np.max(np.abs(oracle.state(n, t, a, psi0=psi0) - want)) < 1e-13
+
+
+# ---------------------------------------------------------------- gradient (adjoint vs FD)
+
+def test_adjoint_gradient_matches_finite_differences():
+    W = workloads.workload("maxcut3reg_n10_p3")
+    g = W.graphs[0]
+    t = oracle.graph_table(g)
+    for a in workloads.random_angles(4, 3, 99):
+        E, N, gr = oracle.grad(g.n, t, a)
+        fd = oracle.fd_grad(g.n, t, a)
+        assert np.max(np.abs(gr - fd)) < 1e-9 * max(1, np.max(np.abs(gr)))
+
+
+# ---------------------------------------------------------------- clique mixer
+
+@pytest.mark.parametrize("n,k", [(4, 2), (6, 3), (7, 2)])
+def test_clique_matrix_is_pauli_sum_restricted(n, k):
+    H = pins.dense_clique_hamiltonian(n)
+    st = oracle.states(n, k).astype(np.int64)
+    # no leakage: H maps weight-k strings only to weight-k strings
+    mask = np.zeros(1 << n, bool); mask[st] = True
+    assert np.max(np.abs(H[np.ix_(~mask, mask)])) == 0
+    Hk = H[np.ix_(st, st)]
+    nb = oracle.clique_neighbours(n, k)
+    M = np.zeros((st.size, st.size))
+    for r in range(st.size):
+        for j in nb[r]:
+            M[r, j] += 2
+    assert np.max(np.abs(Hk - M)) < 1e-14
+
+
+@pytest.mark.parametrize("n,k", [(8, 4), (10, 5), (10, 3)])
+def test_clique_johnson_spectrum(n, k):
+    nb = oracle.clique_neighbours(n, k)
+    N = nb.shape[0]
+    M = np.zeros((N, N))
+    for r in range(N):
+        M[r, nb[r]] += 2
+    ev = np.linalg.eigvalsh(M)
+    assert np.max(np.abs(np.sort(ev) - pins.johnson_spectrum(n, k))) < 1e-10
+
+
+def test_clique_mixer_matches_expm():
+    n, k = 8, 4
+    nb = oracle.clique_neighbours(n, k)
+    N = nb.shape[0]
+    M = np.zeros((N, N))
+    for r in range(N):
+        M[r, nb[r]] += 2
+    rng = np.random.default_rng(1)
+    psi = rng.normal(size=N) + 1j * rng.normal(size=N)
+    for beta in (0.3, 2.9):
+        want = scipy.linalg.expm(-1j * beta * M) @ psi
+        got = psi.copy()
+        oracle.apply_clique_mixer(n, k, beta, got, nb)
+        assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+
+
+def test_clique_dicke_state_is_top_eigenvector():
+    # the Dicke state has eigenvalue 2k(n-k): at gamma = 0 it only picks up a phase
+    g = _er(10, 31)
+    n, k = 10, 5
+    t = oracle.cost_table(n, g.u, g.v, g.w, k)
+    a = np.array([0.4, 1.3, 0.0, 0.0])
+    E, N = oracle.expect(n, t, a, k=k)
+    assert abs(E - g.total_weight * 2 * comb(n - 2, k - 1) / comb(n, k)) < 1e-12 * g.total_weight
+
+
+def test_clique_qaoa_matches_full_space_bruteforce():
+    n, k, p = 8, 4, 3
+    g = _er(n, 41)
+    st = oracle.states(n, k).astype(np.int64)
+    tfull = oracle.graph_table(g)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[st] = 1 / np.sqrt(st.size)                     # Dicke state |D^n_k>
+    a = workloads.random_angles(p, 1, 5)[0]
+    want = pins.dense_evolve(pins.dense_clique_hamiltonian(n), tfull, a, psi0)
+    got = oracle.state(n, tfull[st], a, k=k)
+    assert np.max(np.abs(want[st] - got)) < 1e-12
+    mask = np.ones(1 << n, bool); mask[st] = False
+    assert np.max(np.abs(want[mask])) < 1e-12          # evolution never leaves weight k
+
+
+def test_clique_gradient_matches_finite_differences():
+    n, k, p = 8, 4, 2
+    g = _er(n, 43)
+    t = oracle.cost_table(n, g.u, g.v, g.w, k)
+    a = workloads.random_angles(p, 1, 6)[0]
+    E, N, gr = oracle.grad(n, t, a, k=k)
+    fd = oracle.fd_grad(n, t, a, k=k)
+    assert np.max(np.abs(gr - fd)) < 1e-8 * max(1, np.max(np.abs(gr)))
