@@ -1,0 +1,154 @@
+/*
+ * qaoa.h — C ABI of the MI355X (gfx950) QAOA statevector library (libqaoa.so).
+ *
+ * The library evaluates the p-round QAOA state of Eq. (1) of Golden et al., "JuliQAOA:
+ * Fast, Flexible QAOA Simulation" (SC-W 2023):
+ *
+ *   |beta, gamma> = e^{-i beta_p H_M} e^{-i gamma_p H_C} ... e^{-i beta_1 H_M} e^{-i gamma_1 H_C} |psi0>
+ *
+ * with H_C |x> = C(x) |x> (Sec. 1), the objective <beta,gamma| H_C |beta,gamma> (Sec. 1) and
+ * its gradient in (beta, gamma) (Sec. 2.3 and Sec. 4). The calls follow the paper's problem
+ * statement (a cost function tabulated over the feasible states, an initial state, a mixer,
+ * 2p angles; Sec. 1 and Sec. 2.1) and its simulate/expectation calls (Sec. 3).
+ *
+ * Conventions shared by every call:
+ *  - Basis index x = sum_i x_i 2^i: vertex i of the graph is bit i of x. For a Hamming-weight
+ *    constrained problem the feasible states are the weight-k integers in increasing order
+ *    (the order in which Gosper's hack walks them, Sec. 2.5) and amplitudes are stored in that
+ *    order.
+ *  - Angles are FP64, laid out [beta_1 .. beta_p, gamma_1 .. gamma_p] (first code listing,
+ *    Sec. 3). Gradients use the same layout. Batched angles are [n_sets][2p], row major.
+ *  - <C> is returned as E / Nrm with E = sum_x |psi(x)|^2 C(x) and Nrm = sum_x |psi(x)|^2
+ *    (Nrm is 1 in exact arithmetic; dividing removes rounding drift of the norm). The
+ *    gradient is returned divided by the same Nrm. Callers maximise <C>; to minimise, negate
+ *    (Sec. 3, angle-finding paragraph).
+ *  - Pointers named host_* / out_* are host memory owned by the caller. Pointers named d_*
+ *    are device memory on the context's device, owned by the caller. Handles own their own
+ *    device buffers (the cost table, the mixer eigenbasis, state and scratch vectors), which
+ *    are allocated when the handle or the first evaluation needs them and reused afterwards
+ *    (pre-allocated, reused memory: Sec. 2.2).
+ *  - Streams: every call takes a hipStream_t passed as void* (NULL = the null stream). Work is
+ *    enqueued on that stream; calls with host outputs synchronise that stream before return.
+ *  - Calls that share a context must not overlap in time (same stream, or host-serialised):
+ *    the context's scratch vectors are reused by every evaluation.
+ *  - Errors: every call returns a status (0 = QAOA_OK, negative = error). On error outputs
+ *    are undefined and qaoa_last_error() returns a thread-local message. No C++ exception
+ *    crosses this interface.
+ */
+#ifndef QAOA_H
+#define QAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define QAOA_OK 0
+#define QAOA_ERR_INVALID_ARG (-1)   /* an argument is out of range, NULL, or inconsistent */
+#define QAOA_ERR_OUT_OF_MEMORY (-2) /* a device or host allocation failed                */
+#define QAOA_ERR_HIP (-3)           /* a HIP runtime call or kernel launch failed        */
+#define QAOA_ERR_UNSUPPORTED (-4)   /* valid request this build does not implement        */
+
+/* Arithmetic of the state vector. QAOA_FP32: complex64 amplitudes, FP32 arithmetic, FP64
+ * accumulation of every sum (<C>, norm, gradient). QAOA_FP64: complex128 throughout. */
+#define QAOA_FP32 0
+#define QAOA_FP64 1
+
+typedef struct qaoa_ctx qaoa_ctx;         /* one HIP device + reusable scratch         */
+typedef struct qaoa_problem qaoa_problem; /* cost diagonal C(x) over the feasible set   */
+typedef struct qaoa_mixer qaoa_mixer;     /* H_M: transverse field or clique            */
+
+/* Create a context on HIP device `hip_device` (>= 0). *out receives the handle.
+ * INVALID_ARG for a bad device index or out == NULL; HIP on runtime failure. */
+int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
+
+/* Destroy a context and free its scratch. Problems and mixers created on it must be
+ * destroyed first. NULL is accepted (no-op). */
+int qaoa_ctx_destroy(qaoa_ctx *ctx);
+
+/* Step (a): tabulate the MaxCut cost diagonal on the device (Sec. 2.1, pre-computation):
+ *   C(x) = sum_{e < n_edges} w[e] * [bit u[e] of x != bit v[e] of x]
+ * for every feasible x: all 2^n strings (hamming_k < 0) or the weight-k strings in
+ * increasing order (0 <= hamming_k <= n). u, v, w are host arrays of n_edges int32
+ * (w == NULL: unit weights). Requires 1 <= n <= 32 (hamming_k >= 0: C(n,k) <= 2^26),
+ * 0 <= u, v < n, u != v, w >= 0 and sum of w <= 65535 (the table is stored as uint8 when
+ * every value is <= 255, else uint16). The table is computed exactly (integers).
+ * *out owns the device table. The call synchronises `stream`. */
+int qaoa_cost_table(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const int32_t *v,
+                    const int32_t *w, int hamming_k, qaoa_problem **out, void *stream);
+
+/* Copy the table back as int64 into host_dst (len must equal the feasible-set size), in the
+ * basis order above. For exact comparisons; synchronises `stream`. */
+int qaoa_problem_copy_table(const qaoa_problem *prob, int64_t *host_dst, size_t len, void *stream);
+
+/* Problem metadata: qubits n, hamming_k (-1 = unconstrained), feasible-set size, largest
+ * C value. Any output pointer may be NULL. */
+int qaoa_problem_info(const qaoa_problem *prob, int *n, int *hamming_k, int64_t *size,
+                      int64_t *max_value);
+
+/* Free a problem (NULL accepted). */
+int qaoa_problem_destroy(qaoa_problem *prob);
+
+/* Transverse-field mixer H_M = sum_q X_q on n qubits (Sec. 2.1; the factorisation of
+ * Eq. (2): e^{-i b H_M} is a product of single-qubit rotations). 1 <= n <= 32. */
+int qaoa_mixer_x(qaoa_ctx *ctx, int n, qaoa_mixer **out);
+
+/* Clique mixer H_M = sum_{i<j} X_i X_j + Y_i Y_j restricted to Hamming weight k (Sec. 2.1):
+ * its matrix on the weight-k strings has entry 2 between strings that differ by moving one
+ * 1-bit, else 0. The eigendecomposition H_M = V D V^T is computed once here in FP64 on the
+ * device (V is real orthogonal, so V^{-1} = V^T) and kept by the handle. Requires
+ * 2 <= n <= 20, 1 <= k <= n-1 and C(n,k) <= 16384. Synchronises `stream`. */
+int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream);
+
+/* Free a mixer (NULL accepted). */
+int qaoa_mixer_destroy(qaoa_mixer *mix);
+
+/* <C> for one angle set: evolve Eq. (1) with p >= 1 rounds and reduce step (d).
+ * angles: host double[2p], finite. d_psi0: device initial state (complex64 for QAOA_FP32,
+ * complex128 for QAOA_FP64, feasible-set order, need not be normalised) or NULL for the
+ * default start, the uniform superposition over the feasible set (Sec. 3). The mixer must
+ * act on the problem's space (same n; clique mixers need the same hamming_k).
+ * *out_expect receives E / Nrm. Synchronises `stream`. */
+int qaoa_expect(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles,
+                const void *d_psi0, int precision, double *out_expect, void *stream);
+
+/* <C> and d<C>/d(beta, gamma) for one angle set (gradient: Sec. 2.3 and Sec. 4). The
+ * gradient is formed by a reverse sweep that undoes each layer (inverse mixer and inverse
+ * phase applied to the state and to the adjoint vector), so no per-layer states are kept.
+ * out_grad: host double[2p], layout of `angles`. Other arguments as qaoa_expect. */
+int qaoa_expect_grad(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles,
+                     const void *d_psi0, int precision, double *out_expect, double *out_grad,
+                     void *stream);
+
+/* Final state psi_p of Eq. (1) (Sec. 3: the simulate result holds the state vector), written
+ * to d_out (device, caller-owned, feasible-set length, complex64 or complex128 by
+ * `precision`), not renormalised. Other arguments as qaoa_expect. */
+int qaoa_state(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles,
+               const void *d_psi0, int precision, void *d_out, void *stream);
+
+/* Batched <C>: every problem probs[i] (with mixer mixers[i]) at every angle set
+ * angles[s][0..2p), s < n_sets, default initial state. out_expect: host double
+ * [n_probs][n_sets]. All items run in one graph-captured launch sequence. */
+int qaoa_expect_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
+                        int n_probs, int n_sets, int p, const double *angles, int precision,
+                        double *out_expect, void *stream);
+
+/* Batched <C> and gradient; out_grad: host double [n_probs][n_sets][2p]. */
+int qaoa_expect_grad_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
+                             int n_probs, int n_sets, int p, const double *angles, int precision,
+                             double *out_expect, double *out_grad, void *stream);
+
+/* Static text for a status code. */
+const char *qaoa_status_string(int status);
+
+/* Thread-local detail of the last error on the calling thread ("" if none). */
+const char *qaoa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAOA_H */

@@ -26,7 +26,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (IEEE FP64, OpenMP); returns the library path."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fcx-limited-range", "-fopenmp", "-fPIC", "-shared",
                                _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -67,6 +67,8 @@ def lib():
         L.orc_qaoa_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, i64p, vp,
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), f64p]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_cost_values.restype = ctypes.c_int
+        L.orc_cost_values.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, u64p, ctypes.c_int64, i64p]
         _lib = L
     return _lib
 
@@ -96,6 +98,18 @@ def cost_table(n: int, u, v, w=None, k: int = -1) -> np.ndarray:
     out = np.zeros(N, dtype=np.int64)
     r = lib().orc_cost_table(n, int(u.size), u, v, w, k, out)
     if r != N:
+        raise ValueError("oracle rejected the graph")
+    return out
+
+
+def cost_values(n: int, u, v, w, xs) -> np.ndarray:
+    """C(x) at the given basis strings (for sampled checks of tables too large to build)."""
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    w = np.ones_like(u) if w is None else np.ascontiguousarray(w, dtype=np.int32)
+    xs = np.ascontiguousarray(xs, dtype=np.uint64)
+    out = np.zeros(xs.size, dtype=np.int64)
+    if lib().orc_cost_values(n, int(u.size), u, v, w, xs, xs.size, out):
         raise ValueError("oracle rejected the graph")
     return out
 

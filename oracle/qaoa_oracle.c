@@ -356,3 +356,13 @@ int orc_num_threads(void) { return omp_get_max_threads(); }
 #else
 int orc_num_threads(void) { return 1; }
 #endif
+
+/* C(x) at the given basis strings only (sampled checks of very large tables). */
+int orc_cost_values(int n, int m, const int32_t *u, const int32_t *v, const int32_t *w,
+                    const uint64_t *xs, int64_t count, int64_t *out) {
+    if (n < 1 || n > 63) return -1;
+    for (int e = 0; e < m; e++)
+        if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n || u[e] == v[e]) return -1;
+    for (int64_t i = 0; i < count; i++) out[i] = maxcut_value(xs[i], m, u, v, w);
+    return 0;
+}

@@ -1,0 +1,217 @@
+"""ctypes binding of libqaoa.so: the C ABI of include/qaoa.h, same names, marshalling only.
+
+The library must have been built (``python paper_2312_06451_amd/build.py`` or
+``__graft_entry__.build()``). There is no fallback: if it is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqaoa.so")
+
+QAOA_OK = 0
+QAOA_ERR_INVALID_ARG = -1
+QAOA_ERR_OUT_OF_MEMORY = -2
+QAOA_ERR_HIP = -3
+QAOA_ERR_UNSUPPORTED = -4
+QAOA_FP32 = 0
+QAOA_FP64 = 1
+
+EXPORTED = [
+    "qaoa_ctx_create", "qaoa_ctx_destroy", "qaoa_cost_table", "qaoa_problem_copy_table",
+    "qaoa_problem_info", "qaoa_problem_destroy", "qaoa_mixer_x", "qaoa_mixer_clique",
+    "qaoa_mixer_destroy", "qaoa_expect", "qaoa_expect_grad", "qaoa_state", "qaoa_expect_batched",
+    "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error",
+]
+
+
+class QAOAError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+c_int, c_void_p, c_double, c_size_t = ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
+c_int64 = ctypes.c_int64
+P = ctypes.POINTER
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqaoa.so (raises OSError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch enumerates HIP devices on its own first use; if this library initialises the HIP
+    # runtime before that, torch later reports no GPU. Let torch look first when present.
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: build it first (paper_2312_06451_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    i32p = P(ctypes.c_int32)
+    L.qaoa_ctx_create.argtypes = [c_int, P(c_void_p)]
+    L.qaoa_ctx_destroy.argtypes = [c_void_p]
+    L.qaoa_cost_table.argtypes = [c_void_p, c_int, c_int, i32p, i32p, i32p, c_int, P(c_void_p), c_void_p]
+    L.qaoa_problem_copy_table.argtypes = [c_void_p, P(c_int64), c_size_t, c_void_p]
+    L.qaoa_problem_info.argtypes = [c_void_p, P(c_int), P(c_int), P(c_int64), P(c_int64)]
+    L.qaoa_problem_destroy.argtypes = [c_void_p]
+    L.qaoa_mixer_x.argtypes = [c_void_p, c_int, P(c_void_p)]
+    L.qaoa_mixer_clique.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
+    L.qaoa_mixer_destroy.argtypes = [c_void_p]
+    L.qaoa_expect.argtypes = [c_void_p, c_void_p, c_int, P(c_double), c_void_p, c_int, P(c_double), c_void_p]
+    L.qaoa_expect_grad.argtypes = [c_void_p, c_void_p, c_int, P(c_double), c_void_p, c_int,
+                                   P(c_double), P(c_double), c_void_p]
+    L.qaoa_state.argtypes = [c_void_p, c_void_p, c_int, P(c_double), c_void_p, c_int, c_void_p, c_void_p]
+    L.qaoa_expect_batched.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, c_int, P(c_double), c_int,
+                                      P(c_double), c_void_p]
+    L.qaoa_expect_grad_batched.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, c_int, P(c_double),
+                                           c_int, P(c_double), P(c_double), c_void_p]
+    L.qaoa_status_string.argtypes = [c_int]
+    L.qaoa_status_string.restype = ctypes.c_char_p
+    L.qaoa_last_error.argtypes = []
+    L.qaoa_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("qaoa_status_string", "qaoa_last_error"):
+            getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def check(status: int, where: str) -> None:
+    if status != QAOA_OK:
+        L = lib()
+        detail = L.qaoa_last_error().decode(errors="replace")
+        raise QAOAError(status, where, f"{L.qaoa_status_string(status).decode()}: {detail}")
+
+
+# ---------------------------------------------------------------- same-name wrappers
+
+def qaoa_ctx_create(hip_device: int) -> int:
+    out = c_void_p()
+    check(lib().qaoa_ctx_create(hip_device, ctypes.byref(out)), "qaoa_ctx_create")
+    return out.value
+
+
+def qaoa_ctx_destroy(ctx: int) -> None:
+    check(lib().qaoa_ctx_destroy(ctx), "qaoa_ctx_destroy")
+
+
+def _i32(a):
+    import numpy as np
+    arr = np.ascontiguousarray(a, dtype=np.int32)
+    return arr, arr.ctypes.data_as(P(ctypes.c_int32))
+
+
+def qaoa_cost_table(ctx: int, n: int, u, v, w=None, hamming_k: int = -1, stream: int = 0) -> int:
+    ua, up = _i32(u)
+    va, vp = _i32(v)
+    if w is None:
+        wp = None
+    else:
+        wa, wp = _i32(w)
+    out = c_void_p()
+    check(lib().qaoa_cost_table(ctx, n, int(ua.size), up, vp, wp, hamming_k, ctypes.byref(out), stream),
+          "qaoa_cost_table")
+    return out.value
+
+
+def qaoa_problem_copy_table(prob: int, stream: int = 0):
+    import numpy as np
+    info = qaoa_problem_info(prob)
+    out = np.zeros(info["size"], dtype=np.int64)
+    check(lib().qaoa_problem_copy_table(prob, out.ctypes.data_as(P(c_int64)), out.size, stream),
+          "qaoa_problem_copy_table")
+    return out
+
+
+def qaoa_problem_info(prob: int) -> dict:
+    n, k, size, mx = c_int(), c_int(), c_int64(), c_int64()
+    check(lib().qaoa_problem_info(prob, ctypes.byref(n), ctypes.byref(k), ctypes.byref(size),
+                                  ctypes.byref(mx)), "qaoa_problem_info")
+    return {"n": n.value, "hamming_k": k.value, "size": size.value, "max_value": mx.value}
+
+
+def qaoa_problem_destroy(prob: int) -> None:
+    check(lib().qaoa_problem_destroy(prob), "qaoa_problem_destroy")
+
+
+def qaoa_mixer_x(ctx: int, n: int) -> int:
+    out = c_void_p()
+    check(lib().qaoa_mixer_x(ctx, n, ctypes.byref(out)), "qaoa_mixer_x")
+    return out.value
+
+
+def qaoa_mixer_clique(ctx: int, n: int, k: int, stream: int = 0) -> int:
+    out = c_void_p()
+    check(lib().qaoa_mixer_clique(ctx, n, k, ctypes.byref(out), stream), "qaoa_mixer_clique")
+    return out.value
+
+
+def qaoa_mixer_destroy(mix: int) -> None:
+    check(lib().qaoa_mixer_destroy(mix), "qaoa_mixer_destroy")
+
+
+def _f64(a):
+    import numpy as np
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    return arr, arr.ctypes.data_as(P(c_double))
+
+
+def qaoa_expect(prob: int, mix: int, p: int, angles, d_psi0: int = 0, precision: int = QAOA_FP32,
+                stream: int = 0) -> float:
+    aa, ap = _f64(angles)
+    out = c_double()
+    check(lib().qaoa_expect(prob, mix, p, ap, d_psi0 or None, precision, ctypes.byref(out), stream),
+          "qaoa_expect")
+    return out.value
+
+
+def qaoa_expect_grad(prob: int, mix: int, p: int, angles, d_psi0: int = 0,
+                     precision: int = QAOA_FP32, stream: int = 0):
+    import numpy as np
+    aa, ap = _f64(angles)
+    out = c_double()
+    g = np.zeros(2 * p, dtype=np.float64)
+    check(lib().qaoa_expect_grad(prob, mix, p, ap, d_psi0 or None, precision, ctypes.byref(out),
+                                 g.ctypes.data_as(P(c_double)), stream), "qaoa_expect_grad")
+    return out.value, g
+
+
+def qaoa_state(prob: int, mix: int, p: int, angles, d_out: int, d_psi0: int = 0,
+               precision: int = QAOA_FP32, stream: int = 0) -> None:
+    aa, ap = _f64(angles)
+    check(lib().qaoa_state(prob, mix, p, ap, d_psi0 or None, precision, d_out, stream), "qaoa_state")
+
+
+def _ptrs(handles):
+    arr = (c_void_p * len(handles))(*handles)
+    return arr
+
+
+def qaoa_expect_batched(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+    import numpy as np
+    aa, ap = _f64(angles)
+    n_sets = aa.size // (2 * p)
+    out = np.zeros((len(probs), n_sets), dtype=np.float64)
+    check(lib().qaoa_expect_batched(_ptrs(probs), _ptrs(mixers), len(probs), n_sets, p, ap, precision,
+                                    out.ctypes.data_as(P(c_double)), stream), "qaoa_expect_batched")
+    return out
+
+
+def qaoa_expect_grad_batched(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+    import numpy as np
+    aa, ap = _f64(angles)
+    n_sets = aa.size // (2 * p)
+    out = np.zeros((len(probs), n_sets), dtype=np.float64)
+    g = np.zeros((len(probs), n_sets, 2 * p), dtype=np.float64)
+    check(lib().qaoa_expect_grad_batched(_ptrs(probs), _ptrs(mixers), len(probs), n_sets, p, ap, precision,
+                                         out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)),
+                                         stream), "qaoa_expect_grad_batched")
+    return out, g

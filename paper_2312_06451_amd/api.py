@@ -1,0 +1,137 @@
+"""Handle classes over the C ABI (argument marshalling only)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from ._lib import QAOA_FP32, QAOA_FP64
+
+
+def _stream(stream):
+    """HIP stream handle for a call: an int, a torch stream, or torch's current stream."""
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """One HIP device and the scratch vectors evaluations reuse."""
+
+    def __init__(self, device: int = 0):
+        self.handle = _lib.qaoa_ctx_create(device)
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib.qaoa_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Cost diagonal C(x) of a (weighted) MaxCut instance, tabulated on the device."""
+
+    def __init__(self, ctx: Context, n: int, u, v, w=None, hamming_k: int = -1, stream=None):
+        self.ctx = ctx
+        self.handle = _lib.qaoa_cost_table(ctx.handle, n, u, v, w, hamming_k, _stream(stream))
+        info = _lib.qaoa_problem_info(self.handle)
+        self.n = info["n"]
+        self.hamming_k = info["hamming_k"]
+        self.size = info["size"]
+        self.max_value = info["max_value"]
+
+    @classmethod
+    def from_graph(cls, ctx: Context, g, hamming_k: int = -1, stream=None):
+        return cls(ctx, g.n, g.u, g.v, g.w, hamming_k, stream)
+
+    def table(self, stream=None) -> np.ndarray:
+        return _lib.qaoa_problem_copy_table(self.handle, _stream(stream))
+
+    def close(self):
+        if self.handle:
+            _lib.qaoa_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mixer:
+    """H_M: ``Mixer.x(ctx, n)`` (sum of X_q) or ``Mixer.clique(ctx, n, k)``."""
+
+    def __init__(self, ctx: Context, handle: int, kind: str, n: int, k: int = -1):
+        self.ctx, self.handle, self.kind, self.n, self.k = ctx, handle, kind, n, k
+
+    @classmethod
+    def x(cls, ctx: Context, n: int):
+        return cls(ctx, _lib.qaoa_mixer_x(ctx.handle, n), "x", n)
+
+    @classmethod
+    def clique(cls, ctx: Context, n: int, k: int, stream=None):
+        return cls(ctx, _lib.qaoa_mixer_clique(ctx.handle, n, k, _stream(stream)), "clique", n, k)
+
+    def close(self):
+        if self.handle:
+            _lib.qaoa_mixer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    if t is None:
+        return 0
+    return int(t.data_ptr())
+
+
+def expect(problem: Problem, mixer: Mixer, angles, psi0=None, precision: int = QAOA_FP32, stream=None) -> float:
+    a = np.asarray(angles, dtype=np.float64).reshape(-1)
+    return _lib.qaoa_expect(problem.handle, mixer.handle, a.size // 2, a, _ptr(psi0), precision, _stream(stream))
+
+
+def expect_grad(problem: Problem, mixer: Mixer, angles, psi0=None, precision: int = QAOA_FP32, stream=None):
+    a = np.asarray(angles, dtype=np.float64).reshape(-1)
+    return _lib.qaoa_expect_grad(problem.handle, mixer.handle, a.size // 2, a, _ptr(psi0), precision,
+                                 _stream(stream))
+
+
+def state(problem: Problem, mixer: Mixer, angles, out, psi0=None, precision: int = QAOA_FP32, stream=None):
+    """Write psi_p into the device tensor ``out`` (complex64 / complex128, feasible-set length)."""
+    a = np.asarray(angles, dtype=np.float64).reshape(-1)
+    _lib.qaoa_state(problem.handle, mixer.handle, a.size // 2, a, _ptr(out), _ptr(psi0), precision,
+                    _stream(stream))
+    return out
+
+
+def expect_batched(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
+    a = np.asarray(angles, dtype=np.float64)
+    p = a.shape[-1] // 2
+    return _lib.qaoa_expect_batched([x.handle for x in problems], [m.handle for m in mixers], p, a,
+                                    precision, _stream(stream))
+
+
+def expect_grad_batched(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
+    a = np.asarray(angles, dtype=np.float64)
+    p = a.shape[-1] // 2
+    return _lib.qaoa_expect_grad_batched([x.handle for x in problems], [m.handle for m in mixers], p, a,
+                                         precision, _stream(stream))

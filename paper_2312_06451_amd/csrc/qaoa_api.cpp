@@ -1,0 +1,927 @@
+// Host runtime behind the C ABI of include/qaoa.h: handles, buffer management, the pass
+// planner of the transverse-field path, scale bookkeeping and result assembly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qaoa.h"
+#include "qaoa_internal.h"
+#include "qaoa_clique.h"
+
+using namespace qaoa;
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+namespace {
+struct Err {
+  int code;
+  std::string msg;
+};
+Err fail(int code, const std::string &m) { return Err{code, m}; }
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      throw Err{QAOA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};             \
+  } while (0)
+#define REQUIRE(cond, msg)                                                                    \
+  do {                                                                                        \
+    if (!(cond)) throw Err{QAOA_ERR_INVALID_ARG, msg};                                        \
+  } while (0)
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return QAOA_OK;
+  } catch (const Err &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const qaoa::CliqueUnsupported &) {
+    g_last_error = "the clique mixer path is not available in this build";
+    return QAOA_ERR_UNSUPPORTED;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return QAOA_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    g_last_error = "unexpected exception";
+    return QAOA_ERR_HIP;
+  }
+}
+
+// Device buffer that grows on demand (never shrinks while its owner lives).
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  void *get(size_t bytes) {
+    if (bytes <= cap && p) return p;
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (bytes == 0) return nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Err{QAOA_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    cap = bytes;
+    return p;
+  }
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+};
+
+struct HostBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  void *get(size_t bytes) {
+    if (bytes <= cap && p) return p;
+    if (p) hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc(&p, bytes < 4096 ? 4096 : bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Err{QAOA_ERR_OUT_OF_MEMORY, "hipHostMalloc failed"};
+    }
+    cap = bytes < 4096 ? 4096 : bytes;
+    return p;
+  }
+  ~HostBuf() {
+    if (p) hipHostFree(p);
+  }
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    HIPCHK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+int64_t binom64(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+  return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- handles
+
+struct qaoa_ctx {
+  int device = 0;
+  DevBuf phi, lam, partials, params, luts, results, cnt, items;
+  HostBuf hparams, hresults;
+};
+
+struct qaoa_problem {
+  qaoa_ctx *ctx = nullptr;
+  int n = 0, k = -1;
+  uint64_t N = 0;
+  int tbytes = 1;
+  int64_t max_value = 0;
+  int64_t total_weight = 0;
+  double mean = 0.0;  // mean of C over the feasible set (centre of the adjoint vector)
+  void *table = nullptr;
+  std::map<std::tuple<int, int, int>, void *> layouts;  // (T, c, h0) -> tile-major copy
+  ~qaoa_problem() {
+    if (table) hipFree(table);
+    for (auto &kv : layouts)
+      if (kv.second) hipFree(kv.second);
+  }
+};
+
+struct qaoa_mixer {
+  qaoa_ctx *ctx = nullptr;
+  int kind = 0;  // 0: transverse field, 1: clique
+  int n = 0, k = -1;
+  std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique;
+};
+
+// ---------------------------------------------------------------- plan of the X path
+
+namespace {
+
+struct TileGeo {
+  int c, h0;
+  uint32_t rot;  // tile bits rotated by this tile
+};
+
+std::vector<TileGeo> make_tiles(int n, int T, int cmin) {
+  std::vector<TileGeo> t;
+  t.push_back({T, T, (1u << T) - 1});
+  int next = T;
+  while (next < n) {
+    int width = std::min(n - next, T - cmin);
+    int c = T - width;
+    t.push_back({c, next, ((1u << T) - 1) & ~((1u << c) - 1)});
+    next += width;
+  }
+  return t;
+}
+
+// One forward pass: [rotate tile bits for layer pre] [phase of layer ph] [rotate for layer post]
+struct FwdPass {
+  int tile;
+  int pre = -1, ph = -1, post = -1;
+};
+
+std::vector<FwdPass> make_forward(int K, int p) {
+  std::vector<std::pair<int, int>> seq;  // (tile, layer): layers alternate tile order
+  for (int k = 0; k < p; k++)
+    for (int i = 0; i < K; i++) seq.push_back({(k % 2 == 0) ? i : K - 1 - i, k});
+  std::vector<FwdPass> out;
+  out.push_back(FwdPass{seq[0].first, -1, 0, 0});
+  size_t i = 1;
+  while (i < seq.size()) {
+    if (i + 1 < seq.size() && seq[i + 1].first == seq[i].first) {
+      out.push_back(FwdPass{seq[i].first, seq[i].second, seq[i + 1].second, seq[i + 1].second});
+      i += 2;
+    } else {
+      out.push_back(FwdPass{seq[i].first, seq[i].second, -1, -1});
+      i += 1;
+    }
+  }
+  return out;
+}
+
+// Rotation parameters of e^{-i beta X} (see the kernel file header): tau and swap for the
+// kernel, f = dropped scalar of the forward rotation, finv = of the inverse rotation.
+template <typename R>
+void rot_params(double beta, R &tau, int &swap, cd &f, cd &finv) {
+  double sb = std::sin(beta), cb = std::cos(beta);
+  if (std::fabs(sb) <= std::fabs(cb)) {
+    tau = (R)(sb / cb);
+    swap = 0;
+    double t = (double)tau, nrm = 1.0 / std::sqrt(1.0 + t * t);
+    f = cd(cb < 0 ? -nrm : nrm, 0.0);
+    finv = f;
+  } else {
+    tau = (R)(-cb / sb);
+    swap = 1;
+    double t = (double)tau, s = (sb < 0 ? -1.0 : 1.0) / std::sqrt(1.0 + t * t);
+    f = cd(0.0, -s);
+    finv = cd(0.0, s);
+  }
+}
+
+cd cpow_int(cd z, int m) {
+  cd r(1.0, 0.0);
+  for (int i = 0; i < m; i++) r *= z;
+  return r;
+}
+
+struct OutMap {
+  int nout, p;
+  int E() const { return 0; }
+  int Nr() const { return 1; }
+  int gb(int k) const { return 2 + k; }
+  int gg(int k) const { return 2 + p + k; }
+};
+
+template <typename R>
+void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
+                int grad, double *out_expect, double *out_grad, void *d_state_out, hipStream_t st) {
+  qaoa_ctx *ctx = prob->ctx;
+  const int prec = sizeof(R) == 4 ? QAOA_FP32 : QAOA_FP64;
+  const int T = prec == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
+  const int cmin = prec == QAOA_FP32 ? MIN_CONTIG_F32 : MIN_CONTIG_F64;
+  const int n = prob->n;
+  const std::vector<TileGeo> tiles = make_tiles(n, T, cmin);
+  const int K = (int)tiles.size();
+  const std::vector<FwdPass> fwd = make_forward(K, p);
+  const uint32_t nwg = 1u << (n - T);
+  const uint64_t N = 1ull << n;
+  const size_t esz = 2 * sizeof(R);
+  const int lut_len = (int)prob->max_value + 1;
+  if (lut_len > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+
+  // tile-major table copies for every geometry that reads the table
+  auto table_for = [&](int tile) -> const void * {
+    const TileGeo &g = tiles[tile];
+    if (g.c == T) return prob->table;  // contiguous tile: natural layout
+    auto key = std::make_tuple(T, g.c, g.h0);
+    auto it = prob->layouts.find(key);
+    if (it != prob->layouts.end()) return it->second;
+    void *d = nullptr;
+    if (hipMalloc(&d, N * prob->tbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "table layout allocation failed");
+    }
+    hipError_t e = launch_table_relayout(prob->table, d, prob->tbytes, n, T, g.c, g.h0, st);
+    if (e != hipSuccess) {
+      hipFree(d);
+      throw fail(QAOA_ERR_HIP, std::string("table relayout: ") + hipGetErrorString(e));
+    }
+    prob->layouts[key] = d;
+    return d;
+  };
+
+  // buffers
+  const size_t vbytes = (size_t)nsets * N * esz;
+  void *dphi = ctx->phi.get(vbytes);
+  void *dlam = grad ? ctx->lam.get(vbytes) : nullptr;
+  OutMap om{2 + 2 * p, p};
+  const int nout = om.nout;
+  const int maxc = K + 1;
+  const size_t part_elems = (size_t)nout * maxc * nsets * nwg;
+  double *dpart = (double *)ctx->partials.get(part_elems * sizeof(double));
+
+  // angle-derived parameters per set and layer
+  std::vector<R> tau((size_t)nsets * p);
+  std::vector<int> swp((size_t)nsets * p);
+  std::vector<cd> ff((size_t)nsets * p), fi((size_t)nsets * p);
+  for (int s = 0; s < nsets; s++)
+    for (int k = 0; k < p; k++) {
+      double beta = angles[(size_t)s * 2 * p + k];
+      rot_params<R>(beta, tau[s * p + k], swp[s * p + k], ff[s * p + k], fi[s * p + k]);
+    }
+  auto gam = [&](int s, int k) { return angles[(size_t)s * 2 * p + p + k]; };
+
+  std::vector<PassArgs<R>> passes;
+  std::vector<int> nvs;
+  std::vector<SetParams<R>> sps;
+  std::vector<LutJob> jobs;
+  std::vector<int> cnt(nout, 0);
+  auto slot_for = [&](int o) -> int64_t {
+    int c = cnt[o]++;
+    if (c >= maxc) throw fail(QAOA_ERR_HIP, "internal: too many contributions");
+    return ((int64_t)o * maxc + c) * nsets * (int64_t)nwg;
+  };
+  auto base_args = [&](int tile) {
+    PassArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.c = tiles[tile].c;
+    a.h0 = tiles[tile].h0;
+    a.nwg = nwg;
+    a.xcd_remap = nwg >= 8 ? 1 : 0;
+    a.nsets = nsets;
+    a.vstride = N;
+    a.phi = dphi;
+    a.lam = dlam;
+    a.psi0 = d_psi0;
+    a.table = nullptr;
+    a.luts = nullptr;  // patched after upload
+    a.lut_len = lut_len;
+    a.u0 = (R)(1.0 / std::sqrt((double)N));
+    a.lam_c0 = (R)prob->mean;
+    a.partials = dpart;
+    for (int s = 0; s < NSLOT; s++) a.slot_off[s] = -1;
+    return a;
+  };
+
+  std::vector<cd> sig(nsets, cd(1.0, 0.0));
+  auto rotbits = [&](int tile) { return __builtin_popcount(tiles[tile].rot); };
+  const int npf = (int)fwd.size();
+
+  // ---------------- forward passes (all but the last)
+  for (int j = 0; j < npf - 1; j++) {
+    const FwdPass &fp = fwd[j];
+    PassArgs<R> a = base_args(fp.tile);
+    uint32_t f = 0;
+    if (j == 0) f |= d_psi0 ? PF_LOAD_PSI0 : PF_GEN_PHI;
+    else f |= PF_LOAD_PHI;
+    f |= PF_STORE_PHI;
+    if (fp.pre >= 0) a.mask1 = tiles[fp.tile].rot;
+    if (fp.ph >= 0) {
+      f |= PF_PHASE;
+      a.table = table_for(fp.tile);
+    }
+    if (fp.post >= 0) a.mask2 = tiles[fp.tile].rot;
+    a.flags = f;
+    for (int s = 0; s < nsets; s++) {
+      SetParams<R> q;
+      std::memset(&q, 0, sizeof(q));
+      q.lut = -1;
+      q.w1 = q.w2 = 1.0;
+      q.lam_rho = (R)1;
+      if (fp.pre >= 0) {
+        q.tau1 = tau[s * p + fp.pre];
+        q.swap1 = swp[s * p + fp.pre];
+        sig[s] *= cpow_int(ff[s * p + fp.pre], rotbits(fp.tile));
+      }
+      if (fp.ph >= 0) {
+        q.lut = (int)jobs.size();
+        jobs.push_back(LutJob{gam(s, fp.ph), sig[s].real(), sig[s].imag(), -1.0});
+        sig[s] = cd(1.0, 0.0);
+      }
+      if (fp.post >= 0) {
+        q.tau2 = tau[s * p + fp.post];
+        q.swap2 = swp[s * p + fp.post];
+        sig[s] *= cpow_int(ff[s * p + fp.post], rotbits(fp.tile));
+      }
+      sps.push_back(q);
+    }
+    passes.push_back(a);
+    nvs.push_back(1);
+  }
+
+  // ---------------- last forward pass (alone, or fused with the start of the reverse sweep)
+  const FwdPass &lp = fwd[npf - 1];
+  std::vector<cd> sig_pre_last = sig;
+  std::vector<cd> sig_p(nsets);
+  std::vector<double> rho(nsets);
+  {
+    PassArgs<R> a = base_args(lp.tile);
+    uint32_t f = (npf == 1) ? (d_psi0 ? PF_LOAD_PSI0 : PF_GEN_PHI) : PF_LOAD_PHI;
+    // a single-pass plan would need the phase too; K >= 2 always gives >= 2 passes
+    a.mask1 = tiles[lp.tile].rot;
+    a.table = table_for(lp.tile);
+    f |= PF_EXPECT;
+    a.slot_off[SL_A] = slot_for(om.E());
+    a.slot_off[SL_B] = slot_for(om.Nr());
+    if (d_state_out) f |= PF_STORE_PHI;
+    if (grad) {
+      f |= PF_LAMBDA | PF_XT2 | PF_ROT2_BOTH | PF_STORE_LAM;
+      a.mask2 = tiles[lp.tile].rot;
+      a.slot_off[SL_C] = slot_for(om.gb(lp.pre));
+    }
+    a.flags = f;
+    for (int s = 0; s < nsets; s++) {
+      SetParams<R> q;
+      std::memset(&q, 0, sizeof(q));
+      q.lut = -1;
+      q.tau1 = tau[s * p + lp.pre];
+      q.swap1 = swp[s * p + lp.pre];
+      sig[s] *= cpow_int(ff[s * p + lp.pre], rotbits(lp.tile));
+      sig_p[s] = sig[s];
+      double t = (double)q.tau1;
+      rho[s] = std::pow(1.0 / (1.0 + t * t), rotbits(lp.tile));
+      q.lam_rho = (R)rho[s];
+      q.w1 = 1.0;
+      q.w2 = std::norm(sig_p[s]) / (double)q.lam_rho;
+      q.tau2 = -q.tau1;
+      q.swap2 = q.swap1;
+      sps.push_back(q);
+    }
+    passes.push_back(a);
+    nvs.push_back(grad ? 2 : 1);
+  }
+
+  // ---------------- reverse sweep
+  if (grad) {
+    // after the fused pass: phi (memory) and lam share the scalar sig_pre_last
+    std::vector<cd> sb = sig_pre_last;
+    for (int j = npf - 2; j >= 0; j--) {
+      const FwdPass &fp = fwd[j];
+      PassArgs<R> a = base_args(fp.tile);
+      uint32_t f = PF_LOAD_PHI | PF_LOAD_LAM;
+      const bool last = (j == 0);
+      // part 1 undoes the forward pass's last rotation block
+      int l1 = fp.post >= 0 ? fp.post : fp.pre;
+      a.mask1 = tiles[fp.tile].rot;
+      f |= PF_XT1 | PF_ROT1_BOTH;
+      a.slot_off[SL_A] = slot_for(om.gb(l1));
+      if (fp.ph >= 0) {
+        f |= PF_GGAMMA;
+        a.table = table_for(fp.tile);
+        a.slot_off[SL_B] = slot_for(om.gg(fp.ph));
+        if (!last) f |= PF_PHASE | PF_PHASE_BOTH;
+      }
+      const bool has2 = (fp.post >= 0 && fp.pre >= 0);
+      if (has2) {
+        a.mask2 = tiles[fp.tile].rot;
+        f |= PF_XT2 | PF_ROT2_BOTH;
+        a.slot_off[SL_C] = slot_for(om.gb(fp.pre));
+      }
+      if (!last) f |= PF_STORE_PHI | PF_STORE_LAM;
+      a.flags = f;
+      for (int s = 0; s < nsets; s++) {
+        SetParams<R> q;
+        std::memset(&q, 0, sizeof(q));
+        q.lut = -1;
+        q.lam_rho = (R)1;
+        q.w1 = std::norm(sb[s]);
+        q.tau1 = -tau[s * p + l1];
+        q.swap1 = swp[s * p + l1];
+        sb[s] *= cpow_int(fi[s * p + l1], rotbits(fp.tile));
+        q.w2 = 1.0;
+        if (fp.ph >= 0 && !last) {
+          q.lut = (int)jobs.size();
+          jobs.push_back(LutJob{gam(s, fp.ph), sb[s].real(), sb[s].imag(), 1.0});
+          sb[s] = cd(1.0, 0.0);
+        }
+        if (has2) {
+          q.w2 = std::norm(sb[s]);
+          q.tau2 = -tau[s * p + fp.pre];
+          q.swap2 = swp[s * p + fp.pre];
+          sb[s] *= cpow_int(fi[s * p + fp.pre], rotbits(fp.tile));
+        }
+        sps.push_back(q);
+      }
+      passes.push_back(a);
+      nvs.push_back(2);
+    }
+  }
+
+  // ---------------- upload parameters (one copy), LUTs on the device
+  const size_t sp_bytes = sps.size() * sizeof(SetParams<R>);
+  const size_t job_bytes = jobs.size() * sizeof(LutJob);
+  const size_t cnt_bytes = nout * sizeof(int);
+  const size_t off_jobs = (sp_bytes + 255) & ~size_t(255);
+  const size_t off_cnt = (off_jobs + job_bytes + 255) & ~size_t(255);
+  const size_t total = off_cnt + cnt_bytes;
+  unsigned char *h = (unsigned char *)ctx->hparams.get(total);
+  // the previous call may still read the pinned staging buffer through its async copy
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(h, sps.data(), sp_bytes);
+  if (job_bytes) std::memcpy(h + off_jobs, jobs.data(), job_bytes);
+  std::memcpy(h + off_cnt, cnt.data(), cnt_bytes);
+  unsigned char *d = (unsigned char *)ctx->params.get(total);
+  HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
+  void *dluts = nullptr;
+  if (!jobs.empty()) {
+    dluts = ctx->luts.get(jobs.size() * (size_t)lut_len * esz);
+    HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobs), (int)jobs.size(), lut_len, dluts, st));
+  }
+  // ---------------- passes
+  for (size_t i = 0; i < passes.size(); i++) {
+    PassArgs<R> &a = passes[i];
+    a.sp = (const SetParams<R> *)(d + i * nsets * sizeof(SetParams<R>));
+    a.luts = dluts;
+    hipError_t e;
+    if constexpr (sizeof(R) == 4) e = launch_pass_f32(a, nvs[i], prob->tbytes, st);
+    else e = launch_pass_f64(a, nvs[i], prob->tbytes, st);
+    if (e != hipSuccess) throw fail(QAOA_ERR_HIP, std::string("pass launch: ") + hipGetErrorString(e));
+  }
+  // ---------------- reductions
+  double *dres = (double *)ctx->results.get((size_t)nsets * nout * sizeof(double));
+  HIPCHK(launch_finalize(dpart, (const int *)(d + off_cnt), maxc, nsets, nwg, nout, dres, st));
+  double *hres = (double *)ctx->hresults.get((size_t)nsets * nout * sizeof(double));
+  HIPCHK(hipMemcpyAsync(hres, dres, (size_t)nsets * nout * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (d_state_out) {
+    // nsets == 1 here: final state = sigma_p * phi
+    HIPCHK(launch_scale_copy(prec, dphi, d_state_out, N, sig_p[0].real(), sig_p[0].imag(), st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int s = 0; s < nsets; s++) {
+    const double *r = hres + (size_t)s * nout;
+    const double E = r[om.E()], Nr = r[om.Nr()];
+    if (out_expect) out_expect[s] = E / Nr;
+    if (grad && out_grad) {
+      const double ntrue = std::norm(sig_p[s]) * Nr;
+      for (int k = 0; k < p; k++) {
+        out_grad[(size_t)s * 2 * p + k] = 2.0 * r[om.gb(k)] / ntrue;
+        out_grad[(size_t)s * 2 * p + p + k] = 2.0 * r[om.gg(k)] / ntrue;
+      }
+    }
+  }
+}
+
+// Whole-state path: items of n <= SMALL_MAX_N, one workgroup each.
+void run_small(const std::vector<SmallItem> &items, int precision, const double *angles, int nsets,
+               int p, int grad, double *hout, qaoa_ctx *ctx, hipStream_t st) {
+  (void)nsets;
+  int max_n = 1, max_tb = 1, max_lut = 1;
+  for (auto &it : items) {
+    max_n = std::max(max_n, it.n);
+    max_tb = std::max(max_tb, it.tbytes);
+    max_lut = std::max(max_lut, it.lut_len);
+  }
+  max_lut = (max_lut + 15) & ~15;
+  const int rowlen = 1 + 2 * p;
+  size_t ib = items.size() * sizeof(SmallItem);
+  size_t ab = (size_t)nsets * 2 * p * sizeof(double);
+  size_t off_a = (ib + 255) & ~size_t(255);
+  size_t total = off_a + ab;
+  unsigned char *h = (unsigned char *)ctx->hparams.get(total);
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(h, items.data(), ib);
+  std::memcpy(h + off_a, angles, ab);
+  unsigned char *d = (unsigned char *)ctx->items.get(total);
+  HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
+  int nrow = 0;
+  for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
+  double *dres = (double *)ctx->results.get((size_t)nrow * rowlen * sizeof(double));
+  HIPCHK(launch_small(precision, (const SmallItem *)d, (int)items.size(), max_n, max_tb, max_lut,
+                      (const double *)(d + off_a), p, grad, dres, st));
+  HIPCHK(hipMemcpyAsync(hout, dres, (size_t)nrow * rowlen * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void check_angles(int p, const double *angles, size_t count) {
+  REQUIRE(p >= 1 && p <= 4096, "p must be in [1, 4096]");
+  REQUIRE(angles != nullptr, "angles is NULL");
+  for (size_t i = 0; i < count; i++) REQUIRE(std::isfinite(angles[i]), "angles must be finite");
+}
+
+void check_pair(const qaoa_problem *prob, const qaoa_mixer *mix, int precision) {
+  REQUIRE(prob && mix, "problem or mixer is NULL");
+  REQUIRE(prob->ctx == mix->ctx, "problem and mixer belong to different contexts");
+  REQUIRE(precision == QAOA_FP32 || precision == QAOA_FP64, "precision must be QAOA_FP32 or QAOA_FP64");
+  REQUIRE(prob->n == mix->n, "mixer and problem have different qubit counts");
+  if (mix->kind == 0) REQUIRE(prob->k < 0, "the transverse-field mixer needs an unconstrained problem");
+  else REQUIRE(prob->k == mix->k, "the clique mixer's Hamming weight differs from the problem's");
+}
+
+bool small_path(const qaoa_problem *prob, int precision) {
+  return prob->n <= (precision == QAOA_FP32 ? SMALL_MAX_N_F32 : SMALL_MAX_N_F64);
+}
+
+SmallItem small_item(const qaoa_problem *prob, int set, int row) {
+  SmallItem it;
+  it.table = prob->table;
+  it.n = prob->n;
+  it.tbytes = prob->tbytes;
+  it.lut_len = (int)prob->max_value + 1;
+  it.angle_set = set;
+  it.c0 = prob->mean;
+  it.out_index = row;
+  return it;
+}
+
+void evaluate_x(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
+                int precision, int grad, double *out_expect, double *out_grad, void *d_state,
+                hipStream_t st) {
+  if (small_path(prob, precision) && !d_psi0 && !d_state) {
+    if (prob->max_value + 1 > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+    std::vector<SmallItem> items;
+    for (int s = 0; s < nsets; s++) items.push_back(small_item(prob, s, s));
+    std::vector<double> hout((size_t)nsets * (1 + 2 * p));
+    run_small(items, precision, angles, nsets, p, grad, hout.data(), prob->ctx, st);
+    for (int s = 0; s < nsets; s++) {
+      const double *r = hout.data() + (size_t)s * (1 + 2 * p);
+      if (out_expect) out_expect[s] = r[0];
+      if (grad && out_grad) std::memcpy(out_grad + (size_t)s * 2 * p, r + 1, 2 * p * sizeof(double));
+    }
+    return;
+  }
+  const int T = precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
+  if (prob->n <= T)
+    throw fail(QAOA_ERR_UNSUPPORTED, "initial state or state output needs n > tile size (use n >= 14)");
+  if (precision == QAOA_FP32)
+    run_x_path<float>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, d_state, st);
+  else
+    run_x_path<double>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, d_state, st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *qaoa_status_string(int status) {
+  switch (status) {
+    case QAOA_OK: return "ok";
+    case QAOA_ERR_INVALID_ARG: return "invalid argument";
+    case QAOA_ERR_OUT_OF_MEMORY: return "out of memory";
+    case QAOA_ERR_HIP: return "HIP runtime error";
+    case QAOA_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char *qaoa_last_error(void) { return g_last_error.c_str(); }
+
+int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
+  return guarded([&] {
+    REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    REQUIRE(hip_device >= 0 && hip_device < count, "no such HIP device");
+    DeviceGuard g(hip_device);
+    auto c = std::make_unique<qaoa_ctx>();
+    c->device = hip_device;
+    *out = c.release();
+  });
+}
+
+int qaoa_ctx_destroy(qaoa_ctx *ctx) {
+  return guarded([&] {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    delete ctx;
+  });
+}
+
+int qaoa_cost_table(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const int32_t *v,
+                    const int32_t *w, int hamming_k, qaoa_problem **out, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 32, "n must be in [1, 32]");
+    REQUIRE(n_edges >= 0 && n_edges <= 512, "n_edges must be in [0, 512]");
+    REQUIRE(n_edges == 0 || (u && v), "edge arrays are NULL");
+    REQUIRE(hamming_k <= n, "hamming_k must be <= n");
+    int64_t W = 0;
+    for (int e = 0; e < n_edges; e++) {
+      REQUIRE(u[e] >= 0 && u[e] < n && v[e] >= 0 && v[e] < n, "edge endpoint out of range");
+      REQUIRE(u[e] != v[e], "self-loop edge");
+      int64_t we = w ? w[e] : 1;
+      REQUIRE(we >= 0, "negative edge weight");
+      W += we;
+    }
+    REQUIRE(W <= 65535, "total edge weight must be <= 65535");
+    uint64_t N = hamming_k < 0 ? (1ull << n) : (uint64_t)binom64(n, hamming_k);
+    if (hamming_k >= 0) REQUIRE(N <= (1ull << 26), "feasible subspace larger than 2^26 states");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    auto prob = std::make_unique<qaoa_problem>();
+    prob->ctx = ctx;
+    prob->n = n;
+    prob->k = hamming_k < 0 ? -1 : hamming_k;
+    prob->N = N;
+    prob->tbytes = W <= 255 ? 1 : 2;
+    prob->total_weight = W;
+    if (hamming_k < 0) prob->mean = 0.5 * (double)W;
+    else if (n >= 2 && N > 0)
+      prob->mean = (double)W * 2.0 * (double)binom64(n - 2, hamming_k - 1) / (double)N;
+    // edges to the device
+    DevBuf de;
+    int32_t *dd = nullptr;
+    if (n_edges > 0) {
+      dd = (int32_t *)de.get(3 * n_edges * sizeof(int32_t));
+      std::vector<int32_t> hv(3 * n_edges);
+      for (int e = 0; e < n_edges; e++) {
+        hv[e] = u[e];
+        hv[n_edges + e] = v[e];
+        hv[2 * n_edges + e] = w ? w[e] : 1;
+      }
+      HIPCHK(hipMemcpyAsync(dd, hv.data(), hv.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    if (hipMalloc(&prob->table, N * prob->tbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      prob->table = nullptr;
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "table allocation failed");
+    }
+    const int32_t *du = dd, *dv = dd ? dd + n_edges : nullptr, *dw = dd ? dd + 2 * n_edges : nullptr;
+    if (hamming_k < 0) {
+      HIPCHK(launch_cost_table_full(n, n_edges, du, dv, dw, prob->table, prob->tbytes, st));
+    } else {
+      std::vector<int64_t> hb(33 * 33);
+      for (int a = 0; a <= 32; a++)
+        for (int b = 0; b <= 32; b++) hb[a * 33 + b] = binom64(a, b);
+      DevBuf db;
+      int64_t *dbin = (int64_t *)db.get(hb.size() * sizeof(int64_t));
+      HIPCHK(hipMemcpyAsync(dbin, hb.data(), hb.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      HIPCHK(launch_cost_table_hw(n, hamming_k, n_edges, du, dv, dw, dbin, N, prob->table,
+                                  prob->tbytes, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    DevBuf dm;
+    unsigned *dmax = (unsigned *)dm.get(sizeof(unsigned));
+    HIPCHK(hipMemsetAsync(dmax, 0, sizeof(unsigned), st));
+    HIPCHK(launch_table_max(prob->table, prob->tbytes, N, dmax, st));
+    unsigned hmax = 0;
+    HIPCHK(hipMemcpyAsync(&hmax, dmax, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    prob->max_value = hmax;
+    *out = prob.release();
+  });
+}
+
+int qaoa_problem_copy_table(const qaoa_problem *prob, int64_t *host_dst, size_t len, void *stream) {
+  return guarded([&] {
+    REQUIRE(prob && host_dst, "problem or destination is NULL");
+    REQUIRE(len == prob->N, "len differs from the feasible-set size");
+    DeviceGuard g(prob->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf tmp;
+    int64_t *d = (int64_t *)tmp.get(prob->N * sizeof(int64_t));
+    HIPCHK(launch_table_widen(prob->table, prob->tbytes, d, prob->N, st));
+    HIPCHK(hipMemcpyAsync(host_dst, d, prob->N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+int qaoa_problem_info(const qaoa_problem *prob, int *n, int *hamming_k, int64_t *size,
+                      int64_t *max_value) {
+  return guarded([&] {
+    REQUIRE(prob != nullptr, "problem is NULL");
+    if (n) *n = prob->n;
+    if (hamming_k) *hamming_k = prob->k;
+    if (size) *size = (int64_t)prob->N;
+    if (max_value) *max_value = prob->max_value;
+  });
+}
+
+int qaoa_problem_destroy(qaoa_problem *prob) {
+  return guarded([&] {
+    if (!prob) return;
+    DeviceGuard g(prob->ctx->device);
+    delete prob;
+  });
+}
+
+int qaoa_mixer_x(qaoa_ctx *ctx, int n, qaoa_mixer **out) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 32, "n must be in [1, 32]");
+    auto m = std::make_unique<qaoa_mixer>();
+    m->ctx = ctx;
+    m->kind = 0;
+    m->n = n;
+    *out = m.release();
+  });
+}
+
+int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 2 && n <= 20, "n must be in [2, 20]");
+    REQUIRE(k >= 1 && k <= n - 1, "k must be in [1, n-1]");
+    REQUIRE(binom64(n, k) <= 16384, "C(n,k) must be <= 16384");
+    DeviceGuard g(ctx->device);
+    auto m = std::make_unique<qaoa_mixer>();
+    m->ctx = ctx;
+    m->kind = 1;
+    m->n = n;
+    m->k = k;
+    m->clique = clique_create(n, k, (hipStream_t)stream);
+    *out = m.release();
+  });
+}
+
+int qaoa_mixer_destroy(qaoa_mixer *mix) {
+  return guarded([&] {
+    if (!mix) return;
+    DeviceGuard g(mix->ctx->device);
+    delete mix;
+  });
+}
+
+static void evaluate(const qaoa_problem *cprob, const qaoa_mixer *mix, int p, const double *angles,
+                     int nsets, const void *d_psi0, int precision, int grad, double *out_expect,
+                     double *out_grad, void *d_state, hipStream_t st) {
+  qaoa_problem *prob = const_cast<qaoa_problem *>(cprob);
+  if (mix->kind == 0) {
+    evaluate_x(prob, p, angles, nsets, d_psi0, precision, grad, out_expect, out_grad, d_state, st);
+  } else {
+    CliqueEval ev;
+    ev.table = prob->table;
+    ev.tbytes = prob->tbytes;
+    ev.N = (int64_t)prob->N;
+    ev.lut_len = (int)prob->max_value + 1;
+    ev.c0 = prob->mean;
+    clique_evaluate(*mix->clique, ev, p, angles, nsets, d_psi0, precision, grad, out_expect,
+                    out_grad, d_state, st);
+  }
+}
+
+int qaoa_expect(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles,
+                const void *d_psi0, int precision, double *out_expect, void *stream) {
+  return guarded([&] {
+    check_pair(prob, mix, precision);
+    check_angles(p, angles, 2 * (size_t)p);
+    REQUIRE(out_expect != nullptr, "out_expect is NULL");
+    DeviceGuard g(prob->ctx->device);
+    evaluate(prob, mix, p, angles, 1, d_psi0, precision, 0, out_expect, nullptr, nullptr,
+             (hipStream_t)stream);
+  });
+}
+
+int qaoa_expect_grad(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles,
+                     const void *d_psi0, int precision, double *out_expect, double *out_grad,
+                     void *stream) {
+  return guarded([&] {
+    check_pair(prob, mix, precision);
+    check_angles(p, angles, 2 * (size_t)p);
+    REQUIRE(out_expect && out_grad, "output pointer is NULL");
+    DeviceGuard g(prob->ctx->device);
+    evaluate(prob, mix, p, angles, 1, d_psi0, precision, 1, out_expect, out_grad, nullptr,
+             (hipStream_t)stream);
+  });
+}
+
+int qaoa_state(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles,
+               const void *d_psi0, int precision, void *d_out, void *stream) {
+  return guarded([&] {
+    check_pair(prob, mix, precision);
+    check_angles(p, angles, 2 * (size_t)p);
+    REQUIRE(d_out != nullptr, "d_out is NULL");
+    DeviceGuard g(prob->ctx->device);
+    double e;
+    evaluate(prob, mix, p, angles, 1, d_psi0, precision, 0, &e, nullptr, d_out, (hipStream_t)stream);
+  });
+}
+
+static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_probs,
+                    int n_sets, int p, const double *angles, int precision, int grad,
+                    double *out_expect, double *out_grad, hipStream_t st) {
+  REQUIRE(probs && mixers, "probs or mixers is NULL");
+  REQUIRE(n_probs >= 1 && n_sets >= 1, "n_probs and n_sets must be >= 1");
+  check_angles(p, angles, (size_t)n_sets * 2 * p);
+  REQUIRE(out_expect != nullptr && (!grad || out_grad != nullptr), "output pointer is NULL");
+  qaoa_ctx *ctx = probs[0] ? probs[0]->ctx : nullptr;
+  for (int i = 0; i < n_probs; i++) {
+    check_pair(probs[i], mixers[i], precision);
+    REQUIRE(probs[i]->ctx == ctx, "all problems must share one context");
+  }
+  DeviceGuard g(ctx->device);
+  const int g2p = 2 * p;
+  // whole-state items first (one launch), then the larger problems one by one
+  std::vector<SmallItem> items;
+  std::vector<int> small_probs;
+  for (int i = 0; i < n_probs; i++) {
+    if (mixers[i]->kind == 0 && small_path(probs[i], precision)) {
+      if (probs[i]->max_value + 1 > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+      for (int s = 0; s < n_sets; s++)
+        items.push_back(small_item(probs[i], s, (int)small_probs.size() * n_sets + s));
+      small_probs.push_back(i);
+    }
+  }
+  if (!items.empty()) {
+    std::vector<double> hout((size_t)small_probs.size() * n_sets * (1 + g2p));
+    run_small(items, precision, angles, n_sets, p, grad, hout.data(), ctx, st);
+    for (size_t j = 0; j < small_probs.size(); j++)
+      for (int s = 0; s < n_sets; s++) {
+        const double *r = hout.data() + ((size_t)j * n_sets + s) * (1 + g2p);
+        int i = small_probs[j];
+        out_expect[(size_t)i * n_sets + s] = r[0];
+        if (grad) std::memcpy(out_grad + ((size_t)i * n_sets + s) * g2p, r + 1, g2p * sizeof(double));
+      }
+  }
+  for (int i = 0; i < n_probs; i++) {
+    if (mixers[i]->kind == 0 && small_path(probs[i], precision)) continue;
+    evaluate(probs[i], mixers[i], p, angles, n_sets, nullptr, precision, grad,
+             out_expect + (size_t)i * n_sets, grad ? out_grad + (size_t)i * n_sets * g2p : nullptr,
+             nullptr, st);
+  }
+}
+
+int qaoa_expect_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
+                        int n_probs, int n_sets, int p, const double *angles, int precision,
+                        double *out_expect, void *stream) {
+  return guarded([&] {
+    batched(probs, mixers, n_probs, n_sets, p, angles, precision, 0, out_expect, nullptr,
+            (hipStream_t)stream);
+  });
+}
+
+int qaoa_expect_grad_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
+                             int n_probs, int n_sets, int p, const double *angles, int precision,
+                             double *out_expect, double *out_grad, void *stream) {
+  return guarded([&] {
+    batched(probs, mixers, n_probs, n_sets, p, angles, precision, 1, out_expect, out_grad,
+            (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

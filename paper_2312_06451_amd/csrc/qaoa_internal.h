@@ -1,0 +1,125 @@
+// Internal declarations shared by the HIP kernels (qaoa_kernels.hip) and the host runtime
+// (qaoa_api.cpp). Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qaoa {
+
+// Tile of the X-mixer pass kernels: 2^T amplitudes per workgroup, 256 threads, 2^(T-8)
+// amplitudes per thread and vector held in registers. FP32 uses T=13 (64 KiB of complex64
+// per vector), FP64 uses T=12 (64 KiB of complex128).
+constexpr int TILE_BITS_F32 = 13;
+constexpr int TILE_BITS_F64 = 12;
+constexpr int PASS_THREADS = 256;
+// Shortest run of contiguous amplitudes a strided tile keeps together (256 B either way).
+constexpr int MIN_CONTIG_F32 = 5;
+constexpr int MIN_CONTIG_F64 = 4;
+// Whole-state (one workgroup per item) kernel: both vectors resident in LDS.
+constexpr int SMALL_MAX_N_F32 = 13;
+constexpr int SMALL_MAX_N_F64 = 12;
+constexpr int SMALL_THREADS = 256;
+// Largest phase lookup table (largest C + 1) the kernels stage in LDS.
+constexpr int MAX_LUT = 1024;
+
+// Pass flags (X-mixer tile passes). A pass runs: load, part 1 (register stages H, M, L),
+// middle (elementwise steps at the end of part 1), part 2 (stages L, M, H), store.
+enum : uint32_t {
+  PF_GEN_PHI = 1u << 0,      // phi <- uniform amplitude u0 instead of loading
+  PF_LOAD_PSI0 = 1u << 1,    // phi <- caller's initial state (natural layout)
+  PF_LOAD_PHI = 1u << 2,
+  PF_LOAD_LAM = 1u << 3,
+  PF_EXPECT = 1u << 4,       // middle: E += |phi|^2 C, N += |phi|^2
+  PF_LAMBDA = 1u << 5,       // middle: lam <- rho (C - c0) phi
+  PF_GGAMMA = 1u << 6,       // middle: += w Im(conj(lam) C phi)
+  PF_PHASE = 1u << 7,        // middle: phi *= LUT[C]
+  PF_STORE_PHI = 1u << 8,
+  PF_STORE_LAM = 1u << 9,
+  PF_XT1 = 1u << 10,         // part 1: X-pair terms of each rotated bit, before rotating it
+  PF_XT2 = 1u << 11,         // part 2: same
+  PF_ROT1_BOTH = 1u << 12,   // part 1 also rotates lam
+  PF_ROT2_BOTH = 1u << 13,   // part 2 also rotates lam
+  PF_PHASE_BOTH = 1u << 14,  // the phase also applies to lam
+  PF_SCALE_OUT = 1u << 15,   // phi *= out_scale before storing
+};
+
+// Partial-sum slots of one pass.
+enum { SL_A = 0, SL_B = 1, SL_C = 2, NSLOT = 3 };
+
+// Per (pass, angle set) parameters, read by every workgroup of the set.
+template <typename R>
+struct SetParams {
+  R tau1, tau2;          // rotation parameter of part 1 / part 2
+  int swap1, swap2;      // rotation in the output-swapped form
+  double w1, w2;         // inner-product weight at the start of part 1 / part 2
+  R lam_rho;             // lambda = lam_rho * (C - c0) * phi
+  R out_re, out_im;      // output scale (PF_SCALE_OUT)
+  int lut;               // index of this set's LUT in the LUT array (-1: none)
+};
+
+// Pass descriptor (kernel argument). Geometry: tile bits [0,c) are address bits [0,c);
+// tile bits [c,T) are address bits [h0, h0+T-c); a workgroup's remaining address bits are
+// [c,h0) and [h0+T-c, n), filled from its tile index r.
+template <typename R>
+struct PassArgs {
+  int n, c, h0;
+  uint32_t nwg;            // tiles per vector = 2^(n-T)
+  int xcd_remap;           // give each XCD a contiguous range of tiles
+  int nsets;               // angle sets (grid.y)
+  uint64_t vstride;        // elements between consecutive sets' vectors
+  void *phi, *lam;
+  const void *psi0;        // natural layout, shared by all sets
+  const void *table;       // tile-major table of this geometry: table[r * 2^T + e]
+  const void *luts;        // lut_len complex<R> entries per LUT
+  int lut_len;
+  uint32_t flags;
+  uint32_t mask1, mask2;   // tile bits rotated in part 1 / part 2
+  R u0;                    // uniform initial amplitude
+  R lam_c0;
+  const SetParams<R> *sp;  // [nsets]
+  double *partials;        // slot s of set q, tile b: partials[slot_off[s] + q * nwg + b]
+  int64_t slot_off[NSLOT]; // -1: slot unused
+};
+
+// LUT construction job: luts[i][c] = scale_i * exp(sign_i * i * gamma_i * c), c < lut_len.
+struct LutJob {
+  double gamma, sre, sim, sign;
+};
+
+// Whole-state kernel item: one workgroup evolves one (problem, angle set) pair.
+struct SmallItem {
+  const void *table;    // device table (2^n entries), uint8 or uint16
+  int n;
+  int tbytes;           // 1 or 2
+  int lut_len;          // largest C + 1
+  int angle_set;        // row of the angle array
+  double c0;            // centre of lambda = (C - c0) psi
+  int out_index;        // output row: out[out_index * (1 + 2p) + ...]
+};
+
+// ---------------------------------------------------------------- launch wrappers
+hipError_t launch_cost_table_full(int n, int m, const int32_t *du, const int32_t *dv,
+                                  const int32_t *dw, void *table, int tbytes, hipStream_t s);
+hipError_t launch_cost_table_hw(int n, int k, int m, const int32_t *du, const int32_t *dv,
+                                const int32_t *dw, const int64_t *dbinom, uint64_t N,
+                                void *table, int tbytes, hipStream_t s);
+hipError_t launch_table_max(const void *table, int tbytes, uint64_t N, unsigned *dmax,
+                            hipStream_t s);
+hipError_t launch_table_relayout(const void *src, void *dst, int tbytes, int n, int T, int c,
+                                 int h0, hipStream_t s);
+hipError_t launch_table_widen(const void *src, int tbytes, int64_t *dst, uint64_t N,
+                              hipStream_t s);
+hipError_t launch_luts(int precision, const LutJob *jobs, int njobs, int lut_len, void *luts,
+                       hipStream_t s);
+hipError_t launch_pass_f32(const PassArgs<float> &a, int nv, int tbytes, hipStream_t s);
+hipError_t launch_pass_f64(const PassArgs<double> &a, int nv, int tbytes, hipStream_t s);
+hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
+                           int64_t nwg, int nout, double *out, hipStream_t s);
+hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
+                        int max_tbytes, int max_lut, const double *angles, int p, int grad,
+                        double *out, hipStream_t s);
+hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
+                             double im, hipStream_t s);
+size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
+
+}  // namespace qaoa
