@@ -141,6 +141,27 @@ int qaoa_expect_grad_batched(const qaoa_problem *const *probs, const qaoa_mixer 
                              int n_probs, int n_sets, int p, const double *angles, int precision,
                              double *out_expect, double *out_grad, void *stream);
 
+/* Kernel timing (a tracing aid). While enabled, every kernel launch an evaluation on this
+ * context makes is bracketed by two HIP events recorded on the call's stream; after the
+ * call's final synchronisation the elapsed times are added to per-class totals together
+ * with the launch's algorithmic bytes (each vector read and written once, plus the cost
+ * table when the kernel reads it). Classes: QAOA_KC_FWD_PASS (tile pass over one vector),
+ * QAOA_KC_REV_PASS (tile pass over the state and the adjoint vector), QAOA_KC_SMALL
+ * (whole-state kernel), QAOA_KC_DENSE (constrained-mixer products), QAOA_KC_OTHER
+ * (lookup tables, reductions). enable: 1 on, 0 off; enabling clears the totals. */
+#define QAOA_KC_FWD_PASS 0
+#define QAOA_KC_REV_PASS 1
+#define QAOA_KC_SMALL 2
+#define QAOA_KC_DENSE 3
+#define QAOA_KC_OTHER 4
+#define QAOA_KC_COUNT 5
+int qaoa_profile_enable(qaoa_ctx *ctx, int enable);
+
+/* Totals of class `kernel_class` since the last enable: launches, summed milliseconds,
+ * summed algorithmic bytes and summed algorithmic flops. Any output may be NULL. */
+int qaoa_profile_read(const qaoa_ctx *ctx, int kernel_class, int64_t *launches, double *ms,
+                      double *bytes, double *flops);
+
 /* Static text for a status code. */
 const char *qaoa_status_string(int status);
 

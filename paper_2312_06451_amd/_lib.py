@@ -23,8 +23,10 @@ EXPORTED = [
     "qaoa_ctx_create", "qaoa_ctx_destroy", "qaoa_cost_table", "qaoa_problem_copy_table",
     "qaoa_problem_info", "qaoa_problem_destroy", "qaoa_mixer_x", "qaoa_mixer_clique",
     "qaoa_mixer_destroy", "qaoa_expect", "qaoa_expect_grad", "qaoa_state", "qaoa_expect_batched",
-    "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error",
+    "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error", "qaoa_profile_enable",
+    "qaoa_profile_read",
 ]
+KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4}
 
 
 class QAOAError(RuntimeError):
@@ -73,6 +75,8 @@ def lib() -> ctypes.CDLL:
                                       P(c_double), c_void_p]
     L.qaoa_expect_grad_batched.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, c_int, P(c_double),
                                            c_int, P(c_double), P(c_double), c_void_p]
+    L.qaoa_profile_enable.argtypes = [c_void_p, c_int]
+    L.qaoa_profile_read.argtypes = [c_void_p, c_int, P(c_int64), P(c_double), P(c_double), P(c_double)]
     L.qaoa_status_string.argtypes = [c_int]
     L.qaoa_status_string.restype = ctypes.c_char_p
     L.qaoa_last_error.argtypes = []
@@ -215,3 +219,14 @@ def qaoa_expect_grad_batched(probs, mixers, p: int, angles, precision: int = QAO
                                          out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)),
                                          stream), "qaoa_expect_grad_batched")
     return out, g
+
+
+def qaoa_profile_enable(ctx: int, enable: bool = True) -> None:
+    check(lib().qaoa_profile_enable(ctx, 1 if enable else 0), "qaoa_profile_enable")
+
+
+def qaoa_profile_read(ctx: int, kernel_class: int) -> dict:
+    n, ms, by, fl = c_int64(), c_double(), c_double(), c_double()
+    check(lib().qaoa_profile_read(ctx, kernel_class, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                  ctypes.byref(fl)), "qaoa_profile_read")
+    return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}

@@ -129,11 +129,82 @@ int64_t binom64(int n, int k) {
 
 // ---------------------------------------------------------------- handles
 
+struct KTotals {
+  int64_t launches = 0;
+  double ms = 0, bytes = 0, flops = 0;
+};
+
 struct qaoa_ctx {
   int device = 0;
   DevBuf phi, lam, partials, params, luts, results, cnt, items;
   HostBuf hparams, hresults;
+  // kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<Pending> pending;
+  KTotals totals[QAOA_KC_COUNT];
+  ~qaoa_ctx() {
+    for (auto e : ev_pool) hipEventDestroy(e);
+    for (auto &p : pending) {
+      hipEventDestroy(p.a);
+      hipEventDestroy(p.b);
+    }
+  }
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
 };
+
+// Brackets one launch with events when the context profiles (no-op otherwise).
+struct KTimer {
+  qaoa_ctx *ctx;
+  hipStream_t st;
+  int cls;
+  double bytes, flops;
+  hipEvent_t a = nullptr;
+  KTimer(qaoa_ctx *c, hipStream_t s, int k, double by, double fl) : ctx(c), st(s), cls(k), bytes(by), flops(fl) {
+    if (ctx->profiling) {
+      a = ctx->take_event();
+      HIPCHK(hipEventRecord(a, st));
+    }
+  }
+  void done() {
+    if (!a) return;
+    hipEvent_t b = ctx->take_event();
+    HIPCHK(hipEventRecord(b, st));
+    ctx->pending.push_back({cls, a, b, bytes, flops});
+    a = nullptr;
+  }
+};
+
+// After the stream synchronised: fold recorded event pairs into the totals.
+static void profile_collect(qaoa_ctx *ctx) {
+  for (auto &p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      KTotals &t = ctx->totals[p.cls];
+      t.launches++;
+      t.ms += ms;
+      t.bytes += p.bytes;
+      t.flops += p.flops;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
 
 struct qaoa_problem {
   qaoa_ctx *ctx = nullptr;
@@ -501,14 +572,28 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     PassArgs<R> &a = passes[i];
     a.sp = (const SetParams<R> *)(d + i * nsets * sizeof(SetParams<R>));
     a.luts = dluts;
+    const uint32_t fl = a.flags;
+    double by = 0;
+    if (fl & (PF_LOAD_PHI | PF_LOAD_PSI0)) by += (double)N * esz;
+    if (fl & PF_LOAD_LAM) by += (double)N * esz;
+    if (fl & PF_STORE_PHI) by += (double)N * esz;
+    if (fl & PF_STORE_LAM) by += (double)N * esz;
+    if (fl & (PF_EXPECT | PF_LAMBDA | PF_GGAMMA | PF_PHASE)) by += (double)N * prob->tbytes;
+    by *= nsets;
+    KTimer kt(ctx, st, nvs[i] == 2 ? QAOA_KC_REV_PASS : QAOA_KC_FWD_PASS, by, 0.0);
     hipError_t e;
     if constexpr (sizeof(R) == 4) e = launch_pass_f32(a, nvs[i], prob->tbytes, st);
     else e = launch_pass_f64(a, nvs[i], prob->tbytes, st);
     if (e != hipSuccess) throw fail(QAOA_ERR_HIP, std::string("pass launch: ") + hipGetErrorString(e));
+    kt.done();
   }
   // ---------------- reductions
   double *dres = (double *)ctx->results.get((size_t)nsets * nout * sizeof(double));
-  HIPCHK(launch_finalize(dpart, (const int *)(d + off_cnt), maxc, nsets, nwg, nout, dres, st));
+  {
+    KTimer kt(ctx, st, QAOA_KC_OTHER, (double)part_elems * 8.0, 0.0);
+    HIPCHK(launch_finalize(dpart, (const int *)(d + off_cnt), maxc, nsets, nwg, nout, dres, st));
+    kt.done();
+  }
   double *hres = (double *)ctx->hresults.get((size_t)nsets * nout * sizeof(double));
   HIPCHK(hipMemcpyAsync(hres, dres, (size_t)nsets * nout * sizeof(double), hipMemcpyDeviceToHost, st));
   if (d_state_out) {
@@ -516,6 +601,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     HIPCHK(launch_scale_copy(prec, dphi, d_state_out, N, sig_p[0].real(), sig_p[0].imag(), st));
   }
   HIPCHK(hipStreamSynchronize(st));
+  profile_collect(ctx);
   for (int s = 0; s < nsets; s++) {
     const double *r = hres + (size_t)s * nout;
     const double E = r[om.E()], Nr = r[om.Nr()];
@@ -555,10 +641,15 @@ void run_small(const std::vector<SmallItem> &items, int precision, const double 
   int nrow = 0;
   for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
   double *dres = (double *)ctx->results.get((size_t)nrow * rowlen * sizeof(double));
+  double by = 0;
+  for (auto &it : items) by += (double)it.tbytes * (double)(1ull << it.n);
+  KTimer kt(ctx, st, QAOA_KC_SMALL, by, 0.0);
   HIPCHK(launch_small(precision, (const SmallItem *)d, (int)items.size(), max_n, max_tb, max_lut,
                       (const double *)(d + off_a), p, grad, dres, st));
+  kt.done();
   HIPCHK(hipMemcpyAsync(hout, dres, (size_t)nrow * rowlen * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  profile_collect(ctx);
 }
 
 void check_angles(int p, const double *angles, size_t count) {
@@ -647,6 +738,27 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
     auto c = std::make_unique<qaoa_ctx>();
     c->device = hip_device;
     *out = c.release();
+  });
+}
+
+int qaoa_profile_enable(qaoa_ctx *ctx, int enable) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr, "ctx is NULL");
+    ctx->profiling = enable != 0;
+    for (auto &t : ctx->totals) t = KTotals{};
+  });
+}
+
+int qaoa_profile_read(const qaoa_ctx *ctx, int kernel_class, int64_t *launches, double *ms,
+                      double *bytes, double *flops) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr, "ctx is NULL");
+    REQUIRE(kernel_class >= 0 && kernel_class < QAOA_KC_COUNT, "no such kernel class");
+    const KTotals &t = ctx->totals[kernel_class];
+    if (launches) *launches = t.launches;
+    if (ms) *ms = t.ms;
+    if (bytes) *bytes = t.bytes;
+    if (flops) *flops = t.flops;
   });
 }
 
