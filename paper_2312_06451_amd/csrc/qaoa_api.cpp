@@ -277,20 +277,21 @@ std::vector<FwdPass> make_forward(int K, int p) {
   return out;
 }
 
-// Rotation parameters of e^{-i beta X} (see the kernel file header): tau and swap for the
-// kernel, f = dropped scalar of the forward rotation, finv = of the inverse rotation.
+// Rotation parameters of e^{-i beta X} (see the kernel file header): tau for the kernel,
+// flip = 1 when the applied operator omits an X (tau = -cot beta), f = dropped scalar of the
+// forward rotation, finv = of the inverse rotation.
 template <typename R>
-void rot_params(double beta, R &tau, int &swap, cd &f, cd &finv) {
+void rot_params(double beta, R &tau, int &flip, cd &f, cd &finv) {
   double sb = std::sin(beta), cb = std::cos(beta);
   if (std::fabs(sb) <= std::fabs(cb)) {
     tau = (R)(sb / cb);
-    swap = 0;
+    flip = 0;
     double t = (double)tau, nrm = 1.0 / std::sqrt(1.0 + t * t);
     f = cd(cb < 0 ? -nrm : nrm, 0.0);
     finv = f;
   } else {
     tau = (R)(-cb / sb);
-    swap = 1;
+    flip = 1;
     double t = (double)tau, s = (sb < 0 ? -1.0 : 1.0) / std::sqrt(1.0 + t * t);
     f = cd(0.0, -s);
     finv = cd(0.0, s);
@@ -371,7 +372,9 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   auto gam = [&](int s, int k) { return angles[(size_t)s * 2 * p + p + k]; };
 
   std::vector<PassArgs<R>> passes;
-  std::vector<int> nvs;
+  std::vector<int> nvs;     // kernel kind: 1 forward, 2 reverse, 3 fused
+  std::vector<int> shapes;  // 0: part 1 only, 1: both parts, 2: part 2 only
+  std::vector<int> sxs;     // register stages holding the tile's rotated bits
   std::vector<SetParams<R>> sps;
   std::vector<LutJob> jobs;
   std::vector<int> cnt(nout, 0);
@@ -405,6 +408,21 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
 
   std::vector<cd> sig(nsets, cd(1.0, 0.0));
   auto rotbits = [&](int tile) { return __builtin_popcount(tiles[tile].rot); };
+  // register groups of the pass kernels: H = tile bits [8,T), M = [T-8, 8), L = [0, T-8)
+  auto stage_set = [&](int tile) {
+    const uint32_t rot = tiles[tile].rot, RB = T - 8;
+    const uint32_t H = ((1u << T) - 1) & ~((1u << 8) - 1), M = ((1u << 8) - 1) & ~((1u << RB) - 1),
+                   L = (1u << RB) - 1;
+    int sx = ((rot & H) ? 1 : 0) | ((rot & M) ? 2 : 0) | ((rot & L) ? 4 : 0);
+    if (sx != 7 && sx != 3 && sx != 1) throw fail(QAOA_ERR_HIP, "internal: unsupported tile stage set");
+    return sx;
+  };
+  auto add_pass = [&](const PassArgs<R> &a, int kind, int shape, int tile) {
+    passes.push_back(a);
+    nvs.push_back(kind);
+    shapes.push_back(shape);
+    sxs.push_back(stage_set(tile));
+  };
   const int npf = (int)fwd.size();
 
   // ---------------- forward passes (all but the last)
@@ -430,7 +448,6 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       q.lam_rho = (R)1;
       if (fp.pre >= 0) {
         q.tau1 = tau[s * p + fp.pre];
-        q.swap1 = swp[s * p + fp.pre];
         sig[s] *= cpow_int(ff[s * p + fp.pre], rotbits(fp.tile));
       }
       if (fp.ph >= 0) {
@@ -440,13 +457,11 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       }
       if (fp.post >= 0) {
         q.tau2 = tau[s * p + fp.post];
-        q.swap2 = swp[s * p + fp.post];
         sig[s] *= cpow_int(ff[s * p + fp.post], rotbits(fp.tile));
       }
       sps.push_back(q);
     }
-    passes.push_back(a);
-    nvs.push_back(1);
+    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile);
   }
 
   // ---------------- last forward pass (alone, or fused with the start of the reverse sweep)
@@ -475,7 +490,6 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       std::memset(&q, 0, sizeof(q));
       q.lut = -1;
       q.tau1 = tau[s * p + lp.pre];
-      q.swap1 = swp[s * p + lp.pre];
       sig[s] *= cpow_int(ff[s * p + lp.pre], rotbits(lp.tile));
       sig_p[s] = sig[s];
       double t = (double)q.tau1;
@@ -484,11 +498,10 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       q.w1 = 1.0;
       q.w2 = std::norm(sig_p[s]) / (double)q.lam_rho;
       q.tau2 = -q.tau1;
-      q.swap2 = q.swap1;
       sps.push_back(q);
     }
-    passes.push_back(a);
-    nvs.push_back(grad ? 2 : 1);
+    if (grad) add_pass(a, 3, 1, lp.tile);
+    else add_pass(a, 1, 3, lp.tile);
   }
 
   // ---------------- reverse sweep
@@ -526,7 +539,6 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         q.lam_rho = (R)1;
         q.w1 = std::norm(sb[s]);
         q.tau1 = -tau[s * p + l1];
-        q.swap1 = swp[s * p + l1];
         sb[s] *= cpow_int(fi[s * p + l1], rotbits(fp.tile));
         q.w2 = 1.0;
         if (fp.ph >= 0 && !last) {
@@ -537,13 +549,11 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         if (has2) {
           q.w2 = std::norm(sb[s]);
           q.tau2 = -tau[s * p + fp.pre];
-          q.swap2 = swp[s * p + fp.pre];
           sb[s] *= cpow_int(fi[s * p + fp.pre], rotbits(fp.tile));
         }
         sps.push_back(q);
       }
-      passes.push_back(a);
-      nvs.push_back(2);
+      add_pass(a, 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile);
     }
   }
 
@@ -580,10 +590,10 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (fl & PF_STORE_LAM) by += (double)N * esz;
     if (fl & (PF_EXPECT | PF_LAMBDA | PF_GGAMMA | PF_PHASE)) by += (double)N * prob->tbytes;
     by *= nsets;
-    KTimer kt(ctx, st, nvs[i] == 2 ? QAOA_KC_REV_PASS : QAOA_KC_FWD_PASS, by, 0.0);
+    KTimer kt(ctx, st, nvs[i] >= 2 ? QAOA_KC_REV_PASS : QAOA_KC_FWD_PASS, by, 0.0);
     hipError_t e;
-    if constexpr (sizeof(R) == 4) e = launch_pass_f32(a, nvs[i], prob->tbytes, st);
-    else e = launch_pass_f64(a, nvs[i], prob->tbytes, st);
+    if constexpr (sizeof(R) == 4) e = launch_pass_f32(a, nvs[i], sxs[i], shapes[i], prob->tbytes, st);
+    else e = launch_pass_f64(a, nvs[i], sxs[i], shapes[i], prob->tbytes, st);
     if (e != hipSuccess) throw fail(QAOA_ERR_HIP, std::string("pass launch: ") + hipGetErrorString(e));
     kt.done();
   }
@@ -597,8 +607,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   double *hres = (double *)ctx->hresults.get((size_t)nsets * nout * sizeof(double));
   HIPCHK(hipMemcpyAsync(hres, dres, (size_t)nsets * nout * sizeof(double), hipMemcpyDeviceToHost, st));
   if (d_state_out) {
-    // nsets == 1 here: final state = sigma_p * phi
-    HIPCHK(launch_scale_copy(prec, dphi, d_state_out, N, sig_p[0].real(), sig_p[0].imag(), st));
+    // nsets == 1 here: final state(x) = sigma_p * phi(x ^ F), F = all bits when an odd
+    // number of rounds used the tau = -cot form
+    int odd = 0;
+    for (int k = 0; k < p; k++) odd ^= swp[k];
+    const uint64_t flip = odd ? (N - 1) : 0;
+    HIPCHK(launch_scale_copy(prec, dphi, d_state_out, N, sig_p[0].real(), sig_p[0].imag(), flip, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   profile_collect(ctx);

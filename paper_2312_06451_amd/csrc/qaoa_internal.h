@@ -50,7 +50,6 @@ enum { SL_A = 0, SL_B = 1, SL_C = 2, NSLOT = 3 };
 template <typename R>
 struct SetParams {
   R tau1, tau2;          // rotation parameter of part 1 / part 2
-  int swap1, swap2;      // rotation in the output-swapped form
   double w1, w2;         // inner-product weight at the start of part 1 / part 2
   R lam_rho;             // lambda = lam_rho * (C - c0) * phi
   R out_re, out_im;      // output scale (PF_SCALE_OUT)
@@ -111,15 +110,22 @@ hipError_t launch_table_widen(const void *src, int tbytes, int64_t *dst, uint64_
                               hipStream_t s);
 hipError_t launch_luts(int precision, const LutJob *jobs, int njobs, int lut_len, void *luts,
                        hipStream_t s);
-hipError_t launch_pass_f32(const PassArgs<float> &a, int nv, int tbytes, hipStream_t s);
-hipError_t launch_pass_f64(const PassArgs<double> &a, int nv, int tbytes, hipStream_t s);
+// kind: 1 = forward pass (phi), 2 = reverse-sweep pass (phi, lam), 3 = fused end of the
+// forward sweep and start of the reverse sweep. sx: register stages holding the tile's
+// rotated bits (bit 0: H, bit 1: M, bit 2: L; 7, 3 or 1). shape: 0 = part 1 only,
+// 1 = both parts with the kind's elementwise steps between them, 2 = phase then part 2
+// (first forward pass), 3 = part 1 then a reduction (forward: <C>; reverse: gamma gradient).
+hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes,
+                           hipStream_t s);
+hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
+                           hipStream_t s);
 hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
                            int64_t nwg, int nout, double *out, hipStream_t s);
 hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
                         int max_tbytes, int max_lut, const double *angles, int p, int grad,
                         double *out, hipStream_t s);
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
-                             double im, hipStream_t s);
+                             double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
 
 }  // namespace qaoa

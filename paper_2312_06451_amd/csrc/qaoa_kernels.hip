@@ -9,11 +9,13 @@
 //      sweep that undoes each layer (Sec. 2.3 gets this gradient by reverse-mode AD).
 //
 // Rotation form. A qubit rotation e^{-i b X} = cos b I - i sin b X is applied unnormalised as
-// G(tau) = I - i tau X (tau = tan b; four FMAs per amplitude pair), or, when |tan b| > 1, as
-// X G(tau) with tau = -cot b (the output-swapped form). The dropped factor (cos b, or
-// -i sin b) is a scalar per vector that the host tracks and folds into the next phase
-// lookup table, so every rotation is exactly unitary up to that scalar and norm drift does
-// not accumulate.
+// G(tau) = I - i tau X (four FMAs per amplitude pair) with tau = tan b, or, when |tan b| > 1,
+// as X G(tau) with tau = -cot b. The dropped scalar (cos b, or -i sin b) is tracked by the
+// host and folded into the next phase lookup table, so every applied rotation is exactly
+// unitary up to that scalar and norm drift does not accumulate. The X of the second form is
+// not applied either: the stored vector is the state with a known set of bits flipped
+// (after a full round: all bits or none). MaxCut tables satisfy C(~x) = C(x), so phases,
+// <C> and the gradient sums read the table unchanged; only a state export un-flips.
 //
 // Tile passes. A workgroup of 256 threads holds a tile of 2^T amplitudes in registers
 // (2^(T-8) per thread and vector). Tile bits [0,c) are contiguous address bits; the other
@@ -33,6 +35,20 @@ template <> struct Cplx<float> { using T2 = float2; };
 template <> struct Cplx<double> { using T2 = double2; };
 
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Materialise a partial sum where it is computed. The sums only feed the final reduction, so
+// without this the compiler sinks their arithmetic to the end of the kernel and keeps the
+// amplitudes they read alive across every later stage.
+__device__ __forceinline__ void pin(float &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+// A workgroup-uniform 64-bit value, pinned to scalar registers (so global accesses take the
+// SGPR-base + 32-bit VGPR-offset form).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // ============================================================== (a) cost table
@@ -173,25 +189,63 @@ __device__ constexpr uint32_t group(void) {
                  : (A == AM ? (((1u << G::TB) - 1) & ~((1u << G::RB) - 1)) : ((1u << G::RB) - 1));
 }
 
-// Padded LDS slot of tile element e (one pad slot per 256 bytes: conflict-free in H, M, L).
-template <typename R>
-__device__ __forceinline__ uint32_t lpos(uint32_t e) {
-  return e + (e >> (sizeof(R) == 4 ? 5 : 4));
+// Padded LDS layout: tile element e sits in slot e + (e >> PS), one pad slot per 256 bytes
+// (PS = 5 for complex64, 4 for complex128); conflict-free in all three assignments. For
+// every assignment the slot splits into a per-thread base plus a constant per register.
+template <typename R> struct Pad { static constexpr int PS = sizeof(R) == 4 ? 5 : 4; };
+
+template <typename R, int T, int A>
+__device__ __forceinline__ uint32_t lbase(uint32_t t) {
+  using G = TileCfg<T>;
+  constexpr int PS = Pad<R>::PS;
+  if constexpr (A == AH) return t + (t >> PS);
+  else if constexpr (A == AM)
+    return (t & ((1u << G::MLO) - 1)) +
+           (t >> G::MLO) * ((1u << (G::MLO + G::RB)) + (1u << (G::MLO + G::RB - PS)));
+  else return t * ((1u << G::RB) + (1u << (G::RB - PS)));
 }
-// Padded byte position of the staged table entry e (16 pad bytes per 256 entries).
-__device__ __forceinline__ uint32_t tpos(uint32_t e) { return e + ((e >> 8) << 4); }
+template <typename R, int T, int A>
+__device__ constexpr uint32_t loff(int j) {
+  using G = TileCfg<T>;
+  constexpr int PS = Pad<R>::PS;
+  if constexpr (A == AH) return (uint32_t)j * ((1u << G::TB) + (1u << (G::TB - PS)));
+  else if constexpr (A == AM) return ((uint32_t)j << G::MLO) + (((uint32_t)j << G::MLO) >> PS);
+  else return (uint32_t)j + ((uint32_t)j >> PS);
+}
+
+// Staged table: byte position of entry e is e*s + 16 * ((e*s) >> 8) (s = entry size); per
+// assignment again a per-thread base plus a constant per register.
+template <int T, int A, int S>
+__device__ __forceinline__ uint32_t tbase(uint32_t t) {
+  using G = TileCfg<T>;
+  // e(t, 0) * S, then padding; valid because the register part never carries into the
+  // thread part across a 256-byte boundary in any assignment
+  uint32_t e0;
+  if constexpr (A == AH) e0 = t;
+  else if constexpr (A == AM) e0 = (t & ((1u << G::MLO) - 1)) | ((t >> G::MLO) << (G::MLO + G::RB));
+  else e0 = t << G::RB;
+  return e0 * S + (((e0 * S) >> 8) << 4);
+}
+template <int T, int A, int S>
+__device__ constexpr uint32_t toffc(int j) {
+  using G = TileCfg<T>;
+  uint32_t ej = A == AH ? ((uint32_t)j << G::TB) : (A == AM ? ((uint32_t)j << G::MLO) : (uint32_t)j);
+  return ej * S + (((ej * S) >> 8) << 4);
+}
 
 template <typename R, int T, int A>
 __device__ __forceinline__ void to_lds(typename Cplx<R>::T2 *lds, const typename Cplx<R>::T2 *v,
                                        uint32_t t) {
+  typename Cplx<R>::T2 *p = lds + lbase<R, T, A>(t);
 #pragma unroll
-  for (int j = 0; j < TileCfg<T>::RN; j++) lds[lpos<R>(elem<A, T>(t, j))] = v[j];
+  for (int j = 0; j < TileCfg<T>::RN; j++) p[loff<R, T, A>(j)] = v[j];
 }
 template <typename R, int T, int A>
 __device__ __forceinline__ void from_lds(const typename Cplx<R>::T2 *lds,
                                          typename Cplx<R>::T2 *v, uint32_t t) {
+  const typename Cplx<R>::T2 *p = lds + lbase<R, T, A>(t);
 #pragma unroll
-  for (int j = 0; j < TileCfg<T>::RN; j++) v[j] = lds[lpos<R>(elem<A, T>(t, j))];
+  for (int j = 0; j < TileCfg<T>::RN; j++) v[j] = p[loff<R, T, A>(j)];
 }
 
 // Move one vector from assignment FROM to assignment TO through LDS.
@@ -202,24 +256,6 @@ __device__ __forceinline__ void xchg1(typename Cplx<R>::T2 *lds, typename Cplx<R
   to_lds<R, T, FROM>(lds, v, t);
   __syncthreads();
   from_lds<R, T, TO>(lds, v, t);
-}
-
-template <typename R, int T, int NV, int TO>
-__device__ __forceinline__ void move_to(int &cur, typename Cplx<R>::T2 *lds,
-                                        typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
-                                        uint32_t t) {
-  if (cur == TO) return;
-  if (cur == AH) {
-    xchg1<R, T, AH, TO>(lds, phi, t);
-    if constexpr (NV == 2) xchg1<R, T, AH, TO>(lds, lam, t);
-  } else if (cur == AM) {
-    xchg1<R, T, AM, TO>(lds, phi, t);
-    if constexpr (NV == 2) xchg1<R, T, AM, TO>(lds, lam, t);
-  } else {
-    xchg1<R, T, AL, TO>(lds, phi, t);
-    if constexpr (NV == 2) xchg1<R, T, AL, TO>(lds, lam, t);
-  }
-  cur = TO;
 }
 
 // (a, b) <- (a - i tau b, b - i tau a)
@@ -233,17 +269,6 @@ __device__ __forceinline__ void bfly(T2 &a, T2 &b, R tau) {
   a = na;
   b = nb;
 }
-// (a, b) <- (b - i tau a, a - i tau b): X applied after G(tau)
-template <typename T2, typename R>
-__device__ __forceinline__ void bfly_swap(T2 &a, T2 &b, R tau) {
-  T2 na, nb;
-  na.x = fmaR(tau, a.y, b.x);
-  na.y = fmaR(-tau, a.x, b.y);
-  nb.x = fmaR(tau, b.y, a.x);
-  nb.y = fmaR(-tau, b.x, a.y);
-  a = na;
-  b = nb;
-}
 // Im(conj(la) pb + conj(lb) pa): the X-pair term of one amplitude pair.
 template <typename T2, typename R>
 __device__ __forceinline__ R xpair(const T2 &pa, const T2 &pb, const T2 &la, const T2 &lb, R acc) {
@@ -254,57 +279,105 @@ __device__ __forceinline__ R xpair(const T2 &pa, const T2 &pb, const T2 &la, con
   return acc;
 }
 
-// One register stage: for every register bit of assignment A whose tile bit is in `mask`
-// (and owned by A): optionally accumulate the X-pair terms, then rotate.
-template <typename R, int T, int NV, int A>
-__device__ __forceinline__ void stage(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
-                                      uint32_t mask, R tau, int swap, bool rot_lam, bool xt,
-                                      double &w, double &acc) {
+// X-pair terms of register bit B: sum over the thread's pairs of Im(conj(la) pb + conj(lb) pa),
+// with two accumulators to shorten the dependency chain.
+template <typename R, int T, int B>
+__device__ __forceinline__ R xterm_bit(const typename Cplx<R>::T2 *phi, const typename Cplx<R>::T2 *lam) {
   using G = TileCfg<T>;
-  const double shrink = 1.0 / (1.0 + (double)tau * (double)tau);
+  R s0 = 0, s1 = 0;
+  int k = 0;
 #pragma unroll
-  for (int b = 0; b < G::RB; b++) {
-    constexpr uint32_t grp = group<A, T>();
-    const int tb = regbit<A, T>(b);
-    if (!((grp >> tb) & 1u)) continue;
-    if (!((mask >> tb) & 1u)) continue;
-    if constexpr (NV == 2) {
-      if (xt) {
-        R s = 0;
+  for (int j = 0; j < G::RN; j++) {
+    if (j & (1 << B)) continue;
+    if (k++ & 1) s1 = xpair(phi[j], phi[j | (1 << B)], lam[j], lam[j | (1 << B)], s1);
+    else s0 = xpair(phi[j], phi[j | (1 << B)], lam[j], lam[j | (1 << B)], s0);
+  }
+  return s0 + s1;
+}
+
+// Rotation of register bit B (compile-time, so every register index is a constant and the
+// arrays stay in VGPRs). A tile bit that is not rotated in this pass (a passenger) gets
+// tau = 0, which FMA applies exactly as the identity: the stage is branch-free.
+template <typename R, int T, int NV, int B, bool ROT_LAM>
+__device__ __forceinline__ void rot_bit(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam, R tau) {
+  using G = TileCfg<T>;
 #pragma unroll
-        for (int j = 0; j < G::RN; j++)
-          if (!(j & (1 << b))) s = xpair(phi[j], phi[j | (1 << b)], lam[j], lam[j | (1 << b)], s);
-        acc += w * (double)s;
-      }
+  for (int j = 0; j < G::RN; j++)
+    if (!(j & (1 << B))) bfly(phi[j], phi[j | (1 << B)], tau);
+  if constexpr (NV == 2 && ROT_LAM) {
+#pragma unroll
+    for (int j = 0; j < G::RN; j++)
+      if (!(j & (1 << B))) bfly(lam[j], lam[j | (1 << B)], tau);
+  }
+  // keep the bit-by-bit (in-place) order: interleaving bits multiplies the live registers
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// X-pair terms of the register bits B.. of assignment A that are rotated in this pass, all at
+// the stage's starting point (they do not change under the rotations of the round, up to
+// the tracked scalar), weighted with w.
+template <typename R, int T, int A, int B>
+__device__ __forceinline__ void xterms(const typename Cplx<R>::T2 *phi, const typename Cplx<R>::T2 *lam,
+                                       uint32_t mask, double w, double &acc) {
+  using G = TileCfg<T>;
+  if constexpr (B < G::RB) {
+    constexpr int tb = regbit<A, T>(B);
+    if constexpr ((group<A, T>() >> tb) & 1u) {
+      R sb = xterm_bit<R, T, B>(phi, lam);
+      pin(sb);
+      acc += (((mask >> tb) & 1u) ? w : 0.0) * (double)sb;
     }
-    if (swap) {
-#pragma unroll
-      for (int j = 0; j < G::RN; j++)
-        if (!(j & (1 << b))) bfly_swap(phi[j], phi[j | (1 << b)], tau);
-      if constexpr (NV == 2) {
-        if (rot_lam) {
-#pragma unroll
-          for (int j = 0; j < G::RN; j++)
-            if (!(j & (1 << b))) bfly_swap(lam[j], lam[j | (1 << b)], tau);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < G::RN; j++)
-        if (!(j & (1 << b))) bfly(phi[j], phi[j | (1 << b)], tau);
-      if constexpr (NV == 2) {
-        if (rot_lam) {
-#pragma unroll
-          for (int j = 0; j < G::RN; j++)
-            if (!(j & (1 << b))) bfly(lam[j], lam[j | (1 << b)], tau);
-        }
-      }
-    }
-    w *= shrink;
+    xterms<R, T, A, B + 1>(phi, lam, mask, w, acc);
   }
 }
 
-template <typename R, int T, int NV, typename TT, int A>
+template <typename R, int T, int NV, int A, bool ROT_LAM, int B>
+__device__ __forceinline__ void rot_bits(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
+                                         uint32_t mask, R tau, double shrink, double &w) {
+  using G = TileCfg<T>;
+  if constexpr (B < G::RB) {
+    constexpr int tb = regbit<A, T>(B);
+    if constexpr ((group<A, T>() >> tb) & 1u) {
+      const bool on = (mask >> tb) & 1u;  // uniform
+      rot_bit<R, T, NV, B, ROT_LAM>(phi, lam, on ? tau : (R)0);
+      if (on) w *= shrink;
+    }
+    rot_bits<R, T, NV, A, ROT_LAM, B + 1>(phi, lam, mask, tau, shrink, w);
+  }
+}
+
+// One register stage: every register bit of assignment A whose tile bit belongs to A's group
+// is processed; bits in `mask` are rotated (their X-pair terms taken first when XT), the
+// others pass.
+template <typename R, int T, int NV, int A, bool ROT_LAM, bool XT>
+__device__ __forceinline__ void stage(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
+                                      uint32_t mask, R tau, double &w, double &acc) {
+  if constexpr (NV == 2 && XT) {
+    xterms<R, T, A, 0>(phi, lam, mask, w, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const double shrink = 1.0 / (1.0 + (double)tau * (double)tau);
+  rot_bits<R, T, NV, A, ROT_LAM, 0>(phi, lam, mask, tau, shrink, w);
+}
+
+// Staged table entry of register j (assignment A) of the thread whose base is tb.
+template <typename TT, int T, int A>
+__device__ __forceinline__ uint32_t tab_at(const unsigned char *tb, int j) {
+  return (uint32_t)(*(const TT *)(tb + toffc<T, A, (int)sizeof(TT)>(j)));
+}
+
+template <typename T2, typename R>
+__device__ __forceinline__ T2 cmul(const T2 &v, const T2 &L) {
+  T2 o;
+  o.x = fmaR(v.x, L.x, -v.y * L.y);
+  o.y = fmaR(v.x, L.y, v.y * L.x);
+  return o;
+}
+
+// Elementwise steps in assignment A, each step in its own loop (no per-element branching).
+// MID != 0 fixes the steps at compile time (flag bits of the PF_ set); MID == 0 reads them
+// from the pass flags.
+template <typename R, int T, int NV, typename TT, int A, uint32_t MID>
 __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> &sp,
                                        typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
                                        const unsigned char *ltab,
@@ -312,55 +385,82 @@ __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> 
                                        double *acc) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
-  const uint32_t f = a.flags;
-  R e_acc = 0, n_acc = 0, g_acc = 0;
+  constexpr uint32_t f = MID;
+  const unsigned char *tb = ltab + tbase<T, A, (int)sizeof(TT)>(t);
+  if (f & PF_EXPECT) {
+    R e_acc = 0, n_acc = 0;
 #pragma unroll
-  for (int j = 0; j < G::RN; j++) {
-    const uint32_t e = elem<A, T>(t, j);
-    const uint32_t cv = (uint32_t)(*(const TT *)(ltab + tpos(e * sizeof(TT))));
-    const R cr = (R)cv;
-    if (f & PF_EXPECT) {
+    for (int j = 0; j < G::RN; j++) {
+      const R cr = (R)tab_at<TT, T, A>(tb, j);
       R pr = fmaR(phi[j].x, phi[j].x, phi[j].y * phi[j].y);
       e_acc = fmaR(pr, cr, e_acc);
       n_acc += pr;
     }
-    if constexpr (NV == 2) {
-      if (f & PF_LAMBDA) {
+    pin(e_acc);
+    pin(n_acc);
+    acc[SL_A] += (double)e_acc;
+    acc[SL_B] += (double)n_acc;
+  }
+  if constexpr (NV == 2) {
+    if (f & PF_LAMBDA) {
+#pragma unroll
+      for (int j = 0; j < G::RN; j++) {
+        const R cr = (R)tab_at<TT, T, A>(tb, j);
         R kf = sp.lam_rho * (cr - a.lam_c0);
         lam[j].x = kf * phi[j].x;
         lam[j].y = kf * phi[j].y;
       }
-      if (f & PF_GGAMMA) {
+    }
+    if (f & PF_GGAMMA) {
+      R g_acc = 0;
+#pragma unroll
+      for (int j = 0; j < G::RN; j++) {
+        const R cr = (R)tab_at<TT, T, A>(tb, j);
         R im = fmaR(lam[j].x, phi[j].y, -lam[j].y * phi[j].x);
         g_acc = fmaR(im, cr, g_acc);
       }
-    }
-    if (f & PF_PHASE) {
-      const T2 L = llut[cv];
-      T2 o;
-      o.x = fmaR(phi[j].x, L.x, -phi[j].y * L.y);
-      o.y = fmaR(phi[j].x, L.y, phi[j].y * L.x);
-      phi[j] = o;
-      if constexpr (NV == 2) {
-        if (f & PF_PHASE_BOTH) {
-          o.x = fmaR(lam[j].x, L.x, -lam[j].y * L.y);
-          o.y = fmaR(lam[j].x, L.y, lam[j].y * L.x);
-          lam[j] = o;
-        }
-      }
+      pin(g_acc);
+      acc[SL_B] += w * (double)g_acc;
     }
   }
-  if (f & PF_EXPECT) {
-    acc[SL_A] += (double)e_acc;
-    acc[SL_B] += (double)n_acc;
+  if (f & PF_PHASE) {
+#pragma unroll
+    for (int j = 0; j < G::RN; j++) {
+      const T2 L = llut[tab_at<TT, T, A>(tb, j)];
+      phi[j] = cmul<T2, R>(phi[j], L);
+      if constexpr (NV == 2) lam[j] = cmul<T2, R>(lam[j], L);
+    }
   }
-  if (f & PF_GGAMMA) acc[SL_B] += w * (double)g_acc;
 }
 
-template <typename R, int T, int NV, typename TT>
-__global__ __launch_bounds__(256) void k_pass(const PassArgs<R> a) {
+// Move both vectors (NV of them) from assignment FROM to assignment TO (compile time).
+template <typename R, int T, int NV, int FROM, int TO>
+__device__ __forceinline__ void xchg(typename Cplx<R>::T2 *lds, typename Cplx<R>::T2 *phi,
+                                     typename Cplx<R>::T2 *lam, uint32_t t) {
+  if constexpr (FROM != TO) {
+    xchg1<R, T, FROM, TO>(lds, phi, t);
+    if constexpr (NV == 2) xchg1<R, T, FROM, TO>(lds, lam, t);
+  }
+}
+
+// Register assignment after the stages of set S (bit 0: H, bit 1: M, bit 2: L) visited in the
+// order H, M, L (DOWN) or L, M, H (UP), starting from assignment START.
+template <int S, bool DOWN, int START>
+constexpr int after_stages() {
+  if constexpr (DOWN) return (S & 4) ? AL : ((S & 2) ? AM : ((S & 1) ? AH : START));
+  else return (S & 1) ? AH : ((S & 2) ? AM : ((S & 4) ? AL : START));
+}
+
+// One tile pass. KIND 1: forward over phi. KIND 2: reverse sweep over (phi, lam): part 1 undoes
+// the forward pass's last rotation block (X-pair terms first), the middle reads the gamma
+// gradient and undoes the phase, part 2 undoes the first block. KIND 3: end of the forward
+// sweep on phi (part 1), <C> and lam = rho (C - c0) phi (middle), then the reverse sweep's
+// first block on both (part 2). S1 / S2: register stages of part 1 / part 2.
+template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT>
+__global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
+  constexpr int NV = KIND == 1 ? 1 : 2;
   constexpr int RN = G::RN;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr uint32_t kStateSlots = (1u << T) + ((1u << T) >> (sizeof(R) == 4 ? 5 : 4));
@@ -381,49 +481,56 @@ __global__ __launch_bounds__(256) void k_pass(const PassArgs<R> a) {
   const uint64_t base = (((uint64_t)r & ((1ull << lo_w) - 1)) << a.c) |
                         (((uint64_t)r >> lo_w) << (a.h0 + T - a.c));
   const uint64_t cmask = (1ull << a.c) - 1;
+  // element offset of tile index e (a bit deposit, additive over disjoint bits)
   auto off = [&](uint32_t e) -> uint64_t {
     return ((uint64_t)e & cmask) | (((uint64_t)e >> a.c) << a.h0);
   };
-  const uint64_t tb = base + off(t);
-  const uint64_t vs = (uint64_t)q * a.vstride;
+  // per-thread byte offset (32 bits suffice: the thread's tile bits stay below address bit
+  // n - 3) and uniform per-register byte offsets
+  const uint32_t tbyte = (uint32_t)(off(t) * sizeof(T2));
+  auto jbyte = [&](int j) -> uint64_t { return off((uint32_t)j << G::TB) * sizeof(T2); };
+  // element j of a vector whose (uniform) byte base is vb: a global-address-space pointer with
+  // a scalar base and the thread's 32-bit byte offset
+  using V2 = R __attribute__((ext_vector_type(2)));
+  using gbyte = __attribute__((address_space(1))) unsigned char;
+  using gV2 = __attribute__((address_space(1))) V2;
+  auto at = [&](uint64_t vb, int j) -> gV2 * { return (gV2 *)((gbyte *)uniform64(vb + jbyte(j)) + tbyte); };
+  auto ld = [&](uint64_t vb, int j) -> T2 { V2 v = *at(vb, j); return T2{v.x, v.y}; };
+  auto st = [&](uint64_t vb, int j, const T2 &x) { V2 v; v.x = x.x; v.y = x.y; *at(vb, j) = v; };
+  const uint64_t vs = ((uint64_t)q * a.vstride + base) * sizeof(T2);
 
   T2 phi[RN];
   T2 lam[NV == 2 ? RN : 1];
 
   // ---- load (assignment H: lanes run over contiguous address bits)
-  if (f & PF_LOAD_PHI) {
-    const T2 *src = (const T2 *)a.phi + vs;
+  {
+    const uint64_t src = (f & PF_LOAD_PSI0) ? (uint64_t)a.psi0 + base * sizeof(T2) : (uint64_t)a.phi + vs;
+    if (f & (PF_LOAD_PHI | PF_LOAD_PSI0)) {
 #pragma unroll
-    for (int j = 0; j < RN; j++) phi[j] = src[tb + off((uint32_t)j << G::TB)];
-  } else if (f & PF_LOAD_PSI0) {
-    const T2 *src = (const T2 *)a.psi0;
+      for (int j = 0; j < RN; j++) phi[j] = ld(src, j);
+    } else {
 #pragma unroll
-    for (int j = 0; j < RN; j++) phi[j] = src[tb + off((uint32_t)j << G::TB)];
-  } else {
-#pragma unroll
-    for (int j = 0; j < RN; j++) {
-      phi[j].x = a.u0;
-      phi[j].y = (R)0;
+      for (int j = 0; j < RN; j++) phi[j] = T2{a.u0, (R)0};
     }
   }
   if constexpr (NV == 2) {
-    if (f & PF_LOAD_LAM) {
-      const T2 *src = (const T2 *)a.lam + vs;
+    if (KIND == 2) {
+      const uint64_t src = (uint64_t)a.lam + vs;
 #pragma unroll
-      for (int j = 0; j < RN; j++) lam[j] = src[tb + off((uint32_t)j << G::TB)];
+      for (int j = 0; j < RN; j++) lam[j] = ld(src, j);
     } else {
 #pragma unroll
       for (int j = 0; j < RN; j++) lam[j] = T2{(R)0, (R)0};
     }
   }
   // ---- stage this tile's table entries and the set's LUT in LDS
-  const bool need_tab = (f & (PF_EXPECT | PF_LAMBDA | PF_GGAMMA | PF_PHASE)) != 0;
-  if (need_tab) {
+  constexpr bool need_tab = SHAPE != 0;
+  if constexpr (need_tab) {
     constexpr uint32_t nchunk = ((1u << T) * sizeof(TT)) / 16;
     const uint4 *src = (const uint4 *)((const unsigned char *)a.table +
                                        (uint64_t)r * ((1ull << T) * sizeof(TT)));
-    for (uint32_t i = t; i < nchunk; i += 256) *(uint4 *)(ltab + tpos(i * 16)) = src[i];
-    if ((f & PF_PHASE) && sp.lut >= 0) {
+    for (uint32_t i = t; i < nchunk; i += 256) *(uint4 *)(ltab + i * 16 + ((i >> 4) << 4)) = src[i];
+    if (sp.lut >= 0) {
       const T2 *lsrc = (const T2 *)a.luts + (size_t)sp.lut * a.lut_len;
       for (int i = t; i < a.lut_len; i += 256) llut[i] = lsrc[i];
     }
@@ -431,79 +538,67 @@ __global__ __launch_bounds__(256) void k_pass(const PassArgs<R> a) {
 
   double acc[NSLOT] = {0.0, 0.0, 0.0};
   double w = sp.w1;
-  int cur = AH;
   // ---- part 1: stages H, M, L
-  {
-    const uint32_t m1 = a.mask1;
-    const bool rl = (f & PF_ROT1_BOTH) != 0, xt = (f & PF_XT1) != 0;
-    if (m1 & group<AH, T>()) {
-      move_to<R, T, NV, AH>(cur, lds, phi, lam, t);
-      stage<R, T, NV, AH>(phi, lam, m1, sp.tau1, sp.swap1, rl, xt, w, acc[SL_A]);
-    }
-    if (m1 & group<AM, T>()) {
-      move_to<R, T, NV, AM>(cur, lds, phi, lam, t);
-      stage<R, T, NV, AM>(phi, lam, m1, sp.tau1, sp.swap1, rl, xt, w, acc[SL_A]);
-    }
-    if (m1 & group<AL, T>()) {
-      move_to<R, T, NV, AL>(cur, lds, phi, lam, t);
-      stage<R, T, NV, AL>(phi, lam, m1, sp.tau1, sp.swap1, rl, xt, w, acc[SL_A]);
-    }
+  constexpr bool RL1 = KIND == 2, XT1 = KIND == 2;
+  const uint32_t m1 = a.mask1;
+  if constexpr (S1 & 1) stage<R, T, NV, AH, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
+  if constexpr (S1 & 2) {
+    xchg<R, T, NV, AH, AM>(lds, phi, lam, t);
+    stage<R, T, NV, AM, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
   }
-  // ---- middle: elementwise steps in the current assignment
-  if (need_tab) {
+  if constexpr (S1 & 4) {
+    xchg<R, T, NV, (S1 & 2) ? AM : AH, AL>(lds, phi, lam, t);
+    stage<R, T, NV, AL, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
+  }
+  constexpr int CM = after_stages<S1, true, AH>();
+  // ---- middle: elementwise steps
+  // elementwise steps, fixed by kind and shape (see launch_pass_f32)
+  constexpr uint32_t MID =
+      SHAPE == 0 ? 0u
+      : SHAPE == 3 ? (KIND == 1 ? (uint32_t)PF_EXPECT : (uint32_t)PF_GGAMMA)
+      : (KIND == 1 ? (uint32_t)PF_PHASE
+                   : (KIND == 2 ? (uint32_t)(PF_GGAMMA | PF_PHASE) : (uint32_t)(PF_EXPECT | PF_LAMBDA)));
+  if constexpr (MID != 0) {
     __syncthreads();
-    if (cur == AH) middle<R, T, NV, TT, AH>(a, sp, phi, lam, ltab, llut, t, w, acc);
-    else if (cur == AM) middle<R, T, NV, TT, AM>(a, sp, phi, lam, ltab, llut, t, w, acc);
-    else middle<R, T, NV, TT, AL>(a, sp, phi, lam, ltab, llut, t, w, acc);
+    middle<R, T, NV, TT, CM, MID>(a, sp, phi, lam, ltab, llut, t, w, acc);
   }
   // ---- part 2: stages L, M, H
   w = sp.w2;
-  {
-    const uint32_t m2 = a.mask2;
-    const bool rl = (f & PF_ROT2_BOTH) != 0, xt = (f & PF_XT2) != 0;
-    if (m2 & group<AL, T>()) {
-      move_to<R, T, NV, AL>(cur, lds, phi, lam, t);
-      stage<R, T, NV, AL>(phi, lam, m2, sp.tau2, sp.swap2, rl, xt, w, acc[SL_C]);
-    }
-    if (m2 & group<AM, T>()) {
-      move_to<R, T, NV, AM>(cur, lds, phi, lam, t);
-      stage<R, T, NV, AM>(phi, lam, m2, sp.tau2, sp.swap2, rl, xt, w, acc[SL_C]);
-    }
-    if (m2 & group<AH, T>()) {
-      move_to<R, T, NV, AH>(cur, lds, phi, lam, t);
-      stage<R, T, NV, AH>(phi, lam, m2, sp.tau2, sp.swap2, rl, xt, w, acc[SL_C]);
-    }
+  constexpr bool RL2 = KIND != 1, XT2 = KIND != 1;
+  const uint32_t m2 = a.mask2;
+  if constexpr (S2 & 4) {
+    xchg<R, T, NV, CM, AL>(lds, phi, lam, t);
+    stage<R, T, NV, AL, RL2, XT2>(phi, lam, m2, sp.tau2, w, acc[SL_C]);
   }
+  if constexpr (S2 & 2) {
+    xchg<R, T, NV, (S2 & 4) ? AL : CM, AM>(lds, phi, lam, t);
+    stage<R, T, NV, AM, RL2, XT2>(phi, lam, m2, sp.tau2, w, acc[SL_C]);
+  }
+  if constexpr (S2 & 1) {
+    xchg<R, T, NV, (S2 & 2) ? AM : ((S2 & 4) ? AL : CM), AH>(lds, phi, lam, t);
+    stage<R, T, NV, AH, RL2, XT2>(phi, lam, m2, sp.tau2, w, acc[SL_C]);
+  }
+  constexpr int CE = after_stages<S2, false, CM>();
   // ---- store (assignment H)
   if (f & (PF_STORE_PHI | PF_STORE_LAM)) {
-    move_to<R, T, NV, AH>(cur, lds, phi, lam, t);
-    if (f & PF_STORE_PHI) {
-      T2 *dst = (T2 *)a.phi + vs;
-      if (f & PF_SCALE_OUT) {
-#pragma unroll
-        for (int j = 0; j < RN; j++) {
-          T2 o;
-          o.x = fmaR(phi[j].x, sp.out_re, -phi[j].y * sp.out_im);
-          o.y = fmaR(phi[j].x, sp.out_im, phi[j].y * sp.out_re);
-          phi[j] = o;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < RN; j++) dst[tb + off((uint32_t)j << G::TB)] = phi[j];
+    if constexpr (KIND == 3) {
+      xchg1<R, T, CE, AH>(lds, lam, t);
+    } else {
+      xchg<R, T, NV, CE, AH>(lds, phi, lam, t);
     }
-    if constexpr (NV == 2) {
-      if (f & PF_STORE_LAM) {
-        T2 *dst = (T2 *)a.lam + vs;
+    if constexpr (KIND != 3) {
+      const uint64_t dst = (uint64_t)a.phi + vs;
 #pragma unroll
-        for (int j = 0; j < RN; j++) dst[tb + off((uint32_t)j << G::TB)] = lam[j];
-      }
+      for (int j = 0; j < RN; j++) st(dst, j, phi[j]);
+    }
+    if constexpr (KIND != 1) {
+      const uint64_t dl = (uint64_t)a.lam + vs;
+#pragma unroll
+      for (int j = 0; j < RN; j++) st(dl, j, lam[j]);
     }
   }
   // ---- workgroup reduction of the partial sums (fixed order: deterministic)
-  bool any = false;
-#pragma unroll
-  for (int s = 0; s < NSLOT; s++) any |= a.slot_off[s] >= 0;
-  if (any) {
+  if (a.slot_off[0] >= 0 || a.slot_off[1] >= 0 || a.slot_off[2] >= 0) {
 #pragma unroll
     for (int s = 0; s < NSLOT; s++) {
       double v = acc[s];
@@ -548,13 +643,14 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
   if (threadIdx.x == 0) out[(int64_t)q * nout + o] = red[0];
 }
 
+// dst[i] = (re + i im) * src[i ^ flip]
 template <typename R>
 __global__ void k_scale_copy(const typename Cplx<R>::T2 *__restrict__ src,
                              typename Cplx<R>::T2 *__restrict__ dst, uint64_t N, double re,
-                             double im) {
+                             double im, uint64_t flip) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-    typename Cplx<R>::T2 v = src[i], o;
+    typename Cplx<R>::T2 v = src[i ^ flip], o;
     o.x = (R)((double)v.x * re - (double)v.y * im);
     o.y = (R)((double)v.x * im + (double)v.y * re);
     dst[i] = o;
@@ -579,22 +675,19 @@ struct DC {
 };
 __device__ __forceinline__ DC dmul(DC a, DC b) { return DC{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
-// Rotation parameters of e^{-i beta X} in the unnormalised form (see file header):
-// tau, swap flag and the dropped scalar factor f (forward); the inverse uses -tau, the same
-// swap flag and conj-type factor finv.
+// Rotation parameters of e^{-i beta X} in the unnormalised form (see file header): tau and
+// the dropped scalar f of the forward rotation; the inverse rotation uses -tau and finv.
 template <typename R>
-__device__ void rot_params(double beta, R &tau, int &swap, DC &f, DC &finv) {
+__device__ void rot_params(double beta, R &tau, DC &f, DC &finv) {
   double sb, cb;
   sincos(beta, &sb, &cb);
   if (fabs(sb) <= fabs(cb)) {
     tau = (R)(sb / cb);
-    swap = 0;
     double t = (double)tau, nrm = 1.0 / sqrt(1.0 + t * t);
     f = DC{nrm * (cb < 0 ? -1.0 : 1.0), 0.0};
     finv = f;
   } else {
     tau = (R)(-cb / sb);
-    swap = 1;
     double t = (double)tau, s = (sb < 0 ? -1.0 : 1.0) / sqrt(1.0 + t * t);
     f = DC{0.0, -s};
     finv = DC{0.0, s};
@@ -640,14 +733,14 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     }
     __syncthreads();
   };
-  auto rotate_all = [&](T2 *v, R tau, int swap) {
+  auto rotate_all = [&](T2 *v, R tau) {
     for (int qb = 0; qb < n; qb++) {
       const uint32_t bit = 1u << qb;
       __syncthreads();
       for (uint32_t i = tid; i < N / 2; i += 256) {
         uint32_t x0 = ((i >> qb) << (qb + 1)) | (i & (bit - 1));
         T2 va = v[x0], vb = v[x0 | bit];
-        if (swap) bfly_swap(va, vb, tau); else bfly(va, vb, tau);
+        bfly(va, vb, tau);
         v[x0] = va;
         v[x0 | bit] = vb;
       }
@@ -662,9 +755,9 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
       phi[x] = T2{fmaR(v.x, L.x, -v.y * L.y), fmaR(v.x, L.y, v.y * L.x)};
     }
     sig = DC{1.0, 0.0};
-    R tau; int swap; DC f, finv;
-    rot_params<R>(ang[k], tau, swap, f, finv);
-    rotate_all(phi, tau, swap);
+    R tau; DC f, finv;
+    rot_params<R>(ang[k], tau, f, finv);
+    rotate_all(phi, tau);
     for (int qb = 0; qb < n; qb++) sig = dmul(sig, f);
   }
   double e = 0.0, nr = 0.0;
@@ -700,10 +793,10 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     gb = block_sum(gb, red);
     const double wgt = sig.re * sig.re + sig.im * sig.im;
     if (tid == 0) o[1 + k] = 2.0 * wgt * gb / ntrue;
-    R tau; int swap; DC f, finv;
-    rot_params<R>(ang[k], tau, swap, f, finv);
-    rotate_all(phi, -tau, swap);
-    rotate_all(lam, -tau, swap);
+    R tau; DC f, finv;
+    rot_params<R>(ang[k], tau, f, finv);
+    rotate_all(phi, -tau);
+    rotate_all(lam, -tau);
     for (int qb = 0; qb < n; qb++) sig = dmul(sig, finv);
     // d/dgamma_k: 2 Im <lam| C |phi>
     double gg = 0.0;
@@ -803,34 +896,60 @@ size_t pass_lds_bytes(int precision, int tbytes, int lut_len) {
                         : lds_for<double, TILE_BITS_F64>(tbytes, lut_len);
 }
 
-template <typename R, int T, int NV, typename TT>
+template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT>
 static hipError_t launch_pass_t(const PassArgs<R> &a, hipStream_t s) {
   size_t lds = lds_for<R, T>((int)sizeof(TT), a.lut_len);
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void *)k_pass<R, T, NV, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
+    hipFuncSetAttribute((const void *)k_pass<R, T, KIND, S1, S2, SHAPE, TT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   dim3 grid(a.nwg, a.nsets);
-  hipLaunchKernelGGL((k_pass<R, T, NV, TT>), grid, dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_pass<R, T, KIND, S1, S2, SHAPE, TT>), grid, dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_pass_f32(const PassArgs<float> &a, int nv, int tbytes, hipStream_t s) {
-  constexpr int T = TILE_BITS_F32;
-  if (nv == 1) return tbytes == 1 ? launch_pass_t<float, T, 1, uint8_t>(a, s)
-                                  : launch_pass_t<float, T, 1, uint16_t>(a, s);
-  return tbytes == 1 ? launch_pass_t<float, T, 2, uint8_t>(a, s)
-                     : launch_pass_t<float, T, 2, uint16_t>(a, s);
+// Shapes: 0 = part 1 only; 1 = both parts with the kind's middle steps (forward: phase;
+// reverse: gamma gradient and inverse phase; fused: <C> and lam); 2 = part 2 only after the
+// phase (first forward pass); 3 = part 1 then a reduction (forward: <C>; reverse: gamma
+// gradient).
+template <typename R, int T, int KIND, typename TT, int SX>
+static hipError_t launch_shape(const PassArgs<R> &a, int shape, hipStream_t s) {
+  if constexpr (KIND == 3) return launch_pass_t<R, T, KIND, SX, SX, 1, TT>(a, s);
+  else {
+    if (shape == 0) return launch_pass_t<R, T, KIND, SX, 0, 0, TT>(a, s);
+    if (shape == 3) return launch_pass_t<R, T, KIND, SX, 0, 3, TT>(a, s);
+    if constexpr (KIND == 1)
+      if (shape == 2) return launch_pass_t<R, T, KIND, 0, SX, 2, TT>(a, s);
+    return launch_pass_t<R, T, KIND, SX, SX, 1, TT>(a, s);
+  }
 }
 
-hipError_t launch_pass_f64(const PassArgs<double> &a, int nv, int tbytes, hipStream_t s) {
-  constexpr int T = TILE_BITS_F64;
-  if (nv == 1) return tbytes == 1 ? launch_pass_t<double, T, 1, uint8_t>(a, s)
-                                  : launch_pass_t<double, T, 1, uint16_t>(a, s);
-  return tbytes == 1 ? launch_pass_t<double, T, 2, uint8_t>(a, s)
-                     : launch_pass_t<double, T, 2, uint16_t>(a, s);
+template <typename R, int T, int KIND, typename TT>
+static hipError_t launch_sx(const PassArgs<R> &a, int sx, int shape, hipStream_t s) {
+  if (sx == 7) return launch_shape<R, T, KIND, TT, 7>(a, shape, s);
+  if (sx == 3) return launch_shape<R, T, KIND, TT, 3>(a, shape, s);
+  return launch_shape<R, T, KIND, TT, 1>(a, shape, s);
+}
+
+template <typename R, int T, typename TT>
+static hipError_t launch_kind(const PassArgs<R> &a, int kind, int sx, int shape, hipStream_t s) {
+  if (kind == 1) return launch_sx<R, T, 1, TT>(a, sx, shape, s);
+  if (kind == 2) return launch_sx<R, T, 2, TT>(a, sx, shape, s);
+  return launch_sx<R, T, 3, TT>(a, sx, shape, s);
+}
+
+hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes,
+                           hipStream_t s) {
+  return tbytes == 1 ? launch_kind<float, TILE_BITS_F32, uint8_t>(a, kind, sx, shape, s)
+                     : launch_kind<float, TILE_BITS_F32, uint16_t>(a, kind, sx, shape, s);
+}
+
+hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
+                           hipStream_t s) {
+  return tbytes == 1 ? launch_kind<double, TILE_BITS_F64, uint8_t>(a, kind, sx, shape, s)
+                     : launch_kind<double, TILE_BITS_F64, uint16_t>(a, kind, sx, shape, s);
 }
 
 hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
@@ -862,12 +981,12 @@ hipError_t launch_small(int precision, const SmallItem *items, int n_items, int 
 }
 
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
-                             double im, hipStream_t s) {
+                             double im, uint64_t flip, hipStream_t s) {
   unsigned g = grid_for(N, 256);
   if (precision == 0)
-    k_scale_copy<float><<<g, 256, 0, s>>>((const float2 *)src, (float2 *)dst, N, re, im);
+    k_scale_copy<float><<<g, 256, 0, s>>>((const float2 *)src, (float2 *)dst, N, re, im, flip);
   else
-    k_scale_copy<double><<<g, 256, 0, s>>>((const double2 *)src, (double2 *)dst, N, re, im);
+    k_scale_copy<double><<<g, 256, 0, s>>>((const double2 *)src, (double2 *)dst, N, re, im, flip);
   return hipGetLastError();
 }
 
