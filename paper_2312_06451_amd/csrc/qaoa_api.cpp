@@ -5,6 +5,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -136,7 +137,8 @@ struct KTotals {
 
 struct qaoa_ctx {
   int device = 0;
-  DevBuf phi, lam, partials, params, luts, results, cnt, items;
+  int checkpoint_mode = -1;  // -1: when memory allows, 0: never, 1: always
+  DevBuf phi, lam, ckpt, partials, params, luts, results, cnt, items;
   HostBuf hparams, hresults;
   // kernel timing
   bool profiling = false;
@@ -350,9 +352,26 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     return d;
   };
 
-  // buffers
+  // buffers. With enough free memory the gradient keeps every forward pass's output
+  // (checkpoints) and the reverse sweep reads the state from them instead of undoing and
+  // rewriting it: 24 instead of 32 bytes per amplitude in each reverse pass.
   const size_t vbytes = (size_t)nsets * N * esz;
-  void *dphi = ctx->phi.get(vbytes);
+  const int npf_est = 1 + p * ((int)tiles.size() - 1);
+  bool ckpt = false;
+  if (grad && ctx->checkpoint_mode != 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const size_t need = (size_t)npf_est * vbytes;
+      const size_t have = fr + ctx->ckpt.cap;
+      ckpt = ctx->checkpoint_mode == 1 || need + vbytes <= have / 2;
+      if (need > have) ckpt = false;
+    }
+  }
+  void *dphi = ckpt ? nullptr : ctx->phi.get(vbytes);
+  unsigned char *dck = ckpt ? (unsigned char *)ctx->ckpt.get((size_t)npf_est * vbytes) : nullptr;
+  // forward pass j writes checkpoint j (or the single in-place buffer)
+  auto fwd_out = [&](int j) -> void * { return ckpt ? (void *)(dck + (size_t)j * vbytes) : dphi; };
+  auto fwd_in = [&](int j) -> void * { return j == 0 ? nullptr : fwd_out(j - 1); };
   void *dlam = grad ? ctx->lam.get(vbytes) : nullptr;
   OutMap om{2 + 2 * p, p};
   const int nout = om.nout;
@@ -394,6 +413,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     a.nsets = nsets;
     a.vstride = N;
     a.phi = dphi;
+    a.phi_out = dphi;
     a.lam = dlam;
     a.psi0 = d_psi0;
     a.table = nullptr;
@@ -407,6 +427,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   };
 
   std::vector<cd> sig(nsets, cd(1.0, 0.0));
+  std::vector<cd> sig_fwd;  // [pass][set]: scalar of forward pass j's output
   auto rotbits = [&](int tile) { return __builtin_popcount(tiles[tile].rot); };
   // register groups of the pass kernels: H = tile bits [8,T), M = [T-8, 8), L = [0, T-8)
   auto stage_set = [&](int tile) {
@@ -426,9 +447,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const int npf = (int)fwd.size();
 
   // ---------------- forward passes (all but the last)
+  if (npf != npf_est) throw fail(QAOA_ERR_HIP, "internal: pass count");
   for (int j = 0; j < npf - 1; j++) {
     const FwdPass &fp = fwd[j];
     PassArgs<R> a = base_args(fp.tile);
+    a.phi = fwd_in(j);
+    a.phi_out = fwd_out(j);
     uint32_t f = 0;
     if (j == 0) f |= d_psi0 ? PF_LOAD_PSI0 : PF_GEN_PHI;
     else f |= PF_LOAD_PHI;
@@ -462,6 +486,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       sps.push_back(q);
     }
     add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile);
+    sig_fwd.insert(sig_fwd.end(), sig.begin(), sig.end());
   }
 
   // ---------------- last forward pass (alone, or fused with the start of the reverse sweep)
@@ -471,6 +496,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   std::vector<double> rho(nsets);
   {
     PassArgs<R> a = base_args(lp.tile);
+    a.phi = fwd_in(npf - 1);
+    a.phi_out = fwd_out(npf - 1);
     uint32_t f = (npf == 1) ? (d_psi0 ? PF_LOAD_PSI0 : PF_GEN_PHI) : PF_LOAD_PHI;
     // a single-pass plan would need the phase too; K >= 2 always gives >= 2 passes
     a.mask1 = tiles[lp.tile].rot;
@@ -511,7 +538,10 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     for (int j = npf - 2; j >= 0; j--) {
       const FwdPass &fp = fwd[j];
       PassArgs<R> a = base_args(fp.tile);
-      uint32_t f = PF_LOAD_PHI | PF_LOAD_LAM;
+      // the state after forward pass j: its checkpoint, or the vector undone in place
+      a.phi = ckpt ? fwd_out(j) : dphi;
+      a.phi_out = a.phi;
+      uint32_t f = PF_LOAD_PHI | PF_LOAD_LAM | (ckpt ? (uint32_t)PF_LOAD_SCALE : 0u);
       const bool last = (j == 0);
       // part 1 undoes the forward pass's last rotation block
       int l1 = fp.post >= 0 ? fp.post : fp.pre;
@@ -530,13 +560,20 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         f |= PF_XT2 | PF_ROT2_BOTH;
         a.slot_off[SL_C] = slot_for(om.gb(fp.pre));
       }
-      if (!last) f |= PF_STORE_PHI | PF_STORE_LAM;
+      if (!last) f |= (ckpt ? 0u : (uint32_t)PF_STORE_PHI) | PF_STORE_LAM;
       a.flags = f;
       for (int s = 0; s < nsets; s++) {
         SetParams<R> q;
         std::memset(&q, 0, sizeof(q));
         q.lut = -1;
         q.lam_rho = (R)1;
+        if (ckpt) {
+          // the checkpoint carries the forward sweep's scalar; rescale it to the reverse
+          // sweep's so that phi and lam share one scalar (real inner-product weights)
+          const cd kappa = sig_fwd[(size_t)j * nsets + s] / sb[s];
+          q.out_re = (R)kappa.real();
+          q.out_im = (R)kappa.imag();
+        }
         q.w1 = std::norm(sb[s]);
         q.tau1 = -tau[s * p + l1];
         sb[s] *= cpow_int(fi[s * p + l1], rotbits(fp.tile));
@@ -612,7 +649,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     int odd = 0;
     for (int k = 0; k < p; k++) odd ^= swp[k];
     const uint64_t flip = odd ? (N - 1) : 0;
-    HIPCHK(launch_scale_copy(prec, dphi, d_state_out, N, sig_p[0].real(), sig_p[0].imag(), flip, st));
+    HIPCHK(launch_scale_copy(prec, fwd_out(npf - 1), d_state_out, N, sig_p[0].real(), sig_p[0].imag(),
+                             flip, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   profile_collect(ctx);
@@ -751,6 +789,9 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
     DeviceGuard g(hip_device);
     auto c = std::make_unique<qaoa_ctx>();
     c->device = hip_device;
+    // QAOA_GRAD_CHECKPOINT: "0" never keep forward checkpoints, "1" always, unset: when the
+    // free device memory allows
+    if (const char *e = std::getenv("QAOA_GRAD_CHECKPOINT")) c->checkpoint_mode = std::atoi(e) ? 1 : 0;
     *out = c.release();
   });
 }

@@ -40,7 +40,8 @@ enum : uint32_t {
   PF_ROT1_BOTH = 1u << 12,   // part 1 also rotates lam
   PF_ROT2_BOTH = 1u << 13,   // part 2 also rotates lam
   PF_PHASE_BOTH = 1u << 14,  // the phase also applies to lam
-  PF_SCALE_OUT = 1u << 15,   // phi *= out_scale before storing
+  PF_SCALE_OUT = 1u << 15,   // (unused)
+  PF_LOAD_SCALE = 1u << 16,  // phi *= (out_re + i out_im) right after loading
 };
 
 // Partial-sum slots of one pass.
@@ -52,7 +53,7 @@ struct SetParams {
   R tau1, tau2;          // rotation parameter of part 1 / part 2
   double w1, w2;         // inner-product weight at the start of part 1 / part 2
   R lam_rho;             // lambda = lam_rho * (C - c0) * phi
-  R out_re, out_im;      // output scale (PF_SCALE_OUT)
+  R out_re, out_im;      // load scale of phi (PF_LOAD_SCALE)
   int lut;               // index of this set's LUT in the LUT array (-1: none)
 };
 
@@ -66,7 +67,8 @@ struct PassArgs {
   int xcd_remap;           // give each XCD a contiguous range of tiles
   int nsets;               // angle sets (grid.y)
   uint64_t vstride;        // elements between consecutive sets' vectors
-  void *phi, *lam;
+  void *phi, *lam;         // phi is read from `phi`, written to `phi_out` (equal: in place)
+  void *phi_out;
   const void *psi0;        // natural layout, shared by all sets
   const void *table;       // tile-major table of this geometry: table[r * 2^T + e]
   const void *luts;        // lut_len complex<R> entries per LUT

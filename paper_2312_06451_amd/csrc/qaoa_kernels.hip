@@ -508,6 +508,11 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
     if (f & (PF_LOAD_PHI | PF_LOAD_PSI0)) {
 #pragma unroll
       for (int j = 0; j < RN; j++) phi[j] = ld(src, j);
+      if (f & PF_LOAD_SCALE) {
+        const T2 k{sp.out_re, sp.out_im};
+#pragma unroll
+        for (int j = 0; j < RN; j++) phi[j] = cmul<T2, R>(phi[j], k);
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < RN; j++) phi[j] = T2{a.u0, (R)0};
@@ -580,18 +585,17 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   }
   constexpr int CE = after_stages<S2, false, CM>();
   // ---- store (assignment H)
-  if (f & (PF_STORE_PHI | PF_STORE_LAM)) {
-    if constexpr (KIND == 3) {
-      xchg1<R, T, CE, AH>(lds, lam, t);
-    } else {
-      xchg<R, T, NV, CE, AH>(lds, phi, lam, t);
-    }
-    if constexpr (KIND != 3) {
-      const uint64_t dst = (uint64_t)a.phi + vs;
+  if constexpr (KIND != 3) {
+    if (f & PF_STORE_PHI) {
+      xchg1<R, T, CE, AH>(lds, phi, t);
+      const uint64_t dst = (uint64_t)a.phi_out + vs;
 #pragma unroll
       for (int j = 0; j < RN; j++) st(dst, j, phi[j]);
     }
-    if constexpr (KIND != 1) {
+  }
+  if constexpr (KIND != 1) {
+    if (f & PF_STORE_LAM) {
+      xchg1<R, T, CE, AH>(lds, lam, t);
       const uint64_t dl = (uint64_t)a.lam + vs;
 #pragma unroll
       for (int j = 0; j < RN; j++) st(dl, j, lam[j]);

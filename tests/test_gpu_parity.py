@@ -248,3 +248,23 @@ def test_deterministic_repeat(q, c2):
     r1 = q.expect_grad(P, M, W.angles[0], precision=0)
     r2 = q.expect_grad(P, M, W.angles[0], precision=0)
     assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1])
+
+
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_gradient_sweep_modes(q, mode, monkeypatch):
+    # "0": the reverse sweep undoes every forward pass in place; "1": it reads the forward
+    # passes' stored outputs. Both must match the oracle.
+    monkeypatch.setenv("QAOA_GRAD_CHECKPOINT", mode)
+    c = q.Context(0)
+    for n, p, prec in [(16, 3, 0), (22, 2, 1), (21, 4, 0)]:
+        g = workloads.random_regular_graph(n, 3, 600 + n) if n % 2 == 0 else workloads.erdos_renyi(
+            n, 600 + n, 0.5, (1, 3))
+        t = oracle.graph_table(g)
+        P, M = q.Problem.from_graph(c, g), q.Mixer.x(c, n)
+        a = workloads.random_angles(p, 1, 700 + n)[0]
+        E0, N0, g0 = oracle.grad(n, t, a)
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        assert _rel(e, E0 / N0) < TOL[prec][0]
+        assert _gerr(gr, g0 / N0) < TOL[prec][1]
+        P.close(); M.close()
+    c.close()
