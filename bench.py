@@ -48,6 +48,25 @@ def time_steps(q, P, M, angles, prec, steps, warmup, torch):
     return (t1 - t0), e, g
 
 
+def copy_roof(torch, nbytes=2 << 30, reps=5):
+    """Measured device-to-device copy rate (read + write) of a 2 GiB buffer: the achievable
+    HBM rate for a streaming kernel, and the calibration kernel of the traffic counters."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_read": nbytes, "bytes_written": nbytes, "ms": ms}
+
+
 def cpu_baseline(W, seconds_hint=True):
     """FP64 oracle, fwd + adjoint with p=1 at the full n (one of the p layers), scaled by p."""
     import numpy as np
@@ -84,6 +103,8 @@ def main():
     import paper_2312_06451_amd as q
     from paper_2312_06451_amd import _lib
 
+    roof_copy = copy_roof(torch)
+    log(f"copy roof: {roof_copy['GBps']:.0f} GB/s")
     W = workloads.workload(args.workload)
     g = W.graphs[0]
     angles = W.angles[0]
@@ -126,6 +147,21 @@ def main():
                 err["fp64_expect_rel"] = abs(e64 - ref_e) / abs(ref_e)
                 err["fp64_grad_inf_rel"] = float(np.max(np.abs(g64 - ref_g)) / np.max(np.abs(ref_g)))
 
+    # ---- HBM traffic per launch from the committed rocprofv3 counter summary, valid only
+    # while the kernel source is the one the counters were taken with
+    traffic = {}
+    tpath = os.path.join(ROOT, "profiles", f"pmc_traffic_k_pass_{args.workload}.md")
+    if os.path.exists(tpath):
+        import hashlib
+        txt = open(tpath).read()
+        ksrc = os.path.join(ROOT, "paper_2312_06451_amd", "csrc", "qaoa_kernels.hip")
+        cur = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()
+        if f"kernel_source_sha256 = {cur}" in txt:
+            for line in txt.splitlines():
+                if line.startswith("traffic_bytes_per_launch "):
+                    k, v = line[len("traffic_bytes_per_launch "):].split("=")
+                    traffic[k.strip()] = float(v)
+
     # ---- roofline of the dominant kernel class
     dom = max(("fwd_pass", "rev_pass"), key=lambda k: prof[k]["ms"])
     d = prof[dom]
@@ -133,7 +169,7 @@ def main():
     bytes_per_launch = d["bytes"] / max(d["launches"], 1)
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic.get(dom),
             "kernel": "k_pass<float,13,2,uint8>" if dom == "rev_pass" else "k_pass<float,13,1,uint8>",
             "class": dom, "launches": d["launches"], "mean_ms": round(mean_ms, 4),
             "bytes_per_launch": bytes_per_launch}
@@ -159,7 +195,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "p": p, "graph": "random 3-regular, pairing model",
                    "mixer": "transverse field", "mode": "fwd+grad", "state": "complex64, FP64 sums",
                    "parallelism": "single GPU"},
-        "roofline": roof, "path": path, "fp64": fp64,
+        "roofline": roof, "path": path, "copy_roof": roof_copy, "fp64": fp64,
         "speedup_vs_fp64": (evals32 / fp64["value"]) if fp64 else None,
         "error": err, "cpu_baseline": cpu,
         "kernels": prof,
