@@ -412,15 +412,18 @@ __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> 
       }
     }
     if (f & PF_GGAMMA) {
-      R g_acc = 0;
+      // Im <lam|C|phi> = Im <lam|(C - c0)|phi>: <lam|phi> = <psi_p|(C - c0)|psi_p> is real.
+      // The centred form keeps the multiplier at the spread of C rather than its maximum,
+      // and the products are summed in FP64.
+      double g_acc = 0;
 #pragma unroll
       for (int j = 0; j < G::RN; j++) {
-        const R cr = (R)tab_at<TT, T, A>(tb, j);
+        const R cr = (R)tab_at<TT, T, A>(tb, j) - a.lam_c0;
         R im = fmaR(lam[j].x, phi[j].y, -lam[j].y * phi[j].x);
-        g_acc = fmaR(im, cr, g_acc);
+        g_acc += (double)(im * cr);
       }
       pin(g_acc);
-      acc[SL_B] += w * (double)g_acc;
+      acc[SL_B] += w * g_acc;
     }
   }
   if (f & PF_PHASE) {
@@ -802,11 +805,11 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     rotate_all(phi, -tau);
     rotate_all(lam, -tau);
     for (int qb = 0; qb < n; qb++) sig = dmul(sig, finv);
-    // d/dgamma_k: 2 Im <lam| C |phi>
+    // d/dgamma_k: 2 Im <lam| C |phi> = 2 Im <lam| C - c0 |phi> (<lam|phi> is real)
     double gg = 0.0;
     for (uint32_t x = tid; x < N; x += 256) {
       T2 l = lam[x], v = phi[x];
-      gg += (double)(fmaR(l.x, v.y, -l.y * v.x)) * (double)cval(x);
+      gg += (double)(fmaR(l.x, v.y, -l.y * v.x)) * ((double)cval(x) - it.c0);
     }
     gg = block_sum(gg, red);
     const double wg2 = sig.re * sig.re + sig.im * sig.im;
