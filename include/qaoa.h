@@ -14,7 +14,7 @@
  * Conventions shared by every call:
  *  - Basis index x = sum_i x_i 2^i: vertex i of the graph is bit i of x. For a Hamming-weight
  *    constrained problem the feasible states are the weight-k integers in increasing order
- *    (the order in which Gosper's hack walks them, Sec. 2.5) and amplitudes are stored in that
+ *    (the order in which Gosper's hack walks them, Sec. 2.4) and amplitudes are stored in that
  *    order.
  *  - Angles are FP64, laid out [beta_1 .. beta_p, gamma_1 .. gamma_p] (first code listing,
  *    Sec. 3). Gradients use the same layout. Batched angles are [n_sets][2p], row major.
