@@ -50,9 +50,9 @@ int guarded(F &&f) {
   } catch (const Err &e) {
     g_last_error = e.msg;
     return e.code;
-  } catch (const qaoa::CliqueUnsupported &) {
-    g_last_error = "the clique mixer path is not available in this build";
-    return QAOA_ERR_UNSUPPORTED;
+  } catch (const qaoa::CliqueError &e) {
+    g_last_error = e.msg;
+    return e.code;
   } catch (const std::bad_alloc &) {
     g_last_error = "host allocation failed";
     return QAOA_ERR_OUT_OF_MEMORY;
@@ -190,6 +190,23 @@ struct KTimer {
     a = nullptr;
   }
 };
+
+// Timing hooks handed to the constrained path (same event pairs as KTimer).
+static hipEvent_t g_pending_start = nullptr;
+static void hook_begin(void *c, hipStream_t st) {
+  qaoa_ctx *ctx = (qaoa_ctx *)c;
+  if (!ctx->profiling) return;
+  g_pending_start = ctx->take_event();
+  HIPCHK(hipEventRecord(g_pending_start, st));
+}
+static void hook_end(void *c, hipStream_t st, int cls, double bytes, double flops) {
+  qaoa_ctx *ctx = (qaoa_ctx *)c;
+  if (!ctx->profiling || !g_pending_start) return;
+  hipEvent_t b = ctx->take_event();
+  HIPCHK(hipEventRecord(b, st));
+  ctx->pending.push_back({cls, g_pending_start, b, bytes, flops});
+  g_pending_start = nullptr;
+}
 
 // After the stream synchronised: fold recorded event pairs into the totals.
 static void profile_collect(qaoa_ctx *ctx) {
@@ -987,8 +1004,14 @@ static void evaluate(const qaoa_problem *cprob, const qaoa_mixer *mix, int p, co
     ev.N = (int64_t)prob->N;
     ev.lut_len = (int)prob->max_value + 1;
     ev.c0 = prob->mean;
+    CliqueTimer tm;
+    tm.ctx = prob->ctx;
+    tm.begin = hook_begin;
+    tm.end = hook_end;
+    clique_set_timer(*mix->clique, tm);
     clique_evaluate(*mix->clique, ev, p, angles, nsets, d_psi0, precision, grad, out_expect,
                     out_grad, d_state, st);
+    profile_collect(prob->ctx);
   }
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <memory>
+#include <string>
 
 namespace qaoa {
 
@@ -12,19 +13,30 @@ struct CliqueMixerDeleter {
   void operator()(CliqueMixer *m) const;
 };
 
-struct CliqueUnsupported {};
+// Error raised by the constrained path (status code of include/qaoa.h and a message).
+struct CliqueError {
+  int code;
+  std::string msg;
+};
 
 struct CliqueEval {
-  const void *table;
+  const void *table;  // device table over the weight-k states (increasing order)
   int tbytes;
   int64_t N;
-  int lut_len;
-  double c0;
+  int lut_len;        // largest C + 1
+  double c0;          // mean of C over the states
 };
 
 std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int n, int k, hipStream_t st);
 void clique_evaluate(CliqueMixer &m, const CliqueEval &ev, int p, const double *angles, int nsets,
                      const void *d_psi0, int precision, int grad, double *out_expect,
                      double *out_grad, void *d_state, hipStream_t st);
+// Kernel timing hook: (class, ms-start event, bytes, flops) recorder supplied by the caller.
+struct CliqueTimer {
+  void *ctx = nullptr;
+  void (*begin)(void *ctx, hipStream_t st) = nullptr;
+  void (*end)(void *ctx, hipStream_t st, int cls, double bytes, double flops) = nullptr;
+};
+void clique_set_timer(CliqueMixer &m, const CliqueTimer &t);
 
 }  // namespace qaoa

@@ -1,6 +1,7 @@
 """Write the oracle's full-size reference values (calls only oracle/ and workloads/).
 
     python tests/golden/make_golden.py maxcut3reg_n28_p8
+    python tests/golden/make_golden.py bisection_g16_k8_p6 2
 
 Each output file records the workload, its graph and angles (so a reader can check the
 inputs are the seeded ones), and the FP64 oracle's <C> (E / Nrm) and adjoint gradient
@@ -50,4 +51,4 @@ def make(name: str, n_sets: int = 1, extra_sets=None):
 
 
 if __name__ == "__main__":
-    make(sys.argv[1])
+    make(sys.argv[1], n_sets=int(sys.argv[2]) if len(sys.argv) > 2 else 1)

@@ -1,0 +1,108 @@
+"""GPU parity of the constrained path: clique mixer on the Hamming-weight-k subspace,
+eigenbasis products (FP16-split MFMA products in the FP32 form, DGEMM in the FP64 form).
+
+Tolerances: FP32 form <C> 1e-5 relative and gradient 1e-5 of max|g|; FP64 form 1e-10
+(the eigendecomposition itself carries ~1e-13 relative error per eigenpair, which the 2p
+products compound)."""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {0: 1e-5, 1: 1e-10}
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2312_06451_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("n,k,p", [(6, 3, 2), (8, 4, 3), (10, 5, 2), (12, 6, 2), (9, 2, 3)])
+def test_clique_small_vs_oracle(q, ctx, n, k, p):
+    g = workloads.erdos_renyi(n, 800 + n, 0.5)
+    t = oracle.cost_table(n, g.u, g.v, g.w, k)
+    P = q.Problem.from_graph(ctx, g, hamming_k=k)
+    M = q.Mixer.clique(ctx, n, k)
+    assert np.array_equal(P.table(), t)
+    for a in workloads.random_angles(p, 2, 900 + n):
+        E0, N0, g0 = oracle.grad(n, t, a, k=k)
+        for prec in (0, 1):
+            e, gr = q.expect_grad(P, M, a, precision=prec)
+            assert abs(e - E0 / N0) <= TOL[prec] * abs(E0), (prec, e, E0)
+            assert np.max(np.abs(gr - g0 / N0)) <= TOL[prec] * np.max(np.abs(g0)), (prec, gr, g0)
+            assert abs(q.expect(P, M, a, precision=prec) - e) <= TOL[prec] * abs(E0)
+
+
+def test_clique_state_and_initial_state(q, ctx):
+    import torch
+    n, k, p = 10, 4, 3
+    g = workloads.erdos_renyi(n, 77, 0.5)
+    t = oracle.cost_table(n, g.u, g.v, g.w, k)
+    P, M = q.Problem.from_graph(ctx, g, hamming_k=k), q.Mixer.clique(ctx, n, k)
+    a = workloads.random_angles(p, 1, 78)[0]
+    want = oracle.state(n, t, a, k=k)
+    for prec, dt, tol in ((0, torch.complex64, 1e-5), (1, torch.complex128, 1e-10)):
+        out = torch.empty(comb(n, k), dtype=dt, device="cuda")
+        q.state(P, M, a, out, precision=prec)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(out.cpu().numpy() - want)) * np.sqrt(comb(n, k)) < tol
+    rng = np.random.default_rng(3)
+    psi0 = rng.normal(size=comb(n, k)) + 1j * rng.normal(size=comb(n, k))
+    psi0 /= np.linalg.norm(psi0)
+    E0, N0, g0 = oracle.grad(n, t, a, k=k, psi0=psi0)
+    for prec, dt in ((0, torch.complex64), (1, torch.complex128)):
+        d = torch.tensor(psi0, dtype=dt, device="cuda")
+        e, gr = q.expect_grad(P, M, a, psi0=d, precision=prec)
+        assert abs(e - E0 / N0) <= TOL[prec] * abs(E0)
+        assert np.max(np.abs(gr - g0 / N0)) <= TOL[prec] * np.max(np.abs(g0))
+
+
+def test_clique_identities(q, ctx):
+    # gamma = 0: the Dicke state is an eigenvector, so <C> stays the subspace mean for any
+    # beta; beta = 0 likewise
+    n, k = 12, 6
+    g = workloads.erdos_renyi(n, 31, 0.5)
+    P, M = q.Problem.from_graph(ctx, g, hamming_k=k), q.Mixer.clique(ctx, n, k)
+    mean = g.total_weight * 2 * comb(n - 2, k - 1) / comb(n, k)
+    for a in ([0.7, 1.9, 0.0, 0.0], [0.0, 0.0, 2.5, 0.3]):
+        for prec in (0, 1):
+            assert abs(q.expect(P, M, a, precision=prec) - mean) < 10 * TOL[prec] * mean
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clique_full_size_vs_oracle(q, ctx, prec):
+    path = os.path.join(HERE, "golden", "bisection_g16_k8_p6.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values for the weight-8 workload not generated")
+    G = json.load(open(path))
+    W = workloads.workload("bisection_g16_k8_p6", n_sets=8)
+    g = W.graphs[0]
+    assert G["edges"][0] == g.u.tolist()
+    P, M = q.Problem.from_graph(ctx, g, hamming_k=8), q.Mixer.clique(ctx, 16, 8)
+    for i, s in enumerate(G["sets"]):
+        assert np.array_equal(np.array(s["angles"]), W.angles[i])
+        e, gr = q.expect_grad(P, M, W.angles[i], precision=prec)
+        print("bisection n16 k8 p6 set", i, "prec", prec, "E err", abs(e - s["expect"]) / abs(s["expect"]),
+              "g err", np.max(np.abs(gr - s["grad"])) / np.max(np.abs(s["grad"])))
+        assert abs(e - s["expect"]) <= TOL[prec] * abs(s["expect"])
+        assert np.max(np.abs(gr - np.array(s["grad"]))) <= TOL[prec] * np.max(np.abs(s["grad"]))
+    # the batched call over 8 sets agrees with the single evaluations
+    Eb, Gb = q.expect_grad_batched([P], [M], W.angles, precision=prec)
+    for i in (0, 5):
+        e, gr = q.expect_grad(P, M, W.angles[i], precision=prec)
+        assert abs(Eb[0, i] - e) <= 1e-6 * abs(e) and np.max(np.abs(Gb[0, i] - gr)) <= 1e-5 * np.max(np.abs(gr))
