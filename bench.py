@@ -5,17 +5,27 @@ rotations, <C> reduction and the reverse sweep for d<C>/d(beta, gamma), on one M
 table is built before timing (step (a) runs once per instance); every amplitude is resident
 in HBM when the timed region starts.
 
+Other workloads (--workload):
+  maxcut3reg_n10_p3        n=10, p=3, one angle set (latency of the whole-state kernel)
+  batched_er_n12to20_p10   8 weighted G(n,1/2) instances x 256 angle sets, p=10; one step is
+                           one batched call (2048 evaluations)
+  bisection_g16_k8_p6      clique mixer on Hamming weight 8 of 16 (12870 states), 512 angle
+                           sets, p=6; one step is one batched call (512 evaluations)
+  maxcut3reg_n32_p16       n=32, p=16 (32 GiB complex64 vectors)
+
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
-  roofline         dominant kernel: algorithmic bytes per launch / mean launch time (HIP
-                   events on the launch stream, during the timed region) vs 8 TB/s
+  roofline         dominant kernel class: algorithmic bytes (or flops) per launch / mean launch
+                   time (HIP events on the launch stream, during the timed region) vs the
+                   MI355X peak (8 TB/s HBM; 2.5 PFLOP/s dense FP16 MFMA; 157.3 TFLOP/s FP32)
   cpu_baseline     the FP64 CPU oracle on a bounded sample of the same workload
   fp64             the same kernels with a complex128 state (the plain FP64 GPU path)
-  error            FP32 result vs the oracle's stored FP64 values
+  error            FP32 result vs FP64 oracle values
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,10 +35,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F16_PEAK_TFS = 2500.0
+FP32_VECTOR_PEAK_TFS = 157.3
 METRIC = "fwd+grad QAOA evals/sec & HBM GB/s at n=28 p=8, FP32 vs FP64, err<=1e-5"
-# Algorithmic traffic of one fwd+grad evaluation at one pass per layer (bytes per amplitude):
-# forward 16p (read+write complex64), reverse 32p (two vectors), table (2p+2) x 1 byte.
+
+
 def eval_bytes_per_amp(p: int) -> int:
+    """Algorithmic traffic of one fwd+grad evaluation at one pass per layer (bytes per
+    amplitude): forward 16p (read + write complex64), reverse 32p (two vectors), table
+    (2p + 2) x 1 byte."""
     return 16 * p + 32 * p + (2 * p + 2)
 
 
@@ -36,21 +51,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_steps(q, P, M, angles, prec, steps, warmup, torch):
-    for _ in range(warmup):
-        q.expect_grad(P, M, angles, precision=prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        e, g = q.expect_grad(P, M, angles, precision=prec)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    return (t1 - t0), e, g
-
-
 def copy_roof(torch, nbytes=2 << 30, reps=5):
     """Measured device-to-device copy rate (read + write) of a 2 GiB buffer: the achievable
-    HBM rate for a streaming kernel, and the calibration kernel of the traffic counters."""
+    HBM rate of a streaming kernel, and the calibration kernel of the traffic counters."""
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -67,30 +70,147 @@ def copy_roof(torch, nbytes=2 << 30, reps=5):
     return {"GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_read": nbytes, "bytes_written": nbytes, "ms": ms}
 
 
-def cpu_baseline(W, seconds_hint=True):
-    """FP64 oracle, fwd + adjoint with p=1 at the full n (one of the p layers), scaled by p."""
+class Runner:
+    """One workload on one context: single evaluations or one batched call per step."""
+
+    def __init__(self, q, W):
+        self.q, self.W = q, W
+        self.ctx = q.Context(0)
+        k = W.hamming_k
+        self.problems = [q.Problem.from_graph(self.ctx, g, hamming_k=k) for g in W.graphs]
+        if W.mixer == "clique":
+            self.mixers = [q.Mixer.clique(self.ctx, g.n, k) for g in W.graphs]
+        else:
+            self.mixers = [q.Mixer.x(self.ctx, g.n) for g in W.graphs]
+        self.batched = len(W.graphs) > 1 or W.angles.shape[0] > 1
+        self.evals_per_step = len(W.graphs) * (W.angles.shape[0] if self.batched else 1)
+
+    def step(self, prec, grad):
+        q, W = self.q, self.W
+        if self.batched:
+            if grad:
+                return q.expect_grad_batched(self.problems, self.mixers, W.angles, precision=prec)
+            return q.expect_batched(self.problems, self.mixers, W.angles, precision=prec), None
+        if grad:
+            return q.expect_grad(self.problems[0], self.mixers[0], W.angles[0], precision=prec)
+        return q.expect(self.problems[0], self.mixers[0], W.angles[0], precision=prec), None
+
+    def time(self, prec, grad, steps, warmup, torch):
+        for _ in range(warmup):
+            self.step(prec, grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = self.step(prec, grad)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+
+def cpu_baseline(W, sample):
+    """The FP64 oracle on a bounded sample of the workload; returns (record, sample results)."""
     import numpy as np
     import oracle
-    g = W.graphs[0]
-    table = oracle.graph_table(g)
-    a1 = np.array([W.angles[0][0], W.angles[0][W.p]])
+    k = W.hamming_k
+    if W.name == "maxcut3reg_n28_p8":
+        # one fwd+adjoint evaluation with p=1 at the full n (one of the p layers), scaled by p
+        g = W.graphs[0]
+        table = oracle.graph_table(g)
+        a1 = np.array([W.angles[0][0], W.angles[0][W.p]])
+        t0 = time.perf_counter()
+        oracle.grad(g.n, table, a1)
+        dt = time.perf_counter() - t0
+        return {"value": 1.0 / (dt * W.p), "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"one fwd+adjoint evaluation with p=1 at n={g.n} (1 of the {W.p} layers), "
+                          f"{dt:.1f} s, scaled x{W.p} to one p={W.p} evaluation"}, {}
+    if W.name == "maxcut3reg_n32_p16":
+        return None, {}
+    tables = [oracle.graph_table(g, k) for g in W.graphs]
+    res = {}
     t0 = time.perf_counter()
-    oracle.grad(g.n, table, a1)
+    count = 0
+    grad = W.name != "maxcut3reg_n10_p3"
+    for (i, s) in sample:
+        g = W.graphs[i]
+        if grad:
+            res[(i, s)] = oracle.grad(g.n, tables[i], W.angles[s], k=k)
+        else:
+            res[(i, s)] = oracle.expect(g.n, tables[i], W.angles[s], k=k)
+        count += 1
     dt = time.perf_counter() - t0
-    per_eval = dt * W.p
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one fwd+adjoint evaluation with p=1 at n={g.n} (1 of the {W.p} layers), "
-                      f"{dt:.1f} s, scaled x{W.p} to one p={W.p} evaluation"}
+    # the sample's evaluations have the workload's mix of sizes when the sample covers every
+    # instance equally
+    return {"value": count / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{count} {'fwd+adjoint' if grad else 'forward'} evaluations "
+                      f"({len(set(i for i, _ in sample))} instance(s)), {dt:.1f} s"}, res
+
+
+def sample_for(W):
+    if W.name == "maxcut3reg_n10_p3":
+        return [(0, 0)] * 200
+    if W.name == "batched_er_n12to20_p10":
+        return [(i, s) for i in range(len(W.graphs)) for s in range(2)]
+    if W.name == "bisection_g16_k8_p6":
+        return [(0, 0)]
+    return []
+
+
+def traffic_from_profile(workload, cls):
+    """HBM bytes per launch of the pass kernels from the committed rocprofv3 counter summary,
+    valid only while the kernel source is the one the counters were taken with."""
+    tpath = os.path.join(ROOT, "profiles", f"pmc_traffic_k_pass_{workload}.md")
+    if not os.path.exists(tpath):
+        return None
+    txt = open(tpath).read()
+    ksrc = os.path.join(ROOT, "paper_2312_06451_amd", "csrc", "qaoa_kernels.hip")
+    cur = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()
+    if f"kernel_source_sha256 = {cur}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("traffic_bytes_per_launch "):
+            k, v = line[len("traffic_bytes_per_launch "):].split("=")
+            if k.strip() == cls:
+                return float(v)
+    return None
+
+
+KERNEL_NAMES = {"fwd_pass": "k_pass<float,13,1,uint8> (tile pass, one vector)",
+                "rev_pass": "k_pass<float,13,2|3,uint8> (tile pass, state and adjoint vector)",
+                "small": "k_small<float> (whole state in one workgroup)",
+                "dense": "hipBLASLt GEMM f16 x f16 -> f32 (split eigenbasis product, 2 calls)"}
+
+
+def roofline(prof, workload):
+    cls = max(("fwd_pass", "rev_pass", "small", "dense"), key=lambda k: prof[k]["ms"])
+    d = prof[cls]
+    L = max(d["launches"], 1)
+    mean_ms = d["ms"] / L
+    base = {"kernel": KERNEL_NAMES[cls], "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
+    if cls in ("fwd_pass", "rev_pass"):
+        bpl = d["bytes"] / L
+        a = bpl / (mean_ms * 1e-3) / 1e9
+        return dict({"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(a / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(workload, cls),
+                     "bytes_per_launch": bpl}, **base)
+    if cls == "dense":
+        # one product = three FP16 MFMA products (hi*hi, hi*lo, lo*hi) of 2*N*N*cols flops each
+        fpl = 3.0 * d["flops"] / L
+        a = fpl / (mean_ms * 1e-3) / 1e12
+        return dict({"bound": "mfma", "achieved": round(a, 1), "peak": MFMA_F16_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": round(a / MFMA_F16_PEAK_TFS, 4), "traffic": None, "flops_per_launch": fpl,
+                     "fp32_equivalent_TFLOPs": round(a / 3.0, 1)}, **base)
+    return dict({"bound": "alu", "achieved": None, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                 "frac": None, "traffic": None}, **base)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="maxcut3reg_n28_p8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fwd-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the QAOA state of this workload is evaluated on a single "
@@ -103,102 +223,120 @@ def main():
     import paper_2312_06451_amd as q
     from paper_2312_06451_amd import _lib
 
+    W = workloads.workload(args.workload)
+    steps = args.steps if args.steps is not None else {"maxcut3reg_n10_p3": 200, "maxcut3reg_n32_p16": 2}.get(W.name, 20)
+    warmup = min(args.warmup, 1) if W.name == "maxcut3reg_n32_p16" else args.warmup
+    grad = W.name != "maxcut3reg_n10_p3"
+
     roof_copy = copy_roof(torch)
     log(f"copy roof: {roof_copy['GBps']:.0f} GB/s")
-    W = workloads.workload(args.workload)
-    g = W.graphs[0]
-    angles = W.angles[0]
-    n, p = g.n, W.p
-    ctx = q.Context(0)
-    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
-    log(f"workload {args.workload}: n={n} p={p} edges={g.m}")
+    R = Runner(q, W)
+    h = R.ctx.handle
+    log(f"workload {W.name}: {W.description}")
 
     # ---- FP32 state (timed, with per-kernel events)
-    _lib.qaoa_profile_enable(ctx.handle, False)
-    for _ in range(args.warmup):
-        q.expect_grad(P, M, angles, precision=q.QAOA_FP32)
-    _lib.qaoa_profile_enable(ctx.handle, True)
-    dt32, e32, g32 = time_steps(q, P, M, angles, q.QAOA_FP32, args.steps, 0, torch)
-    prof = {k: _lib.qaoa_profile_read(ctx.handle, v) for k, v in _lib.KERNEL_CLASSES.items()}
-    _lib.qaoa_profile_enable(ctx.handle, False)
-    evals32 = args.steps / dt32
-    log(f"FP32: {dt32 / args.steps * 1e3:.2f} ms/eval, {evals32:.2f} evals/s; kernels {prof}")
+    _lib.qaoa_profile_enable(h, False)
+    for _ in range(warmup):
+        R.step(q.QAOA_FP32, grad)
+    _lib.qaoa_profile_enable(h, True)
+    dt32, out32 = R.time(q.QAOA_FP32, grad, steps, 0, torch)
+    prof = {k: _lib.qaoa_profile_read(h, v) for k, v in _lib.KERNEL_CLASSES.items()}
+    _lib.qaoa_profile_enable(h, False)
+    evals32 = steps * R.evals_per_step / dt32
+    log(f"FP32: {dt32 / steps * 1e3:.3f} ms/step, {evals32:.2f} evals/s; kernels {prof}")
 
-    # ---- FP64 state (the plain FP64 GPU path: same kernels, complex128)
+    # ---- forward only (the cost of the gradient relative to one evaluation)
+    fwd = None
+    if grad and not args.no_fwd_only:
+        sf = max(1, steps // 2)
+        dtf, _ = R.time(q.QAOA_FP32, False, sf, 1, torch)
+        fwd = {"ms_per_step": dtf / sf * 1e3, "grad_over_fwd": (dt32 / steps) / (dtf / sf)}
+        log(f"forward only: {fwd}")
+
+    # ---- FP64 state (the plain FP64 GPU path: same kernels, complex128 / DGEMM)
     fp64 = None
     if not args.no_fp64:
-        s64 = max(2, args.steps // 4)
-        dt64, e64, g64 = time_steps(q, P, M, angles, q.QAOA_FP64, s64, 1, torch)
-        fp64 = {"value": s64 / dt64, "unit": "evals/s", "ms_per_step": dt64 / s64 * 1e3, "steps": s64}
-        log(f"FP64: {dt64 / s64 * 1e3:.2f} ms/eval")
+        s64 = max(1, steps // 4)
+        dt64, out64 = R.time(q.QAOA_FP64, grad, s64, 1, torch)
+        fp64 = {"value": s64 * R.evals_per_step / dt64, "unit": "evals/s", "ms_per_step": dt64 / s64 * 1e3,
+                "steps": s64}
+        log(f"FP64: {dt64 / s64 * 1e3:.3f} ms/step")
 
-    # ---- error vs the oracle's stored FP64 values
-    err = None
-    gpath = os.path.join(ROOT, "tests", "golden", args.workload + ".json")
-    if os.path.exists(gpath):
-        G = json.load(open(gpath))
-        s = G["sets"][0]
-        if np.allclose(s["angles"], angles, rtol=0, atol=0):
-            ref_e, ref_g = s["expect"], np.array(s["grad"])
-            err = {"expect_rel": abs(e32 - ref_e) / abs(ref_e),
-                   "grad_inf_rel": float(np.max(np.abs(g32 - ref_g)) / np.max(np.abs(ref_g))),
-                   "reference": "FP64 CPU oracle (stored)"}
-            if fp64 is not None:
-                err["fp64_expect_rel"] = abs(e64 - ref_e) / abs(ref_e)
-                err["fp64_grad_inf_rel"] = float(np.max(np.abs(g64 - ref_g)) / np.max(np.abs(ref_g)))
+    def pick(out, i, s):
+        e, g = out
+        if R.batched:
+            return float(np.asarray(e)[i, s]), (None if g is None else np.asarray(g)[i, s])
+        return float(e), (None if g is None else np.asarray(g))
 
-    # ---- HBM traffic per launch from the committed rocprofv3 counter summary, valid only
-    # while the kernel source is the one the counters were taken with
-    traffic = {}
-    tpath = os.path.join(ROOT, "profiles", f"pmc_traffic_k_pass_{args.workload}.md")
-    if os.path.exists(tpath):
-        import hashlib
-        txt = open(tpath).read()
-        ksrc = os.path.join(ROOT, "paper_2312_06451_amd", "csrc", "qaoa_kernels.hip")
-        cur = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()
-        if f"kernel_source_sha256 = {cur}" in txt:
-            for line in txt.splitlines():
-                if line.startswith("traffic_bytes_per_launch "):
-                    k, v = line[len("traffic_bytes_per_launch "):].split("=")
-                    traffic[k.strip()] = float(v)
-
-    # ---- roofline of the dominant kernel class
-    dom = max(("fwd_pass", "rev_pass"), key=lambda k: prof[k]["ms"])
-    d = prof[dom]
-    mean_ms = d["ms"] / max(d["launches"], 1)
-    bytes_per_launch = d["bytes"] / max(d["launches"], 1)
-    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic.get(dom),
-            "kernel": "k_pass<float,13,2,uint8>" if dom == "rev_pass" else "k_pass<float,13,1,uint8>",
-            "class": dom, "launches": d["launches"], "mean_ms": round(mean_ms, 4),
-            "bytes_per_launch": bytes_per_launch}
-    all_pass_ms = prof["fwd_pass"]["ms"] + prof["rev_pass"]["ms"]
-    all_pass_bytes = prof["fwd_pass"]["bytes"] + prof["rev_pass"]["bytes"]
-    path = {"algorithmic_bytes_per_eval": eval_bytes_per_amp(p) * 2.0 ** n,
-            "algorithmic_GBps": eval_bytes_per_amp(p) * 2.0 ** n * evals32 / 1e9,
-            "moved_bytes_per_eval": all_pass_bytes / args.steps,
-            "pass_kernels_GBps": all_pass_bytes / (all_pass_ms * 1e-3) / 1e9 if all_pass_ms else None}
-    path["algorithmic_frac"] = path["algorithmic_GBps"] / HBM_PEAK_GBS
-
-    cpu = None
+    # ---- CPU oracle on a bounded sample; its results also give the error of the GPU path
+    cpu, ref = None, {}
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle) ...")
-        cpu = cpu_baseline(W)
+        cpu, ref = cpu_baseline(W, sample_for(W))
         log(f"CPU: {cpu}")
 
+    # ---- error vs FP64 oracle values (stored ones for the single-set workloads)
+    gpath = os.path.join(ROOT, "tests", "golden", W.name + ".json")
+    if os.path.exists(gpath):
+        G = json.load(open(gpath))
+        for s, rec in enumerate(G["sets"]):
+            if s < W.angles.shape[0] and np.array_equal(np.array(rec["angles"]), W.angles[s]):
+                ref[(0, s)] = (rec["expect"], 1.0, np.array(rec["grad"]))
+    err = None
+    if ref:
+        ee, ge, ee64, ge64 = [], [], [], []
+        for (i, s), r in ref.items():
+            if grad:
+                E0, N0, g0 = r
+                e, gr = pick(out32, i, s)
+                ee.append(abs(e - E0 / N0) / abs(E0 / N0))
+                ge.append(float(np.max(np.abs(gr - g0 / N0)) / np.max(np.abs(g0 / N0))))
+                if fp64:
+                    e6, g6 = pick(out64, i, s)
+                    ee64.append(abs(e6 - E0 / N0) / abs(E0 / N0))
+                    ge64.append(float(np.max(np.abs(g6 - g0 / N0)) / np.max(np.abs(g0 / N0))))
+            else:
+                E0, N0 = r[0], r[1]
+                e, _ = pick(out32, i, s)
+                ee.append(abs(e - E0 / N0) / abs(E0 / N0))
+                if fp64:
+                    ee64.append(abs(pick(out64, i, s)[0] - E0 / N0) / abs(E0 / N0))
+        err = {"expect_rel": max(ee), "grad_inf_rel": max(ge) if ge else None,
+               "fp64_expect_rel": max(ee64) if ee64 else None, "fp64_grad_inf_rel": max(ge64) if ge64 else None,
+               "reference": f"FP64 CPU oracle, {len(ref)} evaluation(s)"}
+
+    roof = roofline(prof, W.name)
+    path = None
+    if W.mixer == "x" and len(W.graphs) == 1:
+        g = W.graphs[0]
+        all_pass_ms = prof["fwd_pass"]["ms"] + prof["rev_pass"]["ms"]
+        all_pass_bytes = prof["fwd_pass"]["bytes"] + prof["rev_pass"]["bytes"]
+        path = {"algorithmic_bytes_per_eval": eval_bytes_per_amp(W.p) * 2.0 ** g.n,
+                "algorithmic_GBps": eval_bytes_per_amp(W.p) * 2.0 ** g.n * evals32 / 1e9,
+                "moved_bytes_per_eval": all_pass_bytes / steps if all_pass_ms else None,
+                "pass_kernels_GBps": all_pass_bytes / (all_pass_ms * 1e-3) / 1e9 if all_pass_ms else None}
+        path["algorithmic_frac"] = path["algorithmic_GBps"] / HBM_PEAK_GBS
+    if W.mixer == "clique":
+        d = prof["dense"]
+        path = {"products_per_step": d["launches"] / steps,
+                "algorithmic_TFLOPs_per_step": d["flops"] / steps / 1e12,
+                "dense_share_of_step": d["ms"] / (dt32 * 1e3)}
+
+    cfg = {"workload": W.name, "description": W.description, "p": W.p,
+           "instances": len(W.graphs), "n": [g.n for g in W.graphs] if len(W.graphs) > 1 else W.graphs[0].n,
+           "angle_sets": int(W.angles.shape[0]), "mixer": W.mixer, "mode": "fwd+grad" if grad else "fwd",
+           "state": "complex64, FP64 sums", "parallelism": "single GPU"}
+    if W.hamming_k >= 0:
+        cfg["hamming_k"] = W.hamming_k
     out = {
-        "metric": METRIC, "value": round(evals32, 3), "unit": "evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt32 / args.steps * 1e3, 3),
+        "metric": METRIC if W.name == "maxcut3reg_n28_p8" else f"{cfg['mode']} QAOA evals/sec ({W.name})",
+        "value": round(evals32, 3), "unit": "evals/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(dt32 / steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "p": p, "graph": "random 3-regular, pairing model",
-                   "mixer": "transverse field", "mode": "fwd+grad", "state": "complex64, FP64 sums",
-                   "parallelism": "single GPU"},
+        "data": "synthetic", "config": cfg,
         "roofline": roof, "path": path, "copy_roof": roof_copy, "fp64": fp64,
-        "speedup_vs_fp64": (evals32 / fp64["value"]) if fp64 else None,
-        "error": err, "cpu_baseline": cpu,
-        "kernels": prof,
+        "speedup_vs_fp64": (evals32 / fp64["value"]) if fp64 else None, "forward_only": fwd,
+        "error": err, "cpu_baseline": cpu, "kernels": prof,
     }
     print(json.dumps(out), flush=True)
 

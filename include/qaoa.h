@@ -130,8 +130,12 @@ int qaoa_state(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const dou
                const void *d_psi0, int precision, void *d_out, void *stream);
 
 /* Batched <C>: every problem probs[i] (with mixer mixers[i]) at every angle set
- * angles[s][0..2p), s < n_sets, default initial state. out_expect: host double
- * [n_probs][n_sets]. All items run in one graph-captured launch sequence. */
+ * angles[s][0..2p), s < n_sets, default initial state (the repeated evaluations of the
+ * angle-finding loops, Sec. 2.3 and Sec. 3). out_expect: host double [n_probs][n_sets].
+ * Every (problem, set) pair whose state fits one workgroup (n <= 13 for QAOA_FP32, n <= 12
+ * for QAOA_FP64, transverse-field mixer) runs in one launch, one workgroup per pair; each
+ * larger problem runs as one sequence of tile passes (or eigenbasis products) that covers
+ * all n_sets angle sets per launch. Problems may differ in n and in mixer. */
 int qaoa_expect_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
                         int n_probs, int n_sets, int p, const double *angles, int precision,
                         double *out_expect, void *stream);

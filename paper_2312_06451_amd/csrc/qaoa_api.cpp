@@ -68,7 +68,7 @@ struct DevBuf {
   size_t cap = 0;
   void *get(size_t bytes) {
     if (bytes <= cap && p) return p;
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     cap = 0;
     if (bytes == 0) return nullptr;
@@ -82,7 +82,7 @@ struct DevBuf {
     return p;
   }
   ~DevBuf() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   }
 };
 
@@ -91,7 +91,7 @@ struct HostBuf {
   size_t cap = 0;
   void *get(size_t bytes) {
     if (bytes <= cap && p) return p;
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
     hipError_t e = hipHostMalloc(&p, bytes < 4096 ? 4096 : bytes, hipHostMallocDefault);
@@ -104,7 +104,7 @@ struct HostBuf {
     return p;
   }
   ~HostBuf() {
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   }
 };
 
@@ -115,7 +115,7 @@ struct DeviceGuard {
     HIPCHK(hipSetDevice(dev));
   }
   ~DeviceGuard() {
-    if (prev >= 0) hipSetDevice(prev);
+    if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
 
@@ -151,10 +151,10 @@ struct qaoa_ctx {
   std::vector<Pending> pending;
   KTotals totals[QAOA_KC_COUNT];
   ~qaoa_ctx() {
-    for (auto e : ev_pool) hipEventDestroy(e);
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto &p : pending) {
-      hipEventDestroy(p.a);
-      hipEventDestroy(p.b);
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
     }
   }
   hipEvent_t take_event() {
@@ -236,9 +236,9 @@ struct qaoa_problem {
   void *table = nullptr;
   std::map<std::tuple<int, int, int>, void *> layouts;  // (T, c, h0) -> tile-major copy
   ~qaoa_problem() {
-    if (table) hipFree(table);
+    if (table) (void)hipFree(table);
     for (auto &kv : layouts)
-      if (kv.second) hipFree(kv.second);
+      if (kv.second) (void)hipFree(kv.second);
   }
 };
 
@@ -267,6 +267,16 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin) {
     int c = T - width;
     t.push_back({c, next, ((1u << T) - 1) & ~((1u << c) - 1)});
     next += width;
+  }
+  // Balance the rotation work between passes. The lowest T - 8 address bits (the L register
+  // group) are contiguous bits of every tile, so any tile may rotate them. With three or more
+  // tiles, the middle tile of a layer runs as a single-block pass (memory-bound, with spare
+  // ALU time), while the first tile runs as a two-block pass; moving those bits from the
+  // first tile to the second cuts the largest pass from 2T to 2(T - (T - 8)) rotations.
+  if (t.size() >= 3 && t[1].c >= T - 8) {
+    const uint32_t L = (1u << (T - 8)) - 1;
+    t[0].rot &= ~L;
+    t[1].rot |= L;
   }
   return t;
 }
@@ -362,7 +372,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     }
     hipError_t e = launch_table_relayout(prob->table, d, prob->tbytes, n, T, g.c, g.h0, st);
     if (e != hipSuccess) {
-      hipFree(d);
+      (void)hipFree(d);
       throw fail(QAOA_ERR_HIP, std::string("table relayout: ") + hipGetErrorString(e));
     }
     prob->layouts[key] = d;

@@ -7,8 +7,10 @@
 // i.e. two dense products per round, for all angle sets at once: the state of S angle sets is
 // an N x 2S real matrix (real and imaginary parts as separate columns).
 //
-// FP32 form: each product is formed from FP16 halves with FP32 accumulation (MFMA through
-// rocBLAS): with x = x_hi + 2^-11 x_lo (x_hi = fp16(x), x_lo = fp16(2^11 (x - x_hi))),
+// FP32 form: each product is formed from FP16 halves with FP32 accumulation (MFMA GEMMs of
+// hipBLASLt; for each product shape the fastest of the library's candidate algorithms is
+// timed and kept on first use, rocBLAS when none runs): with x = x_hi + 2^-11 x_lo
+// (x_hi = fp16(x), x_lo = fp16(2^11 (x - x_hi))),
 //     V B ~ V_hi B_hi + 2^-11 (V_hi B_lo + V_lo B_hi),
 // two GEMM calls (K = N, then K = 2N on the stacked halves); the dropped V_lo B_lo term is
 // 2^-22 relative. FP64 form: DGEMM on the FP64 eigenbasis.
@@ -20,11 +22,14 @@
 //   lam = V lam~;    g_gamma = 2 sum_x (C - c0) Im(conj(lam) phi);  lam *= exp(+i gamma C).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <hipblaslt/hipblaslt.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/qaoa.h"
@@ -40,7 +45,7 @@ struct Buf {
   size_t cap = 0;
   void *get(size_t bytes) {
     if (bytes <= cap && p) return p;
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     cap = 0;
     if (bytes == 0) return nullptr;
@@ -53,12 +58,16 @@ struct Buf {
     return p;
   }
   ~Buf() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   }
 };
 
 void hipchk(hipError_t e, const char *what) {
   if (e != hipSuccess) throw CliqueError{QAOA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+void ltchk(hipblasStatus_t s, const char *what) {
+  if (s != HIPBLAS_STATUS_SUCCESS)
+    throw CliqueError{QAOA_ERR_HIP, std::string(what) + ": hipBLASLt status " + std::to_string((int)s)};
 }
 void blaschk(rocblas_status s, const char *what) {
   if (s != rocblas_status_success)
@@ -76,17 +85,37 @@ constexpr int RB_ROWS = 1024;  // rows per block in the elementwise kernels (4 p
 
 }  // namespace
 
+// One FP16 x FP16 -> FP32 GEMM shape of the split products with its selected algorithm.
+struct LtGemm {
+  hipblasLtMatmulDesc_t desc = nullptr;
+  hipblasLtMatrixLayout_t a = nullptr, b = nullptr, c = nullptr;
+  hipblasLtMatmulAlgo_t algo{};
+  size_t ws = 0;
+  bool ok = false;  // false: no hipBLASLt algorithm ran, use rocBLAS
+  ~LtGemm() {
+    if (a) (void)hipblasLtMatrixLayoutDestroy(a);
+    if (b) (void)hipblasLtMatrixLayoutDestroy(b);
+    if (c) (void)hipblasLtMatrixLayoutDestroy(c);
+    if (desc) (void)hipblasLtMatmulDescDestroy(desc);
+  }
+};
+
 struct CliqueMixer {
   int n = 0, k = 0;
   int64_t N = 0;
   rocblas_handle blas = nullptr;
+  hipblasLtHandle_t lt = nullptr;
+  std::map<std::tuple<int, int, int>, std::unique_ptr<LtGemm>> gemms;  // (transpose, K/N, cols)
+  Buf ltws;                                                               // hipBLASLt workspace
   Buf V, D, Vcols, Vrows;  // FP64 eigenbasis (N x N col-major, column j = eigenvector j),
                            // eigenvalues, FP16 halves [V_hi | V_lo] (N x 2N) and [V_hi; V_lo] (2N x N)
   Buf X, Y, B, ckP, ckT, partials, params, luts, results, hres_dev;
   std::vector<double> hres;
   CliqueTimer timer;
   ~CliqueMixer() {
-    if (blas) rocblas_destroy_handle(blas);
+    gemms.clear();
+    if (lt) (void)hipblasLtDestroy(lt);
+    if (blas) (void)rocblas_destroy_handle(blas);
   }
 };
 
@@ -366,16 +395,91 @@ std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int n, int k, hip
 
 namespace {
 
+constexpr size_t LT_WORKSPACE = 64ull << 20;
+
+// Creates the descriptors of one split-product GEMM (D = alpha op(A) B + beta D, A the FP16
+// eigenbasis halves, B the FP16 state halves with leading dimension 2N, D FP32 N x cols) and
+// times the library's candidate algorithms on the given operands; keeps the fastest.
+// Overwrites out (the caller recomputes it afterwards).
+void lt_select(CliqueMixer &m, LtGemm &g, bool transpose, int kmul, int cols, const void *A, const void *B,
+               float *out, hipStream_t st) {
+  const int64_t N = m.N, K = kmul * N;
+  ltchk(hipblasLtMatmulDescCreate(&g.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F), "matmul desc");
+  const int32_t opA = transpose ? HIPBLAS_OP_T : HIPBLAS_OP_N, opB = HIPBLAS_OP_N;
+  ltchk(hipblasLtMatmulDescSetAttribute(g.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opA, sizeof(opA)), "transA");
+  ltchk(hipblasLtMatmulDescSetAttribute(g.desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opB, sizeof(opB)), "transB");
+  if (transpose) ltchk(hipblasLtMatrixLayoutCreate(&g.a, HIP_R_16F, K, N, 2 * N), "layout A");
+  else ltchk(hipblasLtMatrixLayoutCreate(&g.a, HIP_R_16F, N, K, N), "layout A");
+  ltchk(hipblasLtMatrixLayoutCreate(&g.b, HIP_R_16F, K, cols, 2 * N), "layout B");
+  ltchk(hipblasLtMatrixLayoutCreate(&g.c, HIP_R_32F, N, cols, N), "layout C");
+  hipblasLtMatmulPreference_t pref = nullptr;
+  ltchk(hipblasLtMatmulPreferenceCreate(&pref), "preference");
+  const uint64_t wmax = LT_WORKSPACE;
+  (void)hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wmax, sizeof(wmax));
+  hipblasLtMatmulHeuristicResult_t res[16];
+  int found = 0;
+  hipblasStatus_t hs = hipblasLtMatmulAlgoGetHeuristic(m.lt, g.desc, g.a, g.b, g.c, g.c, pref, 16, res, &found);
+  (void)hipblasLtMatmulPreferenceDestroy(pref);
+  if (hs != HIPBLAS_STATUS_SUCCESS || found <= 0) return;
+  void *ws = m.ltws.get(LT_WORKSPACE);
+  hipEvent_t e0, e1;
+  hipchk(hipEventCreate(&e0), "event");
+  hipchk(hipEventCreate(&e1), "event");
+  const float one = 1.0f;
+  float best = 1e30f;
+  for (int i = 0; i < found; i++) {
+    if (res[i].state != HIPBLAS_STATUS_SUCCESS || res[i].workspaceSize > LT_WORKSPACE) continue;
+    bool good = true;
+    for (int r = 0; r < 4 && good; r++) {
+      if (r == 1) (void)hipEventRecord(e0, st);
+      good = hipblasLtMatmul(m.lt, g.desc, &one, A, g.a, B, g.b, &one, out, g.c, out, g.c, &res[i].algo, ws,
+                             res[i].workspaceSize, st) == HIPBLAS_STATUS_SUCCESS;
+    }
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) good = false;
+    float ms = 0.f;
+    if (good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
+      best = ms;
+      g.algo = res[i].algo;
+      g.ws = res[i].workspaceSize;
+      g.ok = true;
+    }
+  }
+  (void)hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 template <typename R>
 struct Dense {
   CliqueMixer &m;
   hipStream_t st;
   int64_t N;
   int cols;  // 2S
+
+  LtGemm *gemm(bool transpose, int kmul, const void *A, const void *B, float *out) {
+    auto key = std::make_tuple(transpose ? 1 : 0, kmul, cols);
+    auto it = m.gemms.find(key);
+    if (it != m.gemms.end()) return it->second.get();
+    auto g = std::make_unique<LtGemm>();
+    lt_select(m, *g, transpose, kmul, cols, A, B, out, st);
+    LtGemm *p = g.get();
+    m.gemms[key] = std::move(g);
+    return p;
+  }
+
   // out (N x cols) = op(V) in (next-product input B), op = V^T (transpose) or V
   void product(bool transpose, const void *B, R *out) {
     const rocblas_int n = (rocblas_int)N, c = cols;
     blaschk(rocblas_set_stream(m.blas, st), "rocblas_set_stream");
+    LtGemm *l1 = nullptr, *l2 = nullptr;
+    if constexpr (sizeof(R) == 4) {
+      // algorithm selection runs before the timed product (it overwrites out)
+      const __half *A = transpose ? (const __half *)m.Vrows.p : (const __half *)m.Vcols.p;
+      if (!m.lt) ltchk(hipblasLtCreate(&m.lt), "hipblasLtCreate");
+      l1 = gemm(transpose, 1, A, (const __half *)B + N, (float *)out);
+      l2 = gemm(transpose, 2, A, B, (float *)out);
+    }
     if (m.timer.begin) m.timer.begin(m.timer.ctx, st);
     double flops;
     if constexpr (sizeof(R) == 4) {
@@ -384,14 +488,25 @@ struct Dense {
       const rocblas_operation op = transpose ? rocblas_operation_transpose : rocblas_operation_none;
       const __half *A = transpose ? (const __half *)m.Vrows.p : (const __half *)m.Vcols.p;
       const rocblas_int lda = transpose ? 2 * n : n;
-      blaschk(rocblas_gemm_ex(m.blas, op, rocblas_operation_none, n, c, n, &one, A, rocblas_datatype_f16_r, lda,
-                              b + N, rocblas_datatype_f16_r, 2 * n, &zero, out, rocblas_datatype_f32_r, n, out,
-                              rocblas_datatype_f32_r, n, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0),
-              "rocblas_gemm_ex (hi x hi)");
-      blaschk(rocblas_gemm_ex(m.blas, op, rocblas_operation_none, n, c, 2 * n, &s11, A, rocblas_datatype_f16_r,
-                              lda, b, rocblas_datatype_f16_r, 2 * n, &one, out, rocblas_datatype_f32_r, n, out,
-                              rocblas_datatype_f32_r, n, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0),
-              "rocblas_gemm_ex (hi x lo + lo x hi)");
+      void *ws = m.ltws.p;
+      if (l1->ok)
+        ltchk(hipblasLtMatmul(m.lt, l1->desc, &one, A, l1->a, b + N, l1->b, &zero, out, l1->c, out, l1->c,
+                              &l1->algo, ws, l1->ws, st),
+              "hipblasLtMatmul (hi x hi)");
+      else
+        blaschk(rocblas_gemm_ex(m.blas, op, rocblas_operation_none, n, c, n, &one, A, rocblas_datatype_f16_r, lda,
+                                b + N, rocblas_datatype_f16_r, 2 * n, &zero, out, rocblas_datatype_f32_r, n, out,
+                                rocblas_datatype_f32_r, n, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0),
+                "rocblas_gemm_ex (hi x hi)");
+      if (l2->ok)
+        ltchk(hipblasLtMatmul(m.lt, l2->desc, &s11, A, l2->a, b, l2->b, &one, out, l2->c, out, l2->c, &l2->algo,
+                              ws, l2->ws, st),
+              "hipblasLtMatmul (hi x lo + lo x hi)");
+      else
+        blaschk(rocblas_gemm_ex(m.blas, op, rocblas_operation_none, n, c, 2 * n, &s11, A, rocblas_datatype_f16_r,
+                                lda, b, rocblas_datatype_f16_r, 2 * n, &one, out, rocblas_datatype_f32_r, n, out,
+                                rocblas_datatype_f32_r, n, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0),
+                "rocblas_gemm_ex (hi x lo + lo x hi)");
       flops = 3.0 * 2.0 * (double)N * N * cols;
     } else {
       const double one = 1.0, zero = 0.0;

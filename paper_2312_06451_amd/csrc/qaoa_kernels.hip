@@ -908,8 +908,9 @@ static hipError_t launch_pass_t(const PassArgs<R> &a, hipStream_t s) {
   size_t lds = lds_for<R, T>((int)sizeof(TT), a.lut_len);
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void *)k_pass<R, T, KIND, S1, S2, SHAPE, TT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void *)k_pass<R, T, KIND, S1, S2, SHAPE, TT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid(a.nwg, a.nsets);
@@ -974,8 +975,11 @@ hipError_t launch_small(int precision, const SmallItem *items, int n_items, int 
                ((((size_t)max_tbytes << max_n) + 15) & ~(size_t)15) + 64;
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipFuncSetAttribute((const void *)k_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
     attr_set = true;
   }
   if (precision == 0)
