@@ -66,7 +66,8 @@ typedef struct qaoa_mixer qaoa_mixer;     /* H_M: transverse field or clique    
 int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
 
 /* Destroy a context and free its scratch. Problems and mixers created on it must be
- * destroyed first. NULL is accepted (no-op). */
+ * destroyed first: while any is alive the call returns QAOA_ERR_INVALID_ARG and destroys
+ * nothing. NULL is accepted (no-op). */
 int qaoa_ctx_destroy(qaoa_ctx *ctx);
 
 /* Step (a): tabulate the MaxCut cost diagonal on the device (Sec. 2.1, pre-computation):

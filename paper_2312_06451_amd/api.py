@@ -1,6 +1,8 @@
 """Handle classes over the C ABI (argument marshalling only)."""
 from __future__ import annotations
 
+import weakref
+
 import numpy as np
 
 from . import _lib
@@ -28,9 +30,13 @@ class Context:
     def __init__(self, device: int = 0):
         self.handle = _lib.qaoa_ctx_create(device)
         self.device = device
+        self._children = weakref.WeakSet()
 
     def close(self):
+        """Destroy the context; problems and mixers still open on it are closed first."""
         if self.handle:
+            for ch in list(self._children):
+                ch.close()
             _lib.qaoa_ctx_destroy(self.handle)
             self.handle = None
 
@@ -47,6 +53,7 @@ class Problem:
     def __init__(self, ctx: Context, n: int, u, v, w=None, hamming_k: int = -1, stream=None):
         self.ctx = ctx
         self.handle = _lib.qaoa_cost_table(ctx.handle, n, u, v, w, hamming_k, _stream(stream))
+        ctx._children.add(self)
         info = _lib.qaoa_problem_info(self.handle)
         self.n = info["n"]
         self.hamming_k = info["hamming_k"]
@@ -77,6 +84,7 @@ class Mixer:
 
     def __init__(self, ctx: Context, handle: int, kind: str, n: int, k: int = -1):
         self.ctx, self.handle, self.kind, self.n, self.k = ctx, handle, kind, n, k
+        ctx._children.add(self)
 
     @classmethod
     def x(cls, ctx: Context, n: int):

@@ -137,6 +137,7 @@ struct KTotals {
 
 struct qaoa_ctx {
   int device = 0;
+  int64_t live = 0;          // problems and mixers created on this context and not yet destroyed
   int checkpoint_mode = -1;  // -1: when memory allows, 0: never, 1: always
   DevBuf phi, lam, ckpt, partials, params, luts, results, cnt, items;
   HostBuf hparams, hresults;
@@ -847,6 +848,7 @@ int qaoa_profile_read(const qaoa_ctx *ctx, int kernel_class, int64_t *launches, 
 int qaoa_ctx_destroy(qaoa_ctx *ctx) {
   return guarded([&] {
     if (!ctx) return;
+    REQUIRE(ctx->live == 0, "problems or mixers created on this context are still alive");
     DeviceGuard g(ctx->device);
     delete ctx;
   });
@@ -926,6 +928,7 @@ int qaoa_cost_table(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const i
     HIPCHK(hipStreamSynchronize(st));
     prob->max_value = hmax;
     *out = prob.release();
+    ctx->live++;
   });
 }
 
@@ -958,6 +961,7 @@ int qaoa_problem_destroy(qaoa_problem *prob) {
   return guarded([&] {
     if (!prob) return;
     DeviceGuard g(prob->ctx->device);
+    prob->ctx->live--;
     delete prob;
   });
 }
@@ -972,6 +976,7 @@ int qaoa_mixer_x(qaoa_ctx *ctx, int n, qaoa_mixer **out) {
     m->kind = 0;
     m->n = n;
     *out = m.release();
+    ctx->live++;
   });
 }
 
@@ -990,6 +995,7 @@ int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *strea
     m->k = k;
     m->clique = clique_create(n, k, (hipStream_t)stream);
     *out = m.release();
+    ctx->live++;
   });
 }
 
@@ -997,6 +1003,7 @@ int qaoa_mixer_destroy(qaoa_mixer *mix) {
   return guarded([&] {
     if (!mix) return;
     DeviceGuard g(mix->ctx->device);
+    mix->ctx->live--;
     delete mix;
   });
 }
