@@ -48,7 +48,7 @@ def lib():
         L.orc_states.argtypes = [ctypes.c_int, ctypes.c_int, u64p]
         L.orc_cost_table.restype = ctypes.c_int64
         L.orc_cost_table.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, ctypes.c_int, i64p]
-        L.orc_apply_phase.argtypes = [ctypes.c_int64, ctypes.c_double, i64p, c128p]
+        L.orc_apply_phase.argtypes = [ctypes.c_int64, ctypes.c_double, f64p, c128p]
         L.orc_apply_x_mixer.argtypes = [ctypes.c_int, ctypes.c_double, c128p]
         L.orc_apply_x_sum.argtypes = [ctypes.c_int, c128p, c128p]
         L.orc_clique_neighbours.restype = ctypes.c_int64
@@ -56,15 +56,15 @@ def lib():
         L.orc_apply_clique_mixer.argtypes = [ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64,
                                              ctypes.c_double, c128p]
         L.orc_expect.restype = ctypes.c_double
-        L.orc_expect.argtypes = [ctypes.c_int64, i64p, c128p, ctypes.POINTER(ctypes.c_double)]
+        L.orc_expect.argtypes = [ctypes.c_int64, f64p, c128p, ctypes.POINTER(ctypes.c_double)]
         vp = ctypes.c_void_p
         L.orc_qaoa_state.restype = ctypes.c_int
-        L.orc_qaoa_state.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, i64p, vp, c128p]
+        L.orc_qaoa_state.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, f64p, vp, c128p]
         L.orc_qaoa_expect.restype = ctypes.c_int
-        L.orc_qaoa_expect.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, i64p, vp,
+        L.orc_qaoa_expect.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, f64p, vp,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.orc_qaoa_grad.restype = ctypes.c_int
-        L.orc_qaoa_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, i64p, vp,
+        L.orc_qaoa_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, f64p, vp,
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), f64p]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_cost_values.restype = ctypes.c_int
@@ -128,8 +128,10 @@ def _psi0_ptr(psi0, N):
 
 
 def _check(n, k, angles, table):
+    """The cost is any list of values over the feasible states (integers from cost_table, or
+    arbitrary reals); the evolution takes it as FP64."""
     angles = np.ascontiguousarray(angles, dtype=np.float64)
-    table = np.ascontiguousarray(table, dtype=np.int64)
+    table = np.ascontiguousarray(table, dtype=np.float64)
     N = (1 << n) if k < 0 else binom(n, k)
     if table.size != N or angles.size % 2:
         raise ValueError("bad table or angle length")
@@ -184,7 +186,7 @@ def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3) -> n
 
 def apply_phase(table, gamma: float, psi: np.ndarray) -> None:
     """In place: psi(x) *= e^{-i gamma C(x)}."""
-    lib().orc_apply_phase(int(psi.size), float(gamma), np.ascontiguousarray(table, dtype=np.int64), psi)
+    lib().orc_apply_phase(int(psi.size), float(gamma), np.ascontiguousarray(table, dtype=np.float64), psi)
 
 
 def apply_x_mixer(n: int, beta: float, psi: np.ndarray) -> None:

@@ -8,7 +8,9 @@
  * What it computes (JuliQAOA, Golden et al., SC-W 2023):
  *   - the cost diagonal C(x) over the feasible set S (Sec. 2.1, "Pre-Computation"):
  *     S = all n-bit strings, or the strings of Hamming weight k in increasing integer order;
- *     index x = sum_i x_i 2^i, vertex i <-> bit i;
+ *     index x = sum_i x_i 2^i, vertex i <-> bit i. The evolution takes C as a list of FP64
+ *     values, one per feasible state (Sec. 3: the objective is handed over as a list of values
+ *     over the states); the MaxCut table is one such list, computed exactly in integers;
  *   - the p-round state of Eq. (1): |b,g> = e^{-i b_p H_M} e^{-i g_p H_C} ... e^{-i b_1 H_M}
  *     e^{-i g_1 H_C} |psi0>, phase separator first in every round, with H_C|x> = C(x)|x>;
  *   - H_M = sum_q X_q (transverse field, Sec. 2.1), applied qubit by qubit as the 2x2 rotation
@@ -112,10 +114,10 @@ static double nsum_val(const nsum *a) { return a->s + a->c; }
 /* ------------------------------------------------------------------ steps (b) and (c) */
 
 /* psi(x) <- e^{-i gamma C(x)} psi(x). */
-void orc_apply_phase(int64_t N, double gamma, const int64_t *table, cplx *psi) {
+void orc_apply_phase(int64_t N, double gamma, const double *cost, cplx *psi) {
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < N; x++) {
-        double a = -gamma * (double)table[x];
+        double a = -gamma * cost[x];
         psi[x] *= cos(a) + I * sin(a);
     }
 }
@@ -225,11 +227,11 @@ void orc_apply_clique_mixer(int n, int k, const int64_t *nb, int64_t N, double b
 /* ------------------------------------------------------------------ step (d): expectation */
 
 /* E = sum |psi|^2 C, Nrm = sum |psi|^2 (Neumaier, sequential). */
-double orc_expect(int64_t N, const int64_t *table, const cplx *psi, double *nrm_out) {
+double orc_expect(int64_t N, const double *cost, const cplx *psi, double *nrm_out) {
     nsum e = {0, 0}, nr = {0, 0};
     for (int64_t x = 0; x < N; x++) {
         double pr = creal(psi[x]) * creal(psi[x]) + cimag(psi[x]) * cimag(psi[x]);
-        nsum_add(&e, pr * (double)table[x]);
+        nsum_add(&e, pr * cost[x]);
         nsum_add(&nr, pr);
     }
     if (nrm_out) *nrm_out = nsum_val(&nr);
@@ -244,9 +246,9 @@ static double im_inner(int64_t N, const cplx *a, const cplx *b) {
 }
 
 /* Im sum conj(a) C b (Neumaier). */
-static double im_inner_c(int64_t N, const int64_t *table, const cplx *a, const cplx *b) {
+static double im_inner_c(int64_t N, const double *cost, const cplx *a, const cplx *b) {
     nsum s = {0, 0};
-    for (int64_t x = 0; x < N; x++) nsum_add(&s, cimag(conj(a[x]) * b[x]) * (double)table[x]);
+    for (int64_t x = 0; x < N; x++) nsum_add(&s, cimag(conj(a[x]) * b[x]) * cost[x]);
     return nsum_val(&s);
 }
 
@@ -276,11 +278,11 @@ static void init_state(int64_t N, const cplx *psi0, cplx *psi) {
     for (int64_t x = 0; x < N; x++) psi[x] = a;
 }
 
-static void evolve(const mixer_t *m, int p, const double *angles, const int64_t *table,
+static void evolve(const mixer_t *m, int p, const double *angles, const double *cost,
                    const cplx *psi0, cplx *psi) {
     init_state(m->N, psi0, psi);
     for (int r = 0; r < p; r++) {
-        orc_apply_phase(m->N, angles[p + r], table, psi);   /* e^{-i gamma_r H_C} */
+        orc_apply_phase(m->N, angles[p + r], cost, psi);    /* e^{-i gamma_r H_C} */
         apply_mixer(m, angles[r], psi);                      /* e^{-i beta_r H_M} */
     }
 }
@@ -301,30 +303,30 @@ static int make_mixer(int n, int k, mixer_t *m, int64_t **nb_store) {
 }
 
 /* Final state psi_p of Eq. (1). k < 0: X mixer; k >= 0: clique mixer on weight k. */
-int orc_qaoa_state(int n, int k, int p, const double *angles, const int64_t *table,
+int orc_qaoa_state(int n, int k, int p, const double *angles, const double *cost,
                    const cplx *psi0, cplx *psi_out) {
     mixer_t m; int64_t *nb;
     if (make_mixer(n, k, &m, &nb)) return -1;
-    evolve(&m, p, angles, table, psi0, psi_out);
+    evolve(&m, p, angles, cost, psi0, psi_out);
     free(nb);
     return 0;
 }
 
 /* <C> (raw E and Nrm) for one angle set. */
-int orc_qaoa_expect(int n, int k, int p, const double *angles, const int64_t *table,
+int orc_qaoa_expect(int n, int k, int p, const double *angles, const double *cost,
                     const cplx *psi0, double *E, double *Nrm) {
     mixer_t m; int64_t *nb;
     if (make_mixer(n, k, &m, &nb)) return -1;
     cplx *psi = (cplx *)malloc(sizeof(cplx) * (size_t)m.N);
     if (!psi) { free(nb); return -1; }
-    evolve(&m, p, angles, table, psi0, psi);
-    *E = orc_expect(m.N, table, psi, Nrm);
+    evolve(&m, p, angles, cost, psi0, psi);
+    *E = orc_expect(m.N, cost, psi, Nrm);
     free(psi); free(nb);
     return 0;
 }
 
 /* <C> and its gradient [d/dbeta_1..p, d/dgamma_1..p] by the adjoint recursion (header). */
-int orc_qaoa_grad(int n, int k, int p, const double *angles, const int64_t *table,
+int orc_qaoa_grad(int n, int k, int p, const double *angles, const double *cost,
                   const cplx *psi0, double *E, double *Nrm, double *grad) {
     mixer_t m; int64_t *nb;
     if (make_mixer(n, k, &m, &nb)) return -1;
@@ -333,17 +335,17 @@ int orc_qaoa_grad(int n, int k, int p, const double *angles, const int64_t *tabl
     cplx *lam = (cplx *)malloc(sizeof(cplx) * (size_t)N);
     cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)N);
     if (!phi || !lam || !tmp) { free(phi); free(lam); free(tmp); free(nb); return -1; }
-    evolve(&m, p, angles, table, psi0, phi);
-    *E = orc_expect(N, table, phi, Nrm);
-    for (int64_t x = 0; x < N; x++) lam[x] = (double)table[x] * phi[x];   /* lambda = H_C psi_p */
+    evolve(&m, p, angles, cost, psi0, phi);
+    *E = orc_expect(N, cost, phi, Nrm);
+    for (int64_t x = 0; x < N; x++) lam[x] = cost[x] * phi[x];             /* lambda = H_C psi_p */
     for (int r = p - 1; r >= 0; r--) {
         apply_mixer_sum(&m, phi, tmp);                                     /* H_M phi */
         grad[r] = 2.0 * im_inner(N, lam, tmp);                              /* d/dbeta_r */
         apply_mixer(&m, -angles[r], phi);                                   /* undo mixer */
         apply_mixer(&m, -angles[r], lam);
-        grad[p + r] = 2.0 * im_inner_c(N, table, lam, phi);                 /* d/dgamma_r */
-        orc_apply_phase(N, -angles[p + r], table, phi);                     /* undo phase */
-        orc_apply_phase(N, -angles[p + r], table, lam);
+        grad[p + r] = 2.0 * im_inner_c(N, cost, lam, phi);                  /* d/dgamma_r */
+        orc_apply_phase(N, -angles[p + r], cost, phi);                      /* undo phase */
+        orc_apply_phase(N, -angles[p + r], cost, lam);
     }
     free(phi); free(lam); free(tmp); free(nb);
     return 0;

@@ -284,3 +284,53 @@ def test_clique_gradient_matches_finite_differences():
     E, N, gr = oracle.grad(n, t, a, k=k)
     fd = oracle.fd_grad(n, t, a, k=k)
     assert np.max(np.abs(gr - fd)) < 1e-8 * max(1, np.max(np.abs(gr)))
+
+
+# ---------------------------------------------------------------- arbitrary objective values
+
+def _real_table(N, seed, distinct=None):
+    """Real, non-integer, complement-asymmetric values (optionally drawn from a small set)."""
+    rng = np.random.default_rng(seed)
+    if distinct is None:
+        return rng.normal(1.5, 2.0, N)
+    pool = rng.normal(0.0, 3.0, distinct)
+    return pool[rng.integers(0, distinct, N)]
+
+
+@pytest.mark.parametrize("n,p", [(5, 3), (7, 2)])
+def test_real_asymmetric_cost_matches_dense_bruteforce(n, p):
+    # Sec. 3: the objective is any list of values over the states; Eq. (1) by dense expm
+    t = _real_table(1 << n, 300 + n)
+    assert np.max(np.abs(t - t[::-1])) > 0.1                      # C(~x) != C(x)
+    a = workloads.random_angles(p, 1, 301 + n)[0]
+    psi0 = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    want = pins.dense_evolve(pins.dense_x_mixer_hamiltonian(n), t, a, psi0)
+    assert np.max(np.abs(oracle.state(n, t, a) - want)) < 1e-13
+    E, N = oracle.expect(n, t, a)
+    assert abs(E - np.sum(np.abs(want) ** 2 * t)) < 1e-12 * np.sum(np.abs(t))
+
+
+def test_real_cost_gradient_matches_finite_differences():
+    n, p = 8, 3
+    t = _real_table(1 << n, 310, distinct=40)
+    a = workloads.random_angles(p, 1, 311)[0]
+    E, N, gr = oracle.grad(n, t, a)
+    fd = oracle.fd_grad(n, t, a)
+    assert np.max(np.abs(gr - fd)) < 1e-9 * max(1, np.max(np.abs(gr)))
+    # a constant shift of C shifts <C> and leaves the gradient unchanged (the adjoint starts
+    # from (C + s) psi_p; the extra s psi_p term has real inner products)
+    E2, N2, gr2 = oracle.grad(n, t + 7.25, a)
+    assert abs(E2 / N2 - E / N - 7.25) < 1e-12
+    assert np.max(np.abs(gr2 - gr)) < 1e-11 * max(1, np.max(np.abs(gr)))
+
+
+def test_real_cost_clique_matches_full_space_bruteforce():
+    n, k, p = 7, 3, 2
+    st = oracle.states(n, k).astype(np.int64)
+    tfull = _real_table(1 << n, 320)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[st] = 1 / np.sqrt(st.size)
+    a = workloads.random_angles(p, 1, 321)[0]
+    want = pins.dense_evolve(pins.dense_clique_hamiltonian(n), tfull, a, psi0)
+    got = oracle.state(n, tfull[st], a, k=k)
+    assert np.max(np.abs(want[st] - got)) < 1e-12
