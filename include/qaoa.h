@@ -81,12 +81,31 @@ int qaoa_ctx_destroy(qaoa_ctx *ctx);
 int qaoa_cost_table(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const int32_t *v,
                     const int32_t *w, int hamming_k, qaoa_problem **out, void *stream);
 
+/* Step (a) for any objective (Sec. 2.1 pre-computation; Sec. 3 hands the objective over as a
+ * list of values, one per feasible state): C(x) = host_values[i] for the i-th feasible state
+ * in the basis order above (x = i over all 2^n strings for hamming_k < 0, the i-th weight-k
+ * integer for 0 <= hamming_k <= n). host_values: len finite doubles, len = feasible-set size,
+ * caller-owned, read during the call only. At most 1024 distinct values (the phase is applied
+ * through a table of e^{-i gamma c} over the distinct values c; QAOA_ERR_UNSUPPORTED beyond
+ * that); the device table stores each state's index among the distinct values in increasing
+ * order (uint8 for up to 256 of them, else uint16). Tables with C(~x) != C(x) are supported
+ * (the transverse-field path then also keeps the reversed table). *out owns the device
+ * table. Synchronises `stream`. */
+int qaoa_problem_from_values(qaoa_ctx *ctx, int n, int hamming_k, const double *host_values, size_t len,
+                             qaoa_problem **out, void *stream);
+
 /* Copy the table back as int64 into host_dst (len must equal the feasible-set size), in the
- * basis order above. For exact comparisons; synchronises `stream`. */
+ * basis order above: the cost values of a graph problem (qaoa_cost_table), the value indices
+ * of a qaoa_problem_from_values problem. For exact comparisons; synchronises `stream`. */
 int qaoa_problem_copy_table(const qaoa_problem *prob, int64_t *host_dst, size_t len, void *stream);
 
+/* Copy C(x) as doubles into host_dst (len = feasible-set size, basis order above), for either
+ * kind of problem. Synchronises `stream`. */
+int qaoa_problem_copy_values(const qaoa_problem *prob, double *host_dst, size_t len, void *stream);
+
 /* Problem metadata: qubits n, hamming_k (-1 = unconstrained), feasible-set size, largest
- * C value. Any output pointer may be NULL. */
+ * table entry (a graph problem's largest C value; for a qaoa_problem_from_values problem the
+ * number of distinct values minus one). Any output pointer may be NULL. */
 int qaoa_problem_info(const qaoa_problem *prob, int *n, int *hamming_k, int64_t *size,
                       int64_t *max_value);
 

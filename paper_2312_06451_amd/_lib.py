@@ -24,7 +24,7 @@ EXPORTED = [
     "qaoa_problem_info", "qaoa_problem_destroy", "qaoa_mixer_x", "qaoa_mixer_clique",
     "qaoa_mixer_destroy", "qaoa_expect", "qaoa_expect_grad", "qaoa_state", "qaoa_expect_batched",
     "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error", "qaoa_profile_enable",
-    "qaoa_profile_read",
+    "qaoa_profile_read", "qaoa_problem_from_values", "qaoa_problem_copy_values",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4}
 
@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
     L.qaoa_ctx_destroy.argtypes = [c_void_p]
     L.qaoa_cost_table.argtypes = [c_void_p, c_int, c_int, i32p, i32p, i32p, c_int, P(c_void_p), c_void_p]
     L.qaoa_problem_copy_table.argtypes = [c_void_p, P(c_int64), c_size_t, c_void_p]
+    L.qaoa_problem_from_values.argtypes = [c_void_p, c_int, c_int, P(c_double), c_size_t, P(c_void_p), c_void_p]
+    L.qaoa_problem_copy_values.argtypes = [c_void_p, P(c_double), c_size_t, c_void_p]
     L.qaoa_problem_info.argtypes = [c_void_p, P(c_int), P(c_int), P(c_int64), P(c_int64)]
     L.qaoa_problem_destroy.argtypes = [c_void_p]
     L.qaoa_mixer_x.argtypes = [c_void_p, c_int, P(c_void_p)]
@@ -124,6 +126,24 @@ def qaoa_cost_table(ctx: int, n: int, u, v, w=None, hamming_k: int = -1, stream:
     check(lib().qaoa_cost_table(ctx, n, int(ua.size), up, vp, wp, hamming_k, ctypes.byref(out), stream),
           "qaoa_cost_table")
     return out.value
+
+
+def qaoa_problem_from_values(ctx: int, n: int, hamming_k: int, values, stream: int = 0) -> int:
+    import numpy as np
+    va = np.ascontiguousarray(values, dtype=np.float64)
+    out = c_void_p()
+    check(lib().qaoa_problem_from_values(ctx, n, hamming_k, va.ctypes.data_as(P(c_double)), va.size,
+                                         ctypes.byref(out), stream), "qaoa_problem_from_values")
+    return out.value
+
+
+def qaoa_problem_copy_values(prob: int, stream: int = 0):
+    import numpy as np
+    info = qaoa_problem_info(prob)
+    out = np.zeros(info["size"], dtype=np.float64)
+    check(lib().qaoa_problem_copy_values(prob, out.ctypes.data_as(P(c_double)), out.size, stream),
+          "qaoa_problem_copy_values")
+    return out
 
 
 def qaoa_problem_copy_table(prob: int, stream: int = 0):

@@ -48,11 +48,16 @@ class Context:
 
 
 class Problem:
-    """Cost diagonal C(x) of a (weighted) MaxCut instance, tabulated on the device."""
+    """Cost diagonal C(x) over the feasible states, tabulated on the device: a (weighted)
+    MaxCut instance (``Problem(ctx, n, u, v, w)``, ``Problem.from_graph``) or any list of
+    values (``Problem.from_values``)."""
 
-    def __init__(self, ctx: Context, n: int, u, v, w=None, hamming_k: int = -1, stream=None):
+    def __init__(self, ctx: Context, n: int, u=None, v=None, w=None, hamming_k: int = -1, stream=None,
+                 _handle=None):
         self.ctx = ctx
-        self.handle = _lib.qaoa_cost_table(ctx.handle, n, u, v, w, hamming_k, _stream(stream))
+        if _handle is None:
+            _handle = _lib.qaoa_cost_table(ctx.handle, n, u, v, w, hamming_k, _stream(stream))
+        self.handle = _handle
         ctx._children.add(self)
         info = _lib.qaoa_problem_info(self.handle)
         self.n = info["n"]
@@ -64,8 +69,19 @@ class Problem:
     def from_graph(cls, ctx: Context, g, hamming_k: int = -1, stream=None):
         return cls(ctx, g.n, g.u, g.v, g.w, hamming_k, stream)
 
+    @classmethod
+    def from_values(cls, ctx: Context, n: int, values, hamming_k: int = -1, stream=None):
+        """C(x) = values[i] for the i-th feasible state (all 2^n strings, or the weight-k
+        strings in increasing order)."""
+        h = _lib.qaoa_problem_from_values(ctx.handle, n, hamming_k, values, _stream(stream))
+        return cls(ctx, n, hamming_k=hamming_k, _handle=h)
+
     def table(self, stream=None) -> np.ndarray:
         return _lib.qaoa_problem_copy_table(self.handle, _stream(stream))
+
+    def values(self, stream=None) -> np.ndarray:
+        """C(x) over the feasible states as FP64."""
+        return _lib.qaoa_problem_copy_values(self.handle, _stream(stream))
 
     def close(self):
         if self.handle:

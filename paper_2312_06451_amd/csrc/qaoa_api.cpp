@@ -2,6 +2,7 @@
 // planner of the transverse-field path, scale bookkeeping and result assembly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -226,22 +227,52 @@ static void profile_collect(qaoa_ctx *ctx) {
   ctx->pending.clear();
 }
 
+// The device table holds, per feasible state, an index into the problem's distinct cost
+// values (increasing order); for a graph table the index is the cost itself (values 0..max).
 struct qaoa_problem {
   qaoa_ctx *ctx = nullptr;
   int n = 0, k = -1;
   uint64_t N = 0;
   int tbytes = 1;
-  int64_t max_value = 0;
+  int64_t max_value = 0;              // largest table index
   int64_t total_weight = 0;
   double mean = 0.0;  // mean of C over the feasible set (centre of the adjoint vector)
+  bool sym = true;    // C(~x) = C(x) for every x (full space only)
+  std::vector<double> hvals;          // cost value of each index
+  double *dvals = nullptr;            // the same, device FP64 and FP32
+  float *dvals_f = nullptr;
   void *table = nullptr;
-  std::map<std::tuple<int, int, int>, void *> layouts;  // (T, c, h0) -> tile-major copy
+  void *table_rev = nullptr;          // reversed natural table (C(~x)), when !sym
+  std::map<std::tuple<int, int, int>, void *> layouts;      // (T, c, h0) -> tile-major copy
+  std::map<std::tuple<int, int, int>, void *> layouts_rev;  // reversed tile-major copies
   ~qaoa_problem() {
     if (table) (void)hipFree(table);
+    if (table_rev) (void)hipFree(table_rev);
+    if (dvals) (void)hipFree(dvals);
+    if (dvals_f) (void)hipFree(dvals_f);
     for (auto &kv : layouts)
+      if (kv.second) (void)hipFree(kv.second);
+    for (auto &kv : layouts_rev)
       if (kv.second) (void)hipFree(kv.second);
   }
 };
+
+namespace {
+// Upload the index -> value map (FP64 and FP32) of a problem.
+void upload_values(qaoa_problem *prob, hipStream_t st) {
+  const size_t L = prob->hvals.size();
+  if (hipMalloc(&prob->dvals, L * sizeof(double)) != hipSuccess ||
+      hipMalloc(&prob->dvals_f, L * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw fail(QAOA_ERR_OUT_OF_MEMORY, "value table allocation failed");
+  }
+  std::vector<float> hf(L);
+  for (size_t i = 0; i < L; i++) hf[i] = (float)prob->hvals[i];
+  HIPCHK(hipMemcpyAsync(prob->dvals, prob->hvals.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(prob->dvals_f, hf.data(), L * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+}  // namespace
 
 struct qaoa_mixer {
   qaoa_ctx *ctx = nullptr;
@@ -278,6 +309,15 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin) {
     const uint32_t L = (1u << (T - 8)) - 1;
     t[0].rot &= ~L;
     t[1].rot |= L;
+  }
+  // With two tiles every pass is a two-block pass. When the second tile's contiguous bits
+  // include the M register group (tile bits [T-8, 8)), it takes those qubits: the first tile
+  // then rotates its H and L groups only (2 x (2T - 16) rotations per pass instead of 2T)
+  // and the second tile the M and H groups.
+  if (t.size() == 2 && t[1].c >= 8) {
+    const uint32_t M = ((1u << 8) - 1) & ~((1u << (T - 8)) - 1);
+    t[0].rot &= ~M;
+    t[1].rot |= M;
   }
   return t;
 }
@@ -379,6 +419,29 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     prob->layouts[key] = d;
     return d;
   };
+  // the same layouts for C(~x): the whole array reversed (complementing x complements the
+  // tile index and the element index); the table itself when C(~x) = C(x)
+  auto table_rev_for = [&](int tile) -> const void * {
+    if (prob->sym) return table_for(tile);
+    const void *src = table_for(tile);
+    const TileGeo &g = tiles[tile];
+    void **slot;
+    if (g.c == T) slot = &prob->table_rev;
+    else slot = &prob->layouts_rev[std::make_tuple(T, g.c, g.h0)];
+    if (*slot) return *slot;
+    void *d = nullptr;
+    if (hipMalloc(&d, N * prob->tbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "reversed table allocation failed");
+    }
+    hipError_t e = launch_table_reverse(src, d, prob->tbytes, N, st);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      throw fail(QAOA_ERR_HIP, std::string("table reverse: ") + hipGetErrorString(e));
+    }
+    *slot = d;
+    return d;
+  };
 
   // buffers. With enough free memory the gradient keeps every forward pass's output
   // (checkpoints) and the reverse sweep reads the state from them instead of undoing and
@@ -416,6 +479,14 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       double beta = angles[(size_t)s * 2 * p + k];
       rot_params<R>(beta, tau[s * p + k], swp[s * p + k], ff[s * p + k], fi[s * p + k]);
     }
+  // flip state of set s's stored vector after `layers` complete rounds (all bits or none):
+  // 1 when an odd number of them used the tau = -cot form; only an asymmetric table cares
+  auto tflip = [&](int s, int layers) {
+    if (prob->sym) return 0;
+    int f = 0;
+    for (int k = 0; k < layers; k++) f ^= swp[s * p + k];
+    return f;
+  };
   auto gam = [&](int s, int k) { return angles[(size_t)s * 2 * p + p + k]; };
 
   std::vector<PassArgs<R>> passes;
@@ -445,6 +516,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     a.lam = dlam;
     a.psi0 = d_psi0;
     a.table = nullptr;
+    a.table_rev = nullptr;
+    a.vals = sizeof(R) == 4 ? (const void *)prob->dvals_f : (const void *)prob->dvals;
     a.luts = nullptr;  // patched after upload
     a.lut_len = lut_len;
     a.u0 = (R)(1.0 / std::sqrt((double)N));
@@ -463,7 +536,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     const uint32_t H = ((1u << T) - 1) & ~((1u << 8) - 1), M = ((1u << 8) - 1) & ~((1u << RB) - 1),
                    L = (1u << RB) - 1;
     int sx = ((rot & H) ? 1 : 0) | ((rot & M) ? 2 : 0) | ((rot & L) ? 4 : 0);
-    if (sx != 7 && sx != 3 && sx != 1) throw fail(QAOA_ERR_HIP, "internal: unsupported tile stage set");
+    if (sx != 7 && sx != 5 && sx != 3 && sx != 1) throw fail(QAOA_ERR_HIP, "internal: unsupported tile stage set");
     return sx;
   };
   auto add_pass = [&](const PassArgs<R> &a, int kind, int shape, int tile) {
@@ -489,6 +562,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (fp.ph >= 0) {
       f |= PF_PHASE;
       a.table = table_for(fp.tile);
+      a.table_rev = table_rev_for(fp.tile);
     }
     if (fp.post >= 0) a.mask2 = tiles[fp.tile].rot;
     a.flags = f;
@@ -504,6 +578,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       }
       if (fp.ph >= 0) {
         q.lut = (int)jobs.size();
+        q.tflip = tflip(s, fp.ph);
         jobs.push_back(LutJob{gam(s, fp.ph), sig[s].real(), sig[s].imag(), -1.0});
         sig[s] = cd(1.0, 0.0);
       }
@@ -530,6 +605,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     // a single-pass plan would need the phase too; K >= 2 always gives >= 2 passes
     a.mask1 = tiles[lp.tile].rot;
     a.table = table_for(lp.tile);
+    a.table_rev = table_rev_for(lp.tile);
     f |= PF_EXPECT;
     a.slot_off[SL_A] = slot_for(om.E());
     a.slot_off[SL_B] = slot_for(om.Nr());
@@ -544,6 +620,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       SetParams<R> q;
       std::memset(&q, 0, sizeof(q));
       q.lut = -1;
+      q.tflip = tflip(s, p);
       q.tau1 = tau[s * p + lp.pre];
       sig[s] *= cpow_int(ff[s * p + lp.pre], rotbits(lp.tile));
       sig_p[s] = sig[s];
@@ -579,6 +656,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       if (fp.ph >= 0) {
         f |= PF_GGAMMA;
         a.table = table_for(fp.tile);
+        a.table_rev = table_rev_for(fp.tile);
         a.slot_off[SL_B] = slot_for(om.gg(fp.ph));
         if (!last) f |= PF_PHASE | PF_PHASE_BOTH;
       }
@@ -595,6 +673,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         std::memset(&q, 0, sizeof(q));
         q.lut = -1;
         q.lam_rho = (R)1;
+        if (fp.ph >= 0) q.tflip = tflip(s, fp.ph);
         if (ckpt) {
           // the checkpoint carries the forward sweep's scalar; rescale it to the reverse
           // sweep's so that phi and lam share one scalar (real inner-product weights)
@@ -640,7 +719,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   void *dluts = nullptr;
   if (!jobs.empty()) {
     dluts = ctx->luts.get(jobs.size() * (size_t)lut_len * esz);
-    HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobs), (int)jobs.size(), lut_len, dluts, st));
+    HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobs), (int)jobs.size(), lut_len, prob->dvals, dluts, st));
   }
   // ---------------- passes
   for (size_t i = 0; i < passes.size(); i++) {
@@ -754,6 +833,8 @@ bool small_path(const qaoa_problem *prob, int precision) {
 SmallItem small_item(const qaoa_problem *prob, int set, int row) {
   SmallItem it;
   it.table = prob->table;
+  it.vals = prob->dvals;
+  it.sym = prob->sym ? 1 : 0;
   it.n = prob->n;
   it.tbytes = prob->tbytes;
   it.lut_len = (int)prob->max_value + 1;
@@ -927,8 +1008,109 @@ int qaoa_cost_table(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const i
     HIPCHK(hipMemcpyAsync(&hmax, dmax, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     prob->max_value = hmax;
+    // a graph table stores the cost itself: index c has value c; C(~x) = C(x) always
+    prob->hvals.resize((size_t)hmax + 1);
+    for (unsigned c = 0; c <= hmax; c++) prob->hvals[c] = (double)c;
+    upload_values(prob.get(), st);
     *out = prob.release();
     ctx->live++;
+  });
+}
+
+int qaoa_problem_from_values(qaoa_ctx *ctx, int n, int hamming_k, const double *host_values, size_t len,
+                             qaoa_problem **out, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out && host_values, "ctx, values or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 32, "n must be in [1, 32]");
+    REQUIRE(hamming_k <= n, "hamming_k must be <= n");
+    const uint64_t N = hamming_k < 0 ? (1ull << n) : (uint64_t)binom64(n, hamming_k);
+    if (hamming_k >= 0) REQUIRE(N <= (1ull << 26), "feasible subspace larger than 2^26 states");
+    REQUIRE(len == N, "len differs from the feasible-set size");
+    for (size_t i = 0; i < len; i++) REQUIRE(std::isfinite(host_values[i]), "values must be finite");
+    // distinct values in increasing order, and each state's index among them: an
+    // open-addressing hash on the value's bits (-0 folded into +0), 4 slots per allowed value
+    constexpr int HB = 12;
+    constexpr size_t HS = size_t(1) << HB;
+    static_assert(HS >= 4 * (size_t)MAX_LUT, "hash table too small");
+    std::vector<uint64_t> hkey(HS);
+    std::vector<int> hidx(HS, -1);
+    auto bits_of = [](double v) {
+      if (v == 0.0) v = 0.0;
+      uint64_t b;
+      std::memcpy(&b, &v, sizeof(b));
+      return b;
+    };
+    auto slot_of = [&](uint64_t b) {
+      size_t h = (size_t)((b * 0x9E3779B97F4A7C15ull) >> (64 - HB));
+      while (hidx[h] >= 0 && hkey[h] != b) h = (h + 1) & (HS - 1);
+      return h;
+    };
+    std::vector<double> distinct;
+    for (size_t i = 0; i < len; i++) {
+      const uint64_t b = bits_of(host_values[i]);
+      const size_t h = slot_of(b);
+      if (hidx[h] < 0) {
+        if (distinct.size() == (size_t)MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "more than 1024 distinct cost values");
+        hkey[h] = b;
+        hidx[h] = (int)distinct.size();
+        distinct.push_back(host_values[i] == 0.0 ? 0.0 : host_values[i]);
+      }
+    }
+    std::vector<double> sorted = distinct;
+    std::sort(sorted.begin(), sorted.end());
+    std::vector<int> rank(distinct.size());
+    for (size_t j = 0; j < distinct.size(); j++)
+      rank[j] = (int)(std::lower_bound(sorted.begin(), sorted.end(), distinct[j]) - sorted.begin());
+    auto prob = std::make_unique<qaoa_problem>();
+    prob->ctx = ctx;
+    prob->n = n;
+    prob->k = hamming_k < 0 ? -1 : hamming_k;
+    prob->N = N;
+    prob->tbytes = sorted.size() <= 256 ? 1 : 2;
+    prob->max_value = (int64_t)sorted.size() - 1;
+    prob->hvals = sorted;
+    std::vector<unsigned char> h1;
+    std::vector<uint16_t> h2;
+    if (prob->tbytes == 1) h1.resize(N);
+    else h2.resize(N);
+    long double sum = 0.0L;
+    for (size_t i = 0; i < len; i++) {
+      const int idx = rank[hidx[slot_of(bits_of(host_values[i]))]];
+      if (prob->tbytes == 1) h1[i] = (unsigned char)idx;
+      else h2[i] = (uint16_t)idx;
+      sum += (long double)host_values[i];
+    }
+    prob->mean = (double)(sum / (long double)N);
+    if (hamming_k < 0)
+      for (size_t i = 0; i < len / 2 && prob->sym; i++)
+        if (host_values[i] != host_values[N - 1 - i]) prob->sym = false;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMalloc(&prob->table, N * prob->tbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      prob->table = nullptr;
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "table allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(prob->table, prob->tbytes == 1 ? (const void *)h1.data() : (const void *)h2.data(),
+                          N * prob->tbytes, hipMemcpyHostToDevice, st));
+    upload_values(prob.get(), st);
+    *out = prob.release();
+    ctx->live++;
+  });
+}
+
+int qaoa_problem_copy_values(const qaoa_problem *prob, double *host_dst, size_t len, void *stream) {
+  return guarded([&] {
+    REQUIRE(prob && host_dst, "problem or destination is NULL");
+    REQUIRE(len == prob->N, "len differs from the feasible-set size");
+    DeviceGuard g(prob->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf tmp;
+    double *d = (double *)tmp.get(prob->N * sizeof(double));
+    HIPCHK(launch_table_values(prob->table, prob->tbytes, prob->dvals, d, prob->N, st));
+    HIPCHK(hipMemcpyAsync(host_dst, d, prob->N * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
   });
 }
 
@@ -1017,6 +1199,7 @@ static void evaluate(const qaoa_problem *cprob, const qaoa_mixer *mix, int p, co
   } else {
     CliqueEval ev;
     ev.table = prob->table;
+    ev.vals = prob->dvals;
     ev.tbytes = prob->tbytes;
     ev.N = (int64_t)prob->N;
     ev.lut_len = (int)prob->max_value + 1;

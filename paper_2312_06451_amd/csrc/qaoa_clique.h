@@ -20,11 +20,12 @@ struct CliqueError {
 };
 
 struct CliqueEval {
-  const void *table;  // device table over the weight-k states (increasing order)
+  const void *table;   // device table over the weight-k states (increasing order): value index
+  const double *vals;  // device: cost value of each index (lut_len entries)
   int tbytes;
   int64_t N;
-  int lut_len;        // largest C + 1
-  double c0;          // mean of C over the states
+  int lut_len;         // number of indices
+  double c0;           // mean of C over the states
 };
 
 std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int n, int k, hipStream_t st);

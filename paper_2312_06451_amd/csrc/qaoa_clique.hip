@@ -299,14 +299,15 @@ __global__ __launch_bounds__(256) void k_eig(const R *__restrict__ Y, int64_t N,
 // E and Nrm partials of the final state.
 template <typename R, typename TT>
 __global__ __launch_bounds__(256) void k_expect(const R *__restrict__ X, int64_t N, const void *table,
-                                                double *epart, double *npart, int nblk) {
+                                                const double *__restrict__ vals, double *epart, double *npart,
+                                                int nblk) {
   const int s = blockIdx.y;
   double e = 0.0, nr = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * RB_ROWS;
   for (int64_t x = r0 + threadIdx.x; x < N && x < r0 + RB_ROWS; x += 256) {
     const double a = X[(int64_t)(2 * s) * N + x], b = X[(int64_t)(2 * s + 1) * N + x];
     const double pr = a * a + b * b;
-    e += pr * (double)cval<TT>(table, x);
+    e += pr * vals[cval<TT>(table, x)];
     nr += pr;
   }
   block_sum2(e, nr, epart + (int64_t)s * nblk + blockIdx.x, npart + (int64_t)s * nblk + blockIdx.x);
@@ -314,10 +315,11 @@ __global__ __launch_bounds__(256) void k_expect(const R *__restrict__ X, int64_t
 
 // lam = (C - c0) psi_p, emitted for V^T.
 template <typename R, typename TT>
-__global__ void k_lambda(const R *__restrict__ X, int64_t N, const void *table, double c0, void *B) {
+__global__ void k_lambda(const R *__restrict__ X, int64_t N, const void *table, const double *__restrict__ vals,
+                         double c0, void *B) {
   const int s = blockIdx.y;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
-    const R k = (R)((double)cval<TT>(table, x) - c0);
+    const R k = (R)(vals[cval<TT>(table, x)] - c0);
     emit<R>(B, N, x, s, k * X[(int64_t)(2 * s) * N + x], k * X[(int64_t)(2 * s + 1) * N + x]);
   }
 }
@@ -326,7 +328,7 @@ __global__ void k_lambda(const R *__restrict__ X, int64_t N, const void *table, 
 // lam *= LUT_s[C] (inverse phase) and emit it for the next V^T (if B).
 template <typename R, typename TT>
 __global__ __launch_bounds__(256) void k_gamma(const R *__restrict__ L, int64_t N, const void *table,
-                                               double c0, const R *__restrict__ phi,
+                                               const double *__restrict__ vals, double c0, const R *__restrict__ phi,
                                                const typename CT<R>::T2 *luts, int lut_len, void *B,
                                                double *gpart, int nblk) {
   const int s = blockIdx.y;
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(256) void k_gamma(const R *__restrict__ L, int64_t 
     const R a = L[(int64_t)(2 * s) * N + x], b = L[(int64_t)(2 * s + 1) * N + x];
     const R pa = phi[(int64_t)(2 * s) * N + x], pb = phi[(int64_t)(2 * s + 1) * N + x];
     const uint32_t c = cval<TT>(table, x);
-    acc += ((double)c - c0) * ((double)a * pb - (double)b * pa);
+    acc += (vals[c] - c0) * ((double)a * pb - (double)b * pa);
     if (B) {
       const typename CT<R>::T2 l = luts[(int64_t)s * lut_len + c];
       emit<R>(B, N, x, s, a * l.x - b * l.y, a * l.y + b * l.x);
@@ -561,7 +563,8 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
   hipchk(hipMemcpyAsync(d, h.data(), total, hipMemcpyHostToDevice, st), "parameter upload");
   const double *dbeta = (const double *)d;
   T2 *dluts = (T2 *)m.luts.get(jobs.size() * (size_t)ev.lut_len * sizeof(T2));
-  hipchk(launch_luts(sizeof(R) == 4 ? 0 : 1, (const LutJob *)(d + off_j), (int)jobs.size(), ev.lut_len, dluts, st),
+  hipchk(launch_luts(sizeof(R) == 4 ? 0 : 1, (const LutJob *)(d + off_j), (int)jobs.size(), ev.lut_len, ev.vals,
+                     dluts, st),
          "LUTs");
   auto lut_f = [&](int k) { return dluts + (size_t)k * S * ev.lut_len; };
   auto lut_b = [&](int k) { return dluts + (size_t)(p + k) * S * ev.lut_len; };
@@ -596,7 +599,7 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
     dense.product(false, B, X);
   }
   tbegin();
-  k_expect<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, pslot(0), pslot(1), nblk);
+  k_expect<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.vals, pslot(0), pslot(1), nblk);
   launched("k_expect");
   tend((double)mat);
   if (d_state) {
@@ -605,7 +608,7 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
   }
   // reverse sweep (only the adjoint vector is multiplied; phi comes from the forward keeps)
   if (grad) {
-    k_lambda<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, ev.c0, B);
+    k_lambda<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, ev.vals, ev.c0, B);
     launched("k_lambda");
     for (int k = p - 1; k >= 0; k--) {
       dense.product(true, B, Y);
@@ -616,7 +619,7 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
       tend((double)mat * 3);
       dense.product(false, B, X);
       tbegin();
-      k_gamma<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.c0, ckP + (size_t)k * N * cols, lut_b(k), ev.lut_len,
+      k_gamma<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.vals, ev.c0, ckP + (size_t)k * N * cols, lut_b(k), ev.lut_len,
                                          k > 0 ? B : nullptr, pslot(2 + p + k), nblk);
       launched("k_gamma");
       tend((double)mat * 3);

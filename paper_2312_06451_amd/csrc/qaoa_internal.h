@@ -19,7 +19,9 @@ constexpr int MIN_CONTIG_F64 = 4;
 constexpr int SMALL_MAX_N_F32 = 13;
 constexpr int SMALL_MAX_N_F64 = 12;
 constexpr int SMALL_THREADS = 256;
-// Largest phase lookup table (largest C + 1) the kernels stage in LDS.
+// Largest phase lookup table the kernels stage in LDS: the cost table stores, per state, the
+// index of its value among at most MAX_LUT distinct values (a graph table's index is the
+// value itself).
 constexpr int MAX_LUT = 1024;
 
 // Pass flags (X-mixer tile passes). A pass runs: load, part 1 (register stages H, M, L),
@@ -55,6 +57,8 @@ struct SetParams {
   R lam_rho;             // lambda = lam_rho * (C - c0) * phi
   R out_re, out_im;      // load scale of phi (PF_LOAD_SCALE)
   int lut;               // index of this set's LUT in the LUT array (-1: none)
+  int tflip;             // 1: the stored vector is the state with every bit flipped at this
+                         // pass's elementwise steps, so they read C(~x) (the reversed table)
 };
 
 // Pass descriptor (kernel argument). Geometry: tile bits [0,c) are address bits [0,c);
@@ -71,6 +75,8 @@ struct PassArgs {
   void *phi_out;
   const void *psi0;        // natural layout, shared by all sets
   const void *table;       // tile-major table of this geometry: table[r * 2^T + e]
+  const void *table_rev;   // the same array reversed (C(~x)); equal to table when C(~x) = C(x)
+  const void *vals;        // R[lut_len]: cost value of each table index
   const void *luts;        // lut_len complex<R> entries per LUT
   int lut_len;
   uint32_t flags;
@@ -82,7 +88,8 @@ struct PassArgs {
   int64_t slot_off[NSLOT]; // -1: slot unused
 };
 
-// LUT construction job: luts[i][c] = scale_i * exp(sign_i * i * gamma_i * c), c < lut_len.
+// LUT construction job: luts[i][c] = scale_i * exp(sign_i * i * gamma_i * vals[c]),
+// c < lut_len.
 struct LutJob {
   double gamma, sre, sim, sign;
 };
@@ -90,9 +97,11 @@ struct LutJob {
 // Whole-state kernel item: one workgroup evolves one (problem, angle set) pair.
 struct SmallItem {
   const void *table;    // device table (2^n entries), uint8 or uint16
+  const double *vals;   // cost value of each table index (lut_len entries)
   int n;
   int tbytes;           // 1 or 2
-  int lut_len;          // largest C + 1
+  int sym;              // 1: C(~x) = C(x) for every x (flipped states read the table as is)
+  int lut_len;          // number of table indices (largest index + 1)
   int angle_set;        // row of the angle array
   double c0;            // centre of lambda = (C - c0) psi
   int out_index;        // output row: out[out_index * (1 + 2p) + ...]
@@ -110,11 +119,16 @@ hipError_t launch_table_relayout(const void *src, void *dst, int tbytes, int n, 
                                  int h0, hipStream_t s);
 hipError_t launch_table_widen(const void *src, int tbytes, int64_t *dst, uint64_t N,
                               hipStream_t s);
-hipError_t launch_luts(int precision, const LutJob *jobs, int njobs, int lut_len, void *luts,
-                       hipStream_t s);
+hipError_t launch_luts(int precision, const LutJob *jobs, int njobs, int lut_len, const double *vals,
+                       void *luts, hipStream_t s);
+// dst[i] = src[count - 1 - i] (tables of 1 or 2 bytes per entry)
+hipError_t launch_table_reverse(const void *src, void *dst, int tbytes, uint64_t count, hipStream_t s);
+// dst[x] = vals[table[x]]
+hipError_t launch_table_values(const void *table, int tbytes, const double *vals, double *dst, uint64_t N,
+                               hipStream_t s);
 // kind: 1 = forward pass (phi), 2 = reverse-sweep pass (phi, lam), 3 = fused end of the
 // forward sweep and start of the reverse sweep. sx: register stages holding the tile's
-// rotated bits (bit 0: H, bit 1: M, bit 2: L; 7, 3 or 1). shape: 0 = part 1 only,
+// rotated bits (bit 0: H, bit 1: M, bit 2: L; 7, 5, 3 or 1). shape: 0 = part 1 only,
 // 1 = both parts with the kind's elementwise steps between them, 2 = phase then part 2
 // (first forward pass), 3 = part 1 then a reduction (forward: <C>; reverse: gamma gradient).
 hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes,

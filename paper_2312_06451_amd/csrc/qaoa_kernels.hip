@@ -14,8 +14,13 @@
 // host and folded into the next phase lookup table, so every applied rotation is exactly
 // unitary up to that scalar and norm drift does not accumulate. The X of the second form is
 // not applied either: the stored vector is the state with a known set of bits flipped
-// (after a full round: all bits or none). MaxCut tables satisfy C(~x) = C(x), so phases,
-// <C> and the gradient sums read the table unchanged; only a state export un-flips.
+// (after a full round: all bits or none, so at every phase point). Steps that read the cost
+// then read C(~x): tables with C(~x) = C(x) (every MaxCut table) are read unchanged, other
+// tables through their reversed copy, chosen per angle set; a state export un-flips.
+//
+// Cost tables hold, per state, the index of its value among at most 1024 distinct values;
+// the phase lookup tables and a small value table (staged in LDS) map indices to
+// e^{-i gamma c} and to c.
 //
 // Tile passes. A workgroup of 256 threads holds a tile of 2^T amplitudes in registers
 // (2^(T-8) per thread and vector). Tile bits [0,c) are contiguous address bits; the other
@@ -136,16 +141,34 @@ __global__ void k_table_widen(const TT *__restrict__ src, int64_t *__restrict__ 
     dst[i] = (int64_t)src[i];
 }
 
+// dst[i] = src[N - 1 - i]: the table of C(~x) over the full space, in any tile-major layout
+// (complementing x complements both the tile index and the element index).
+template <typename TT>
+__global__ void k_table_reverse(const TT *__restrict__ src, TT *__restrict__ dst, uint64_t N) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+    dst[i] = src[N - 1 - i];
+}
+
+template <typename TT>
+__global__ void k_table_values(const TT *__restrict__ src, const double *__restrict__ vals,
+                               double *__restrict__ dst, uint64_t N) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+    dst[i] = vals[src[i]];
+}
+
 // ============================================================== phase lookup tables
 
-// luts[j][c] = s_j * exp(sign_j * i * gamma_j * c): FP64 argument and sincos, one rounding.
+// luts[j][c] = s_j * exp(sign_j * i * gamma_j * vals[c]): FP64 argument and sincos, one
+// rounding.
 template <typename R>
-__global__ void k_luts(const LutJob *__restrict__ jobs, int lut_len,
+__global__ void k_luts(const LutJob *__restrict__ jobs, int lut_len, const double *__restrict__ vals,
                        typename Cplx<R>::T2 *__restrict__ luts) {
   const LutJob J = jobs[blockIdx.x];
   for (int c = threadIdx.x; c < lut_len; c += blockDim.x) {
     double s, co;
-    sincos(J.sign * J.gamma * (double)c, &s, &co);
+    sincos(J.sign * J.gamma * vals[c], &s, &co);
     typename Cplx<R>::T2 o;
     o.x = (R)(J.sre * co - J.sim * s);
     o.y = (R)(J.sre * s + J.sim * co);
@@ -381,8 +404,8 @@ template <typename R, int T, int NV, typename TT, int A, uint32_t MID>
 __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> &sp,
                                        typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
                                        const unsigned char *ltab,
-                                       const typename Cplx<R>::T2 *llut, uint32_t t, double w,
-                                       double *acc) {
+                                       const typename Cplx<R>::T2 *llut, const R *lval, uint32_t t,
+                                       double w, double *acc) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
   constexpr uint32_t f = MID;
@@ -391,7 +414,7 @@ __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> 
     R e_acc = 0, n_acc = 0;
 #pragma unroll
     for (int j = 0; j < G::RN; j++) {
-      const R cr = (R)tab_at<TT, T, A>(tb, j);
+      const R cr = lval[tab_at<TT, T, A>(tb, j)];
       R pr = fmaR(phi[j].x, phi[j].x, phi[j].y * phi[j].y);
       e_acc = fmaR(pr, cr, e_acc);
       n_acc += pr;
@@ -405,7 +428,7 @@ __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> 
     if (f & PF_LAMBDA) {
 #pragma unroll
       for (int j = 0; j < G::RN; j++) {
-        const R cr = (R)tab_at<TT, T, A>(tb, j);
+        const R cr = lval[tab_at<TT, T, A>(tb, j)];
         R kf = sp.lam_rho * (cr - a.lam_c0);
         lam[j].x = kf * phi[j].x;
         lam[j].y = kf * phi[j].y;
@@ -418,7 +441,7 @@ __device__ __forceinline__ void middle(const PassArgs<R> &a, const SetParams<R> 
       double g_acc = 0;
 #pragma unroll
       for (int j = 0; j < G::RN; j++) {
-        const R cr = (R)tab_at<TT, T, A>(tb, j) - a.lam_c0;
+        const R cr = lval[tab_at<TT, T, A>(tb, j)] - a.lam_c0;
         R im = fmaR(lam[j].x, phi[j].y, -lam[j].y * phi[j].x);
         g_acc += (double)(im * cr);
       }
@@ -471,6 +494,7 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   T2 *lds = (T2 *)smem;
   unsigned char *ltab = smem + kStateSlots * sizeof(T2);
   T2 *llut = (T2 *)(ltab + kTabBytes);
+  R *lval = (R *)(llut + a.lut_len);
   double *lred = (double *)smem;  // reused after the last exchange
 
   const uint32_t t = threadIdx.x;
@@ -535,12 +559,16 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   constexpr bool need_tab = SHAPE != 0;
   if constexpr (need_tab) {
     constexpr uint32_t nchunk = ((1u << T) * sizeof(TT)) / 16;
-    const uint4 *src = (const uint4 *)((const unsigned char *)a.table +
+    const uint4 *src = (const uint4 *)((const unsigned char *)(sp.tflip ? a.table_rev : a.table) +
                                        (uint64_t)r * ((1ull << T) * sizeof(TT)));
     for (uint32_t i = t; i < nchunk; i += 256) *(uint4 *)(ltab + i * 16 + ((i >> 4) << 4)) = src[i];
     if (sp.lut >= 0) {
       const T2 *lsrc = (const T2 *)a.luts + (size_t)sp.lut * a.lut_len;
       for (int i = t; i < a.lut_len; i += 256) llut[i] = lsrc[i];
+    }
+    if constexpr (SHAPE != 2) {
+      const R *vsrc = (const R *)a.vals;
+      for (int i = t; i < a.lut_len; i += 256) lval[i] = vsrc[i];
     }
   }
 
@@ -568,7 +596,7 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
                    : (KIND == 2 ? (uint32_t)(PF_GGAMMA | PF_PHASE) : (uint32_t)(PF_EXPECT | PF_LAMBDA)));
   if constexpr (MID != 0) {
     __syncthreads();
-    middle<R, T, NV, TT, CM, MID>(a, sp, phi, lam, ltab, llut, t, w, acc);
+    middle<R, T, NV, TT, CM, MID>(a, sp, phi, lam, ltab, llut, lval, t, w, acc);
   }
   // ---- part 2: stages L, M, H
   w = sp.w2;
@@ -685,10 +713,11 @@ __device__ __forceinline__ DC dmul(DC a, DC b) { return DC{a.re * b.re - a.im * 
 // Rotation parameters of e^{-i beta X} in the unnormalised form (see file header): tau and
 // the dropped scalar f of the forward rotation; the inverse rotation uses -tau and finv.
 template <typename R>
-__device__ void rot_params(double beta, R &tau, DC &f, DC &finv) {
+__device__ void rot_params(double beta, R &tau, DC &f, DC &finv, bool &flip) {
   double sb, cb;
   sincos(beta, &sb, &cb);
-  if (fabs(sb) <= fabs(cb)) {
+  flip = !(fabs(sb) <= fabs(cb));
+  if (!flip) {
     tau = (R)(sb / cb);
     double t = (double)tau, nrm = 1.0 / sqrt(1.0 + t * t);
     f = DC{nrm * (cb < 0 ? -1.0 : 1.0), 0.0};
@@ -725,9 +754,16 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     if (it.tbytes == 1) ((unsigned char *)tab)[x] = ((const unsigned char *)it.table)[x];
     else ((uint16_t *)tab)[x] = ((const uint16_t *)it.table)[x];
   }
+  // the stored vector is the state with the bits of F flipped (tangent form, see the file
+  // header): its amplitude at x belongs to basis state x ^ F. F is all bits or none at every
+  // phase point; a table with C(~x) = C(x) may ignore it.
+  uint32_t F = 0;
+  const uint32_t FALL = it.sym ? 0u : N - 1;
   auto cval = [&](uint32_t x) -> uint32_t {
+    x ^= F;
     return it.tbytes == 1 ? (uint32_t)tab[x] : (uint32_t)((const uint16_t *)tab)[x];
   };
+  auto cost = [&](uint32_t x) -> double { return it.vals[cval(x)]; };
   const R u0 = (R)(1.0 / sqrt((double)N));
   for (uint32_t x = tid; x < N; x += 256) phi[x] = T2{u0, (R)0};
   DC sig{1.0, 0.0};
@@ -735,7 +771,7 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     __syncthreads();
     for (int c = tid; c < it.lut_len; c += 256) {
       double s, co;
-      sincos(sign * gamma * (double)c, &s, &co);
+      sincos(sign * gamma * it.vals[c], &s, &co);
       lut[c] = T2{(R)(sig.re * co - sig.im * s), (R)(sig.re * s + sig.im * co)};
     }
     __syncthreads();
@@ -763,14 +799,16 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     }
     sig = DC{1.0, 0.0};
     R tau; DC f, finv;
-    rot_params<R>(ang[k], tau, f, finv);
+    bool fl;
+    rot_params<R>(ang[k], tau, f, finv, fl);
     rotate_all(phi, tau);
+    if (fl) F ^= FALL;
     for (int qb = 0; qb < n; qb++) sig = dmul(sig, f);
   }
   double e = 0.0, nr = 0.0;
   for (uint32_t x = tid; x < N; x += 256) {
     double pr = (double)phi[x].x * phi[x].x + (double)phi[x].y * phi[x].y;
-    e += pr * (double)cval(x);
+    e += pr * cost(x);
     nr += pr;
   }
   e = block_sum(e, red);
@@ -781,7 +819,7 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
   if (!grad) return;
 
   for (uint32_t x = tid; x < N; x += 256) {
-    R kf = (R)((double)cval(x) - it.c0);
+    R kf = (R)(cost(x) - it.c0);
     lam[x] = T2{kf * phi[x].x, kf * phi[x].y};
   }
   __syncthreads();
@@ -801,15 +839,17 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
     const double wgt = sig.re * sig.re + sig.im * sig.im;
     if (tid == 0) o[1 + k] = 2.0 * wgt * gb / ntrue;
     R tau; DC f, finv;
-    rot_params<R>(ang[k], tau, f, finv);
+    bool fl;
+    rot_params<R>(ang[k], tau, f, finv, fl);
     rotate_all(phi, -tau);
     rotate_all(lam, -tau);
+    if (fl) F ^= FALL;
     for (int qb = 0; qb < n; qb++) sig = dmul(sig, finv);
     // d/dgamma_k: 2 Im <lam| C |phi> = 2 Im <lam| C - c0 |phi> (<lam|phi> is real)
     double gg = 0.0;
     for (uint32_t x = tid; x < N; x += 256) {
       T2 l = lam[x], v = phi[x];
-      gg += (double)(fmaR(l.x, v.y, -l.y * v.x)) * ((double)cval(x) - it.c0);
+      gg += (double)(fmaR(l.x, v.y, -l.y * v.x)) * (cost(x) - it.c0);
     }
     gg = block_sum(gg, red);
     const double wg2 = sig.re * sig.re + sig.im * sig.im;
@@ -882,11 +922,26 @@ hipError_t launch_table_widen(const void *src, int tbytes, int64_t *dst, uint64_
   return hipGetLastError();
 }
 
-hipError_t launch_luts(int precision, const LutJob *jobs, int njobs, int lut_len, void *luts,
-                       hipStream_t s) {
+hipError_t launch_luts(int precision, const LutJob *jobs, int njobs, int lut_len, const double *vals,
+                       void *luts, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  if (precision == 0) k_luts<float><<<njobs, 256, 0, s>>>(jobs, lut_len, (float2 *)luts);
-  else k_luts<double><<<njobs, 256, 0, s>>>(jobs, lut_len, (double2 *)luts);
+  if (precision == 0) k_luts<float><<<njobs, 256, 0, s>>>(jobs, lut_len, vals, (float2 *)luts);
+  else k_luts<double><<<njobs, 256, 0, s>>>(jobs, lut_len, vals, (double2 *)luts);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_reverse(const void *src, void *dst, int tbytes, uint64_t count, hipStream_t s) {
+  unsigned g = grid_for(count, 256);
+  if (tbytes == 1) k_table_reverse<uint8_t><<<g, 256, 0, s>>>((const uint8_t *)src, (uint8_t *)dst, count);
+  else k_table_reverse<uint16_t><<<g, 256, 0, s>>>((const uint16_t *)src, (uint16_t *)dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_values(const void *table, int tbytes, const double *vals, double *dst, uint64_t N,
+                               hipStream_t s) {
+  unsigned g = grid_for(N, 256);
+  if (tbytes == 1) k_table_values<uint8_t><<<g, 256, 0, s>>>((const uint8_t *)table, vals, dst, N);
+  else k_table_values<uint16_t><<<g, 256, 0, s>>>((const uint16_t *)table, vals, dst, N);
   return hipGetLastError();
 }
 
@@ -895,7 +950,7 @@ static size_t lds_for(int tbytes, int lut_len) {
   size_t st = ((1u << T) + ((1u << T) >> (sizeof(R) == 4 ? 5 : 4))) * 2 * sizeof(R);
   size_t tb = ((size_t)(1u << T) * tbytes);
   tb += (tb >> 8) * 16;
-  return st + tb + (size_t)lut_len * 2 * sizeof(R);
+  return st + tb + (size_t)lut_len * 3 * sizeof(R);
 }
 
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len) {
@@ -937,6 +992,7 @@ static hipError_t launch_shape(const PassArgs<R> &a, int shape, hipStream_t s) {
 template <typename R, int T, int KIND, typename TT>
 static hipError_t launch_sx(const PassArgs<R> &a, int sx, int shape, hipStream_t s) {
   if (sx == 7) return launch_shape<R, T, KIND, TT, 7>(a, shape, s);
+  if (sx == 5) return launch_shape<R, T, KIND, TT, 5>(a, shape, s);
   if (sx == 3) return launch_shape<R, T, KIND, TT, 3>(a, shape, s);
   return launch_shape<R, T, KIND, TT, 1>(a, shape, s);
 }
