@@ -66,6 +66,16 @@ def lib():
         L.orc_qaoa_grad.restype = ctypes.c_int
         L.orc_qaoa_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, f64p, f64p, vp,
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), f64p]
+        i = ctypes.c_int
+        L.orc_qaoa_state_m.restype = ctypes.c_int
+        L.orc_qaoa_state_m.argtypes = [i, i, i, i, f64p, f64p, vp, c128p]
+        L.orc_qaoa_expect_m.restype = ctypes.c_int
+        L.orc_qaoa_expect_m.argtypes = [i, i, i, i, f64p, f64p, vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.orc_qaoa_grad_m.restype = ctypes.c_int
+        L.orc_qaoa_grad_m.argtypes = [i, i, i, i, f64p, f64p, vp, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), f64p]
+        L.orc_apply_grover_mixer.argtypes = [ctypes.c_int64, ctypes.c_double, c128p]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_cost_values.restype = ctypes.c_int
         L.orc_cost_values.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, u64p, ctypes.c_int64, i64p]
@@ -138,38 +148,45 @@ def _check(n, k, angles, table):
     return angles, table, N, angles.size // 2
 
 
-def state(n: int, table, angles, k: int = -1, psi0=None) -> np.ndarray:
-    """psi_p of Eq. (1) (complex128, order of ``states``)."""
+def state(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False) -> np.ndarray:
+    """psi_p of Eq. (1) (complex128, order of ``states``). Mixer: X (k < 0) or clique
+    (k >= 0); ``grover=True``: the Grover mixer on the same states (Sec. 2.4)."""
     angles, table, N, p = _check(n, k, angles, table)
     keep, ptr = _psi0_ptr(psi0, N)
     out = np.zeros(N, dtype=np.complex128)
-    if lib().orc_qaoa_state(n, k, p, angles, table, ptr, out):
+    if lib().orc_qaoa_state_m(n, k, int(grover), p, angles, table, ptr, out):
         raise RuntimeError("oracle failed")
     return out
 
 
-def expect(n: int, table, angles, k: int = -1, psi0=None):
+def expect(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False):
     """(E, Nrm): E = sum |psi_p|^2 C, Nrm = sum |psi_p|^2."""
     angles, table, N, p = _check(n, k, angles, table)
     keep, ptr = _psi0_ptr(psi0, N)
     E, Nr = ctypes.c_double(), ctypes.c_double()
-    if lib().orc_qaoa_expect(n, k, p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr)):
+    if lib().orc_qaoa_expect_m(n, k, int(grover), p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr)):
         raise RuntimeError("oracle failed")
     return E.value, Nr.value
 
 
-def grad(n: int, table, angles, k: int = -1, psi0=None):
+def grad(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False):
     """(E, Nrm, g) with g = [d/dbeta_1..p, d/dgamma_1..p] from the adjoint recursion."""
     angles, table, N, p = _check(n, k, angles, table)
     keep, ptr = _psi0_ptr(psi0, N)
     E, Nr = ctypes.c_double(), ctypes.c_double()
     g = np.zeros(2 * p, dtype=np.float64)
-    if lib().orc_qaoa_grad(n, k, p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr), g):
+    if lib().orc_qaoa_grad_m(n, k, int(grover), p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr), g):
         raise RuntimeError("oracle failed")
     return E.value, Nr.value, g
 
 
-def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3) -> np.ndarray:
+def degeneracies(table):
+    """Distinct values of C over the feasible states and how many states take each (Sec. 2.4)."""
+    vals, counts = np.unique(np.asarray(table), return_counts=True)
+    return vals, counts
+
+
+def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3, grover: bool = False) -> np.ndarray:
     """Central finite differences with one Richardson step (error O(h^4)), forward-only."""
     angles = np.asarray(angles, dtype=np.float64)
     g = np.zeros(angles.size)
@@ -177,7 +194,7 @@ def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3) -> n
         def f(d):
             a = angles.copy()
             a[j] += d
-            return expect(n, table, a, k, psi0)[0]
+            return expect(n, table, a, k, psi0, grover)[0]
         d1 = (f(h) - f(-h)) / (2 * h)
         d2 = (f(h / 2) - f(-h / 2)) / h
         g[j] = (4 * d2 - d1) / 3
@@ -192,6 +209,11 @@ def apply_phase(table, gamma: float, psi: np.ndarray) -> None:
 def apply_x_mixer(n: int, beta: float, psi: np.ndarray) -> None:
     """In place: psi <- prod_q e^{-i beta X_q} psi."""
     lib().orc_apply_x_mixer(n, float(beta), psi)
+
+
+def apply_grover_mixer(beta: float, psi: np.ndarray) -> None:
+    """In place: psi += (e^{-i beta} - 1) <psi0|psi> psi0 over len(psi) states."""
+    lib().orc_apply_grover_mixer(int(psi.size), float(beta), psi)
 
 
 def apply_x_sum(n: int, psi: np.ndarray) -> np.ndarray:

@@ -15,6 +15,8 @@
  *     e^{-i g_1 H_C} |psi0>, phase separator first in every round, with H_C|x> = C(x)|x>;
  *   - H_M = sum_q X_q (transverse field, Sec. 2.1), applied qubit by qubit as the 2x2 rotation
  *     e^{-i b X_q} = cos b I - i sin b X_q (the factorisation behind Eq. (2));
+ *   - H_M = |psi0><psi0| (Grover mixer, Sec. 2.4) with psi0 the equal superposition over S:
+ *     e^{-i b H_M} = I + (e^{-i b} - 1)|psi0><psi0|, applied as psi += (e^{-i b} - 1) <psi0|psi> psi0;
  *   - H_M = sum_{i<j} X_i X_j + Y_i Y_j (clique mixer, Sec. 2.1) restricted to weight k: it
  *     maps |x> to 2|y> for every y obtained from x by moving one 1 to a 0 position;
  *     e^{-i b H_M} psi is formed by a scaled Taylor series of the sparse matrix;
@@ -150,6 +152,29 @@ void orc_apply_x_sum(int n, const cplx *psi, cplx *out) {
     }
 }
 
+/* <psi0|psi> for the equal superposition psi0 over N states: sum_x psi(x) / sqrt(N). */
+static cplx overlap_uniform(int64_t N, const cplx *psi) {
+    double sr = 0.0, si = 0.0, cr = 0.0, ci = 0.0;   /* Neumaier on both parts */
+    for (int64_t x = 0; x < N; x++) {
+        double a = creal(psi[x]), b = cimag(psi[x]);
+        double t = sr + a; cr += fabs(sr) >= fabs(a) ? (sr - t) + a : (a - t) + sr; sr = t;
+        t = si + b; ci += fabs(si) >= fabs(b) ? (si - t) + b : (b - t) + si; si = t;
+    }
+    return ((sr + cr) + I * (si + ci)) / sqrt((double)N);
+}
+
+/* Grover mixer (Sec. 2.4): psi <- psi + (e^{-i beta} - 1) <psi0|psi> psi0. */
+void orc_apply_grover_mixer(int64_t N, double beta, cplx *psi) {
+    cplx c = (cexp(-I * beta) - 1.0) * overlap_uniform(N, psi) / sqrt((double)N);
+    for (int64_t x = 0; x < N; x++) psi[x] += c;
+}
+
+/* H_G psi = psi0 <psi0|psi>: the constant vector <psi0|psi> / sqrt(N). */
+static void grover_sum(int64_t N, const cplx *psi, cplx *out) {
+    cplx c = overlap_uniform(N, psi) / sqrt((double)N);
+    for (int64_t x = 0; x < N; x++) out[x] = c;
+}
+
 /* Index of state y in the increasing list st[0..N) (binary search); -1 if absent. */
 static int64_t find_state(const uint64_t *st, int64_t N, uint64_t y) {
     int64_t lo = 0, hi = N - 1;
@@ -255,18 +280,21 @@ static double im_inner_c(int64_t N, const double *cost, const cplx *a, const cpl
 /* ------------------------------------------------------------------ Eq. (1), both mixers */
 
 typedef struct {
-    int n, k;              /* k < 0: X mixer on all 2^n states; else clique on weight k */
+    int n, k;              /* k < 0: all 2^n states; else the weight-k states */
+    int grover;            /* 1: Grover mixer on those states; 0: X mixer (k < 0) or clique */
     int64_t N;
-    const int64_t *nb;     /* clique neighbour lists (NULL for X) */
+    const int64_t *nb;     /* clique neighbour lists (NULL otherwise) */
 } mixer_t;
 
 static void apply_mixer(const mixer_t *m, double beta, cplx *psi) {
-    if (m->k < 0) orc_apply_x_mixer(m->n, beta, psi);
+    if (m->grover) orc_apply_grover_mixer(m->N, beta, psi);
+    else if (m->k < 0) orc_apply_x_mixer(m->n, beta, psi);
     else orc_apply_clique_mixer(m->n, m->k, m->nb, m->N, beta, psi);
 }
 
 static void apply_mixer_sum(const mixer_t *m, const cplx *psi, cplx *out) {
-    if (m->k < 0) orc_apply_x_sum(m->n, psi, out);
+    if (m->grover) grover_sum(m->N, psi, out);
+    else if (m->k < 0) orc_apply_x_sum(m->n, psi, out);
     else clique_matvec(m->N, m->k * (m->n - m->k), m->nb, psi, out);
 }
 
@@ -287,10 +315,11 @@ static void evolve(const mixer_t *m, int p, const double *angles, const double *
     }
 }
 
-static int make_mixer(int n, int k, mixer_t *m, int64_t **nb_store) {
-    m->n = n; m->k = k; m->nb = NULL; *nb_store = NULL;
+static int make_mixer(int n, int k, int grover, mixer_t *m, int64_t **nb_store) {
+    m->n = n; m->k = k; m->grover = grover; m->nb = NULL; *nb_store = NULL;
     if (k < 0) { m->N = 1ll << n; return 0; }
     m->N = orc_binom(n, k);
+    if (grover) return 0;
     uint64_t *st = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m->N);
     int deg = k * (n - k);
     int64_t *nb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m->N * (deg > 0 ? deg : 1)));
@@ -303,20 +332,21 @@ static int make_mixer(int n, int k, mixer_t *m, int64_t **nb_store) {
 }
 
 /* Final state psi_p of Eq. (1). k < 0: X mixer; k >= 0: clique mixer on weight k. */
-int orc_qaoa_state(int n, int k, int p, const double *angles, const double *cost,
-                   const cplx *psi0, cplx *psi_out) {
+/* mixer: 0 = X (k < 0) or clique (k >= 0); 1 = Grover on the feasible set. */
+int orc_qaoa_state_m(int n, int k, int mixer, int p, const double *angles, const double *cost,
+                     const cplx *psi0, cplx *psi_out) {
     mixer_t m; int64_t *nb;
-    if (make_mixer(n, k, &m, &nb)) return -1;
+    if (make_mixer(n, k, mixer, &m, &nb)) return -1;
     evolve(&m, p, angles, cost, psi0, psi_out);
     free(nb);
     return 0;
 }
 
 /* <C> (raw E and Nrm) for one angle set. */
-int orc_qaoa_expect(int n, int k, int p, const double *angles, const double *cost,
-                    const cplx *psi0, double *E, double *Nrm) {
+int orc_qaoa_expect_m(int n, int k, int mixer, int p, const double *angles, const double *cost,
+                      const cplx *psi0, double *E, double *Nrm) {
     mixer_t m; int64_t *nb;
-    if (make_mixer(n, k, &m, &nb)) return -1;
+    if (make_mixer(n, k, mixer, &m, &nb)) return -1;
     cplx *psi = (cplx *)malloc(sizeof(cplx) * (size_t)m.N);
     if (!psi) { free(nb); return -1; }
     evolve(&m, p, angles, cost, psi0, psi);
@@ -326,10 +356,10 @@ int orc_qaoa_expect(int n, int k, int p, const double *angles, const double *cos
 }
 
 /* <C> and its gradient [d/dbeta_1..p, d/dgamma_1..p] by the adjoint recursion (header). */
-int orc_qaoa_grad(int n, int k, int p, const double *angles, const double *cost,
-                  const cplx *psi0, double *E, double *Nrm, double *grad) {
+int orc_qaoa_grad_m(int n, int k, int mixer, int p, const double *angles, const double *cost,
+                    const cplx *psi0, double *E, double *Nrm, double *grad) {
     mixer_t m; int64_t *nb;
-    if (make_mixer(n, k, &m, &nb)) return -1;
+    if (make_mixer(n, k, mixer, &m, &nb)) return -1;
     int64_t N = m.N;
     cplx *phi = (cplx *)malloc(sizeof(cplx) * (size_t)N);
     cplx *lam = (cplx *)malloc(sizeof(cplx) * (size_t)N);
@@ -349,6 +379,20 @@ int orc_qaoa_grad(int n, int k, int p, const double *angles, const double *cost,
     }
     free(phi); free(lam); free(tmp); free(nb);
     return 0;
+}
+
+/* The same with the default mixer of the state space (X for k < 0, clique for k >= 0). */
+int orc_qaoa_state(int n, int k, int p, const double *angles, const double *cost, const cplx *psi0,
+                   cplx *psi_out) {
+    return orc_qaoa_state_m(n, k, 0, p, angles, cost, psi0, psi_out);
+}
+int orc_qaoa_expect(int n, int k, int p, const double *angles, const double *cost, const cplx *psi0,
+                    double *E, double *Nrm) {
+    return orc_qaoa_expect_m(n, k, 0, p, angles, cost, psi0, E, Nrm);
+}
+int orc_qaoa_grad(int n, int k, int p, const double *angles, const double *cost, const cplx *psi0,
+                  double *E, double *Nrm, double *grad) {
+    return orc_qaoa_grad_m(n, k, 0, p, angles, cost, psi0, E, Nrm, grad);
 }
 
 /* Thread count OpenMP would use (for reporting the CPU baseline). */

@@ -334,3 +334,67 @@ def test_real_cost_clique_matches_full_space_bruteforce():
     want = pins.dense_evolve(pins.dense_clique_hamiltonian(n), tfull, a, psi0)
     got = oracle.state(n, tfull[st], a, k=k)
     assert np.max(np.abs(want[st] - got)) < 1e-12
+
+
+# ---------------------------------------------------------------- Grover mixer (Sec. 2.4)
+
+def _projector_uniform(N):
+    u = np.full(N, 1 / np.sqrt(N), dtype=np.complex128)
+    return np.outer(u, u.conj())
+
+
+@pytest.mark.parametrize("N", [64, 70])
+def test_grover_mixer_matches_expm(N):
+    rng = np.random.default_rng(N)
+    psi = rng.normal(size=N) + 1j * rng.normal(size=N)
+    for beta in (0.3, 1.7, -2.4):
+        want = scipy.linalg.expm(-1j * beta * _projector_uniform(N)) @ psi
+        got = psi.copy()
+        oracle.apply_grover_mixer(beta, got)
+        assert np.max(np.abs(got - want)) < 1e-13
+
+
+@pytest.mark.parametrize("n,k,p", [(6, -1, 3), (8, 3, 2)])
+def test_grover_qaoa_matches_dense(n, k, p):
+    N = (1 << n) if k < 0 else comb(n, k)
+    t = _real_table(N, 330 + n)
+    a = workloads.random_angles(p, 1, 331 + n)[0]
+    psi0 = np.full(N, 1 / np.sqrt(N), dtype=np.complex128)
+    want = pins.dense_evolve(_projector_uniform(N), t, a, psi0)
+    assert np.max(np.abs(oracle.state(n, t, a, k=k, grover=True) - want)) < 1e-13
+
+
+def test_grover_fair_sampling():
+    # states with equal cost keep equal amplitudes (Sec. 2.4, third property)
+    g = _er(10, 77, (1, 3))
+    t = oracle.graph_table(g)
+    psi = oracle.state(10, t, workloads.random_angles(4, 1, 78)[0], grover=True)
+    for c in np.unique(t):
+        cls = psi[t == c]
+        assert np.max(np.abs(cls - cls[0])) < 1e-14
+
+
+def test_grover_p1_closed_form_from_degeneracies():
+    # p = 1: psi(x) = (e^{-i g C(x)} + (e^{-i b} - 1) F(g)) / sqrt(N) with F(g) the mean of
+    # e^{-i g C} over the states, so <C> = sum_c m_c c |e^{-i g c} + (e^{-i b} - 1) F|^2 / N
+    g = _er(9, 79, (1, 4))
+    t = oracle.graph_table(g)
+    vals, cnt = oracle.degeneracies(t)
+    assert cnt.sum() == 1 << 9 and np.array_equal(vals, np.unique(t))
+    N = cnt.sum()
+    for b, gm in ((0.4, 1.1), (2.2, 0.35), (1.57, 2.9)):
+        F = np.sum(cnt * np.exp(-1j * gm * vals)) / N
+        amp = np.exp(-1j * gm * vals) + (np.exp(-1j * b) - 1) * F
+        want = np.sum(cnt * vals * np.abs(amp) ** 2) / N
+        E, Nr = oracle.expect(9, t, [b, gm], grover=True)
+        assert abs(E - want) < 1e-12 * abs(want) and abs(Nr - 1) < 1e-13
+
+
+def test_grover_gradient_matches_finite_differences():
+    for n, k in ((8, -1), (9, 4)):
+        N = (1 << n) if k < 0 else comb(n, k)
+        t = _real_table(N, 340 + n, distinct=25)
+        a = workloads.random_angles(3, 1, 341 + n)[0]
+        E, Nr, gr = oracle.grad(n, t, a, k=k, grover=True)
+        fd = oracle.fd_grad(n, t, a, k=k, grover=True)
+        assert np.max(np.abs(gr - fd)) < 1e-9 * max(1, np.max(np.abs(gr)))
