@@ -123,6 +123,33 @@ int qaoa_mixer_x(qaoa_ctx *ctx, int n, qaoa_mixer **out);
  * 2 <= n <= 20, 1 <= k <= n-1 and C(n,k) <= 16384. Synchronises `stream`. */
 int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream);
 
+/* Grover mixer H_M = |psi0><psi0| (Sec. 2.4), psi0 the equal superposition over the feasible
+ * states of an n-qubit problem (all 2^n for hamming_k < 0, else the weight-k states; the mixer
+ * keeps the Hamming weight). 1 <= n <= 62. Evaluations with it use fair sampling (Sec. 2.4):
+ * states of equal cost keep equal amplitudes, so the rounds run on the problem's distinct cost
+ * values weighted by their degeneracies (counted once per problem, on first use), in FP64 for
+ * either precision argument; at most 2048 distinct values (table indices for a tabulated
+ * problem). Only the default initial state (d_psi0 == NULL). qaoa_state expands the result
+ * over a tabulated problem's states. */
+int qaoa_mixer_grover(qaoa_ctx *ctx, int n, int hamming_k, qaoa_mixer **out);
+
+/* Degeneracies of the MaxCut cost without a table (Sec. 2.4: for the Grover mixer only the
+ * distinct values and how many states take each are stored, counted in parallel over the
+ * states): all 2^n strings (hamming_k < 0, 1 <= n <= 40; consecutive states in Gray-code order)
+ * or the weight-k strings (Gosper's order, n <= 32). Edges as qaoa_cost_table, total
+ * weight <= 16383. *out is a problem with no table: it serves qaoa_mixer_grover evaluations
+ * (batched included) and qaoa_problem_degeneracies; other mixers, qaoa_state and the table
+ * copies return QAOA_ERR_UNSUPPORTED. Synchronises `stream`. */
+int qaoa_cost_degeneracies(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const int32_t *v,
+                           const int32_t *w, int hamming_k, qaoa_problem **out, void *stream);
+
+/* Distinct cost values (increasing) that at least one feasible state takes, with their
+ * degeneracies: values[i], counts[i] for i < *count (host arrays of cap entries, either may
+ * be NULL to query *count only; INVALID_ARG when cap is too small). Counts a tabulated
+ * problem's table on first use. */
+int qaoa_problem_degeneracies(const qaoa_problem *prob, double *values, int64_t *counts, size_t cap,
+                              size_t *count, void *stream);
+
 /* Free a mixer (NULL accepted). */
 int qaoa_mixer_destroy(qaoa_mixer *mix);
 
@@ -172,13 +199,16 @@ int qaoa_expect_grad_batched(const qaoa_problem *const *probs, const qaoa_mixer 
  * table when the kernel reads it). Classes: QAOA_KC_FWD_PASS (tile pass over one vector),
  * QAOA_KC_REV_PASS (tile pass over the state and the adjoint vector), QAOA_KC_SMALL
  * (whole-state kernel), QAOA_KC_DENSE (constrained-mixer products), QAOA_KC_OTHER
- * (lookup tables, reductions). enable: 1 on, 0 off; enabling clears the totals. */
+ * (lookup tables, reductions), QAOA_KC_GROVER and QAOA_KC_COUNT_STATES (Grover mixer).
+ * enable: 1 on, 0 off; enabling clears the totals. */
 #define QAOA_KC_FWD_PASS 0
 #define QAOA_KC_REV_PASS 1
 #define QAOA_KC_SMALL 2
 #define QAOA_KC_DENSE 3
 #define QAOA_KC_OTHER 4
-#define QAOA_KC_COUNT 5
+#define QAOA_KC_GROVER 5       /* Grover-mixer rounds on the cost classes */
+#define QAOA_KC_COUNT_STATES 6 /* table-free degeneracy counting */
+#define QAOA_KC_COUNT 7
 int qaoa_profile_enable(qaoa_ctx *ctx, int enable);
 
 /* Totals of class `kernel_class` since the last enable: launches, summed milliseconds,

@@ -24,9 +24,11 @@ EXPORTED = [
     "qaoa_problem_info", "qaoa_problem_destroy", "qaoa_mixer_x", "qaoa_mixer_clique",
     "qaoa_mixer_destroy", "qaoa_expect", "qaoa_expect_grad", "qaoa_state", "qaoa_expect_batched",
     "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error", "qaoa_profile_enable",
-    "qaoa_profile_read", "qaoa_problem_from_values", "qaoa_problem_copy_values",
+    "qaoa_profile_read", "qaoa_problem_from_values", "qaoa_problem_copy_values", "qaoa_mixer_grover",
+    "qaoa_cost_degeneracies", "qaoa_problem_degeneracies",
 ]
-KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4}
+KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
+                  "count_states": 6}
 
 
 class QAOAError(RuntimeError):
@@ -68,6 +70,9 @@ def lib() -> ctypes.CDLL:
     L.qaoa_problem_destroy.argtypes = [c_void_p]
     L.qaoa_mixer_x.argtypes = [c_void_p, c_int, P(c_void_p)]
     L.qaoa_mixer_clique.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
+    L.qaoa_mixer_grover.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
+    L.qaoa_cost_degeneracies.argtypes = [c_void_p, c_int, c_int, i32p, i32p, i32p, c_int, P(c_void_p), c_void_p]
+    L.qaoa_problem_degeneracies.argtypes = [c_void_p, P(c_double), P(c_int64), c_size_t, P(c_size_t), c_void_p]
     L.qaoa_mixer_destroy.argtypes = [c_void_p]
     L.qaoa_expect.argtypes = [c_void_p, c_void_p, c_int, P(c_double), c_void_p, c_int, P(c_double), c_void_p]
     L.qaoa_expect_grad.argtypes = [c_void_p, c_void_p, c_int, P(c_double), c_void_p, c_int,
@@ -170,6 +175,37 @@ def qaoa_mixer_x(ctx: int, n: int) -> int:
     out = c_void_p()
     check(lib().qaoa_mixer_x(ctx, n, ctypes.byref(out)), "qaoa_mixer_x")
     return out.value
+
+
+def qaoa_mixer_grover(ctx: int, n: int, hamming_k: int = -1) -> int:
+    out = c_void_p()
+    check(lib().qaoa_mixer_grover(ctx, n, hamming_k, ctypes.byref(out)), "qaoa_mixer_grover")
+    return out.value
+
+
+def qaoa_cost_degeneracies(ctx: int, n: int, u, v, w=None, hamming_k: int = -1, stream: int = 0) -> int:
+    ua, up = _i32(u)
+    va, vp = _i32(v)
+    if w is None:
+        wp = None
+    else:
+        wa, wp = _i32(w)
+    out = c_void_p()
+    check(lib().qaoa_cost_degeneracies(ctx, n, int(ua.size), up, vp, wp, hamming_k, ctypes.byref(out), stream),
+          "qaoa_cost_degeneracies")
+    return out.value
+
+
+def qaoa_problem_degeneracies(prob: int, stream: int = 0):
+    """(values, counts) of the distinct costs taken by at least one feasible state."""
+    import numpy as np
+    cnt = c_size_t()
+    check(lib().qaoa_problem_degeneracies(prob, None, None, 0, ctypes.byref(cnt), stream), "qaoa_problem_degeneracies")
+    vals = np.zeros(cnt.value, dtype=np.float64)
+    counts = np.zeros(cnt.value, dtype=np.int64)
+    check(lib().qaoa_problem_degeneracies(prob, vals.ctypes.data_as(P(c_double)), counts.ctypes.data_as(P(c_int64)),
+                                          cnt.value, ctypes.byref(cnt), stream), "qaoa_problem_degeneracies")
+    return vals, counts
 
 
 def qaoa_mixer_clique(ctx: int, n: int, k: int, stream: int = 0) -> int:

@@ -79,6 +79,16 @@ class Problem:
     def table(self, stream=None) -> np.ndarray:
         return _lib.qaoa_problem_copy_table(self.handle, _stream(stream))
 
+    @classmethod
+    def degeneracies_of_graph(cls, ctx: Context, g, hamming_k: int = -1, stream=None):
+        """MaxCut degeneracies counted on the device without a table (Grover mixer only)."""
+        h = _lib.qaoa_cost_degeneracies(ctx.handle, g.n, g.u, g.v, g.w, hamming_k, _stream(stream))
+        return cls(ctx, g.n, hamming_k=hamming_k, _handle=h)
+
+    def degeneracies(self, stream=None):
+        """(distinct values, how many feasible states take each)."""
+        return _lib.qaoa_problem_degeneracies(self.handle, _stream(stream))
+
     def values(self, stream=None) -> np.ndarray:
         """C(x) over the feasible states as FP64."""
         return _lib.qaoa_problem_copy_values(self.handle, _stream(stream))
@@ -96,7 +106,8 @@ class Problem:
 
 
 class Mixer:
-    """H_M: ``Mixer.x(ctx, n)`` (sum of X_q) or ``Mixer.clique(ctx, n, k)``."""
+    """H_M: ``Mixer.x(ctx, n)`` (sum of X_q), ``Mixer.clique(ctx, n, k)`` or
+    ``Mixer.grover(ctx, n, hamming_k)`` (|psi0><psi0|)."""
 
     def __init__(self, ctx: Context, handle: int, kind: str, n: int, k: int = -1):
         self.ctx, self.handle, self.kind, self.n, self.k = ctx, handle, kind, n, k
@@ -105,6 +116,10 @@ class Mixer:
     @classmethod
     def x(cls, ctx: Context, n: int):
         return cls(ctx, _lib.qaoa_mixer_x(ctx.handle, n), "x", n)
+
+    @classmethod
+    def grover(cls, ctx: Context, n: int, hamming_k: int = -1):
+        return cls(ctx, _lib.qaoa_mixer_grover(ctx.handle, n, hamming_k), "grover", n, hamming_k)
 
     @classmethod
     def clique(cls, ctx: Context, n: int, k: int, stream=None):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa.so")
-SOURCES = ["qaoa_kernels.hip", "qaoa_clique.hip", "qaoa_api.cpp"]
+SOURCES = ["qaoa_kernels.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP source of this library.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -140,7 +140,7 @@ struct qaoa_ctx {
   int device = 0;
   int64_t live = 0;          // problems and mixers created on this context and not yet destroyed
   int checkpoint_mode = -1;  // -1: when memory allows, 0: never, 1: always
-  DevBuf phi, lam, ckpt, partials, params, luts, results, cnt, items;
+  DevBuf phi, lam, ckpt, partials, params, luts, results, cnt, items, gitems, gamps;
   HostBuf hparams, hresults;
   // kernel timing
   bool profiling = false;
@@ -241,6 +241,8 @@ struct qaoa_problem {
   std::vector<double> hvals;          // cost value of each index
   double *dvals = nullptr;            // the same, device FP64 and FP32
   float *dvals_f = nullptr;
+  std::vector<double> hcounts;        // degeneracy of each index (Grover mixer; filled on first use)
+  double *dcounts = nullptr;
   void *table = nullptr;
   void *table_rev = nullptr;          // reversed natural table (C(~x)), when !sym
   std::map<std::tuple<int, int, int>, void *> layouts;      // (T, c, h0) -> tile-major copy
@@ -250,6 +252,7 @@ struct qaoa_problem {
     if (table_rev) (void)hipFree(table_rev);
     if (dvals) (void)hipFree(dvals);
     if (dvals_f) (void)hipFree(dvals_f);
+    if (dcounts) (void)hipFree(dcounts);
     for (auto &kv : layouts)
       if (kv.second) (void)hipFree(kv.second);
     for (auto &kv : layouts_rev)
@@ -276,7 +279,7 @@ void upload_values(qaoa_problem *prob, hipStream_t st) {
 
 struct qaoa_mixer {
   qaoa_ctx *ctx = nullptr;
-  int kind = 0;  // 0: transverse field, 1: clique
+  int kind = 0;  // 0: transverse field, 1: clique, 2: Grover
   int n = 0, k = -1;
   std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique;
 };
@@ -823,7 +826,9 @@ void check_pair(const qaoa_problem *prob, const qaoa_mixer *mix, int precision) 
   REQUIRE(precision == QAOA_FP32 || precision == QAOA_FP64, "precision must be QAOA_FP32 or QAOA_FP64");
   REQUIRE(prob->n == mix->n, "mixer and problem have different qubit counts");
   if (mix->kind == 0) REQUIRE(prob->k < 0, "the transverse-field mixer needs an unconstrained problem");
-  else REQUIRE(prob->k == mix->k, "the clique mixer's Hamming weight differs from the problem's");
+  else REQUIRE(prob->k == mix->k, "the mixer's Hamming weight differs from the problem's");
+  if (mix->kind != 2 && !prob->table)
+    throw fail(QAOA_ERR_UNSUPPORTED, "the problem holds degeneracies only: it serves the Grover mixer");
 }
 
 bool small_path(const qaoa_problem *prob, int precision) {
@@ -842,6 +847,96 @@ SmallItem small_item(const qaoa_problem *prob, int set, int row) {
   it.c0 = prob->mean;
   it.out_index = row;
   return it;
+}
+
+// ---------------------------------------------------------------- Grover mixer
+
+// Degeneracy of every table index (histogram of the stored table), on first use.
+void ensure_counts(qaoa_problem *prob, hipStream_t st) {
+  if (!prob->hcounts.empty()) return;
+  const int nb = (int)prob->max_value + 1;
+  if (nb > GROVER_MAX_CLASSES) throw fail(QAOA_ERR_UNSUPPORTED, "more than 2048 cost classes for the Grover mixer");
+  DevBuf dc;
+  unsigned long long *d = (unsigned long long *)dc.get((size_t)nb * sizeof(unsigned long long));
+  HIPCHK(hipMemsetAsync(d, 0, (size_t)nb * sizeof(unsigned long long), st));
+  HIPCHK(launch_hist_table(prob->table, prob->tbytes, prob->N, nb, d, st));
+  std::vector<unsigned long long> h(nb);
+  HIPCHK(hipMemcpyAsync(h.data(), d, (size_t)nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> c(nb);
+  for (int i = 0; i < nb; i++) c[i] = (double)h[i];
+  if (hipMalloc(&prob->dcounts, (size_t)nb * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    prob->dcounts = nullptr;
+    throw fail(QAOA_ERR_OUT_OF_MEMORY, "degeneracy allocation failed");
+  }
+  HIPCHK(hipMemcpyAsync(prob->dcounts, c.data(), (size_t)nb * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  prob->hcounts = c;
+}
+
+GroverItem grover_item(const qaoa_problem *prob, int set, int row) {
+  GroverItem it;
+  it.vals = prob->dvals;
+  it.counts = prob->dcounts;
+  it.nclass = (int)prob->hcounts.size();
+  it.angle_set = set;
+  it.out_index = row;
+  it.total = (double)prob->N;
+  it.c0 = prob->mean;
+  it.amp_out = nullptr;
+  return it;
+}
+
+// Grover-mixer items (one workgroup each, FP64 on the cost classes); hout rows of 1 + 2p.
+void run_grover(const std::vector<GroverItem> &items, const double *angles, int nsets, int p, int grad,
+                double *hout, qaoa_ctx *ctx, hipStream_t st) {
+  const int rowlen = 1 + 2 * p;
+  size_t ib = items.size() * sizeof(GroverItem);
+  size_t ab = (size_t)nsets * 2 * p * sizeof(double);
+  size_t off_a = (ib + 255) & ~size_t(255);
+  unsigned char *h = (unsigned char *)ctx->hparams.get(off_a + ab);
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(h, items.data(), ib);
+  std::memcpy(h + off_a, angles, ab);
+  unsigned char *d = (unsigned char *)ctx->gitems.get(off_a + ab);
+  HIPCHK(hipMemcpyAsync(d, h, off_a + ab, hipMemcpyHostToDevice, st));
+  int nrow = 0;
+  for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
+  double *dres = (double *)ctx->results.get((size_t)nrow * rowlen * sizeof(double));
+  double work = 0;
+  for (auto &it : items) work += (double)it.nclass;
+  KTimer kt(ctx, st, QAOA_KC_GROVER, work * 8.0 * 2.0, 0.0);
+  HIPCHK(launch_grover((const GroverItem *)d, (int)items.size(), (const double *)(d + off_a), p, grad, dres, st));
+  kt.done();
+  HIPCHK(hipMemcpyAsync(hout, dres, (size_t)nrow * rowlen * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  profile_collect(ctx);
+}
+
+void evaluate_grover(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0, int precision,
+                     int grad, double *out_expect, double *out_grad, void *d_state, hipStream_t st) {
+  if (d_psi0) throw fail(QAOA_ERR_UNSUPPORTED, "the Grover mixer path starts from the equal superposition only");
+  ensure_counts(prob, st);
+  std::vector<GroverItem> items;
+  for (int s = 0; s < nsets; s++) items.push_back(grover_item(prob, s, s));
+  double2 *amp = nullptr;
+  if (d_state) {
+    REQUIRE(prob->table != nullptr, "state output needs a tabulated problem");
+    amp = (double2 *)prob->ctx->gamps.get(items[0].nclass * sizeof(double2));
+    items[0].amp_out = amp;
+  }
+  std::vector<double> hout((size_t)nsets * (1 + 2 * p));
+  run_grover(items, angles, nsets, p, grad, hout.data(), prob->ctx, st);
+  for (int s = 0; s < nsets; s++) {
+    const double *r = hout.data() + (size_t)s * (1 + 2 * p);
+    if (out_expect) out_expect[s] = r[0];
+    if (grad && out_grad) std::memcpy(out_grad + (size_t)s * 2 * p, r + 1, 2 * p * sizeof(double));
+  }
+  if (d_state) {
+    HIPCHK(launch_grover_expand(prob->table, prob->tbytes, prob->N, amp, d_state, precision, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
 }
 
 void evaluate_x(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
@@ -1104,6 +1199,7 @@ int qaoa_problem_copy_values(const qaoa_problem *prob, double *host_dst, size_t 
   return guarded([&] {
     REQUIRE(prob && host_dst, "problem or destination is NULL");
     REQUIRE(len == prob->N, "len differs from the feasible-set size");
+    if (!prob->table) throw fail(QAOA_ERR_UNSUPPORTED, "the problem holds degeneracies only (no table)");
     DeviceGuard g(prob->ctx->device);
     hipStream_t st = (hipStream_t)stream;
     DevBuf tmp;
@@ -1118,6 +1214,7 @@ int qaoa_problem_copy_table(const qaoa_problem *prob, int64_t *host_dst, size_t 
   return guarded([&] {
     REQUIRE(prob && host_dst, "problem or destination is NULL");
     REQUIRE(len == prob->N, "len differs from the feasible-set size");
+    if (!prob->table) throw fail(QAOA_ERR_UNSUPPORTED, "the problem holds degeneracies only (no table)");
     DeviceGuard g(prob->ctx->device);
     hipStream_t st = (hipStream_t)stream;
     DevBuf tmp;
@@ -1162,6 +1259,159 @@ int qaoa_mixer_x(qaoa_ctx *ctx, int n, qaoa_mixer **out) {
   });
 }
 
+int qaoa_mixer_grover(qaoa_ctx *ctx, int n, int hamming_k, qaoa_mixer **out) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 62, "n must be in [1, 62]");
+    REQUIRE(hamming_k <= n, "hamming_k must be <= n");
+    auto m = std::make_unique<qaoa_mixer>();
+    m->ctx = ctx;
+    m->kind = 2;
+    m->n = n;
+    m->k = hamming_k < 0 ? -1 : hamming_k;
+    *out = m.release();
+    ctx->live++;
+  });
+}
+
+int qaoa_cost_degeneracies(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, const int32_t *v, const int32_t *w,
+                           int hamming_k, qaoa_problem **out, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 40, "n must be in [1, 40]");
+    REQUIRE(n_edges >= 0 && n_edges <= 512, "n_edges must be in [0, 512]");
+    REQUIRE(n_edges == 0 || (u && v), "edge arrays are NULL");
+    REQUIRE(hamming_k <= n, "hamming_k must be <= n");
+    int64_t W = 0;
+    for (int e = 0; e < n_edges; e++) {
+      REQUIRE(u[e] >= 0 && u[e] < n && v[e] >= 0 && v[e] < n, "edge endpoint out of range");
+      REQUIRE(u[e] != v[e], "self-loop edge");
+      int64_t we = w ? w[e] : 1;
+      REQUIRE(we >= 0, "negative edge weight");
+      W += we;
+    }
+    REQUIRE(W <= 16383, "total edge weight must be <= 16383");
+    if (hamming_k >= 0) REQUIRE(n <= 32, "n must be <= 32 for a Hamming-weight subspace");
+    const uint64_t N = hamming_k < 0 ? (1ull << n) : (uint64_t)binom64(n, hamming_k);
+    const int nbins = (int)W + 1;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    // edges and adjacency (CSR: neighbour << 16 | weight) to the device
+    std::vector<int32_t> hv(3 * (size_t)n_edges), off(n + 1, 0), adj(2 * (size_t)n_edges);
+    for (int e = 0; e < n_edges; e++) {
+      hv[e] = u[e];
+      hv[n_edges + e] = v[e];
+      hv[2 * n_edges + e] = w ? w[e] : 1;
+      off[u[e] + 1]++;
+      off[v[e] + 1]++;
+    }
+    for (int i = 0; i < n; i++) off[i + 1] += off[i];
+    {
+      std::vector<int32_t> fill(off.begin(), off.end() - 1);
+      for (int e = 0; e < n_edges; e++) {
+        const int32_t we = w ? w[e] : 1;
+        adj[fill[u[e]]++] = (v[e] << 16) | we;
+        adj[fill[v[e]]++] = (u[e] << 16) | we;
+      }
+    }
+    std::vector<int64_t> hb(33 * 33);
+    for (int a = 0; a <= 32; a++)
+      for (int b = 0; b <= 32; b++) hb[a * 33 + b] = binom64(a, b);
+    const size_t bytes_e = std::max<size_t>(1, hv.size()) * 4, bytes_o = off.size() * 4,
+                 bytes_a = std::max<size_t>(1, adj.size()) * 4, bytes_b = hb.size() * 8;
+    DevBuf de, dof, dad, dbn, dcnt;
+    int32_t *d_e = (int32_t *)de.get(bytes_e);
+    int32_t *d_off = (int32_t *)dof.get(bytes_o);
+    int32_t *d_adj = (int32_t *)dad.get(bytes_a);
+    int64_t *d_bin = (int64_t *)dbn.get(bytes_b);
+    unsigned long long *d_cnt = (unsigned long long *)dcnt.get((size_t)nbins * 8);
+    if (!hv.empty()) HIPCHK(hipMemcpyAsync(d_e, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_off, off.data(), bytes_o, hipMemcpyHostToDevice, st));
+    if (!adj.empty()) HIPCHK(hipMemcpyAsync(d_adj, adj.data(), adj.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_bin, hb.data(), bytes_b, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d_cnt, 0, (size_t)nbins * 8, st));
+    const int32_t *eu = d_e, *ev = d_e + n_edges, *ew = d_e + 2 * n_edges;
+    // the count, in launches of at most 2^18 threads
+    const uint64_t LAUNCH = 1ull << 18;
+    KTimer kt(ctx, st, QAOA_KC_COUNT_STATES, 0.0, 0.0);
+    if (hamming_k < 0) {
+      const int lo = std::max(0, std::min(24, n - 20));
+      const uint64_t T = 1ull << (n - lo);
+      const bool priv = nbins <= 64;
+      for (uint64_t b0 = 0; b0 < T; b0 += LAUNCH)
+        HIPCHK(launch_enum_full(n, n_edges, eu, ev, ew, d_off, d_adj, lo, b0, std::min(LAUNCH, T - b0), nbins, priv,
+                                d_cnt, st));
+    } else {
+      const uint64_t T = std::min<uint64_t>(N, 1ull << 20);
+      const uint64_t per = (N + T - 1) / T;
+      for (uint64_t t0 = 0; t0 < T; t0 += LAUNCH) {
+        const uint64_t nt = std::min(LAUNCH, T - t0);
+        HIPCHK(launch_enum_hw(n, hamming_k, n_edges, eu, ev, ew, d_bin, t0 * per, per, N, nt, nbins, d_cnt, st));
+      }
+    }
+    kt.done();
+    std::vector<unsigned long long> hc(nbins);
+    HIPCHK(hipMemcpyAsync(hc.data(), d_cnt, (size_t)nbins * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    profile_collect(ctx);
+    auto prob = std::make_unique<qaoa_problem>();
+    prob->ctx = ctx;
+    prob->n = n;
+    prob->k = hamming_k < 0 ? -1 : hamming_k;
+    prob->N = N;
+    prob->total_weight = W;
+    long double sum = 0.0L;
+    unsigned long long seen = 0;
+    for (int c = 0; c < nbins; c++)
+      if (hc[c]) {
+        prob->hvals.push_back((double)c);
+        prob->hcounts.push_back((double)hc[c]);
+        sum += (long double)c * (long double)hc[c];
+        seen += hc[c];
+      }
+    if (seen != N) throw fail(QAOA_ERR_HIP, "internal: degeneracies do not add up to the state count");
+    if (prob->hvals.size() > (size_t)GROVER_MAX_CLASSES)
+      throw fail(QAOA_ERR_UNSUPPORTED, "more than 2048 distinct cost values");
+    prob->mean = (double)(sum / (long double)N);
+    prob->max_value = (int64_t)prob->hvals.size() - 1;
+    upload_values(prob.get(), st);
+    if (hipMalloc(&prob->dcounts, prob->hcounts.size() * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      prob->dcounts = nullptr;
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "degeneracy allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(prob->dcounts, prob->hcounts.data(), prob->hcounts.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *out = prob.release();
+    ctx->live++;
+  });
+}
+
+int qaoa_problem_degeneracies(const qaoa_problem *cprob, double *values, int64_t *counts, size_t cap, size_t *count,
+                              void *stream) {
+  return guarded([&] {
+    REQUIRE(cprob != nullptr, "problem is NULL");
+    qaoa_problem *prob = const_cast<qaoa_problem *>(cprob);
+    DeviceGuard g(prob->ctx->device);
+    ensure_counts(prob, (hipStream_t)stream);
+    // classes with at least one state, in increasing value order
+    size_t j = 0;
+    for (size_t i = 0; i < prob->hcounts.size(); i++) {
+      if (prob->hcounts[i] == 0.0) continue;
+      if (j < cap) {
+        if (values) values[j] = prob->hvals[i];
+        if (counts) counts[j] = (int64_t)prob->hcounts[i];
+      }
+      j++;
+    }
+    if (count) *count = j;
+    REQUIRE(j <= cap || (!values && !counts), "cap is smaller than the number of distinct values");
+  });
+}
+
 int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream) {
   return guarded([&] {
     REQUIRE(ctx && out, "ctx or out is NULL");
@@ -1196,6 +1446,8 @@ static void evaluate(const qaoa_problem *cprob, const qaoa_mixer *mix, int p, co
   qaoa_problem *prob = const_cast<qaoa_problem *>(cprob);
   if (mix->kind == 0) {
     evaluate_x(prob, p, angles, nsets, d_psi0, precision, grad, out_expect, out_grad, d_state, st);
+  } else if (mix->kind == 2) {
+    evaluate_grover(prob, p, angles, nsets, d_psi0, precision, grad, out_expect, out_grad, d_state, st);
   } else {
     CliqueEval ev;
     ev.table = prob->table;
@@ -1288,8 +1540,30 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
         if (grad) std::memcpy(out_grad + ((size_t)i * n_sets + s) * g2p, r + 1, g2p * sizeof(double));
       }
   }
+  // Grover-mixer problems: every (problem, set) pair in one launch
+  std::vector<GroverItem> gitems;
+  std::vector<int> gprobs;
+  for (int i = 0; i < n_probs; i++) {
+    if (mixers[i]->kind != 2) continue;
+    qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
+    ensure_counts(pr, st);
+    for (int s = 0; s < n_sets; s++) gitems.push_back(grover_item(pr, s, (int)gprobs.size() * n_sets + s));
+    gprobs.push_back(i);
+  }
+  if (!gitems.empty()) {
+    std::vector<double> hout((size_t)gprobs.size() * n_sets * (1 + g2p));
+    run_grover(gitems, angles, n_sets, p, grad, hout.data(), ctx, st);
+    for (size_t j = 0; j < gprobs.size(); j++)
+      for (int s = 0; s < n_sets; s++) {
+        const double *r = hout.data() + ((size_t)j * n_sets + s) * (1 + g2p);
+        int i = gprobs[j];
+        out_expect[(size_t)i * n_sets + s] = r[0];
+        if (grad) std::memcpy(out_grad + ((size_t)i * n_sets + s) * g2p, r + 1, g2p * sizeof(double));
+      }
+  }
   for (int i = 0; i < n_probs; i++) {
     if (mixers[i]->kind == 0 && small_path(probs[i], precision)) continue;
+    if (mixers[i]->kind == 2) continue;
     evaluate(probs[i], mixers[i], p, angles, n_sets, nullptr, precision, grad,
              out_expect + (size_t)i * n_sets, grad ? out_grad + (size_t)i * n_sets * g2p : nullptr,
              nullptr, st);

@@ -1,0 +1,322 @@
+// Grover mixer (Golden et al., JuliQAOA, SC-W 2023, Sec. 2.4): H_M = |psi0><psi0|, psi0 the
+// equal superposition over the feasible states. Every state of equal cost keeps an equal
+// amplitude under the rounds of Eq. (1), so a whole evaluation runs on the distinct cost
+// values c weighted by their degeneracies m_c (how many feasible states have cost c):
+//
+//   a_c <- e^{-i gamma c} a_c;   s = sum_c m_c a_c / sqrt(M);   a_c <- a_c + (e^{-i beta} - 1) s / sqrt(M)
+//
+// (M = number of feasible states, psi(x) = a_{C(x)}). The degeneracies are the data-parallel
+// part: a histogram of a stored table, or, for MaxCut, a table-free count over all states
+// (Gray-code order: consecutive states differ in one qubit, so the cut changes by the weights
+// of that qubit's edges) or over the weight-k states (Gosper's order, Sec. 2.4).
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "qaoa_internal.h"
+
+namespace qaoa {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum over a 256-thread block (all threads get the result); red holds 8 doubles.
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+struct Z {
+  double re, im;
+};
+__device__ __forceinline__ Z zmul(Z a, Z b) { return Z{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- degeneracies
+
+// counts[t[x]] += 1 over a stored table (block histogram in LDS, then 64-bit global adds).
+template <typename TT>
+__global__ __launch_bounds__(256) void k_hist_table(const TT *__restrict__ t, uint64_t N, int nbins,
+                                                    unsigned long long *__restrict__ counts) {
+  extern __shared__ unsigned int hs[];
+  for (int b = threadIdx.x; b < nbins; b += 256) hs[b] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride) atomicAdd(&hs[t[x]], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += 256)
+    if (hs[b]) atomicAdd(&counts[b], (unsigned long long)hs[b]);
+}
+
+// Full space, MaxCut: thread g walks the 2^lo states whose high bits are base + g, in Gray-code
+// order. Adjacency (CSR over vertices) and the histogram live in LDS; with PRIV, each thread
+// owns a column of the histogram (no atomics).
+template <bool PRIV>
+__global__ __launch_bounds__(256) void k_enum_full(int n, int m, const int32_t *__restrict__ eu,
+                                                   const int32_t *__restrict__ ev, const int32_t *__restrict__ ew,
+                                                   const int32_t *__restrict__ adj_off,
+                                                   const int32_t *__restrict__ adj, int lo, uint64_t base,
+                                                   uint64_t nthreads, int nbins,
+                                                   unsigned long long *__restrict__ counts) {
+  extern __shared__ unsigned int smem_u[];
+  unsigned int *hist = smem_u;                         // PRIV: [nbins][256], else [nbins]
+  const int hsz = PRIV ? nbins * 256 : nbins;
+  int32_t *s_off = (int32_t *)(hist + hsz);            // [n + 1]
+  int32_t *s_adj = s_off + (n + 1);                    // [2m]: neighbour << 16 | weight
+  for (int i = threadIdx.x; i < hsz; i += 256) hist[i] = 0;
+  for (int i = threadIdx.x; i <= n; i += 256) s_off[i] = adj_off[i];
+  for (int i = threadIdx.x; i < 2 * m; i += 256) s_adj[i] = adj[i];
+  __syncthreads();
+  const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g < nthreads) {
+    uint64_t x = (base + g) << lo;
+    int c = 0;
+    for (int e = 0; e < m; e++) c += ew[e] * (int)(((x >> eu[e]) ^ (x >> ev[e])) & 1ull);
+    auto bump = [&](int v) {
+      if (PRIV) hist[v * 256 + threadIdx.x] += 1u;
+      else atomicAdd(&hist[v], 1u);
+    };
+    bump(c);
+    const uint64_t steps = 1ull << lo;
+    for (uint64_t i = 1; i < steps; i++) {
+      const int q = __builtin_ctzll(i);
+      const int xq = (int)((x >> q) & 1ull);
+      for (int j = s_off[q]; j < s_off[q + 1]; j++) {
+        const int a = s_adj[j];
+        const int vtx = a >> 16, wt = a & 0xffff;
+        // the edge is cut after the flip iff the endpoints agree before it
+        c += (xq == (int)((x >> vtx) & 1ull)) ? wt : -wt;
+      }
+      x ^= 1ull << q;
+      bump(c);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += 256) {
+    unsigned long long s = 0;
+    if (PRIV)
+      for (int t = 0; t < 256; t++) s += hist[b * 256 + ((t + b) & 255)];
+    else
+      s = hist[b];
+    if (s) atomicAdd(&counts[b], s);
+  }
+}
+
+// Weight-k states, MaxCut (n <= 32: binomials C(a, i) at binom[a * 33 + i]): thread g < nthreads
+// takes ranks [r0 + g * per, ...) of the weight-k integers in increasing order, unranks the
+// first one and steps with Gosper's hack.
+__global__ __launch_bounds__(256) void k_enum_hw(int n, int k, int m, const int32_t *__restrict__ eu,
+                                                 const int32_t *__restrict__ ev, const int32_t *__restrict__ ew,
+                                                 const int64_t *__restrict__ binom, uint64_t r0, uint64_t per,
+                                                 uint64_t total, uint64_t nthreads, int nbins,
+                                                 unsigned long long *__restrict__ counts) {
+  extern __shared__ unsigned int hist[];
+  for (int i = threadIdx.x; i < nbins; i += 256) hist[i] = 0;
+  __syncthreads();
+  const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t first = r0 + g * per;
+  if (g < nthreads && first < total) {
+    const uint64_t cnt = (total - first < per) ? total - first : per;
+    uint64_t rem = first, x = 0;
+    int a = n - 1;
+    for (int i = k; i >= 1; i--) {
+      while (a >= i && (uint64_t)binom[a * 33 + i] > rem) a--;
+      x |= 1ull << a;
+      rem -= (uint64_t)binom[a * 33 + i];
+      a--;
+    }
+    for (uint64_t s = 0; s < cnt; s++) {
+      int c = 0;
+      for (int e = 0; e < m; e++) c += ew[e] * (int)(((x >> eu[e]) ^ (x >> ev[e])) & 1ull);
+      atomicAdd(&hist[c], 1u);
+      if (k > 0) {  // next larger integer with the same number of ones
+        const uint64_t lowbit = x & (~x + 1ull);
+        const uint64_t r = x + lowbit;
+        x = (((r ^ x) >> 2) >> __builtin_ctzll(lowbit)) | r;
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += 256)
+    if (hist[b]) atomicAdd(&counts[b], (unsigned long long)hist[b]);
+}
+
+// ---------------------------------------------------------------- evaluation on the classes
+
+// One workgroup per item: FP64 rounds on the classes, <C> and (grad) the adjoint sweep.
+// Classes c = tid + 256 j, j < GROVER_CPT, held in registers.
+__global__ __launch_bounds__(256) void k_grover(const GroverItem *__restrict__ items, const double *__restrict__ angles,
+                                                int p, int grad, double *__restrict__ out) {
+  __shared__ double red[8];
+  const GroverItem it = items[blockIdx.x];
+  const int tid = threadIdx.x, D = it.nclass;
+  const double *ang = angles + (size_t)it.angle_set * 2 * p;
+  const double rM = 1.0 / sqrt(it.total);
+  double v[GROVER_CPT], mc[GROVER_CPT];
+  Z phi[GROVER_CPT], lam[GROVER_CPT];
+#pragma unroll
+  for (int j = 0; j < GROVER_CPT; j++) {
+    const int c = tid + 256 * j;
+    v[j] = c < D ? it.vals[c] : 0.0;
+    mc[j] = c < D ? it.counts[c] : 0.0;
+    phi[j] = Z{rM, 0.0};
+  }
+  // <psi0|u> = sum_c m_c u_c / sqrt(M)
+  auto overlap = [&](const Z *u) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int j = 0; j < GROVER_CPT; j++) {
+      sr += mc[j] * u[j].re;
+      si += mc[j] * u[j].im;
+    }
+    sr = block_sum(sr, red);
+    si = block_sum(si, red + 4);
+    return Z{sr * rM, si * rM};
+  };
+  auto phase = [&](Z *u, double gamma) {
+#pragma unroll
+    for (int j = 0; j < GROVER_CPT; j++) {
+      double s, c;
+      sincos(-gamma * v[j], &s, &c);
+      u[j] = zmul(u[j], Z{c, s});
+    }
+  };
+  auto mix = [&](Z *u, double beta, Z ov) {  // u += (e^{-i beta} - 1) <psi0|u> psi0
+    double s, c;
+    sincos(-beta, &s, &c);
+    const Z d = zmul(Z{c - 1.0, s}, ov);
+#pragma unroll
+    for (int j = 0; j < GROVER_CPT; j++) u[j] = Z{u[j].re + d.re * rM, u[j].im + d.im * rM};
+  };
+  for (int k = 0; k < p; k++) {
+    phase(phi, ang[p + k]);
+    mix(phi, ang[k], overlap(phi));
+  }
+  double e = 0.0, nr = 0.0;
+#pragma unroll
+  for (int j = 0; j < GROVER_CPT; j++) {
+    const double pr = mc[j] * (phi[j].re * phi[j].re + phi[j].im * phi[j].im);
+    e += pr * v[j];
+    nr += pr;
+  }
+  e = block_sum(e, red);
+  nr = block_sum(nr, red + 4);
+  double *o = out + (size_t)it.out_index * (1 + 2 * p);
+  if (tid == 0) o[0] = e / nr;
+  if (it.amp_out) {
+#pragma unroll
+    for (int j = 0; j < GROVER_CPT; j++) {
+      const int c = tid + 256 * j;
+      if (c < D) it.amp_out[c] = double2{phi[j].re, phi[j].im};
+    }
+  }
+  if (!grad) return;
+  // lambda = (C - c0) psi_p; then for k = p..1: g_beta = 2 Im <lam|H_G|phi>
+  // = 2 Im(conj(<psi0|lam>) <psi0|phi>), undo the mixer, g_gamma = 2 Im <lam|(C - c0)|phi>,
+  // undo the phase
+#pragma unroll
+  for (int j = 0; j < GROVER_CPT; j++) lam[j] = Z{(v[j] - it.c0) * phi[j].re, (v[j] - it.c0) * phi[j].im};
+  for (int k = p - 1; k >= 0; k--) {
+    const Z ol = overlap(lam), op = overlap(phi);
+    if (tid == 0) o[1 + k] = 2.0 * (ol.re * op.im - ol.im * op.re) / nr;
+    mix(phi, -ang[k], op);
+    mix(lam, -ang[k], ol);
+    double gg = 0.0;
+#pragma unroll
+    for (int j = 0; j < GROVER_CPT; j++) gg += mc[j] * (v[j] - it.c0) * (lam[j].re * phi[j].im - lam[j].im * phi[j].re);
+    gg = block_sum(gg, red);
+    if (tid == 0) o[1 + p + k] = 2.0 * gg / nr;
+    phase(phi, -ang[p + k]);
+    phase(lam, -ang[p + k]);
+  }
+}
+
+// psi(x) = amp[t[x]] for the state output (complex64 or complex128).
+template <typename TT, typename T2>
+__global__ void k_grover_expand(const TT *__restrict__ t, uint64_t N, const double2 *__restrict__ amp, T2 *out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += stride) {
+    const double2 a = amp[t[x]];
+    out[x] = T2{(decltype(T2::x))a.x, (decltype(T2::x))a.y};
+  }
+}
+
+// ---------------------------------------------------------------- launch wrappers
+
+static unsigned grid_of(uint64_t N) {
+  uint64_t g = (N + 255) / 256;
+  if (g > 65536) g = 65536;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_hist_table(const void *table, int tbytes, uint64_t N, int nbins, unsigned long long *counts,
+                             hipStream_t s) {
+  const size_t lds = (size_t)nbins * sizeof(unsigned int);
+  if (tbytes == 1)
+    k_hist_table<uint8_t><<<grid_of(N), 256, lds, s>>>((const uint8_t *)table, N, nbins, counts);
+  else
+    k_hist_table<uint16_t><<<grid_of(N), 256, lds, s>>>((const uint16_t *)table, N, nbins, counts);
+  return hipGetLastError();
+}
+
+size_t enum_full_lds(int n, int m, int nbins, bool priv) {
+  return (size_t)(priv ? nbins * 256 : nbins) * 4 + (size_t)(n + 1) * 4 + (size_t)2 * m * 4;
+}
+
+hipError_t launch_enum_full(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
+                            const int32_t *adj_off, const int32_t *adj, int lo, uint64_t base, uint64_t nthreads,
+                            int nbins, bool priv, unsigned long long *counts, hipStream_t s) {
+  const size_t lds = enum_full_lds(n, m, nbins, priv);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_enum_full<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_enum_full<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const unsigned blocks = (unsigned)((nthreads + 255) / 256);
+  if (priv)
+    k_enum_full<true><<<blocks, 256, lds, s>>>(n, m, eu, ev, ew, adj_off, adj, lo, base, nthreads, nbins, counts);
+  else
+    k_enum_full<false><<<blocks, 256, lds, s>>>(n, m, eu, ev, ew, adj_off, adj, lo, base, nthreads, nbins, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum_hw(int n, int k, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
+                          const int64_t *binom, uint64_t r0, uint64_t per, uint64_t total, uint64_t nthreads,
+                          int nbins, unsigned long long *counts, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nthreads + 255) / 256);
+  k_enum_hw<<<blocks, 256, (size_t)nbins * 4, s>>>(n, k, m, eu, ev, ew, binom, r0, per, total, nthreads, nbins,
+                                                   counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_grover(const GroverItem *items, int n_items, const double *angles, int p, int grad, double *out,
+                         hipStream_t s) {
+  k_grover<<<n_items, 256, 0, s>>>(items, angles, p, grad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grover_expand(const void *table, int tbytes, uint64_t N, const double2 *amp, void *out,
+                                int precision, hipStream_t s) {
+  if (precision == 0) {
+    if (tbytes == 1) k_grover_expand<uint8_t, float2><<<grid_of(N), 256, 0, s>>>((const uint8_t *)table, N, amp, (float2 *)out);
+    else k_grover_expand<uint16_t, float2><<<grid_of(N), 256, 0, s>>>((const uint16_t *)table, N, amp, (float2 *)out);
+  } else {
+    if (tbytes == 1) k_grover_expand<uint8_t, double2><<<grid_of(N), 256, 0, s>>>((const uint8_t *)table, N, amp, (double2 *)out);
+    else k_grover_expand<uint16_t, double2><<<grid_of(N), 256, 0, s>>>((const uint16_t *)table, N, amp, (double2 *)out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qaoa

@@ -107,6 +107,21 @@ struct SmallItem {
   int out_index;        // output row: out[out_index * (1 + 2p) + ...]
 };
 
+// Grover-mixer evaluation on the distinct cost values: one workgroup per item, classes held in
+// registers (GROVER_CPT per thread, at most 256 * GROVER_CPT classes).
+constexpr int GROVER_CPT = 8;
+constexpr int GROVER_MAX_CLASSES = 256 * GROVER_CPT;
+struct GroverItem {
+  const double *vals;    // class values (nclass)
+  const double *counts;  // degeneracy of each class (FP64, exact below 2^53)
+  int nclass;
+  int angle_set;         // row of the angle array
+  int out_index;         // output row: out[out_index * (1 + 2p) + ...]
+  double total;          // number of feasible states
+  double c0;             // centre of lambda = (C - c0) psi
+  double2 *amp_out;      // optional: final class amplitudes (nclass)
+};
+
 // ---------------------------------------------------------------- launch wrappers
 hipError_t launch_cost_table_full(int n, int m, const int32_t *du, const int32_t *dv,
                                   const int32_t *dw, void *table, int tbytes, hipStream_t s);
@@ -143,5 +158,19 @@ hipError_t launch_small(int precision, const SmallItem *items, int n_items, int 
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
                              double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
+// Grover path (qaoa_grover.hip)
+hipError_t launch_hist_table(const void *table, int tbytes, uint64_t N, int nbins, unsigned long long *counts,
+                             hipStream_t s);
+size_t enum_full_lds(int n, int m, int nbins, bool priv);
+hipError_t launch_enum_full(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
+                            const int32_t *adj_off, const int32_t *adj, int lo, uint64_t base, uint64_t nthreads,
+                            int nbins, bool priv, unsigned long long *counts, hipStream_t s);
+hipError_t launch_enum_hw(int n, int k, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
+                          const int64_t *binom, uint64_t r0, uint64_t per, uint64_t total, uint64_t nthreads,
+                          int nbins, unsigned long long *counts, hipStream_t s);
+hipError_t launch_grover(const GroverItem *items, int n_items, const double *angles, int p, int grad, double *out,
+                         hipStream_t s);
+hipError_t launch_grover_expand(const void *table, int tbytes, uint64_t N, const double2 *amp, void *out,
+                                int precision, hipStream_t s);
 
 }  // namespace qaoa
