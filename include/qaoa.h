@@ -199,7 +199,8 @@ int qaoa_expect_grad_batched(const qaoa_problem *const *probs, const qaoa_mixer 
  * table when the kernel reads it). Classes: QAOA_KC_FWD_PASS (tile pass over one vector),
  * QAOA_KC_REV_PASS (tile pass over the state and the adjoint vector), QAOA_KC_SMALL
  * (whole-state kernel), QAOA_KC_DENSE (constrained-mixer products), QAOA_KC_OTHER
- * (lookup tables, reductions), QAOA_KC_GROVER and QAOA_KC_COUNT_STATES (Grover mixer).
+ * (lookup tables, reductions), QAOA_KC_GROVER and QAOA_KC_COUNT_STATES (Grover mixer; the
+ * flops total of the latter counts states).
  * enable: 1 on, 0 off; enabling clears the totals. */
 #define QAOA_KC_FWD_PASS 0
 #define QAOA_KC_REV_PASS 1

@@ -1333,16 +1333,47 @@ int qaoa_cost_degeneracies(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, 
     HIPCHK(hipMemcpyAsync(d_bin, hb.data(), bytes_b, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(d_cnt, 0, (size_t)nbins * 8, st));
     const int32_t *eu = d_e, *ev = d_e + n_edges, *ew = d_e + 2 * n_edges;
+    // neighbour masks per (vertex, distinct edge weight), when there are at most 8 weights
+    std::vector<int32_t> wv;
+    for (int e = 0; e < n_edges; e++) {
+      const int32_t we = w ? w[e] : 1;
+      if (std::find(wv.begin(), wv.end(), we) == wv.end()) wv.push_back(we);
+    }
+    const int nw0 = (int)wv.size();
+    const bool use_masks = nw0 >= 1 && nw0 <= 8;
+    const int nw = nw0 <= 1 ? 1 : (nw0 <= 2 ? 2 : (nw0 <= 4 ? 4 : 8));  // padded class count
+    while ((int)wv.size() < nw) wv.push_back(0);
+    DevBuf dmask, dmdeg, dwv;
+    uint64_t *d_mask = nullptr;
+    int32_t *d_mdeg = nullptr, *d_wv = nullptr;
+    if (use_masks) {
+      std::vector<uint64_t> hm((size_t)n * nw, 0);
+      std::vector<int32_t> hd((size_t)n * nw, 0);
+      for (int e = 0; e < n_edges; e++) {
+        const int32_t we = w ? w[e] : 1;
+        const int j = (int)(std::find(wv.begin(), wv.end(), we) - wv.begin());
+        hm[(size_t)u[e] * nw + j] |= 1ull << v[e];
+        hm[(size_t)v[e] * nw + j] |= 1ull << u[e];
+        hd[(size_t)u[e] * nw + j]++;
+        hd[(size_t)v[e] * nw + j]++;
+      }
+      d_mask = (uint64_t *)dmask.get(hm.size() * 8);
+      d_mdeg = (int32_t *)dmdeg.get(hd.size() * 4);
+      d_wv = (int32_t *)dwv.get(wv.size() * 4);
+      HIPCHK(hipMemcpyAsync(d_mask, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(d_mdeg, hd.data(), hd.size() * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(d_wv, wv.data(), wv.size() * 4, hipMemcpyHostToDevice, st));
+    }
     // the count, in launches of at most 2^18 threads
     const uint64_t LAUNCH = 1ull << 18;
-    KTimer kt(ctx, st, QAOA_KC_COUNT_STATES, 0.0, 0.0);
+    KTimer kt(ctx, st, QAOA_KC_COUNT_STATES, 0.0, (double)N);  // "flops": states counted
     if (hamming_k < 0) {
       const int lo = std::max(0, std::min(24, n - 20));
       const uint64_t T = 1ull << (n - lo);
       const bool priv = nbins <= 64;
       for (uint64_t b0 = 0; b0 < T; b0 += LAUNCH)
-        HIPCHK(launch_enum_full(n, n_edges, eu, ev, ew, d_off, d_adj, lo, b0, std::min(LAUNCH, T - b0), nbins, priv,
-                                d_cnt, st));
+        HIPCHK(launch_enum_full(n, n_edges, eu, ev, ew, d_off, d_adj, d_mask, d_mdeg, d_wv, nw, lo, b0,
+                                std::min(LAUNCH, T - b0), nbins, priv, d_cnt, st));
     } else {
       const uint64_t T = std::min<uint64_t>(N, 1ull << 20);
       const uint64_t per = (N + T - 1) / T;

@@ -56,23 +56,32 @@ __global__ __launch_bounds__(256) void k_hist_table(const TT *__restrict__ t, ui
 }
 
 // Full space, MaxCut: thread g walks the 2^lo states whose high bits are base + g, in Gray-code
-// order. Adjacency (CSR over vertices) and the histogram live in LDS; with PRIV, each thread
-// owns a column of the histogram (no atomics).
-template <bool PRIV>
+// order. Step i flips qubit q = ctz(i), the same qubit in every lane, so q's edges are
+// wave-uniform data. With NW > 0 they are neighbour bitmasks, one per distinct edge weight w_j
+// (masks[q * NW + j], classes beyond the graph's padded with empty masks), and the cut changes
+// by (x_q ? -1 : 1) sum_j w_j (deg_j(q) - 2 popcount(mask_j(q) & x)) (an edge of q is cut after
+// the flip iff its endpoints agree before it). The walk is unrolled by 16: within a block of
+// 16 steps the first 15 flip qubits 0..3, whose masks are loaded once; only every 16th step
+// reads the masks of a higher qubit. With NW == 0, q's adjacency list (neighbour << 16 |
+// weight, CSR) is walked instead. The histogram lives in LDS; with PRIV each thread owns a
+// column of it.
+template <int NW>
+struct QMasks {
+  uint64_t mk[NW > 0 ? NW : 1];
+  int dg[NW > 0 ? NW : 1];
+};
+
+template <bool PRIV, int NW>
 __global__ __launch_bounds__(256) void k_enum_full(int n, int m, const int32_t *__restrict__ eu,
                                                    const int32_t *__restrict__ ev, const int32_t *__restrict__ ew,
-                                                   const int32_t *__restrict__ adj_off,
-                                                   const int32_t *__restrict__ adj, int lo, uint64_t base,
-                                                   uint64_t nthreads, int nbins,
-                                                   unsigned long long *__restrict__ counts) {
+                                                   const int32_t *__restrict__ adj_off, const int32_t *__restrict__ adj,
+                                                   const uint64_t *__restrict__ masks, const int32_t *__restrict__ mdeg,
+                                                   const int32_t *__restrict__ wvals, int lo, uint64_t base,
+                                                   uint64_t nthreads, int nbins, unsigned long long *__restrict__ counts) {
   extern __shared__ unsigned int smem_u[];
-  unsigned int *hist = smem_u;                         // PRIV: [nbins][256], else [nbins]
+  unsigned int *hist = smem_u;  // PRIV: [nbins][256], else [nbins]
   const int hsz = PRIV ? nbins * 256 : nbins;
-  int32_t *s_off = (int32_t *)(hist + hsz);            // [n + 1]
-  int32_t *s_adj = s_off + (n + 1);                    // [2m]: neighbour << 16 | weight
   for (int i = threadIdx.x; i < hsz; i += 256) hist[i] = 0;
-  for (int i = threadIdx.x; i <= n; i += 256) s_off[i] = adj_off[i];
-  for (int i = threadIdx.x; i < 2 * m; i += 256) s_adj[i] = adj[i];
   __syncthreads();
   const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (g < nthreads) {
@@ -80,22 +89,90 @@ __global__ __launch_bounds__(256) void k_enum_full(int n, int m, const int32_t *
     int c = 0;
     for (int e = 0; e < m; e++) c += ew[e] * (int)(((x >> eu[e]) ^ (x >> ev[e])) & 1ull);
     auto bump = [&](int v) {
-      if (PRIV) hist[v * 256 + threadIdx.x] += 1u;
+      if (PRIV) atomicAdd(&hist[v * 256 + threadIdx.x], 1u);  // private slot: no contention
       else atomicAdd(&hist[v], 1u);
     };
     bump(c);
     const uint64_t steps = 1ull << lo;
-    for (uint64_t i = 1; i < steps; i++) {
-      const int q = __builtin_ctzll(i);
-      const int xq = (int)((x >> q) & 1ull);
-      for (int j = s_off[q]; j < s_off[q + 1]; j++) {
-        const int a = s_adj[j];
-        const int vtx = a >> 16, wt = a & 0xffff;
-        // the edge is cut after the flip iff the endpoints agree before it
-        c += (xq == (int)((x >> vtx) & 1ull)) ? wt : -wt;
+    if constexpr (NW > 0) {
+      int w[NW];
+#pragma unroll
+      for (int j = 0; j < NW; j++) w[j] = wvals[j];
+      auto load = [&](int q) {
+        QMasks<NW> r;
+#pragma unroll
+        for (int j = 0; j < NW; j++) {
+          r.mk[j] = masks[q * NW + j];
+          r.dg[j] = mdeg[q * NW + j];
+        }
+        return r;
+      };
+      auto flip = [&](int q, const QMasks<NW> &Q) {
+        int t = 0;
+#pragma unroll
+        for (int j = 0; j < NW; j++)  // 24-bit products: weights <= 16383, |deg - 2 popcount| <= 64
+          t += __mul24(w[j], __mul24(-2, (int)__builtin_popcountll(Q.mk[j] & x)) + Q.dg[j]);
+        c += ((x >> q) & 1ull) ? -t : t;
+        x ^= 1ull << q;
+        bump(c);
+      };
+      if (lo >= 4) {
+        // Block b covers steps 16b + 1 .. 16b + 15 (qubits 0..3) and the step 16(b + 1). Before
+        // step 16b + r the low four bits of x are G(r - 1) ^ 8 beta, with G(r) = r ^ (r >> 1)
+        // the Gray code and beta = b & 1, and the bits above stay fixed: with H = x & ~15,
+        //   popcount(mask & x) = popcount(mask & H) + popcount(mask & low bits),
+        // so each flip adds s (A_q - 2 K) with A_q = sum_j w_j (deg_j(q) - 2 popcount(mask_j(q)
+        // & H)) per block and lane, and s = (x_q ? -1 : 1), K = sum_j w_j popcount(mask_j(q)
+        // & low bits) wave-uniform.
+        const QMasks<NW> Qs[4] = {load(0), load(1), load(2), load(3)};
+        const uint64_t blocks = steps >> 4;
+        for (uint64_t b = 0; b < blocks; b++) {
+          const uint32_t beta = (uint32_t)(b & 1ull);
+          const uint64_t H = x & ~15ull;
+          int A[4];
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            int a = 0;
+#pragma unroll
+            for (int j = 0; j < NW; j++)
+              a += __mul24(w[j], __mul24(-2, (int)__builtin_popcountll(Qs[q].mk[j] & H)) + Qs[q].dg[j]);
+            A[q] = a;
+          }
+#pragma unroll
+          for (int r = 1; r < 16; r++) {
+            const int q = __builtin_ctz(r);
+            const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (beta << 3);
+            int K = 0;
+#pragma unroll
+            for (int j = 0; j < NW; j++) K += w[j] * __builtin_popcount((uint32_t)Qs[q].mk[j] & low);
+            const int t = A[q] - 2 * K;
+            c += ((low >> q) & 1u) ? -t : t;
+            bump(c);
+          }
+          x = H | (uint64_t)(8u ^ (beta << 3));  // low bits G(15) ^ 8 beta
+          if (b + 1 < blocks) {
+            const int q = __builtin_ctzll((b + 1) << 4);
+            flip(q, load(q));
+          }
+        }
+      } else {
+        for (uint64_t i = 1; i < steps; i++) {
+          const int q = __builtin_ctzll(i);
+          flip(q, load(q));
+        }
       }
-      x ^= 1ull << q;
-      bump(c);
+    } else {
+      for (uint64_t i = 1; i < steps; i++) {
+        const int q = __builtin_ctzll(i);
+        const uint64_t d = ((x >> q) & 1ull) ? ~x : x;
+        for (int j = adj_off[q]; j < adj_off[q + 1]; j++) {
+          const int a = adj[j];
+          const int vtx = a >> 16, wt = a & 0xffff;
+          c += ((d >> vtx) & 1ull) ? -wt : wt;
+        }
+        x ^= 1ull << q;
+        bump(c);
+      }
     }
   }
   __syncthreads();
@@ -266,30 +343,42 @@ hipError_t launch_hist_table(const void *table, int tbytes, uint64_t N, int nbin
   return hipGetLastError();
 }
 
-size_t enum_full_lds(int n, int m, int nbins, bool priv) {
-  return (size_t)(priv ? nbins * 256 : nbins) * 4 + (size_t)(n + 1) * 4 + (size_t)2 * m * 4;
-}
+size_t enum_full_lds(int nbins, bool priv) { return (size_t)(priv ? nbins * 256 : nbins) * 4; }
 
-hipError_t launch_enum_full(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
-                            const int32_t *adj_off, const int32_t *adj, int lo, uint64_t base, uint64_t nthreads,
-                            int nbins, bool priv, unsigned long long *counts, hipStream_t s) {
-  const size_t lds = enum_full_lds(n, m, nbins, priv);
+template <bool P, int NW>
+static hipError_t enum_full_t(dim3 blocks, size_t lds, hipStream_t s, int n, int m, const int32_t *eu,
+                              const int32_t *ev, const int32_t *ew, const int32_t *adj_off, const int32_t *adj,
+                              const uint64_t *masks, const int32_t *mdeg, const int32_t *wvals, int lo, uint64_t base,
+                              uint64_t nthreads, int nbins, unsigned long long *counts) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_enum_full<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)k_enum_full<P, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_enum_full<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const unsigned blocks = (unsigned)((nthreads + 255) / 256);
-  if (priv)
-    k_enum_full<true><<<blocks, 256, lds, s>>>(n, m, eu, ev, ew, adj_off, adj, lo, base, nthreads, nbins, counts);
-  else
-    k_enum_full<false><<<blocks, 256, lds, s>>>(n, m, eu, ev, ew, adj_off, adj, lo, base, nthreads, nbins, counts);
+  k_enum_full<P, NW><<<blocks, 256, lds, s>>>(n, m, eu, ev, ew, adj_off, adj, masks, mdeg, wvals, lo, base, nthreads,
+                                              nbins, counts);
   return hipGetLastError();
+}
+
+hipError_t launch_enum_full(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
+                            const int32_t *adj_off, const int32_t *adj, const uint64_t *masks, const int32_t *mdeg,
+                            const int32_t *wvals, int nw, int lo, uint64_t base, uint64_t nthreads, int nbins,
+                            bool priv, unsigned long long *counts, hipStream_t s) {
+  const size_t lds = enum_full_lds(nbins, priv);
+  const dim3 blocks((unsigned)((nthreads + 255) / 256));
+  if (masks && nw != 1 && nw != 2 && nw != 4 && nw != 8) return hipErrorInvalidValue;
+  const int k = masks ? nw : 0;
+#define QAOA_ENUM_CASE(P, NW)                                                                                 \
+  if (priv == P && k == NW)                                                                                    \
+    return enum_full_t<P, NW>(blocks, lds, s, n, m, eu, ev, ew, adj_off, adj, masks, mdeg, wvals, lo, base, nthreads, \
+                              nbins, counts);
+  QAOA_ENUM_CASE(true, 0) QAOA_ENUM_CASE(true, 1) QAOA_ENUM_CASE(true, 2) QAOA_ENUM_CASE(true, 4)
+  QAOA_ENUM_CASE(true, 8) QAOA_ENUM_CASE(false, 0) QAOA_ENUM_CASE(false, 1) QAOA_ENUM_CASE(false, 2)
+  QAOA_ENUM_CASE(false, 4) QAOA_ENUM_CASE(false, 8)
+#undef QAOA_ENUM_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_enum_hw(int n, int k, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,

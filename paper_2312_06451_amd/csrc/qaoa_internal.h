@@ -161,10 +161,14 @@ size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
 // Grover path (qaoa_grover.hip)
 hipError_t launch_hist_table(const void *table, int tbytes, uint64_t N, int nbins, unsigned long long *counts,
                              hipStream_t s);
-size_t enum_full_lds(int n, int m, int nbins, bool priv);
+size_t enum_full_lds(int nbins, bool priv);
+// masks == nullptr: adjacency-list walk; else nw (1, 2, 4 or 8) neighbour masks per vertex, one
+// per distinct edge weight wvals[j] (padding classes: empty mask, weight 0), and their popcounts
+// mdeg
 hipError_t launch_enum_full(int n, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
-                            const int32_t *adj_off, const int32_t *adj, int lo, uint64_t base, uint64_t nthreads,
-                            int nbins, bool priv, unsigned long long *counts, hipStream_t s);
+                            const int32_t *adj_off, const int32_t *adj, const uint64_t *masks, const int32_t *mdeg,
+                            const int32_t *wvals, int nw, int lo, uint64_t base, uint64_t nthreads, int nbins,
+                            bool priv, unsigned long long *counts, hipStream_t s);
 hipError_t launch_enum_hw(int n, int k, int m, const int32_t *eu, const int32_t *ev, const int32_t *ew,
                           const int64_t *binom, uint64_t r0, uint64_t per, uint64_t total, uint64_t nthreads,
                           int nbins, unsigned long long *counts, hipStream_t s);

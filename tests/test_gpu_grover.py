@@ -86,7 +86,8 @@ def test_grover_batched_with_other_mixers(q, ctx):
             assert abs(Eb[1, s] - e2) <= 1e-6 * abs(e2)
 
 
-@pytest.mark.parametrize("n,k,wr", [(20, -1, None), (18, -1, (1, 9)), (16, 7, None), (14, 6, (2, 5))])
+@pytest.mark.parametrize("n,k,wr", [(20, -1, None), (18, -1, (1, 9)), (16, 7, None), (14, 6, (2, 5)),
+                                    (24, -1, None), (26, -1, (1, 3)), (27, -1, (2, 2)), (25, -1, (1, 6))])
 def test_table_free_degeneracies(q, ctx, n, k, wr):
     g = workloads.erdos_renyi(n, 940 + n, 0.5, wr)
     Pd = q.Problem.degeneracies_of_graph(ctx, g, hamming_k=k)
@@ -99,7 +100,9 @@ def test_table_free_degeneracies(q, ctx, n, k, wr):
     for a in workloads.random_angles(5, 2, 950 + n):
         e1, g1 = q.expect_grad(Pd, M, a)
         e2, g2 = q.expect_grad(Pt, M, a)
-        assert abs(e1 - e2) <= 1e-12 * abs(e2) and np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g2))
+        # same classes, same FP64 rounds: agreement to rounding, on the scale of <C>
+        scale = max(abs(e2), np.max(np.abs(g2)))
+        assert abs(e1 - e2) <= 1e-12 * abs(e2) and np.max(np.abs(g1 - g2)) <= 1e-12 * scale
 
 
 def test_table_free_degeneracies_n34_moments(q, ctx):
