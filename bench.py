@@ -12,6 +12,9 @@ Other workloads (--workload):
   bisection_g16_k8_p6      clique mixer on Hamming weight 8 of 16 (12870 states), 512 angle
                            sets, p=6; one step is one batched call (512 evaluations)
   maxcut3reg_n32_p16       n=32, p=16 (32 GiB complex64 vectors)
+  grover_maxcut3reg_n40_p16  Grover mixer: one step = the table-free degeneracy count over all
+                           2^40 states plus one batched fwd+grad over 512 angle sets (p=16);
+                           value in states/s
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
@@ -37,6 +40,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_F16_PEAK_TFS = 2500.0
 FP32_VECTOR_PEAK_TFS = 157.3
+# 32-bit integer VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+INT32_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "fwd+grad QAOA evals/sec & HBM GB/s at n=28 p=8, FP32 vs FP64, err<=1e-5"
 
 
@@ -202,6 +207,107 @@ def roofline(prof, workload):
                  "frac": None, "traffic": None}, **base)
 
 
+def valu_per_state_from_profile(workload):
+    """VALU lane-instructions per counted state from the committed rocprofv3 SQ_INSTS_VALU
+    summary, valid only while the counting kernel's source is the one it was taken with."""
+    tpath = os.path.join(ROOT, "profiles", f"pmc_valu_k_enum_full_{workload}.md")
+    if not os.path.exists(tpath):
+        return None
+    txt = open(tpath).read()
+    src = os.path.join(ROOT, "paper_2312_06451_amd", "csrc", "qaoa_grover.hip")
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"kernel_source_sha256 = {cur}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("valu_lane_instructions_per_state = "):
+            return float(line.split("=")[1])
+    return None
+
+
+def main_grover(args, W, q, _lib, torch, np):
+    """Grover mixer: table-free degeneracy count + batched fwd+grad on the cost classes."""
+    import oracle
+    g = W.graphs[0]
+    n, p = g.n, W.p
+    steps = args.steps if args.steps is not None else 5
+    warmup = args.warmup
+    ctx = q.Context(0)
+    h = ctx.handle
+    M = q.Mixer.grover(ctx, n)
+    log(f"workload {W.name}: {W.description}")
+
+    def step():
+        P = q.Problem.degeneracies_of_graph(ctx, g)
+        E, G = q.expect_grad_batched([P], [M], W.angles)
+        vals, cnt = P.degeneracies()
+        P.close()
+        return E, G, vals, cnt
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.qaoa_profile_enable(h, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        E, G, vals, cnt = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {k: _lib.qaoa_profile_read(h, v) for k, v in _lib.KERNEL_CLASSES.items()}
+    _lib.qaoa_profile_enable(h, False)
+    N = 2 ** n
+    cs, gv = prof["count_states"], prof["grover"]
+    count_rate = cs["flops"] / (cs["ms"] * 1e-3)
+    eval_rate = gv["launches"] and W.angles.shape[0] * gv["launches"] / (gv["ms"] * 1e-3)
+    log(f"step {dt / steps * 1e3:.1f} ms; count {count_rate / 1e12:.3f} Tstates/s; class rounds {eval_rate:.0f} evals/s")
+    # exactness: over all 2^n strings the edges' cut indicators are pairwise independent fair
+    # bits, so sum m_c = 2^n, sum c m_c = W 2^(n-1), sum (2c - W)^2 m_c = 2^n sum w^2
+    c = [int(v) for v in vals]
+    m = [int(x) for x in cnt]
+    Wt = int(g.w.sum())
+    exact = (sum(m) == N and sum(ci * mi for ci, mi in zip(c, m)) == Wt * N // 2
+             and sum((2 * ci - Wt) ** 2 * mi for ci, mi in zip(c, m)) == N * int((g.w.astype(np.int64) ** 2).sum()))
+    vps = valu_per_state_from_profile(W.name)
+    roof = {"bound": "alu", "achieved": None if vps is None else round(count_rate * vps / 1e12, 2),
+            "peak": INT32_VALU_PEAK_TOPS, "unit": "Tops/s (32-bit VALU lane-instructions)",
+            "frac": None if vps is None else round(count_rate * vps / 1e12 / INT32_VALU_PEAK_TOPS, 4),
+            "traffic": None, "kernel": "k_enum_full (Gray-code walk, private LDS histogram)",
+            "class": "count_states", "launches": cs["launches"], "mean_ms": round(cs["ms"] / max(1, cs["launches"]), 3),
+            "states_per_launch": cs["flops"] / max(1, cs["launches"]), "valu_per_state": vps}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's table of a 3-regular graph on 28 vertices (same family, 2^28 states) and its
+        # histogram, scaled to states/s
+        gs = workloads_mod().workload("maxcut3reg_n28_p8").graphs[0]
+        t1 = time.perf_counter()
+        tab = oracle.graph_table(gs)
+        np.bincount(tab)
+        d1 = time.perf_counter() - t1
+        cpu = {"value": 2 ** 28 / d1, "unit": "states/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"degeneracies of a random 3-regular graph on 28 vertices: oracle table + histogram, "
+                         f"{d1:.1f} s"}
+    out = {
+        "metric": f"Grover-QAOA table-free degeneracy count + fwd+grad, states/sec ({W.name})",
+        "value": round(steps * N / dt, 1), "unit": "states/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(dt / steps * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 (count), f64 (class rounds)", "data": "synthetic",
+        "config": {"workload": W.name, "description": W.description, "n": n, "p": p,
+                   "angle_sets": int(W.angles.shape[0]), "mixer": "grover", "mode": "count + fwd+grad",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "path": {"count_states_per_s": count_rate, "classes": len(c), "grover_evals_per_s": eval_rate,
+                 "count_share_of_step": cs["ms"] / (dt * 1e3)},
+        "error": {"degeneracy_identities_exact": bool(exact),
+                  "reference": "sum, mean and variance identities of the MaxCut cost over all 2^n states"},
+        "cpu_baseline": cpu, "kernels": prof,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def workloads_mod():
+    import workloads
+    return workloads
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +330,8 @@ def main():
     from paper_2312_06451_amd import _lib
 
     W = workloads.workload(args.workload)
+    if W.mixer == "grover":
+        return main_grover(args, W, q, _lib, torch, np)
     steps = args.steps if args.steps is not None else {"maxcut3reg_n10_p3": 200, "maxcut3reg_n32_p16": 2}.get(W.name, 20)
     warmup = min(args.warmup, 1) if W.name == "maxcut3reg_n32_p16" else args.warmup
     grad = W.name != "maxcut3reg_n10_p3"

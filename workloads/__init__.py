@@ -120,7 +120,7 @@ class Workload:
     graphs: List[Graph]
     p: int
     angles: np.ndarray             # [n_sets, 2p]
-    mixer: str = "x"               # "x" (transverse field) or "clique"
+    mixer: str = "x"               # "x" (transverse field), "clique" or "grover"
     hamming_k: int = -1            # feasible subspace weight, -1 = all 2^n states
     extra: dict = field(default_factory=dict)
 
@@ -154,6 +154,11 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
         ns = 512 if n_sets is None else n_sets
         return Workload(name, "max-bisection G(16,1/2) on Hamming weight 8, clique mixer, p=6, 512 sets",
                         [g], 6, random_angles(6, ns, 4017), mixer="clique", hamming_k=8)
+    if name == "grover_maxcut3reg_n40_p16":
+        g, _ = _maxcut_3reg(40, 16, 6040)
+        ns = 512 if n_sets is None else n_sets
+        return Workload(name, "MaxCut, random 3-regular n=40, Grover mixer (table-free degeneracies), p=16, "
+                              "512 sets", [g], 16, random_angles(16, ns, 6041), mixer="grover")
     if name == "maxcut3reg_n32_p16":
         g, a = _maxcut_3reg(32, 16, 5032)
         return Workload(name, "MaxCut, random 3-regular n=32, X mixer, p=16, fwd+grad",
@@ -162,4 +167,4 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
 
 
 WORKLOADS = ["maxcut3reg_n10_p3", "maxcut3reg_n28_p8", "batched_er_n12to20_p10",
-             "bisection_g16_k8_p6", "maxcut3reg_n32_p16"]
+             "bisection_g16_k8_p6", "maxcut3reg_n32_p16", "grover_maxcut3reg_n40_p16"]
