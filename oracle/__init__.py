@@ -76,6 +76,8 @@ def lib():
         L.orc_qaoa_grad_m.argtypes = [i, i, i, i, f64p, f64p, vp, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), f64p]
         L.orc_apply_grover_mixer.argtypes = [ctypes.c_int64, ctypes.c_double, c128p]
+        L.orc_ring_neighbours.restype = ctypes.c_int64
+        L.orc_ring_neighbours.argtypes = [ctypes.c_int, ctypes.c_int, u64p, ctypes.c_int64, i64p]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_cost_values.restype = ctypes.c_int
         L.orc_cost_values.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, u64p, ctypes.c_int64, i64p]
@@ -148,36 +150,77 @@ def _check(n, k, angles, table):
     return angles, table, N, angles.size // 2
 
 
-def state(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False) -> np.ndarray:
+def _code(grover, ring):
+    return 1 if grover else (2 if ring else 0)
+
+
+def state(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False, ring: bool = False) -> np.ndarray:
     """psi_p of Eq. (1) (complex128, order of ``states``). Mixer: X (k < 0) or clique
-    (k >= 0); ``grover=True``: the Grover mixer on the same states (Sec. 2.4)."""
+    (k >= 0); ``grover=True``: the Grover mixer on the same states (Sec. 2.4); ``ring=True``:
+    the ring mixer on weight k."""
     angles, table, N, p = _check(n, k, angles, table)
     keep, ptr = _psi0_ptr(psi0, N)
     out = np.zeros(N, dtype=np.complex128)
-    if lib().orc_qaoa_state_m(n, k, int(grover), p, angles, table, ptr, out):
+    if lib().orc_qaoa_state_m(n, k, _code(grover, ring), p, angles, table, ptr, out):
         raise RuntimeError("oracle failed")
     return out
 
 
-def expect(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False):
+def expect(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False, ring: bool = False):
     """(E, Nrm): E = sum |psi_p|^2 C, Nrm = sum |psi_p|^2."""
     angles, table, N, p = _check(n, k, angles, table)
     keep, ptr = _psi0_ptr(psi0, N)
     E, Nr = ctypes.c_double(), ctypes.c_double()
-    if lib().orc_qaoa_expect_m(n, k, int(grover), p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr)):
+    if lib().orc_qaoa_expect_m(n, k, _code(grover, ring), p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr)):
         raise RuntimeError("oracle failed")
     return E.value, Nr.value
 
 
-def grad(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False):
+def grad(n: int, table, angles, k: int = -1, psi0=None, grover: bool = False, ring: bool = False):
     """(E, Nrm, g) with g = [d/dbeta_1..p, d/dgamma_1..p] from the adjoint recursion."""
     angles, table, N, p = _check(n, k, angles, table)
     keep, ptr = _psi0_ptr(psi0, N)
     E, Nr = ctypes.c_double(), ctypes.c_double()
     g = np.zeros(2 * p, dtype=np.float64)
-    if lib().orc_qaoa_grad_m(n, k, int(grover), p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr), g):
+    if lib().orc_qaoa_grad_m(n, k, _code(grover, ring), p, angles, table, ptr, ctypes.byref(E), ctypes.byref(Nr), g):
         raise RuntimeError("oracle failed")
     return E.value, Nr.value, g
+
+
+def dense_mixer_grad(table, angles, H, psi0=None):
+    """Eq. (1) with a mixer given as a real symmetric matrix H on the feasible states
+    (Sec. 2.1: any mixer can be handed over as a matrix): each round psi <- expm(-i b H)
+    (e^{-i g C} psi), expm by scipy; <C> and the adjoint gradient as in the C oracle, in plain
+    dense FP64 linear algebra. Returns (E, Nrm, g)."""
+    import scipy.linalg
+    angles = np.asarray(angles, dtype=np.float64)
+    C = np.asarray(table, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    N, p = C.size, angles.size // 2
+    psi = np.full(N, 1 / np.sqrt(N), dtype=np.complex128) if psi0 is None else np.array(psi0, dtype=np.complex128)
+    U = [scipy.linalg.expm(-1j * angles[r] * H) for r in range(p)]
+    for r in range(p):
+        psi = U[r] @ (np.exp(-1j * angles[p + r] * C) * psi)
+    pr = np.abs(psi) ** 2
+    E, Nr = float(np.sum(pr * C)), float(np.sum(pr))
+    phi, lam = psi.copy(), C * psi
+    g = np.zeros(2 * p)
+    for r in range(p - 1, -1, -1):
+        g[r] = 2 * np.imag(np.vdot(lam, H @ phi))
+        phi, lam = U[r].conj().T @ phi, U[r].conj().T @ lam
+        g[p + r] = 2 * np.imag(np.vdot(lam, C * phi))
+        ph = np.exp(1j * angles[p + r] * C)
+        phi, lam = ph * phi, ph * lam
+    return E, Nr, g
+
+
+def ring_neighbours(n: int, k: int) -> np.ndarray:
+    """[C(n,k), ring edges] neighbour indices of the ring mixer on weight k (-1: no swap)."""
+    st = states(n, k)
+    deg = n if n >= 3 else (1 if n == 2 else 0)
+    nb = np.zeros(st.size * max(deg, 1), dtype=np.int64)
+    lib().orc_ring_neighbours(n, k, st, st.size, nb)
+    return nb.reshape(st.size, max(deg, 1))[:, :deg]
 
 
 def degeneracies(table):
@@ -186,7 +229,8 @@ def degeneracies(table):
     return vals, counts
 
 
-def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3, grover: bool = False) -> np.ndarray:
+def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3, grover: bool = False,
+            ring: bool = False) -> np.ndarray:
     """Central finite differences with one Richardson step (error O(h^4)), forward-only."""
     angles = np.asarray(angles, dtype=np.float64)
     g = np.zeros(angles.size)
@@ -194,7 +238,7 @@ def fd_grad(n: int, table, angles, k: int = -1, psi0=None, h: float = 1e-3, grov
         def f(d):
             a = angles.copy()
             a[j] += d
-            return expect(n, table, a, k, psi0, grover)[0]
+            return expect(n, table, a, k, psi0, grover, ring)[0]
         d1 = (f(h) - f(-h)) / (2 * h)
         d2 = (f(h / 2) - f(-h / 2)) / h
         g[j] = (4 * d2 - d1) / 3

@@ -17,6 +17,8 @@
  *     e^{-i b X_q} = cos b I - i sin b X_q (the factorisation behind Eq. (2));
  *   - H_M = |psi0><psi0| (Grover mixer, Sec. 2.4) with psi0 the equal superposition over S:
  *     e^{-i b H_M} = I + (e^{-i b} - 1)|psi0><psi0|, applied as psi += (e^{-i b} - 1) <psi0|psi> psi0;
+ *   - H_M = sum_i X_i X_{i+1} + Y_i Y_{i+1} (ring mixer, Sec. 2.1; i + 1 mod n) on weight k:
+ *     the same construction with only cyclically adjacent swaps;
  *   - H_M = sum_{i<j} X_i X_j + Y_i Y_j (clique mixer, Sec. 2.1) restricted to weight k: it
  *     maps |x> to 2|y> for every y obtained from x by moving one 1 to a 0 position;
  *     e^{-i b H_M} psi is formed by a scaled Taylor series of the sparse matrix;
@@ -207,21 +209,47 @@ int64_t orc_clique_neighbours(int n, int k, const uint64_t *st, int64_t N, int64
     return deg;
 }
 
-/* out <- H_clique psi on the weight-k subspace: every single-swap neighbour contributes 2. */
+/* Neighbour lists of the ring mixer sum_i X_i X_{i+1} + Y_i Y_{i+1} (i + 1 taken mod n, so the
+ * ring closes for n >= 3) on weight-k strings: nb[r*deg + e] = index of the state reached from
+ * st[r] by swapping the bits of ring edge e, or -1 when they are equal (deg = ring edges). */
+int64_t orc_ring_neighbours(int n, int k, const uint64_t *st, int64_t N, int64_t *nb) {
+    (void)k;
+    int deg = n >= 3 ? n : (n == 2 ? 1 : 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < N; r++) {
+        uint64_t x = st[r];
+        for (int e = 0; e < deg; e++) {
+            int a = e, b = (e + 1) % n;
+            if (((x >> a) & 1u) == ((x >> b) & 1u)) { nb[r * deg + e] = -1; continue; }
+            nb[r * deg + e] = find_state(st, N, x ^ (1ull << a) ^ (1ull << b));
+        }
+    }
+    return deg;
+}
+
+/* out <- H psi for a swap mixer on the weight-k subspace: every neighbour (nb >= 0)
+ * contributes 2. */
 static void clique_matvec(int64_t N, int deg, const int64_t *nb, const cplx *psi, cplx *out) {
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < N; r++) {
         cplx acc = 0;
-        for (int j = 0; j < deg; j++) acc += 2.0 * psi[nb[r * deg + j]];
+        for (int j = 0; j < deg; j++)
+            if (nb[r * deg + j] >= 0) acc += 2.0 * psi[nb[r * deg + j]];
         out[r] = acc;
     }
 }
 
-/* psi <- e^{-i beta H_clique} psi by a scaled Taylor series: s steps with
- * |beta| * ||H||_1 / s <= 1 (||H||_1 = 2 k (n-k)), each step summing terms until they fall
- * below 1e-18 relative (at most 60 terms). */
+/* psi <- e^{-i beta H} psi for a swap mixer given by its neighbour lists (deg per state) by
+ * a scaled Taylor series: s steps with |beta| * ||H||_1 / s <= 1 (||H||_1 <= 2 deg), each
+ * step summing terms until they fall below 1e-18 relative (at most 60 terms). */
+void orc_apply_swap_mixer(int deg, const int64_t *nb, int64_t N, double beta, cplx *psi);
+
+/* psi <- e^{-i beta H_clique} psi (deg = k (n - k) neighbours per state). */
 void orc_apply_clique_mixer(int n, int k, const int64_t *nb, int64_t N, double beta, cplx *psi) {
-    int deg = k * (n - k);
+    orc_apply_swap_mixer(k * (n - k), nb, N, beta, psi);
+}
+
+void orc_apply_swap_mixer(int deg, const int64_t *nb, int64_t N, double beta, cplx *psi) {
     double norm1 = 2.0 * deg;
     int steps = (int)ceil(fabs(beta) * norm1);
     if (steps < 1) steps = 1;
@@ -281,21 +309,24 @@ static double im_inner_c(int64_t N, const double *cost, const cplx *a, const cpl
 
 typedef struct {
     int n, k;              /* k < 0: all 2^n states; else the weight-k states */
-    int grover;            /* 1: Grover mixer on those states; 0: X mixer (k < 0) or clique */
+    int grover;            /* 1: Grover mixer on those states; 0: X mixer (k < 0) or a swap
+                              mixer (k >= 0: clique, or ring when ring = 1) */
+    int ring;
     int64_t N;
-    const int64_t *nb;     /* clique neighbour lists (NULL otherwise) */
+    int deg;               /* swap mixer: neighbour slots per state */
+    const int64_t *nb;     /* swap mixer neighbour lists (NULL otherwise) */
 } mixer_t;
 
 static void apply_mixer(const mixer_t *m, double beta, cplx *psi) {
     if (m->grover) orc_apply_grover_mixer(m->N, beta, psi);
     else if (m->k < 0) orc_apply_x_mixer(m->n, beta, psi);
-    else orc_apply_clique_mixer(m->n, m->k, m->nb, m->N, beta, psi);
+    else orc_apply_swap_mixer(m->deg, m->nb, m->N, beta, psi);
 }
 
 static void apply_mixer_sum(const mixer_t *m, const cplx *psi, cplx *out) {
     if (m->grover) grover_sum(m->N, psi, out);
     else if (m->k < 0) orc_apply_x_sum(m->n, psi, out);
-    else clique_matvec(m->N, m->k * (m->n - m->k), m->nb, psi, out);
+    else clique_matvec(m->N, m->deg, m->nb, psi, out);
 }
 
 /* Initial state: psi0 if given, else the uniform superposition over S (Sec. 3: the default
@@ -315,24 +346,27 @@ static void evolve(const mixer_t *m, int p, const double *angles, const double *
     }
 }
 
-static int make_mixer(int n, int k, int grover, mixer_t *m, int64_t **nb_store) {
-    m->n = n; m->k = k; m->grover = grover; m->nb = NULL; *nb_store = NULL;
-    if (k < 0) { m->N = 1ll << n; return 0; }
+/* mixer code: 0 = X (k < 0) or clique (k >= 0); 1 = Grover; 2 = ring (k >= 0) */
+static int make_mixer(int n, int k, int code, mixer_t *m, int64_t **nb_store) {
+    m->n = n; m->k = k; m->grover = code == 1; m->ring = code == 2; m->nb = NULL; m->deg = 0; *nb_store = NULL;
+    if (k < 0) { m->N = 1ll << n; return code == 2 ? -1 : 0; }
     m->N = orc_binom(n, k);
-    if (grover) return 0;
+    if (m->grover) return 0;
     uint64_t *st = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m->N);
-    int deg = k * (n - k);
+    int deg = m->ring ? (n >= 3 ? n : (n == 2 ? 1 : 0)) : k * (n - k);
+    m->deg = deg;
     int64_t *nb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m->N * (deg > 0 ? deg : 1)));
     if (!st || !nb) { free(st); free(nb); return -1; }
     orc_states(n, k, st);
-    orc_clique_neighbours(n, k, st, m->N, nb);
+    if (m->ring) orc_ring_neighbours(n, k, st, m->N, nb);
+    else orc_clique_neighbours(n, k, st, m->N, nb);
     free(st);
     m->nb = nb; *nb_store = nb;
     return 0;
 }
 
 /* Final state psi_p of Eq. (1). k < 0: X mixer; k >= 0: clique mixer on weight k. */
-/* mixer: 0 = X (k < 0) or clique (k >= 0); 1 = Grover on the feasible set. */
+/* mixer: 0 = X (k < 0) or clique (k >= 0); 1 = Grover on the feasible set; 2 = ring (k >= 0). */
 int orc_qaoa_state_m(int n, int k, int mixer, int p, const double *angles, const double *cost,
                      const cplx *psi0, cplx *psi_out) {
     mixer_t m; int64_t *nb;

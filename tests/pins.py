@@ -91,3 +91,12 @@ def johnson_spectrum(n, k):
         mult = comb(n, j) - (comb(n, j - 1) if j > 0 else 0)
         out += [lam] * mult
     return np.sort(np.array(out, dtype=np.float64))
+
+
+def dense_ring_hamiltonian(n):
+    """sum_i X_i X_{i+1} + Y_i Y_{i+1} with i + 1 mod n (one edge for n = 2)."""
+    H = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    edges = [(i, (i + 1) % n) for i in range(n)] if n >= 3 else [(0, 1)]
+    for i, j in edges:
+        H += _op_on(n, {i: X, j: X}) + _op_on(n, {i: Y, j: Y})
+    return H

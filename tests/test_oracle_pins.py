@@ -398,3 +398,50 @@ def test_grover_gradient_matches_finite_differences():
         E, Nr, gr = oracle.grad(n, t, a, k=k, grover=True)
         fd = oracle.fd_grad(n, t, a, k=k, grover=True)
         assert np.max(np.abs(gr - fd)) < 1e-9 * max(1, np.max(np.abs(gr)))
+
+
+# ---------------------------------------------------------------- ring mixer, matrix mixers
+
+@pytest.mark.parametrize("n,k", [(5, 2), (6, 3), (2, 1)])
+def test_ring_matrix_is_pauli_sum_restricted(n, k):
+    st = oracle.states(n, k).astype(np.int64)
+    Hd = pins.dense_ring_hamiltonian(n)[np.ix_(st, st)]
+    nb = oracle.ring_neighbours(n, k)
+    Hn = np.zeros((st.size, st.size))
+    for r in range(st.size):
+        for j in nb[r]:
+            if j >= 0:
+                Hn[j, r] += 2.0
+    assert np.max(np.abs(Hd - Hn)) == 0
+    # the Pauli sum never leaves weight k
+    full = pins.dense_ring_hamiltonian(n)
+    off = np.setdiff1d(np.arange(1 << n), st)
+    assert np.max(np.abs(full[np.ix_(off, st)])) == 0
+
+
+def test_ring_qaoa_matches_full_space_bruteforce():
+    n, k, p = 7, 3, 3
+    st = oracle.states(n, k).astype(np.int64)
+    tfull = _real_table(1 << n, 350)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[st] = 1 / np.sqrt(st.size)
+    a = workloads.random_angles(p, 1, 351)[0]
+    want = pins.dense_evolve(pins.dense_ring_hamiltonian(n), tfull, a, psi0)
+    got = oracle.state(n, tfull[st], a, k=k, ring=True)
+    assert np.max(np.abs(want[st] - got)) < 1e-12
+
+
+def test_ring_gradient_and_dense_matrix_reference():
+    n, k, p = 8, 4, 2
+    st = oracle.states(n, k).astype(np.int64)
+    t = _real_table(st.size, 360, distinct=30)
+    a = workloads.random_angles(p, 1, 361)[0]
+    E, N, gr = oracle.grad(n, t, a, k=k, ring=True)
+    assert np.max(np.abs(gr - oracle.fd_grad(n, t, a, k=k, ring=True))) < 1e-9 * max(1, np.max(np.abs(gr)))
+    # the dense-matrix reference (scipy expm on the restricted matrix) agrees with the C
+    # oracle's sparse Taylor path, for the ring and the clique mixer
+    for H, kw in ((pins.dense_ring_hamiltonian(n), {"ring": True}), (pins.dense_clique_hamiltonian(n), {})):
+        Hr = np.real(H[np.ix_(st, st)])
+        E0, N0, g0 = oracle.grad(n, t, a, k=k, **kw)
+        E1, N1, g1 = oracle.dense_mixer_grad(t, a, Hr)
+        assert abs(E0 - E1) < 1e-12 * np.sum(np.abs(t)) and np.max(np.abs(g0 - g1)) < 1e-11 * max(1, np.max(np.abs(g0)))
