@@ -123,6 +123,21 @@ int qaoa_mixer_x(qaoa_ctx *ctx, int n, qaoa_mixer **out);
  * 2 <= n <= 20, 1 <= k <= n-1 and C(n,k) <= 16384. Synchronises `stream`. */
 int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream);
 
+/* Ring mixer H_M = sum_i X_i X_{i+1} + Y_i Y_{i+1} (Sec. 2.1; i + 1 taken mod n, so the ring
+ * closes for n >= 3) restricted to Hamming weight k: entry 2 between strings that differ by
+ * swapping the bits of one ring edge. Applied like the clique mixer (FP64 eigendecomposition
+ * once, V kept by the handle); same limits. Synchronises `stream`. */
+int qaoa_mixer_ring(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream);
+
+/* Mixer given as a matrix (Sec. 2.1: any mixer can be handed over as a matrix, and its
+ * eigendecomposition is computed and stored): host_matrix is an N x N real symmetric matrix
+ * (row i, column j at host_matrix[i * N + j]; symmetric to 1e-12 of its largest entry, else
+ * INVALID_ARG) over the feasible states in the basis order above, N = 2^n for hamming_k < 0
+ * or C(n, hamming_k) otherwise, N <= 16384, read during the call only. Applied like the clique
+ * mixer. Synchronises `stream`. */
+int qaoa_mixer_matrix(qaoa_ctx *ctx, int n, int hamming_k, const double *host_matrix, qaoa_mixer **out,
+                      void *stream);
+
 /* Grover mixer H_M = |psi0><psi0| (Sec. 2.4), psi0 the equal superposition over the feasible
  * states of an n-qubit problem (all 2^n for hamming_k < 0, else the weight-k states; the mixer
  * keeps the Hamming weight). 1 <= n <= 62. Evaluations with it use fair sampling (Sec. 2.4):

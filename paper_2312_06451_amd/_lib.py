@@ -25,7 +25,7 @@ EXPORTED = [
     "qaoa_mixer_destroy", "qaoa_expect", "qaoa_expect_grad", "qaoa_state", "qaoa_expect_batched",
     "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error", "qaoa_profile_enable",
     "qaoa_profile_read", "qaoa_problem_from_values", "qaoa_problem_copy_values", "qaoa_mixer_grover",
-    "qaoa_cost_degeneracies", "qaoa_problem_degeneracies",
+    "qaoa_cost_degeneracies", "qaoa_problem_degeneracies", "qaoa_mixer_ring", "qaoa_mixer_matrix",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
                   "count_states": 6}
@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
     L.qaoa_mixer_x.argtypes = [c_void_p, c_int, P(c_void_p)]
     L.qaoa_mixer_clique.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
     L.qaoa_mixer_grover.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
+    L.qaoa_mixer_ring.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
+    L.qaoa_mixer_matrix.argtypes = [c_void_p, c_int, c_int, P(c_double), P(c_void_p), c_void_p]
     L.qaoa_cost_degeneracies.argtypes = [c_void_p, c_int, c_int, i32p, i32p, i32p, c_int, P(c_void_p), c_void_p]
     L.qaoa_problem_degeneracies.argtypes = [c_void_p, P(c_double), P(c_int64), c_size_t, P(c_size_t), c_void_p]
     L.qaoa_mixer_destroy.argtypes = [c_void_p]
@@ -174,6 +176,21 @@ def qaoa_problem_destroy(prob: int) -> None:
 def qaoa_mixer_x(ctx: int, n: int) -> int:
     out = c_void_p()
     check(lib().qaoa_mixer_x(ctx, n, ctypes.byref(out)), "qaoa_mixer_x")
+    return out.value
+
+
+def qaoa_mixer_ring(ctx: int, n: int, k: int, stream: int = 0) -> int:
+    out = c_void_p()
+    check(lib().qaoa_mixer_ring(ctx, n, k, ctypes.byref(out), stream), "qaoa_mixer_ring")
+    return out.value
+
+
+def qaoa_mixer_matrix(ctx: int, n: int, hamming_k: int, matrix, stream: int = 0) -> int:
+    import numpy as np
+    m = np.ascontiguousarray(matrix, dtype=np.float64)
+    out = c_void_p()
+    check(lib().qaoa_mixer_matrix(ctx, n, hamming_k, m.ctypes.data_as(P(c_double)), ctypes.byref(out), stream),
+          "qaoa_mixer_matrix")
     return out.value
 
 

@@ -118,6 +118,15 @@ class Mixer:
         return cls(ctx, _lib.qaoa_mixer_x(ctx.handle, n), "x", n)
 
     @classmethod
+    def ring(cls, ctx: Context, n: int, k: int, stream=None):
+        return cls(ctx, _lib.qaoa_mixer_ring(ctx.handle, n, k, _stream(stream)), "ring", n, k)
+
+    @classmethod
+    def matrix(cls, ctx: Context, n: int, H, hamming_k: int = -1, stream=None):
+        """Any real symmetric mixer matrix over the feasible states (eigendecomposed once)."""
+        return cls(ctx, _lib.qaoa_mixer_matrix(ctx.handle, n, hamming_k, H, _stream(stream)), "matrix", n, hamming_k)
+
+    @classmethod
     def grover(cls, ctx: Context, n: int, hamming_k: int = -1):
         return cls(ctx, _lib.qaoa_mixer_grover(ctx.handle, n, hamming_k), "grover", n, hamming_k)
 

@@ -1443,6 +1443,19 @@ int qaoa_problem_degeneracies(const qaoa_problem *cprob, double *values, int64_t
   });
 }
 
+static void eigen_mixer(qaoa_ctx *ctx, int kind, int n, int k, const double *host_matrix, qaoa_mixer **out,
+                        void *stream) {
+  DeviceGuard g(ctx->device);
+  auto m = std::make_unique<qaoa_mixer>();
+  m->ctx = ctx;
+  m->kind = 1;
+  m->n = n;
+  m->k = k < 0 ? -1 : k;
+  m->clique = clique_create(kind, n, m->k, host_matrix, (hipStream_t)stream);
+  *out = m.release();
+  ctx->live++;
+}
+
 int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream) {
   return guarded([&] {
     REQUIRE(ctx && out, "ctx or out is NULL");
@@ -1450,15 +1463,39 @@ int qaoa_mixer_clique(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *strea
     REQUIRE(n >= 2 && n <= 20, "n must be in [2, 20]");
     REQUIRE(k >= 1 && k <= n - 1, "k must be in [1, n-1]");
     REQUIRE(binom64(n, k) <= 16384, "C(n,k) must be <= 16384");
-    DeviceGuard g(ctx->device);
-    auto m = std::make_unique<qaoa_mixer>();
-    m->ctx = ctx;
-    m->kind = 1;
-    m->n = n;
-    m->k = k;
-    m->clique = clique_create(n, k, (hipStream_t)stream);
-    *out = m.release();
-    ctx->live++;
+    eigen_mixer(ctx, MIX_CLIQUE, n, k, nullptr, out, stream);
+  });
+}
+
+int qaoa_mixer_ring(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 2 && n <= 20, "n must be in [2, 20]");
+    REQUIRE(k >= 1 && k <= n - 1, "k must be in [1, n-1]");
+    REQUIRE(binom64(n, k) <= 16384, "C(n,k) must be <= 16384");
+    eigen_mixer(ctx, MIX_RING, n, k, nullptr, out, stream);
+  });
+}
+
+int qaoa_mixer_matrix(qaoa_ctx *ctx, int n, int hamming_k, const double *host_matrix, qaoa_mixer **out,
+                      void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out && host_matrix, "ctx, matrix or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 20, "n must be in [1, 20]");
+    REQUIRE(hamming_k <= n, "hamming_k must be <= n");
+    const int64_t N = hamming_k < 0 ? (int64_t(1) << n) : binom64(n, hamming_k);
+    REQUIRE(N >= 1 && N <= 16384, "the feasible set must have at most 16384 states");
+    double mx = 0.0;
+    for (int64_t i = 0; i < N * N; i++) {
+      REQUIRE(std::isfinite(host_matrix[i]), "matrix entries must be finite");
+      mx = std::max(mx, std::fabs(host_matrix[i]));
+    }
+    for (int64_t i = 0; i < N; i++)
+      for (int64_t j = 0; j < i; j++)
+        REQUIRE(std::fabs(host_matrix[i * N + j] - host_matrix[j * N + i]) <= 1e-12 * mx, "matrix is not symmetric");
+    eigen_mixer(ctx, MIX_MATRIX, n, hamming_k, host_matrix, out, stream);
   });
 }
 

@@ -28,7 +28,11 @@ struct CliqueEval {
   double c0;           // mean of C over the states
 };
 
-std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int n, int k, hipStream_t st);
+// kind: MIX_CLIQUE, MIX_RING (matrices built on the device over the weight-k states) or
+// MIX_MATRIX (host_matrix: N x N real symmetric, N = 2^n for k < 0 else C(n, k)).
+enum { MIX_CLIQUE = 0, MIX_RING = 1, MIX_MATRIX = 2 };
+std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, int k, const double *host_matrix,
+                                                                 hipStream_t st);
 void clique_evaluate(CliqueMixer &m, const CliqueEval &ev, int p, const double *angles, int nsets,
                      const void *d_psi0, int precision, int grad, double *out_expect,
                      double *out_grad, void *d_state, hipStream_t st);

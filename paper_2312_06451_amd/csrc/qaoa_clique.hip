@@ -1,8 +1,9 @@
-// Constrained QAOA with the clique mixer (Golden et al., JuliQAOA, SC-W 2023, Sec. 2.1-2.2).
-//
-// On the weight-k states (increasing integer order) the clique mixer sum_{i<j} X_iX_j + Y_iY_j
-// is a real symmetric matrix H with entry 2 between states that differ by moving one 1-bit.
-// It is diagonalised once in FP64 (H = V D V^T, rocSOLVER), and every round applies
+// Mixers applied through their eigendecomposition (Golden et al., JuliQAOA, SC-W 2023,
+// Sec. 2.1-2.2): the clique mixer sum_{i<j} X_iX_j + Y_iY_j, the ring mixer
+// sum_i X_iX_{i+1} + Y_iY_{i+1} (i + 1 mod n), or any real symmetric matrix handed over by the
+// caller. On the weight-k states (increasing integer order) the clique and ring mixers are
+// real symmetric matrices H with entry 2 between states that differ by one allowed swap.
+// H is diagonalised once in FP64 (H = V D V^T, rocSOLVER), and every round applies
 //     psi <- exp(-i gamma C) psi,   psi <- V exp(-i beta D) V^T psi,
 // i.e. two dense products per round, for all angle sets at once: the state of S angle sets is
 // an N x 2S real matrix (real and imaginary parts as separate columns).
@@ -153,8 +154,9 @@ __device__ uint64_t unrank_hw(int64_t r, int n, int k, const int64_t *binom) {
   return x;
 }
 
-// H[c, r] = 2 for every single-swap neighbour c of state r (H zeroed beforehand).
-__global__ void k_clique_matrix(int n, int k, int64_t N, const int64_t *__restrict__ binom,
+// H[c, r] = 2 for every swap neighbour c of state r (H zeroed beforehand): any 1-bit moved to
+// any 0-bit (clique), or only across the ring edges (i, i + 1 mod n) (ring).
+__global__ void k_clique_matrix(int n, int k, int ring, int64_t N, const int64_t *__restrict__ binom,
                                 double *__restrict__ H) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
@@ -163,6 +165,7 @@ __global__ void k_clique_matrix(int n, int k, int64_t N, const int64_t *__restri
     if (!((x >> a) & 1u)) continue;
     for (int b = 0; b < n; b++) {
       if ((x >> b) & 1u) continue;
+      if (ring && b != (a + 1) % n && a != (b + 1) % n) continue;
       const uint64_t y = x ^ (1ull << a) ^ (1ull << b);
       H[rank_hw(y, binom) + r * N] = 2.0;
     }
@@ -355,11 +358,12 @@ __global__ void k_export(const R *__restrict__ X, int64_t N, typename CT<R>::T2 
 
 // ---------------------------------------------------------------- setup
 
-std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int n, int k, hipStream_t st) {
+std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, int k, const double *host_matrix,
+                                                                 hipStream_t st) {
   std::unique_ptr<CliqueMixer, CliqueMixerDeleter> m(new CliqueMixer());
   m->n = n;
   m->k = k;
-  const int64_t N = binom64(n, k);
+  const int64_t N = k < 0 ? (int64_t(1) << n) : binom64(n, k);
   m->N = N;
   blaschk(rocblas_create_handle(&m->blas), "rocblas_create_handle");
   blaschk(rocblas_set_stream(m->blas, st), "rocblas_set_stream");
@@ -372,9 +376,13 @@ std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int n, int k, hip
   Buf dbin, E, info;
   int64_t *db = (int64_t *)dbin.get(hb.size() * sizeof(int64_t));
   hipchk(hipMemcpyAsync(db, hb.data(), hb.size() * sizeof(int64_t), hipMemcpyHostToDevice, st), "binom upload");
-  hipchk(hipMemsetAsync(H, 0, (size_t)N * N * sizeof(double), st), "clear H");
-  k_clique_matrix<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(n, k, N, db, H);
-  hipchk(hipGetLastError(), "k_clique_matrix");
+  if (kind == MIX_MATRIX) {
+    hipchk(hipMemcpyAsync(H, host_matrix, (size_t)N * N * sizeof(double), hipMemcpyHostToDevice, st), "matrix upload");
+  } else {
+    hipchk(hipMemsetAsync(H, 0, (size_t)N * N * sizeof(double), st), "clear H");
+    k_clique_matrix<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(n, k, kind == MIX_RING ? 1 : 0, N, db, H);
+    hipchk(hipGetLastError(), "k_clique_matrix");
+  }
   double *dE = (double *)E.get((size_t)N * sizeof(double));
   rocblas_int *dinfo = (rocblas_int *)info.get(sizeof(rocblas_int));
   blaschk(rocsolver_dsyevd(m->blas, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N, H,

@@ -1,0 +1,107 @@
+"""GPU parity of the ring mixer and of mixers handed over as matrices (Sec. 2.1: mixers applied
+through a stored eigendecomposition), against the FP64 oracle (sparse Taylor series for the
+ring, dense expm for matrices). Tolerances as for the clique mixer: FP32 form 1e-5, FP64 form
+1e-10 (relative to max|C| for <C>, to max|g| for the gradient)."""
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-5, 1: 1e-10}
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2312_06451_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def check(q, P, M, a, ref, scale_c):
+    E0, N0, g0 = ref
+    for prec in (0, 1):
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        assert abs(e - E0 / N0) <= TOL[prec] * scale_c, (prec, e, E0 / N0)
+        assert np.max(np.abs(gr - g0 / N0)) <= TOL[prec] * np.max(np.abs(g0 / N0)), (prec, gr, g0)
+
+
+@pytest.mark.parametrize("n,k,p", [(10, 5, 3), (12, 4, 2), (7, 3, 4)])
+def test_ring_vs_oracle(q, ctx, n, k, p):
+    g = workloads.erdos_renyi(n, 1000 + n, 0.5, (1, 3))
+    t = oracle.graph_table(g, k)
+    P, M = q.Problem.from_graph(ctx, g, hamming_k=k), q.Mixer.ring(ctx, n, k)
+    for a in workloads.random_angles(p, 2, 1010 + n):
+        check(q, P, M, a, oracle.grad(n, t, a, k=k, ring=True), np.max(t))
+
+
+def test_ring_full_size_bisection(q, ctx):
+    W = workloads.workload("bisection_g16_k8_p6", n_sets=2)
+    g = W.graphs[0]
+    t = oracle.graph_table(g, 8)
+    P, M = q.Problem.from_graph(ctx, g, hamming_k=8), q.Mixer.ring(ctx, 16, 8)
+    a = W.angles[0][np.r_[0:3, 6:9]]                 # p = 3 slice of the stored angle set
+    check(q, P, M, a, oracle.grad(16, t, a, k=8, ring=True), np.max(t))
+
+
+@pytest.mark.parametrize("n,k", [(8, 3), (7, -1)])
+def test_matrix_mixer_vs_dense_reference(q, ctx, n, k):
+    N = (1 << n) if k < 0 else comb(n, k)
+    rng = np.random.default_rng(1020 + n)
+    A = rng.normal(size=(N, N)) * (rng.random((N, N)) < 0.1)
+    H = A + A.T
+    vals = rng.normal(1.0, 2.0, 30)[rng.integers(0, 30, N)]
+    P, M = q.Problem.from_values(ctx, n, vals, hamming_k=k), q.Mixer.matrix(ctx, n, H, hamming_k=k)
+    for a in workloads.random_angles(3, 2, 1030 + n):
+        check(q, P, M, a, oracle.dense_mixer_grad(vals, a, H), np.max(np.abs(vals)))
+
+
+def test_matrix_equal_to_clique_matches_clique(q, ctx):
+    n, k = 9, 4
+    st = oracle.states(n, k).astype(np.int64)
+    H = np.real(pins.dense_clique_hamiltonian(n)[np.ix_(st, st)])
+    g = workloads.erdos_renyi(n, 1040, 0.5)
+    P = q.Problem.from_graph(ctx, g, hamming_k=k)
+    Mc, Mm = q.Mixer.clique(ctx, n, k), q.Mixer.matrix(ctx, n, H, hamming_k=k)
+    for a in workloads.random_angles(3, 2, 1041):
+        for prec in (0, 1):
+            e1, g1 = q.expect_grad(P, Mc, a, precision=prec)
+            e2, g2 = q.expect_grad(P, Mm, a, precision=prec)
+            assert abs(e1 - e2) <= TOL[prec] * abs(e1) and np.max(np.abs(g1 - g2)) <= TOL[prec] * np.max(np.abs(g1))
+
+
+def test_batched_mixture_of_mixers(q, ctx):
+    n, k = 10, 4
+    g = workloads.erdos_renyi(n, 1050, 0.5)
+    Pk, Pf = q.Problem.from_graph(ctx, g, hamming_k=k), q.Problem.from_graph(ctx, g)
+    probs = [Pk, Pk, Pf, Pf]
+    mixers = [q.Mixer.ring(ctx, n, k), q.Mixer.grover(ctx, n, k), q.Mixer.x(ctx, n), q.Mixer.grover(ctx, n)]
+    angles = workloads.random_angles(3, 4, 1051)
+    for prec in (0, 1):
+        Eb, Gb = q.expect_grad_batched(probs, mixers, angles, precision=prec)
+        for i in range(4):
+            for s in range(4):
+                e, gr = q.expect_grad(probs[i], mixers[i], angles[s], precision=prec)
+                assert abs(Eb[i, s] - e) <= 1e-6 * abs(e) and np.max(np.abs(Gb[i, s] - gr)) <= 1e-6 * np.max(np.abs(gr))
+
+
+def test_matrix_mixer_errors(q, ctx):
+    from paper_2312_06451_amd import _lib
+    rng = np.random.default_rng(1060)
+    H = rng.normal(size=(35, 35))
+    with pytest.raises(q.QAOAError) as ei:
+        q.Mixer.matrix(ctx, 7, H, hamming_k=3)                 # not symmetric
+    assert ei.value.status == _lib.QAOA_ERR_INVALID_ARG
+    with pytest.raises(q.QAOAError) as ei:
+        q.Mixer.matrix(ctx, 15, np.zeros((2, 2)))             # 2^15 states: too many (checked before reading)
+    assert ei.value.status == _lib.QAOA_ERR_INVALID_ARG
