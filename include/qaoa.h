@@ -138,6 +138,20 @@ int qaoa_mixer_ring(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream)
 int qaoa_mixer_matrix(qaoa_ctx *ctx, int n, int hamming_k, const double *host_matrix, qaoa_mixer **out,
                       void *stream);
 
+/* Stored eigendecomposition of a clique, ring or matrix mixer (Sec. 2.1: the decomposition
+ * is computed once and stored for re-use): copies the FP64 eigenvectors (column j, the j-th
+ * eigenvector, at host_V[j * N .. j * N + N)) and eigenvalues host_D[0..N) to the host. N must
+ * equal the mixer's state count. QAOA_ERR_UNSUPPORTED for the transverse-field and Grover
+ * mixers. Synchronises `stream`. */
+int qaoa_mixer_eigen(const qaoa_mixer *mix, double *host_V, double *host_D, size_t N, void *stream);
+
+/* A mixer from a stored eigendecomposition H_M = V diag(D) V^T (the layout of qaoa_mixer_eigen)
+ * over the feasible states of (n, hamming_k), N <= 16384: no eigensolver runs. V must be real
+ * orthogonal; the call checks that entries are finite and columns have unit length (to 1e-9),
+ * not full orthogonality. Applied like the clique mixer. Synchronises `stream`. */
+int qaoa_mixer_from_eigen(qaoa_ctx *ctx, int n, int hamming_k, const double *host_V, const double *host_D,
+                          qaoa_mixer **out, void *stream);
+
 /* Grover mixer H_M = |psi0><psi0| (Sec. 2.4), psi0 the equal superposition over the feasible
  * states of an n-qubit problem (all 2^n for hamming_k < 0, else the weight-k states; the mixer
  * keeps the Hamming weight). 1 <= n <= 62. Evaluations with it use fair sampling (Sec. 2.4):

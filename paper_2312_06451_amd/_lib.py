@@ -26,6 +26,7 @@ EXPORTED = [
     "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error", "qaoa_profile_enable",
     "qaoa_profile_read", "qaoa_problem_from_values", "qaoa_problem_copy_values", "qaoa_mixer_grover",
     "qaoa_cost_degeneracies", "qaoa_problem_degeneracies", "qaoa_mixer_ring", "qaoa_mixer_matrix",
+    "qaoa_mixer_eigen", "qaoa_mixer_from_eigen",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
                   "count_states": 6}
@@ -72,6 +73,8 @@ def lib() -> ctypes.CDLL:
     L.qaoa_mixer_clique.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
     L.qaoa_mixer_grover.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
     L.qaoa_mixer_ring.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
+    L.qaoa_mixer_eigen.argtypes = [c_void_p, P(c_double), P(c_double), c_size_t, c_void_p]
+    L.qaoa_mixer_from_eigen.argtypes = [c_void_p, c_int, c_int, P(c_double), P(c_double), P(c_void_p), c_void_p]
     L.qaoa_mixer_matrix.argtypes = [c_void_p, c_int, c_int, P(c_double), P(c_void_p), c_void_p]
     L.qaoa_cost_degeneracies.argtypes = [c_void_p, c_int, c_int, i32p, i32p, i32p, c_int, P(c_void_p), c_void_p]
     L.qaoa_problem_degeneracies.argtypes = [c_void_p, P(c_double), P(c_int64), c_size_t, P(c_size_t), c_void_p]
@@ -191,6 +194,26 @@ def qaoa_mixer_matrix(ctx: int, n: int, hamming_k: int, matrix, stream: int = 0)
     out = c_void_p()
     check(lib().qaoa_mixer_matrix(ctx, n, hamming_k, m.ctypes.data_as(P(c_double)), ctypes.byref(out), stream),
           "qaoa_mixer_matrix")
+    return out.value
+
+
+def qaoa_mixer_eigen(mix: int, N: int, stream: int = 0):
+    """(V, D): eigenvectors as columns of V (N x N) and eigenvalues."""
+    import numpy as np
+    Vt = np.zeros((N, N), dtype=np.float64)   # row j = eigenvector j
+    D = np.zeros(N, dtype=np.float64)
+    check(lib().qaoa_mixer_eigen(mix, Vt.ctypes.data_as(P(c_double)), D.ctypes.data_as(P(c_double)), N, stream),
+          "qaoa_mixer_eigen")
+    return Vt.T.copy(), D
+
+
+def qaoa_mixer_from_eigen(ctx: int, n: int, hamming_k: int, V, D, stream: int = 0) -> int:
+    import numpy as np
+    Vt = np.ascontiguousarray(np.asarray(V, dtype=np.float64).T)   # row j = eigenvector j
+    Da = np.ascontiguousarray(D, dtype=np.float64)
+    out = c_void_p()
+    check(lib().qaoa_mixer_from_eigen(ctx, n, hamming_k, Vt.ctypes.data_as(P(c_double)), Da.ctypes.data_as(P(c_double)),
+                                      ctypes.byref(out), stream), "qaoa_mixer_from_eigen")
     return out.value
 
 

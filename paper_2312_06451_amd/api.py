@@ -127,6 +127,18 @@ class Mixer:
         return cls(ctx, _lib.qaoa_mixer_matrix(ctx.handle, n, hamming_k, H, _stream(stream)), "matrix", n, hamming_k)
 
     @classmethod
+    def from_eigen(cls, ctx: Context, n: int, V, D, hamming_k: int = -1, stream=None):
+        """A mixer V diag(D) V^T from a stored eigendecomposition (no eigensolver)."""
+        h = _lib.qaoa_mixer_from_eigen(ctx.handle, n, hamming_k, V, D, _stream(stream))
+        return cls(ctx, h, "eigen", n, hamming_k)
+
+    def eigen(self, stream=None):
+        """(V, D) of a clique, ring or matrix mixer: eigenvectors as columns of V."""
+        from math import comb
+        N = (1 << self.n) if self.k < 0 else comb(self.n, self.k)
+        return _lib.qaoa_mixer_eigen(self.handle, N, _stream(stream))
+
+    @classmethod
     def grover(cls, ctx: Context, n: int, hamming_k: int = -1):
         return cls(ctx, _lib.qaoa_mixer_grover(ctx.handle, n, hamming_k), "grover", n, hamming_k)
 

@@ -1444,14 +1444,14 @@ int qaoa_problem_degeneracies(const qaoa_problem *cprob, double *values, int64_t
 }
 
 static void eigen_mixer(qaoa_ctx *ctx, int kind, int n, int k, const double *host_matrix, qaoa_mixer **out,
-                        void *stream) {
+                        void *stream, const double *host_eigenvalues = nullptr) {
   DeviceGuard g(ctx->device);
   auto m = std::make_unique<qaoa_mixer>();
   m->ctx = ctx;
   m->kind = 1;
   m->n = n;
   m->k = k < 0 ? -1 : k;
-  m->clique = clique_create(kind, n, m->k, host_matrix, (hipStream_t)stream);
+  m->clique = clique_create(kind, n, m->k, host_matrix, host_eigenvalues, (hipStream_t)stream);
   *out = m.release();
   ctx->live++;
 }
@@ -1496,6 +1496,38 @@ int qaoa_mixer_matrix(qaoa_ctx *ctx, int n, int hamming_k, const double *host_ma
       for (int64_t j = 0; j < i; j++)
         REQUIRE(std::fabs(host_matrix[i * N + j] - host_matrix[j * N + i]) <= 1e-12 * mx, "matrix is not symmetric");
     eigen_mixer(ctx, MIX_MATRIX, n, hamming_k, host_matrix, out, stream);
+  });
+}
+
+int qaoa_mixer_from_eigen(qaoa_ctx *ctx, int n, int hamming_k, const double *host_V, const double *host_D,
+                          qaoa_mixer **out, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx && out && host_V && host_D, "ctx, V, D or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 20, "n must be in [1, 20]");
+    REQUIRE(hamming_k <= n, "hamming_k must be <= n");
+    const int64_t N = hamming_k < 0 ? (int64_t(1) << n) : binom64(n, hamming_k);
+    REQUIRE(N >= 1 && N <= 16384, "the feasible set must have at most 16384 states");
+    for (int64_t j = 0; j < N; j++) {
+      REQUIRE(std::isfinite(host_D[j]), "eigenvalues must be finite");
+      double nn = 0.0;
+      for (int64_t i = 0; i < N; i++) {
+        REQUIRE(std::isfinite(host_V[j * N + i]), "eigenvectors must be finite");
+        nn += host_V[j * N + i] * host_V[j * N + i];
+      }
+      REQUIRE(std::fabs(nn - 1.0) <= 1e-9, "eigenvectors must have unit length");
+    }
+    eigen_mixer(ctx, MIX_EIGEN, n, hamming_k, host_V, out, stream, host_D);
+  });
+}
+
+int qaoa_mixer_eigen(const qaoa_mixer *mix, double *host_V, double *host_D, size_t N, void *stream) {
+  return guarded([&] {
+    REQUIRE(mix && host_V && host_D, "mixer, V or D is NULL");
+    if (mix->kind != 1) throw fail(QAOA_ERR_UNSUPPORTED, "the mixer is not applied through an eigendecomposition");
+    REQUIRE((int64_t)N == clique_size(*mix->clique), "N differs from the mixer's state count");
+    DeviceGuard g(mix->ctx->device);
+    clique_export(*mix->clique, host_V, host_D, (hipStream_t)stream);
   });
 }
 

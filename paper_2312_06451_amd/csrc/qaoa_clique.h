@@ -28,11 +28,15 @@ struct CliqueEval {
   double c0;           // mean of C over the states
 };
 
-// kind: MIX_CLIQUE, MIX_RING (matrices built on the device over the weight-k states) or
-// MIX_MATRIX (host_matrix: N x N real symmetric, N = 2^n for k < 0 else C(n, k)).
-enum { MIX_CLIQUE = 0, MIX_RING = 1, MIX_MATRIX = 2 };
+// kind: MIX_CLIQUE, MIX_RING (matrices built on the device over the weight-k states),
+// MIX_MATRIX (host_matrix: N x N real symmetric, N = 2^n for k < 0 else C(n, k)) or MIX_EIGEN
+// (host_matrix: eigenvectors, column j at host_matrix[j * N ..], host_eigenvalues: N values).
+enum { MIX_CLIQUE = 0, MIX_RING = 1, MIX_MATRIX = 2, MIX_EIGEN = 3 };
 std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, int k, const double *host_matrix,
-                                                                 hipStream_t st);
+                                                                 const double *host_eigenvalues, hipStream_t st);
+// Copy the FP64 eigenbasis (column j = eigenvector j) and eigenvalues to the host.
+void clique_export(const CliqueMixer &m, double *host_V, double *host_D, hipStream_t st);
+int64_t clique_size(const CliqueMixer &m);
 void clique_evaluate(CliqueMixer &m, const CliqueEval &ev, int p, const double *angles, int nsets,
                      const void *d_psi0, int precision, int grad, double *out_expect,
                      double *out_grad, void *d_state, hipStream_t st);

@@ -359,7 +359,7 @@ __global__ void k_export(const R *__restrict__ X, int64_t N, typename CT<R>::T2 
 // ---------------------------------------------------------------- setup
 
 std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, int k, const double *host_matrix,
-                                                                 hipStream_t st) {
+                                                                 const double *host_eigenvalues, hipStream_t st) {
   std::unique_ptr<CliqueMixer, CliqueMixerDeleter> m(new CliqueMixer());
   m->n = n;
   m->k = k;
@@ -376,22 +376,28 @@ std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, 
   Buf dbin, E, info;
   int64_t *db = (int64_t *)dbin.get(hb.size() * sizeof(int64_t));
   hipchk(hipMemcpyAsync(db, hb.data(), hb.size() * sizeof(int64_t), hipMemcpyHostToDevice, st), "binom upload");
-  if (kind == MIX_MATRIX) {
+  if (kind == MIX_EIGEN) {
+    // a stored eigendecomposition: V (column j = eigenvector j) and D, no eigensolver
+    hipchk(hipMemcpyAsync(H, host_matrix, (size_t)N * N * sizeof(double), hipMemcpyHostToDevice, st), "V upload");
+    hipchk(hipMemcpyAsync(Dv, host_eigenvalues, (size_t)N * sizeof(double), hipMemcpyHostToDevice, st), "D upload");
+  } else if (kind == MIX_MATRIX) {
     hipchk(hipMemcpyAsync(H, host_matrix, (size_t)N * N * sizeof(double), hipMemcpyHostToDevice, st), "matrix upload");
   } else {
     hipchk(hipMemsetAsync(H, 0, (size_t)N * N * sizeof(double), st), "clear H");
     k_clique_matrix<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(n, k, kind == MIX_RING ? 1 : 0, N, db, H);
     hipchk(hipGetLastError(), "k_clique_matrix");
   }
-  double *dE = (double *)E.get((size_t)N * sizeof(double));
-  rocblas_int *dinfo = (rocblas_int *)info.get(sizeof(rocblas_int));
-  blaschk(rocsolver_dsyevd(m->blas, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N, H,
-                           (rocblas_int)N, Dv, dE, dinfo),
-          "rocsolver_dsyevd");
-  rocblas_int hinfo = 0;
-  hipchk(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st), "info download");
-  hipchk(hipStreamSynchronize(st), "eigendecomposition");
-  if (hinfo != 0) throw CliqueError{QAOA_ERR_HIP, "eigendecomposition did not converge"};
+  if (kind != MIX_EIGEN) {
+    double *dE = (double *)E.get((size_t)N * sizeof(double));
+    rocblas_int *dinfo = (rocblas_int *)info.get(sizeof(rocblas_int));
+    blaschk(rocsolver_dsyevd(m->blas, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N, H,
+                             (rocblas_int)N, Dv, dE, dinfo),
+            "rocsolver_dsyevd");
+    rocblas_int hinfo = 0;
+    hipchk(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st), "info download");
+    hipchk(hipStreamSynchronize(st), "eigendecomposition");
+    if (hinfo != 0) throw CliqueError{QAOA_ERR_HIP, "eigendecomposition did not converge"};
+  }
   // FP16 halves for the FP32 form
   __half *Vc = (__half *)m->Vcols.get((size_t)2 * N * N * sizeof(__half));
   __half *Vr = (__half *)m->Vrows.get((size_t)2 * N * N * sizeof(__half));
@@ -400,6 +406,15 @@ std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, 
   hipchk(hipStreamSynchronize(st), "split V");
   return m;
 }
+
+void clique_export(const CliqueMixer &m, double *host_V, double *host_D, hipStream_t st) {
+  const size_t N = (size_t)m.N;
+  hipchk(hipMemcpyAsync(host_V, m.V.p, N * N * sizeof(double), hipMemcpyDeviceToHost, st), "V download");
+  hipchk(hipMemcpyAsync(host_D, m.D.p, N * sizeof(double), hipMemcpyDeviceToHost, st), "D download");
+  hipchk(hipStreamSynchronize(st), "eigenbasis download");
+}
+
+int64_t clique_size(const CliqueMixer &m) { return m.N; }
 
 // ---------------------------------------------------------------- evaluation
 

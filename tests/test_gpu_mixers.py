@@ -105,3 +105,51 @@ def test_matrix_mixer_errors(q, ctx):
     with pytest.raises(q.QAOAError) as ei:
         q.Mixer.matrix(ctx, 15, np.zeros((2, 2)))             # 2^15 states: too many (checked before reading)
     assert ei.value.status == _lib.QAOA_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kind", ["clique", "ring"])
+def test_eigen_export_import_roundtrip(q, ctx, kind):
+    """The stored decomposition (Sec. 2.1) rebuilds the same operator: V is orthogonal and
+    V diag(D) V^T equals the mixer matrix; a mixer loaded from (V, D) gives the same results."""
+    n, k = 10, 4
+    N = comb(n, k)
+    st = oracle.states(n, k).astype(np.int64)
+    if kind == "clique":
+        H = np.real(pins.dense_clique_hamiltonian(n)[np.ix_(st, st)])
+        M = q.Mixer.clique(ctx, n, k)
+    else:
+        H = np.real(pins.dense_ring_hamiltonian(n)[np.ix_(st, st)])
+        M = q.Mixer.ring(ctx, n, k)
+    V, D = M.eigen()
+    assert V.shape == (N, N) and D.shape == (N,)
+    assert np.max(np.abs(V.T @ V - np.eye(N))) < 1e-12
+    assert np.max(np.abs((V * D) @ V.T - H)) < 1e-11
+    assert np.allclose(np.sort(D), np.linalg.eigvalsh(H), atol=1e-11)
+    M2 = q.Mixer.from_eigen(ctx, n, V, D, hamming_k=k)
+    g = workloads.erdos_renyi(n, 1050, 0.5, (1, 3))
+    P = q.Problem.from_graph(ctx, g, hamming_k=k)
+    for a in workloads.random_angles(3, 2, 1051):
+        for prec in (0, 1):
+            e1, g1 = q.expect_grad(P, M, a, precision=prec)
+            e2, g2 = q.expect_grad(P, M2, a, precision=prec)
+            assert e1 == e2 and np.array_equal(g1, g2)
+
+
+def test_eigen_import_full_space_and_errors(q, ctx):
+    n = 6
+    rng = np.random.default_rng(1060)
+    A = rng.normal(size=(64, 64))
+    H = A + A.T
+    D, V = np.linalg.eigh(H)
+    vals = rng.normal(0.0, 1.0, 64)
+    P = q.Problem.from_values(ctx, n, vals)
+    M = q.Mixer.from_eigen(ctx, n, V, D)
+    for a in workloads.random_angles(2, 2, 1061):
+        E0, N0, g0 = oracle.dense_mixer_grad(vals, a, H)
+        e, gr = q.expect_grad(P, M, a, precision=1)
+        assert abs(e - E0 / N0) <= 1e-10 * np.max(np.abs(vals))
+        assert np.max(np.abs(gr - g0 / N0)) <= 1e-10 * np.max(np.abs(g0 / N0))
+    with pytest.raises(q.QAOAError):
+        q.Mixer.from_eigen(ctx, n, 2.0 * V, D)          # columns not of unit length
+    with pytest.raises(q.QAOAError):
+        q.Mixer.x(ctx, n).eigen()                        # no stored decomposition
