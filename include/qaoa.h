@@ -221,6 +221,89 @@ int qaoa_expect_grad_batched(const qaoa_problem *const *probs, const qaoa_mixer 
                              int n_probs, int n_sets, int p, const double *angles, int precision,
                              double *out_expect, double *out_grad, void *stream);
 
+/* <C> of n_pairs independent evaluations: pair i is problem probs[i] with mixer mixers[i] at
+ * angles[i][0..2p) (the many instances of an angle-finding study, each at its own point).
+ * probs and mixers are arrays of n_pairs handles (repeats allowed, one context); out_expect:
+ * host double [n_pairs]. Whole-state transverse-field pairs and Grover-mixer pairs each run
+ * as one launch over all pairs; the other pairs run grouped by (problem, mixer). */
+int qaoa_expect_pairs(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs, int p,
+                      const double *angles, int precision, double *out_expect, void *stream);
+
+/* As qaoa_expect_pairs, with the gradient; out_grad: host double [n_pairs][2p]. */
+int qaoa_expect_grad_pairs(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs, int p,
+                           const double *angles, int precision, double *out_expect, double *out_grad,
+                           void *stream);
+
+/* ---------------------------------------------------------------- angle finding (Sec. 2.3)
+ *
+ * Host-side outer loop over the paired evaluation: every objective value and gradient comes
+ * from qaoa_expect_grad_pairs, with all restarts (or basinhopping chains) of a step, of every
+ * instance being solved, as its pairs, so one launch advances all of them. The objective is <C> (maximised by
+ * default, Sec. 3; minimised with maximize = 0). The optimiser state lives in host memory. */
+typedef struct qaoa_angle_opts {
+  int maximize;          /* 1: maximise <C> (default); 0: minimise                          */
+  int precision;         /* QAOA_FP32 (default) or QAOA_FP64 evaluations                    */
+  int max_iter;          /* BFGS: accepted steps per local minimisation (default 100)       */
+  double gtol;           /* BFGS: stop once max_i |d<C>/d angle_i| <= gtol (default 1e-6)    */
+  int n_chains;          /* basinhopping chains run side by side (default 8), <= 65535     */
+  int n_hops;            /* basinhopping steps per chain after the first minimisation (10)  */
+  double step;           /* hop: each angle moves by a uniform draw in [-step, step] (0.5)  */
+  double temperature;    /* Metropolis temperature in units of <C> (1.0); 0: improvements only */
+  uint64_t seed;         /* counter-based random draws (SplitMix64), keyed by round, chain, hop */
+  int max_sets_per_call; /* angle sets per batched call; 0: automatic (see qaoa_minimize)    */
+} qaoa_angle_opts;
+
+/* Fill *opts with the defaults above. */
+void qaoa_angle_opts_default(qaoa_angle_opts *opts);
+
+/* Local minimisation from n_starts points at once (Sec. 2.3: BFGS to the closest local
+ * optimum): BFGS with a backtracking Armijo line search, inverse-Hessian form, started from
+ * the identity and rescaled after the first step. angles: host double [n_starts][2p], in:
+ * starting points, out: the optima found; out_values: host double [n_starts], <C> there;
+ * out_iters (NULL allowed): accepted steps taken. Starts are batched max_sets_per_call at a
+ * time (automatic: as many as keep 2 x sets x states x 16 bytes under 4 GiB). Stops on
+ * gtol, max_iter, or a line search that fails to decrease the objective in 30 halvings. */
+int qaoa_minimize(const qaoa_problem *prob, const qaoa_mixer *mix, int p, int n_starts, double *angles,
+                  double *out_values, int *out_iters, const qaoa_angle_opts *opts, void *stream);
+
+/* Basinhopping (Sec. 2.3 and Sec. 3) from one point x0 (host double [2p]): n_chains chains
+ * each minimise from x0, then take n_hops steps of perturb, minimise, Metropolis accept; all
+ * chains' minimisations of a step run as one batch. out_angles (host [2p]) and out_value
+ * receive the best optimum seen by any chain (ties: earliest step, then lowest chain). */
+int qaoa_basinhopping(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *x0,
+                      const qaoa_angle_opts *opts, double *out_angles, double *out_value, void *stream);
+
+/* Iterative angle finding (Sec. 2.3 and Sec. 3): round 1 runs basinhopping from uniform
+ * random angles in [0, 2 pi); round r > 1 seeds chain 0 with the round r-1 optimum padded by
+ * a zero layer (the same state, so the optimum never gets worse with r) and the other chains
+ * with its linear interpolation to r layers (endpoints kept). out_angles: host double
+ * [p_max][2 p_max], row r-1 holds round r's 2r angles (beta_1..beta_r, gamma_1..gamma_r),
+ * the rest zero; out_values: host double [p_max]. checkpoint_path (NULL: none): a text file
+ * that receives each round's result as it completes (written to path.tmp, then renamed); if
+ * it exists, its rounds are loaded and the search resumes after the last one. A file made
+ * for another problem shape or objective sense is refused (QAOA_ERR_INVALID_ARG). Rounds
+ * draw their random numbers from (seed, round) only, so a resumed run gives the same results
+ * as an uninterrupted one. */
+int qaoa_find_angles(const qaoa_problem *prob, const qaoa_mixer *mix, int p_max, const qaoa_angle_opts *opts,
+                     const char *checkpoint_path, double *out_angles, double *out_values, void *stream);
+
+/* qaoa_find_angles for n_inst instances at once (the studies of Sec. 2.3 run many instances,
+ * e.g. 50 graphs to p = 10): every optimiser step of every instance shares one paired
+ * evaluation. Instance i uses probs[i], mixers[i] and checkpoint_paths[i] (checkpoint_paths
+ * may be NULL, or hold NULL entries); it gets the same result as a qaoa_find_angles call of
+ * its own. Instances may resume from different rounds. out_angles: host double
+ * [n_inst][p_max][2 p_max]; out_values: host double [n_inst][p_max]. */
+int qaoa_find_angles_multi(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_inst,
+                           int p_max, const qaoa_angle_opts *opts, const char *const *checkpoint_paths,
+                           double *out_angles, double *out_values, void *stream);
+
+/* Random local-minima search (the listing of Sec. 3): n_restarts starts uniform in
+ * [0, 2 pi)^{2p}, all minimised as one batch; out_angles (host [2p]) and out_value receive
+ * the best (ties: lowest restart index). out_all_values (NULL allowed): host [n_restarts]. */
+int qaoa_find_angles_random(const qaoa_problem *prob, const qaoa_mixer *mix, int p, int n_restarts,
+                            const qaoa_angle_opts *opts, double *out_angles, double *out_value,
+                            double *out_all_values, void *stream);
+
 /* Kernel timing (a tracing aid). While enabled, every kernel launch an evaluation on this
  * context makes is bracketed by two HIP events recorded on the call's stream; after the
  * call's final synchronisation the elapsed times are added to per-class totals together

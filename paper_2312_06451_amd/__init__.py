@@ -6,4 +6,6 @@ arguments through the C ABI (``_lib``), wraps handles in small classes (``api``)
 device memory (optional initial states, state outputs) and the current stream.
 """
 from ._lib import QAOA_FP32, QAOA_FP64, QAOAError, lib  # noqa: F401
-from .api import Context, Mixer, Problem, expect, expect_grad, expect_batched, expect_grad_batched, state  # noqa: F401
+from .api import (Context, Mixer, Problem, angle_opts, basinhopping, expect, expect_batched, expect_grad,  # noqa: F401
+                  expect_grad_batched, expect_grad_pairs, expect_pairs, find_angles, find_angles_multi,
+                  find_angles_random, minimize, state)

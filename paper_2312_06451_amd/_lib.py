@@ -26,10 +26,20 @@ EXPORTED = [
     "qaoa_expect_grad_batched", "qaoa_status_string", "qaoa_last_error", "qaoa_profile_enable",
     "qaoa_profile_read", "qaoa_problem_from_values", "qaoa_problem_copy_values", "qaoa_mixer_grover",
     "qaoa_cost_degeneracies", "qaoa_problem_degeneracies", "qaoa_mixer_ring", "qaoa_mixer_matrix",
-    "qaoa_mixer_eigen", "qaoa_mixer_from_eigen",
+    "qaoa_mixer_eigen", "qaoa_mixer_from_eigen", "qaoa_angle_opts_default", "qaoa_minimize",
+    "qaoa_basinhopping", "qaoa_find_angles", "qaoa_find_angles_random", "qaoa_find_angles_multi",
+    "qaoa_expect_pairs", "qaoa_expect_grad_pairs",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
                   "count_states": 6}
+
+
+class qaoa_angle_opts(ctypes.Structure):
+    """Mirror of struct qaoa_angle_opts (include/qaoa.h)."""
+    _fields_ = [("maximize", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("gtol", ctypes.c_double), ("n_chains", ctypes.c_int), ("n_hops", ctypes.c_int),
+                ("step", ctypes.c_double), ("temperature", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("max_sets_per_call", ctypes.c_int)]
 
 
 class QAOAError(RuntimeError):
@@ -89,13 +99,30 @@ def lib() -> ctypes.CDLL:
                                            c_int, P(c_double), P(c_double), c_void_p]
     L.qaoa_profile_enable.argtypes = [c_void_p, c_int]
     L.qaoa_profile_read.argtypes = [c_void_p, c_int, P(c_int64), P(c_double), P(c_double), P(c_double)]
+    opts_p = P(qaoa_angle_opts)
+    L.qaoa_angle_opts_default.argtypes = [opts_p]
+    L.qaoa_minimize.argtypes = [c_void_p, c_void_p, c_int, c_int, P(c_double), P(c_double), P(c_int), opts_p,
+                                c_void_p]
+    L.qaoa_basinhopping.argtypes = [c_void_p, c_void_p, c_int, P(c_double), opts_p, P(c_double), P(c_double),
+                                    c_void_p]
+    L.qaoa_find_angles.argtypes = [c_void_p, c_void_p, c_int, opts_p, ctypes.c_char_p, P(c_double), P(c_double),
+                                   c_void_p]
+    L.qaoa_find_angles_multi.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, opts_p, P(ctypes.c_char_p),
+                                         P(c_double), P(c_double), c_void_p]
+    L.qaoa_expect_pairs.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, P(c_double), c_int, P(c_double),
+                                    c_void_p]
+    L.qaoa_expect_grad_pairs.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, P(c_double), c_int,
+                                         P(c_double), P(c_double), c_void_p]
+    L.qaoa_find_angles_random.argtypes = [c_void_p, c_void_p, c_int, c_int, opts_p, P(c_double), P(c_double),
+                                          P(c_double), c_void_p]
     L.qaoa_status_string.argtypes = [c_int]
     L.qaoa_status_string.restype = ctypes.c_char_p
     L.qaoa_last_error.argtypes = []
     L.qaoa_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("qaoa_status_string", "qaoa_last_error"):
+        if name not in ("qaoa_status_string", "qaoa_last_error", "qaoa_angle_opts_default"):
             getattr(L, name).restype = c_int
+    L.qaoa_angle_opts_default.restype = None
     _lib = L
     return L
 
@@ -317,6 +344,33 @@ def qaoa_expect_grad_batched(probs, mixers, p: int, angles, precision: int = QAO
     return out, g
 
 
+def qaoa_expect_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+    """<C> of pair i = (probs[i], mixers[i], angles[i])."""
+    import numpy as np
+    aa, ap = _f64(angles)
+    n = len(probs)
+    if aa.size != n * 2 * p or len(mixers) != n:
+        raise ValueError("one mixer and 2p angles per pair")
+    out = np.zeros(n, dtype=np.float64)
+    check(lib().qaoa_expect_pairs(_ptrs(probs), _ptrs(mixers), n, p, ap, precision,
+                                  out.ctypes.data_as(P(c_double)), stream), "qaoa_expect_pairs")
+    return out
+
+
+def qaoa_expect_grad_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+    import numpy as np
+    aa, ap = _f64(angles)
+    n = len(probs)
+    if aa.size != n * 2 * p or len(mixers) != n:
+        raise ValueError("one mixer and 2p angles per pair")
+    out = np.zeros(n, dtype=np.float64)
+    g = np.zeros((n, 2 * p), dtype=np.float64)
+    check(lib().qaoa_expect_grad_pairs(_ptrs(probs), _ptrs(mixers), n, p, ap, precision,
+                                       out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)), stream),
+          "qaoa_expect_grad_pairs")
+    return out, g
+
+
 def qaoa_profile_enable(ctx: int, enable: bool = True) -> None:
     check(lib().qaoa_profile_enable(ctx, 1 if enable else 0), "qaoa_profile_enable")
 
@@ -326,3 +380,73 @@ def qaoa_profile_read(ctx: int, kernel_class: int) -> dict:
     check(lib().qaoa_profile_read(ctx, kernel_class, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
                                   ctypes.byref(fl)), "qaoa_profile_read")
     return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+
+# ---------------------------------------------------------------- angle finding
+
+def qaoa_angle_opts_default() -> qaoa_angle_opts:
+    o = qaoa_angle_opts()
+    lib().qaoa_angle_opts_default(ctypes.byref(o))
+    return o
+
+
+def qaoa_minimize(prob: int, mix: int, p: int, starts, opts: qaoa_angle_opts, stream: int = 0):
+    """(optima [n_starts][2p], <C> there [n_starts], accepted steps [n_starts])."""
+    import numpy as np
+    xs = np.array(starts, dtype=np.float64, order="C").reshape(-1, 2 * p)
+    vals = np.zeros(xs.shape[0], dtype=np.float64)
+    its = np.zeros(xs.shape[0], dtype=np.int32)
+    check(lib().qaoa_minimize(prob, mix, p, xs.shape[0], xs.ctypes.data_as(P(c_double)),
+                              vals.ctypes.data_as(P(c_double)), its.ctypes.data_as(P(c_int)), ctypes.byref(opts),
+                              stream), "qaoa_minimize")
+    return xs, vals, its
+
+
+def qaoa_basinhopping(prob: int, mix: int, p: int, x0, opts: qaoa_angle_opts, stream: int = 0):
+    import numpy as np
+    xa, xp = _f64(x0)
+    out = np.zeros(2 * p, dtype=np.float64)
+    val = c_double()
+    check(lib().qaoa_basinhopping(prob, mix, p, xp, ctypes.byref(opts), out.ctypes.data_as(P(c_double)),
+                                  ctypes.byref(val), stream), "qaoa_basinhopping")
+    return out, val.value
+
+
+def qaoa_find_angles(prob: int, mix: int, p_max: int, opts: qaoa_angle_opts, checkpoint_path=None,
+                     stream: int = 0):
+    """(angles [p_max][2 p_max], row r-1 holding round r's 2r angles; values [p_max])."""
+    import numpy as np
+    out = np.zeros((p_max, 2 * p_max), dtype=np.float64)
+    vals = np.zeros(p_max, dtype=np.float64)
+    path = os.fsencode(checkpoint_path) if checkpoint_path is not None else None
+    check(lib().qaoa_find_angles(prob, mix, p_max, ctypes.byref(opts), path, out.ctypes.data_as(P(c_double)),
+                                 vals.ctypes.data_as(P(c_double)), stream), "qaoa_find_angles")
+    return out, vals
+
+
+def qaoa_find_angles_random(prob: int, mix: int, p: int, n_restarts: int, opts: qaoa_angle_opts, stream: int = 0):
+    """(best angles [2p], best <C>, <C> of every restart's optimum [n_restarts])."""
+    import numpy as np
+    out = np.zeros(2 * p, dtype=np.float64)
+    allv = np.zeros(n_restarts, dtype=np.float64)
+    val = c_double()
+    check(lib().qaoa_find_angles_random(prob, mix, p, n_restarts, ctypes.byref(opts), out.ctypes.data_as(P(c_double)),
+                                        ctypes.byref(val), allv.ctypes.data_as(P(c_double)), stream),
+          "qaoa_find_angles_random")
+    return out, val.value, allv
+
+
+def qaoa_find_angles_multi(probs, mixers, p_max: int, opts: qaoa_angle_opts, checkpoint_paths=None,
+                           stream: int = 0):
+    """(angles [n][p_max][2 p_max], values [n][p_max]) for n instances solved together."""
+    import numpy as np
+    n = len(probs)
+    out = np.zeros((n, p_max, 2 * p_max), dtype=np.float64)
+    vals = np.zeros((n, p_max), dtype=np.float64)
+    paths = None
+    if checkpoint_paths is not None:
+        paths = (ctypes.c_char_p * n)(*[os.fsencode(x) if x is not None else None for x in checkpoint_paths])
+    check(lib().qaoa_find_angles_multi(_ptrs(probs), _ptrs(mixers), n, p_max, ctypes.byref(opts), paths,
+                                       out.ctypes.data_as(P(c_double)), vals.ctypes.data_as(P(c_double)), stream),
+          "qaoa_find_angles_multi")
+    return out, vals

@@ -195,3 +195,65 @@ def expect_grad_batched(problems, mixers, angles, precision: int = QAOA_FP32, st
     p = a.shape[-1] // 2
     return _lib.qaoa_expect_grad_batched([x.handle for x in problems], [m.handle for m in mixers], p, a,
                                          precision, _stream(stream))
+
+
+# ---------------------------------------------------------------- angle finding (Sec. 2.3)
+
+def angle_opts(**kw):
+    """qaoa_angle_opts with the library defaults, overridden by keyword (maximize, precision,
+    max_iter, gtol, n_chains, n_hops, step, temperature, seed, max_sets_per_call)."""
+    o = _lib.qaoa_angle_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown angle-finding option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def minimize(problem: Problem, mixer: Mixer, starts, stream=None, **opts):
+    """BFGS from every row of ``starts`` (n_starts x 2p) as one batch: (optima, <C>, steps)."""
+    s = np.asarray(starts, dtype=np.float64)
+    p = s.shape[-1] // 2
+    return _lib.qaoa_minimize(problem.handle, mixer.handle, p, s, angle_opts(**opts), _stream(stream))
+
+
+def basinhopping(problem: Problem, mixer: Mixer, x0, stream=None, **opts):
+    """Basinhopping from ``x0`` (2p angles): (best angles, best <C>)."""
+    a = np.asarray(x0, dtype=np.float64).reshape(-1)
+    return _lib.qaoa_basinhopping(problem.handle, mixer.handle, a.size // 2, a, angle_opts(**opts),
+                                  _stream(stream))
+
+
+def find_angles(problem: Problem, mixer: Mixer, p: int, file=None, stream=None, **opts):
+    """Iterative angle finding up to p rounds, resuming from / saving to ``file``:
+    (list of per-round angle arrays, array of <C> per round)."""
+    out, vals = _lib.qaoa_find_angles(problem.handle, mixer.handle, p, angle_opts(**opts), file,
+                                      _stream(stream))
+    return [out[r - 1, :2 * r].copy() for r in range(1, p + 1)], vals
+
+
+def find_angles_multi(problems, mixers, p: int, files=None, stream=None, **opts):
+    """find_angles for many instances at once (one launch per optimiser step for all of them):
+    per instance, (list of per-round angle arrays, array of <C> per round)."""
+    out, vals = _lib.qaoa_find_angles_multi([x.handle for x in problems], [m.handle for m in mixers], p,
+                                            angle_opts(**opts), files, _stream(stream))
+    return [([out[i, r - 1, :2 * r].copy() for r in range(1, p + 1)], vals[i]) for i in range(len(problems))]
+
+
+def expect_pairs(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
+    """<C> of pair i = (problems[i], mixers[i], angles[i])."""
+    a = np.asarray(angles, dtype=np.float64)
+    return _lib.qaoa_expect_pairs([x.handle for x in problems], [m.handle for m in mixers], a.shape[-1] // 2, a,
+                                  precision, _stream(stream))
+
+
+def expect_grad_pairs(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
+    a = np.asarray(angles, dtype=np.float64)
+    return _lib.qaoa_expect_grad_pairs([x.handle for x in problems], [m.handle for m in mixers], a.shape[-1] // 2,
+                                       a, precision, _stream(stream))
+
+
+def find_angles_random(problem: Problem, mixer: Mixer, p: int, restarts: int = 100, stream=None, **opts):
+    """Random local-minima search: (best angles, best <C>, <C> of every restart)."""
+    return _lib.qaoa_find_angles_random(problem.handle, mixer.handle, p, restarts, angle_opts(**opts),
+                                        _stream(stream))

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa.so")
-SOURCES = ["qaoa_kernels.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_api.cpp"]
+SOURCES = ["qaoa_kernels.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_api.cpp", "qaoa_angles.cpp"]
+HOST_ONLY = {"qaoa_angles.cpp"}  # plain C++ above the C ABI: no device code
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP source of this library.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -26,7 +27,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        lang = ["-x", "hip"] if src.endswith(".cpp") and src not in HOST_ONLY else []
         cmd = [HIPCC] + FLAGS + lang + ["-I", os.path.join(ROOT, "include"), "-c",
                                         os.path.join(CSRC, src), "-o", obj]
         if verbose:

@@ -42,6 +42,14 @@ Err fail(int code, const std::string &m) { return Err{code, m}; }
     if (!(cond)) throw Err{QAOA_ERR_INVALID_ARG, msg};                                        \
   } while (0)
 
+}  // namespace
+
+// Lets the angle-finding loop (its own translation unit) report through qaoa_last_error.
+namespace qaoa {
+void set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
+}  // namespace qaoa
+
+namespace {
 template <typename F>
 int guarded(F &&f) {
   try {
@@ -1668,6 +1676,95 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
              out_expect + (size_t)i * n_sets, grad ? out_grad + (size_t)i * n_sets * g2p : nullptr,
              nullptr, st);
   }
+}
+
+// Pair i: probs[i] with mixers[i] at angle set i. Whole-state and Grover pairs of every problem
+// share one launch each; the other pairs run problem by problem, all of a problem's sets at once.
+static void paired(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs, int p,
+                   const double *angles, int precision, int grad, double *out_expect, double *out_grad,
+                   hipStream_t st) {
+  REQUIRE(probs && mixers, "probs or mixers is NULL");
+  REQUIRE(n_pairs >= 1, "n_pairs must be >= 1");
+  check_angles(p, angles, (size_t)n_pairs * 2 * p);
+  REQUIRE(out_expect != nullptr && (!grad || out_grad != nullptr), "output pointer is NULL");
+  qaoa_ctx *ctx = probs[0] ? probs[0]->ctx : nullptr;
+  for (int i = 0; i < n_pairs; i++) {
+    check_pair(probs[i], mixers[i], precision);
+    REQUIRE(probs[i]->ctx == ctx, "all problems must share one context");
+  }
+  DeviceGuard g(ctx->device);
+  const int g2p = 2 * p;
+  auto scatter = [&](const double *r, int i) {
+    out_expect[i] = r[0];
+    if (grad) std::memcpy(out_grad + (size_t)i * g2p, r + 1, g2p * sizeof(double));
+  };
+  std::vector<SmallItem> items;
+  std::vector<GroverItem> gitems;
+  std::vector<int> rows, grows;
+  std::vector<std::pair<const qaoa_problem *, const qaoa_mixer *>> keys;
+  std::vector<std::vector<int>> groups;
+  for (int i = 0; i < n_pairs; i++) {
+    if (mixers[i]->kind == 0 && small_path(probs[i], precision)) {
+      if (probs[i]->max_value + 1 > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+      items.push_back(small_item(probs[i], i, (int)rows.size()));
+      rows.push_back(i);
+    } else if (mixers[i]->kind == 2) {
+      qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
+      ensure_counts(pr, st);
+      gitems.push_back(grover_item(pr, i, (int)grows.size()));
+      grows.push_back(i);
+    } else {
+      const auto key = std::make_pair(probs[i], mixers[i]);
+      size_t j = 0;
+      while (j < keys.size() && keys[j] != key) j++;
+      if (j == keys.size()) {
+        keys.push_back(key);
+        groups.emplace_back();
+      }
+      groups[j].push_back(i);
+    }
+  }
+  if (!items.empty()) {
+    std::vector<double> hout(rows.size() * (1 + g2p));
+    run_small(items, precision, angles, n_pairs, p, grad, hout.data(), ctx, st);
+    for (size_t j = 0; j < rows.size(); j++) scatter(hout.data() + j * (1 + g2p), rows[j]);
+  }
+  if (!gitems.empty()) {
+    std::vector<double> hout(grows.size() * (1 + g2p));
+    run_grover(gitems, angles, n_pairs, p, grad, hout.data(), ctx, st);
+    for (size_t j = 0; j < grows.size(); j++) scatter(hout.data() + j * (1 + g2p), grows[j]);
+  }
+  std::vector<double> a, e, gr;
+  for (size_t j = 0; j < keys.size(); j++) {
+    const int m = (int)groups[j].size();
+    a.resize((size_t)m * g2p);
+    e.resize(m);
+    gr.resize((size_t)m * g2p);
+    for (int t = 0; t < m; t++)
+      std::memcpy(&a[(size_t)t * g2p], angles + (size_t)groups[j][t] * g2p, g2p * sizeof(double));
+    evaluate(keys[j].first, keys[j].second, p, a.data(), m, nullptr, precision, grad, e.data(),
+             grad ? gr.data() : nullptr, nullptr, st);
+    for (int t = 0; t < m; t++) {
+      const int i = groups[j][t];
+      out_expect[i] = e[t];
+      if (grad) std::memcpy(out_grad + (size_t)i * g2p, &gr[(size_t)t * g2p], g2p * sizeof(double));
+    }
+  }
+}
+
+int qaoa_expect_pairs(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs, int p,
+                      const double *angles, int precision, double *out_expect, void *stream) {
+  return guarded([&] {
+    paired(probs, mixers, n_pairs, p, angles, precision, 0, out_expect, nullptr, (hipStream_t)stream);
+  });
+}
+
+int qaoa_expect_grad_pairs(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs, int p,
+                           const double *angles, int precision, double *out_expect, double *out_grad,
+                           void *stream) {
+  return guarded([&] {
+    paired(probs, mixers, n_pairs, p, angles, precision, 1, out_expect, out_grad, (hipStream_t)stream);
+  });
 }
 
 int qaoa_expect_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
