@@ -15,6 +15,8 @@ Other workloads (--workload):
   grover_maxcut3reg_n40_p16  Grover mixer: one step = the table-free degeneracy count over all
                            2^40 states plus one batched fwd+grad over 512 angle sets (p=16);
                            value in states/s
+  angles_er_n12_p10        angle finding: one step = iterative basinhopping rounds 1..10 for 50
+                           G(12,1/2) MaxCut instances at once; value in evals/s inside the loop
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
@@ -303,6 +305,92 @@ def main_grover(args, W, q, _lib, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def main_angles(args, W, q, _lib, torch, np):
+    """Angle-finding study: iterative basinhopping rounds 1..p for every instance at once, one
+    paired fwd+grad launch per optimiser step for all instances and chains."""
+    import oracle
+    from oracle import angles as A
+    ctx = q.Context(0)
+    h = ctx.handle
+    probs = [q.Problem.from_graph(ctx, g) for g in W.graphs]
+    mixers = [q.Mixer.x(ctx, g.n) for g in W.graphs]
+    opts = dict(W.extra)
+    steps = args.steps if args.steps is not None else 1
+    warmup = min(args.warmup, 1)
+    log(f"workload {W.name}: {W.description}")
+    for _ in range(warmup):
+        q.find_angles_multi(probs, mixers, W.p, **opts)
+    torch.cuda.synchronize()
+    _lib.qaoa_profile_enable(h, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = q.find_angles_multi(probs, mixers, W.p, **opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {k: _lib.qaoa_profile_read(h, v) for k, v in _lib.KERNEL_CLASSES.items()}
+    _lib.qaoa_profile_enable(h, False)
+    sm = prof["small"]
+    N = 2 ** W.graphs[0].n
+    evals = sm["bytes"] / N          # one byte of table per amplitude and evaluation (uint8 tables)
+    rate = evals / dt
+    mean_ms = sm["ms"] / max(1, sm["launches"])
+    achieved = sm["flops"] / (sm["ms"] * 1e-3) / 1e12
+    log(f"study {dt / steps:.2f} s; {evals / steps:.0f} evaluations/study, {rate:.0f} evals/s; "
+        f"{sm['launches'] / steps:.0f} launches/study, mean {mean_ms * 1e3:.1f} us, kernel share "
+        f"{sm['ms'] / (dt * 1e3):.3f}")
+    # validity: every round's value is the oracle's <C> at the returned angles; rounds never get worse
+    worst, mono = 0.0, True
+    for (ang, vals), g in zip(res, W.graphs):
+        t = oracle.graph_table(g)
+        mono = mono and bool(np.all(np.diff(vals) >= -1e-6 * t.max()))
+        for r in (1, W.p):
+            E, Nr = oracle.expect(g.n, t, ang[r - 1])
+            worst = max(worst, abs(E / Nr - vals[r - 1]) / t.max())
+    roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFS, 4), "traffic": None,
+            "kernel": KERNEL_NAMES["small"], "class": "small", "launches": sm["launches"],
+            "mean_ms": round(mean_ms, 4), "flops_per_launch": sm["flops"] / max(1, sm["launches"])}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's own search (same options) on the first instance, rounds 1..3
+        g = W.graphs[0]
+        t = oracle.graph_table(g)
+        calls = [0]
+
+        def fun_for(r):
+            f = A.Objective(g.n, t)
+
+            def counted(x):
+                calls[0] += 1
+                return f(x)
+            return counted
+        t1 = time.perf_counter()
+        A.find_angles(fun_for, 3, **opts)
+        d1 = time.perf_counter() - t1
+        cpu = {"value": calls[0] / d1, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"the oracle's find_angles (same options) on 1 of the {len(W.graphs)} instances, "
+                         f"rounds 1..3: {calls[0]} fwd+adjoint evaluations in {d1:.1f} s (cheaper p than the "
+                         f"study's 1..{W.p} mix)"}
+    mean_values = np.mean([v for _, v in res], axis=0)
+    out = {
+        "metric": f"fwd+grad QAOA evals/sec inside the angle-finding loop ({W.name})",
+        "value": round(rate, 1), "unit": "evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(dt / steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W.name, "description": W.description, "instances": len(W.graphs),
+                   "n": W.graphs[0].n, "p_max": W.p, "mixer": "x", "mode": "find_angles (basinhopping rounds)",
+                   "options": opts, "state": "complex64, FP64 sums", "parallelism": "single GPU"},
+        "roofline": roof,
+        "path": {"studies_per_s": steps / dt, "instances_per_s": steps * len(W.graphs) / dt,
+                 "evaluations_per_study": evals / steps, "launches_per_study": sm["launches"] / steps,
+                 "kernel_share_of_wall": sm["ms"] / (dt * 1e3), "mean_value_per_round": mean_values.tolist()},
+        "error": {"value_vs_oracle_max_rel": worst, "rounds_monotone": mono,
+                  "reference": "FP64 oracle <C> at the returned angles (rounds 1 and p of every instance)"},
+        "cpu_baseline": cpu, "kernels": prof,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def workloads_mod():
     import workloads
     return workloads
@@ -332,6 +420,8 @@ def main():
     W = workloads.workload(args.workload)
     if W.mixer == "grover":
         return main_grover(args, W, q, _lib, torch, np)
+    if W.name == "angles_er_n12_p10":
+        return main_angles(args, W, q, _lib, torch, np)
     steps = args.steps if args.steps is not None else {"maxcut3reg_n10_p3": 200, "maxcut3reg_n32_p16": 2}.get(W.name, 20)
     warmup = min(args.warmup, 1) if W.name == "maxcut3reg_n32_p16" else args.warmup
     grad = W.name != "maxcut3reg_n10_p3"

@@ -244,7 +244,7 @@ typedef struct qaoa_angle_opts {
   int maximize;          /* 1: maximise <C> (default); 0: minimise                          */
   int precision;         /* QAOA_FP32 (default) or QAOA_FP64 evaluations                    */
   int max_iter;          /* BFGS: accepted steps per local minimisation (default 100)       */
-  double gtol;           /* BFGS: stop once max_i |d<C>/d angle_i| <= gtol (default 1e-6)    */
+  double gtol;           /* BFGS: stop once max_i |d<C>/d angle_i| <= gtol max(1, |<C>|) (1e-5) */
   int n_chains;          /* basinhopping chains run side by side (default 8), <= 65535     */
   int n_hops;            /* basinhopping steps per chain after the first minimisation (10)  */
   double step;           /* hop: each angle moves by a uniform draw in [-step, step] (0.5)  */
@@ -257,18 +257,21 @@ typedef struct qaoa_angle_opts {
 void qaoa_angle_opts_default(qaoa_angle_opts *opts);
 
 /* Local minimisation from n_starts points at once (Sec. 2.3: BFGS to the closest local
- * optimum): BFGS with a backtracking Armijo line search, inverse-Hessian form, started from
- * the identity and rescaled after the first step. angles: host double [n_starts][2p], in:
+ * optimum): BFGS in inverse-Hessian form, started from the identity and rescaled after the
+ * first step, with a backtracking line search that accepts on sufficient decrease or on the
+ * approximate Wolfe conditions (a slope test that still works where single-precision
+ * rounding hides the change of <C>). angles: host double [n_starts][2p], in:
  * starting points, out: the optima found; out_values: host double [n_starts], <C> there;
  * out_iters (NULL allowed): accepted steps taken. Starts are batched max_sets_per_call at a
  * time (automatic: as many as keep 2 x sets x states x 16 bytes under 4 GiB). Stops on
- * gtol, max_iter, or a line search that fails to decrease the objective in 30 halvings. */
+ * gtol, max_iter, or a line search that finds no acceptable step in 20 halvings. */
 int qaoa_minimize(const qaoa_problem *prob, const qaoa_mixer *mix, int p, int n_starts, double *angles,
                   double *out_values, int *out_iters, const qaoa_angle_opts *opts, void *stream);
 
 /* Basinhopping (Sec. 2.3 and Sec. 3) from one point x0 (host double [2p]): n_chains chains
- * each minimise from x0, then take n_hops steps of perturb, minimise, Metropolis accept; all
- * chains' minimisations of a step run as one batch. out_angles (host [2p]) and out_value
+ * each minimise from x0, then take n_hops steps of perturb, minimise, Metropolis accept. The
+ * chains run independently (each starts its next hop when its minimisation ends) and every
+ * optimiser step evaluates the pending points of all chains as one batch. out_angles (host [2p]) and out_value
  * receive the best optimum seen by any chain (ties: earliest step, then lowest chain). */
 int qaoa_basinhopping(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *x0,
                       const qaoa_angle_opts *opts, double *out_angles, double *out_value, void *stream);

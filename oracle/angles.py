@@ -9,9 +9,11 @@ numpy FP64, on the oracle's <C> and adjoint gradient:
 
 * BFGS in inverse-Hessian form (Nocedal and Wright, Numerical Optimization, Alg. 6.1 with the
   update of their Eq. 6.17), H_0 = I rescaled to (s.y / y.y) I before the first update (their
-  Eq. 6.20), an update skipped when s.y <= 1e-10 |s| |y|; backtracking Armijo line search
-  (their Alg. 3.1) with c1 = 1e-4, halving, at most 30 halvings; first trial step 1, except
-  while H = I, where it is min(1, 1 / max|g|).
+  Eq. 6.20), an update skipped when s.y <= 1e-10 |s| |y|; backtracking line search by halving
+  (their Alg. 3.1), at most 20 halvings, accepting a step on sufficient decrease (c1 = 1e-4)
+  or on the approximate Wolfe conditions of Hager and Zhang (SIAM J. Optim. 16, 170 (2005);
+  sigma = 0.9, delta = 0.1, eps = 1e-6); first trial step 1, except while H = I, where it is
+  min(1, 1 / max|g|); converged when max|g| <= gtol max(1, |f|).
 * Basinhopping (Wales and Doye, J. Phys. Chem. A 101, 5111 (1997)): local minimisation,
   uniform perturbation in [-step, step] per angle, local minimisation, Metropolis acceptance
   with probability exp(-(f_new - f_cur) / T).
@@ -31,7 +33,8 @@ from . import grad as _grad
 MASK = (1 << 64) - 1
 GOLDEN = 0x9E3779B97F4A7C15
 ARMIJO = 1e-4
-MAX_HALVINGS = 30
+SIGMA, DELTA, EPS = 0.9, 0.1, 1e-6
+MAX_HALVINGS = 20
 
 
 # ---------------------------------------------------------------- SplitMix64
@@ -79,7 +82,7 @@ class Objective:
 
 # ---------------------------------------------------------------- BFGS
 
-def bfgs(fun, x0, gtol=1e-6, max_iter=100):
+def bfgs(fun, x0, gtol=1e-5, max_iter=100):
     """Local minimisation of fun (returning (f, grad)) from x0: (x, f, accepted steps)."""
     x = np.array(x0, dtype=np.float64)
     D = x.size
@@ -87,7 +90,11 @@ def bfgs(fun, x0, gtol=1e-6, max_iter=100):
     H = np.eye(D)
     unscaled = True
     steps = 0
-    if not np.isfinite(f) or np.max(np.abs(g)) <= gtol or max_iter <= 0:
+
+    def done(f, g):
+        return np.max(np.abs(g)) <= gtol * max(1.0, abs(f))
+
+    if not np.isfinite(f) or done(f, g) or max_iter <= 0:
         return x, f, steps
     while True:
         d = -H @ g
@@ -103,9 +110,13 @@ def bfgs(fun, x0, gtol=1e-6, max_iter=100):
         for _ in range(MAX_HALVINGS + 1):
             xt = x + alpha * d
             ft, gt = fun(xt)
-            if np.isfinite(ft) and ft <= f + ARMIJO * alpha * gd:
-                accepted = True
-                break
+            if np.isfinite(ft):
+                armijo = ft <= f + ARMIJO * alpha * gd
+                slope = gt @ d
+                wolfe = ft <= f + EPS * abs(f) and SIGMA * gd <= slope <= (2 * DELTA - 1) * gd
+                if armijo or wolfe:
+                    accepted = True
+                    break
             alpha *= 0.5
         if not accepted:
             break
@@ -120,14 +131,14 @@ def bfgs(fun, x0, gtol=1e-6, max_iter=100):
             H = V.T @ H @ V + rho * np.outer(s, s)
         x, f, g = xt, ft, gt
         steps += 1
-        if np.max(np.abs(g)) <= gtol or steps >= max_iter:
+        if done(f, g) or steps >= max_iter:
             break
     return x, f, steps
 
 
 # ---------------------------------------------------------------- basinhopping
 
-def basinhopping(fun, seeds, rnd, seed=0, n_hops=10, step=0.5, temperature=1.0, gtol=1e-6, max_iter=100):
+def basinhopping(fun, seeds, rnd, seed=0, n_hops=10, step=0.5, temperature=1.0, gtol=1e-5, max_iter=100):
     """Chains c start at seeds[c]; returns (best x, best f) over every minimum found, ties to
     the earliest hop, then the lowest chain."""
     seeds = np.asarray(seeds, dtype=np.float64)
@@ -174,7 +185,7 @@ def pad_zero_layer(x):
     return np.concatenate([x[:q], [0.0], x[q:], [0.0]])
 
 
-def find_angles(fun_for_round, p_max, seed=0, n_chains=8, n_hops=10, step=0.5, temperature=1.0, gtol=1e-6,
+def find_angles(fun_for_round, p_max, seed=0, n_chains=8, n_hops=10, step=0.5, temperature=1.0, gtol=1e-5,
                 max_iter=100, maximize=True):
     """Iterative rounds 1..p_max; fun_for_round(r) is the objective at r rounds. Round 1: chains
     from uniform angles in [0, 2 pi); round r: chain 0 from the padded round r-1 optimum, the
@@ -195,7 +206,7 @@ def find_angles(fun_for_round, p_max, seed=0, n_chains=8, n_hops=10, step=0.5, t
     return angles, np.array(values)
 
 
-def find_angles_random(fun, p, n_restarts, seed=0, gtol=1e-6, max_iter=100, maximize=True):
+def find_angles_random(fun, p, n_restarts, seed=0, gtol=1e-5, max_iter=100, maximize=True):
     """Random local-minima search: BFGS from n_restarts uniform starts in [0, 2 pi)^{2p}.
     Returns (best x, best <C>, <C> of every restart), ties to the lowest restart."""
     sign = -1.0 if maximize else 1.0

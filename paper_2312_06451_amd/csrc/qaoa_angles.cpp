@@ -8,10 +8,12 @@
 // Algorithms (the paper names them and leaves their details open):
 //  * BFGS in inverse-Hessian form (Nocedal and Wright, Numerical Optimization, Alg. 6.1 and
 //    Eq. 6.17), H_0 = I rescaled to (s.y / y.y) I before the first update (their Eq. 6.20),
-//    updates skipped when s.y <= 1e-10 |s| |y|; backtracking Armijo line search (their Alg.
-//    3.1) with c1 = 1e-4 and halving, first trial step 1 except after H = I, where it is
-//    min(1, 1 / max|g|) so no angle moves more than one radian; 30 halvings without
-//    sufficient decrease end the minimisation.
+//    updates skipped when s.y <= 1e-10 |s| |y|; backtracking line search by halving (their
+//    Alg. 3.1) that accepts on sufficient decrease (c1 = 1e-4) or on the approximate Wolfe
+//    conditions (sigma = 0.9, delta = 0.1, eps = 1e-6); first trial step 1 except while
+//    H = I, where it is min(1, 1 / max|g|) so no angle moves more than one radian; 20
+//    halvings without acceptance end the minimisation; converged when
+//    max|g| <= gtol max(1, |f|).
 //  * Basinhopping (Wales and Doye, J. Phys. Chem. A 101, 5111 (1997)): minimise, perturb every
 //    angle by a uniform draw in [-step, step], minimise, accept by the Metropolis rule
 //    exp(-(f_new - f_cur) / T).
@@ -170,18 +172,41 @@ double dot(const double *a, const double *b, int D) {
 struct Run {
   std::vector<double> x, g, H, d, xt;
   double f = 0.0, gd = 0.0, alpha = 1.0;
-  int iters = 0, halvings = 0;
+  int iters = 0, halvings = 0, owner = 0;
   bool unscaled = true;  // H = I, not yet rescaled by a first update
+  bool init = true;      // xt is the starting point, not yet evaluated
   bool done = false;
 };
 
-constexpr double kArmijo = 1e-4;
-constexpr int kMaxHalvings = 30;
+constexpr double kArmijo = 1e-4;  // sufficient decrease
+constexpr double kSigma = 0.9;    // approximate Wolfe: slope no steeper than sigma times the first
+constexpr double kDelta = 0.1;    // approximate Wolfe: slope no larger than (1 - 2 delta) |first|
+constexpr double kEps = 1e-6;     // approximate Wolfe: f may rise by eps |f|
+constexpr int kMaxHalvings = 20;
 
 void set_identity(Run &r, int D) {
   std::fill(r.H.begin(), r.H.end(), 0.0);
   for (int i = 0; i < D; i++) r.H[(size_t)i * D + i] = 1.0;
   r.unscaled = true;
+}
+
+void start_run(Run &r, int owner, const double *x0, int D) {
+  r.x.assign(D, 0.0);
+  r.g.assign(D, 0.0);
+  r.d.assign(D, 0.0);
+  r.H.assign((size_t)D * D, 0.0);
+  r.xt.assign(x0, x0 + D);
+  r.f = r.gd = 0.0;
+  r.alpha = 1.0;
+  r.iters = r.halvings = 0;
+  r.owner = owner;
+  r.init = true;
+  r.done = false;
+  set_identity(r, D);
+}
+
+bool converged(const Run &r, const qaoa_angle_opts &o, int D) {
+  return maxabs(r.g.data(), D) <= o.gtol * std::max(1.0, std::fabs(r.f));
 }
 
 // Search direction from the current (x, g, H); ends the run when g vanishes.
@@ -229,65 +254,82 @@ void bfgs_update(Run &r, const double *s, const double *y, int D) {
       r.H[(size_t)i * D + j] += -rho * (s[i] * Hy[j] + Hy[i] * s[j]) + c * s[i] * s[j];
 }
 
+// Consume the evaluation (ft, gt) of r.xt: the start point, or a line-search trial. A trial
+// is accepted on sufficient decrease (Armijo) or on the approximate Wolfe conditions of Hager
+// and Zhang (SIAM J. Optim. 16, 170 (2005)), which judge the step by the slope at the trial
+// point: with single-precision evaluations the change of f near an optimum drops below the
+// rounding of f while the gradient is still accurate.
+void advance(Run &r, double ft, const double *gt, int D, const qaoa_angle_opts &o) {
+  if (r.init) {
+    r.init = false;
+    r.x = r.xt;
+    r.f = ft;
+    r.g.assign(gt, gt + D);
+    if (!std::isfinite(r.f) || converged(r, o, D) || o.max_iter <= 0) r.done = true;
+    else new_direction(r, D);
+    return;
+  }
+  bool accept = false;
+  if (std::isfinite(ft)) {
+    const double slope = dot(gt, r.d.data(), D);
+    accept = ft <= r.f + kArmijo * r.alpha * r.gd ||
+             (ft <= r.f + kEps * std::fabs(r.f) && slope >= kSigma * r.gd && slope <= (2.0 * kDelta - 1.0) * r.gd);
+  }
+  if (accept) {
+    std::vector<double> s(D), y(D);
+    for (int j = 0; j < D; j++) {
+      s[j] = r.xt[j] - r.x[j];
+      y[j] = gt[j] - r.g[j];
+    }
+    bfgs_update(r, s.data(), y.data(), D);
+    r.x = r.xt;
+    r.f = ft;
+    r.g.assign(gt, gt + D);
+    r.iters++;
+    if (converged(r, o, D) || r.iters >= o.max_iter) r.done = true;
+    else new_direction(r, D);
+  } else {
+    r.alpha *= 0.5;
+    if (++r.halvings > kMaxHalvings) r.done = true;
+    else
+      for (int j = 0; j < D; j++) r.xt[j] = r.x[j] + r.alpha * r.d[j];
+  }
+}
+
+// Evaluate every live run's pending point in one paired call and advance each run.
+struct Stepper {
+  std::vector<double> pts, fv, gv;
+  std::vector<int> own;
+  void operator()(Objective &obj, const std::vector<Run *> &live, const qaoa_angle_opts &o) {
+    const int D = 2 * obj.p, L = (int)live.size();
+    pts.resize((size_t)L * D);
+    gv.resize((size_t)L * D);
+    fv.resize(L);
+    own.resize(L);
+    for (int a = 0; a < L; a++) {
+      std::memcpy(&pts[(size_t)a * D], live[a]->xt.data(), D * sizeof(double));
+      own[a] = live[a]->owner;
+    }
+    obj.eval(L, own.data(), pts.data(), fv.data(), gv.data());
+    for (int a = 0; a < L; a++) advance(*live[a], fv[a], &gv[(size_t)a * D], D, o);
+  }
+};
+
 // Minimise from m starts (xs, in place; start i belongs to instance owner[i]) -> f[m]
-// (objective f), iters[m].
+// (objective f), iters[m]. Every step evaluates all unfinished runs together.
 void minimize_many(Objective &obj, int m, const int *owner, double *xs, double *fout, int *iters,
                    const qaoa_angle_opts &o) {
   const int D = 2 * obj.p;
   std::vector<Run> runs(m);
-  std::vector<double> pts((size_t)m * D), fv(m), gv((size_t)m * D);
-  std::vector<int> own(m);
-  obj.eval(m, owner, xs, fv.data(), gv.data());
-  for (int i = 0; i < m; i++) {
-    Run &r = runs[i];
-    r.x.assign(xs + (size_t)i * D, xs + (size_t)(i + 1) * D);
-    r.g.assign(gv.begin() + (size_t)i * D, gv.begin() + (size_t)(i + 1) * D);
-    r.f = fv[i];
-    r.H.assign((size_t)D * D, 0.0);
-    r.d.assign(D, 0.0);
-    r.xt.assign(D, 0.0);
-    set_identity(r, D);
-    if (!std::isfinite(r.f) || maxabs(r.g.data(), D) <= o.gtol || o.max_iter <= 0) r.done = true;
-    else new_direction(r, D);
-  }
-  std::vector<int> live;
-  std::vector<double> s(D), y(D);
+  for (int i = 0; i < m; i++) start_run(runs[i], owner[i], xs + (size_t)i * D, D);
+  std::vector<Run *> live;
+  Stepper step;
   for (;;) {
     live.clear();
-    for (int i = 0; i < m; i++)
-      if (!runs[i].done) live.push_back(i);
+    for (auto &r : runs)
+      if (!r.done) live.push_back(&r);
     if (live.empty()) break;
-    const int L = (int)live.size();
-    for (int a = 0; a < L; a++) {
-      std::memcpy(&pts[(size_t)a * D], runs[live[a]].xt.data(), D * sizeof(double));
-      own[a] = owner[live[a]];
-    }
-    obj.eval(L, own.data(), pts.data(), fv.data(), gv.data());
-    for (int a = 0; a < L; a++) {
-      Run &r = runs[live[a]];
-      const double ft = fv[a];
-      const double *gt = &gv[(size_t)a * D];
-      if (std::isfinite(ft) && ft <= r.f + kArmijo * r.alpha * r.gd) {
-        for (int j = 0; j < D; j++) {
-          s[j] = r.xt[j] - r.x[j];
-          y[j] = gt[j] - r.g[j];
-        }
-        bfgs_update(r, s.data(), y.data(), D);
-        r.x = r.xt;
-        r.f = ft;
-        r.g.assign(gt, gt + D);
-        r.iters++;
-        if (maxabs(r.g.data(), D) <= o.gtol || r.iters >= o.max_iter) r.done = true;
-        else new_direction(r, D);
-      } else {
-        r.alpha *= 0.5;
-        if (++r.halvings > kMaxHalvings) {
-          r.done = true;
-        } else {
-          for (int j = 0; j < D; j++) r.xt[j] = r.x[j] + r.alpha * r.d[j];
-        }
-      }
-    }
+    step(obj, live, o);
   }
   for (int i = 0; i < m; i++) {
     std::memcpy(xs + (size_t)i * D, runs[i].x.data(), D * sizeof(double));
@@ -300,42 +342,69 @@ void minimize_many(Objective &obj, int m, const int *owner, double *xs, double *
 
 // Basinhopping for n_inst instances at once: chain c of instance i starts at
 // seeds[(i * C + c) * 2p ..]; instance i's best optimum -> best_x[i * 2p ..], best_f[i]
-// (objective f). Draws depend on (round, c, hop) only, so an instance's result does not depend
-// on the other instances solved with it.
+// (objective f), ties to the earliest hop, then the lowest chain. Chains run independently:
+// a chain starts its next hop as soon as its minimisation ends, and every step evaluates the
+// pending points of all chains together. Draws depend on (round, c, hop) only, so a chain's
+// path, and an instance's result, do not depend on the other chains or instances.
 void basinhop(Objective &obj, int round, int n_inst, const double *seeds, const qaoa_angle_opts &o, double *best_x,
               double *best_f) {
   const int D = 2 * obj.p, C = o.n_chains, m = n_inst * C;
-  std::vector<double> cur(seeds, seeds + (size_t)m * D), fcur(m), trial((size_t)m * D), ft(m);
-  std::vector<int> owner(m);
-  for (int i = 0; i < m; i++) owner[i] = i / C;
-  minimize_many(obj, m, owner.data(), cur.data(), fcur.data(), nullptr, o);
-  for (int i = 0; i < n_inst; i++) {
-    int bi = i * C;
-    for (int c = 1; c < C; c++)
-      if (fcur[i * C + c] < fcur[bi]) bi = i * C + c;
-    std::memcpy(best_x + (size_t)i * D, &cur[(size_t)bi * D], D * sizeof(double));
-    best_f[i] = fcur[bi];
-  }
-  for (int h = 0; h < o.n_hops; h++) {
-    for (int i = 0; i < m; i++)
-      for (int j = 0; j < D; j++)
-        trial[(size_t)i * D + j] = cur[(size_t)i * D + j] + o.step * (2.0 * uniform(o.seed, round, i % C, h, j) - 1.0);
-    minimize_many(obj, m, owner.data(), trial.data(), ft.data(), nullptr, o);
+  struct Chain {
+    Run run;
+    std::vector<double> cur, bx;
+    double fcur = 0.0, bf = 0.0;
+    int hop = -1, bh = -1;
+    bool finished = false;
+  };
+  std::vector<Chain> ch(m);
+  for (int i = 0; i < m; i++) start_run(ch[i].run, i / C, seeds + (size_t)i * D, D);
+  std::vector<Run *> live;
+  std::vector<double> xt(D);
+  Stepper step;
+  for (;;) {
+    live.clear();
+    for (auto &c : ch)
+      if (!c.finished) live.push_back(&c.run);
+    if (live.empty()) break;
+    step(obj, live, o);
     for (int i = 0; i < m; i++) {
-      const double df = ft[i] - fcur[i];
-      bool accept = ft[i] < fcur[i];
-      if (!accept && o.temperature > 0.0 && std::isfinite(df))
-        accept = uniform(o.seed, round, i % C, h, D) < std::exp(-df / o.temperature);
-      if (accept) {
-        std::memcpy(&cur[(size_t)i * D], &trial[(size_t)i * D], D * sizeof(double));
-        fcur[i] = ft[i];
+      Chain &c = ch[i];
+      if (c.finished || !c.run.done) continue;
+      const int cc = i % C;
+      if (c.hop < 0) {
+        c.cur = c.run.x;
+        c.fcur = c.run.f;
+        c.bx = c.cur;
+        c.bf = c.fcur;
+      } else {
+        const double ft = c.run.f, df = ft - c.fcur;
+        bool accept = ft < c.fcur;
+        if (!accept && o.temperature > 0.0 && std::isfinite(df))
+          accept = uniform(o.seed, round, cc, c.hop, D) < std::exp(-df / o.temperature);
+        if (ft < c.bf) {
+          c.bf = ft;
+          c.bh = c.hop;
+          c.bx = c.run.x;
+        }
+        if (accept) {
+          c.cur = c.run.x;
+          c.fcur = ft;
+        }
       }
-      const int inst = i / C;
-      if (ft[i] < best_f[inst]) {
-        best_f[inst] = ft[i];
-        std::memcpy(best_x + (size_t)inst * D, &trial[(size_t)i * D], D * sizeof(double));
+      if (++c.hop < o.n_hops) {
+        for (int j = 0; j < D; j++) xt[j] = c.cur[j] + o.step * (2.0 * uniform(o.seed, round, cc, c.hop, j) - 1.0);
+        start_run(c.run, i / C, xt.data(), D);
+      } else {
+        c.finished = true;
       }
     }
+  }
+  for (int i = 0; i < n_inst; i++) {
+    int b = i * C;
+    for (int c = i * C + 1; c < (i + 1) * C; c++)
+      if (ch[c].bf < ch[b].bf || (ch[c].bf == ch[b].bf && ch[c].bh < ch[b].bh)) b = c;
+    std::memcpy(best_x + (size_t)i * D, ch[b].bx.data(), D * sizeof(double));
+    best_f[i] = ch[b].bf;
   }
 }
 
@@ -468,7 +537,7 @@ void qaoa_angle_opts_default(qaoa_angle_opts *o) {
   o->maximize = 1;
   o->precision = QAOA_FP32;
   o->max_iter = 100;
-  o->gtol = 1e-6;
+  o->gtol = 1e-5;
   o->n_chains = 8;
   o->n_hops = 10;
   o->step = 0.5;

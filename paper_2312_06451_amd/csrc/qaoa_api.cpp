@@ -811,9 +811,17 @@ void run_small(const std::vector<SmallItem> &items, int precision, const double 
   int nrow = 0;
   for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
   double *dres = (double *)ctx->results.get((size_t)nrow * rowlen * sizeof(double));
-  double by = 0;
-  for (auto &it : items) by += (double)it.tbytes * (double)(1ull << it.n);
-  KTimer kt(ctx, st, QAOA_KC_SMALL, by, 0.0);
+  // algorithmic work per item: the table read once; FP32 flops of the method per amplitude:
+  // 6 per qubit rotation and 6 per phase multiply in each layer, and with the gradient the
+  // same again on the state and on the adjoint vector plus 4 per qubit and 4 per layer for
+  // the derivative sums; 4 for <C> and the norm
+  double by = 0, fl = 0;
+  for (auto &it : items) {
+    const double N = (double)(1ull << it.n);
+    by += (double)it.tbytes * N;
+    fl += (double)p * N * (grad ? 22.0 * it.n + 22.0 : 6.0 * it.n + 6.0) + 4.0 * N;
+  }
+  KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
   HIPCHK(launch_small(precision, (const SmallItem *)d, (int)items.size(), max_n, max_tb, max_lut,
                       (const double *)(d + off_a), p, grad, dres, st));
   kt.done();

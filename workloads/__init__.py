@@ -159,6 +159,12 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
         ns = 512 if n_sets is None else n_sets
         return Workload(name, "MaxCut, random 3-regular n=40, Grover mixer (table-free degeneracies), p=16, "
                               "512 sets", [g], 16, random_angles(16, ns, 6041), mixer="grover")
+    if name == "angles_er_n12_p10":
+        # the angle-finding study of Sec. 2.3: 50 unweighted G(12, 1/2) MaxCut instances, rounds
+        # 1..10 of iterative basinhopping; the search draws its own angles (seed in extra)
+        graphs = [erdos_renyi(12, 7000 + i, 0.5) for i in range(50 if n_sets is None else n_sets)]
+        return Workload(name, "angle finding: 50 MaxCut G(12,1/2) instances, iterative basinhopping to p=10",
+                        graphs, 10, np.zeros((0, 20)), extra={"seed": 7100, "n_chains": 8, "n_hops": 10})
     if name == "maxcut3reg_n32_p16":
         g, a = _maxcut_3reg(32, 16, 5032)
         return Workload(name, "MaxCut, random 3-regular n=32, X mixer, p=16, fwd+grad",
@@ -167,4 +173,4 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
 
 
 WORKLOADS = ["maxcut3reg_n10_p3", "maxcut3reg_n28_p8", "batched_er_n12to20_p10",
-             "bisection_g16_k8_p6", "maxcut3reg_n32_p16", "grover_maxcut3reg_n40_p16"]
+             "bisection_g16_k8_p6", "maxcut3reg_n32_p16", "grover_maxcut3reg_n40_p16", "angles_er_n12_p10"]
