@@ -787,14 +787,28 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
 }
 
 // Whole-state path: items of n <= SMALL_MAX_N, one workgroup each.
-void run_small(const std::vector<SmallItem> &items, int precision, const double *angles, int nsets,
+void run_small(const std::vector<SmallItem> &items_in, int precision, const double *angles, int nsets,
                int p, int grad, double *hout, qaoa_ctx *ctx, hipStream_t st) {
-  (void)nsets;
+  // items whose state fits the register-resident kernel go first, grouped by (n, table width);
+  // the rest run in the LDS kernel
+  std::vector<SmallItem> items;
+  std::vector<std::tuple<int, int, size_t, size_t>> groups;  // n, tbytes, first, count (first = LDS kernel)
+  for (int n : {12, 13})
+    for (int tb : {1, 2}) {
+      if (!whole_supported(precision, n)) continue;
+      const size_t first = items.size();
+      for (auto &it : items_in)
+        if (it.n == n && it.tbytes == tb) items.push_back(it);
+      if (items.size() > first) groups.emplace_back(n, tb, first, items.size() - first);
+    }
+  const size_t nwhole = items.size();
   int max_n = 1, max_tb = 1, max_lut = 1;
-  for (auto &it : items) {
+  for (auto &it : items_in) {
+    max_lut = std::max(max_lut, it.lut_len);
+    if (whole_supported(precision, it.n)) continue;
+    items.push_back(it);
     max_n = std::max(max_n, it.n);
     max_tb = std::max(max_tb, it.tbytes);
-    max_lut = std::max(max_lut, it.lut_len);
   }
   max_lut = (max_lut + 15) & ~15;
   const int rowlen = 1 + 2 * p;
@@ -811,20 +825,37 @@ void run_small(const std::vector<SmallItem> &items, int precision, const double 
   int nrow = 0;
   for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
   double *dres = (double *)ctx->results.get((size_t)nrow * rowlen * sizeof(double));
+  const SmallItem *ditems = (const SmallItem *)d;
+  const double *dang = (const double *)(d + off_a);
   // algorithmic work per item: the table read once; FP32 flops of the method per amplitude:
   // 6 per qubit rotation and 6 per phase multiply in each layer, and with the gradient the
   // same again on the state and on the adjoint vector plus 4 per qubit and 4 per layer for
   // the derivative sums; 4 for <C> and the norm
-  double by = 0, fl = 0;
-  for (auto &it : items) {
-    const double N = (double)(1ull << it.n);
-    by += (double)it.tbytes * N;
-    fl += (double)p * N * (grad ? 22.0 * it.n + 22.0 : 6.0 * it.n + 6.0) + 4.0 * N;
+  auto work = [&](size_t first, size_t count, double &by, double &fl) {
+    by = fl = 0.0;
+    for (size_t i = first; i < first + count; i++) {
+      const SmallItem &it = items[i];
+      const double N = (double)(1ull << it.n);
+      by += (double)it.tbytes * N;
+      fl += (double)p * N * (grad ? 22.0 * it.n + 22.0 : 6.0 * it.n + 6.0) + 4.0 * N;
+    }
+  };
+  for (auto &g : groups) {
+    double by, fl;
+    work(std::get<2>(g), std::get<3>(g), by, fl);
+    KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
+    HIPCHK(launch_whole(precision, std::get<0>(g), std::get<1>(g), ditems + std::get<2>(g), (int)std::get<3>(g),
+                        max_lut, dang, p, grad, dres, st));
+    kt.done();
   }
-  KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
-  HIPCHK(launch_small(precision, (const SmallItem *)d, (int)items.size(), max_n, max_tb, max_lut,
-                      (const double *)(d + off_a), p, grad, dres, st));
-  kt.done();
+  if (items.size() > nwhole) {
+    double by, fl;
+    work(nwhole, items.size() - nwhole, by, fl);
+    KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
+    HIPCHK(launch_small(precision, ditems + nwhole, (int)(items.size() - nwhole), max_n, max_tb, max_lut, dang, p,
+                        grad, dres, st));
+    kt.done();
+  }
   HIPCHK(hipMemcpyAsync(hout, dres, (size_t)nrow * rowlen * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   profile_collect(ctx);

@@ -155,6 +155,11 @@ hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int
 hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
                         int max_tbytes, int max_lut, const double *angles, int p, int grad,
                         double *out, hipStream_t s);
+// Whole-state evaluation with the state in registers, for n = 12, 13 (FP32) or n = 12 (FP64):
+// every item must have that n and table width.
+bool whole_supported(int precision, int n);
+hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items, int n_items, int max_lut,
+                        const double *angles, int p, int grad, double *out, hipStream_t s);
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
                              double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);

@@ -30,6 +30,8 @@
 // LDS buffer. The phase multiply, the <C> reduction, the adjoint initialisation and the
 // gradient inner products are fused into the passes.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <cstdint>
 #include "qaoa_internal.h"
 
@@ -225,7 +227,7 @@ __device__ __forceinline__ uint32_t lbase(uint32_t t) {
   else if constexpr (A == AM)
     return (t & ((1u << G::MLO) - 1)) +
            (t >> G::MLO) * ((1u << (G::MLO + G::RB)) + (1u << (G::MLO + G::RB - PS)));
-  else return t * ((1u << G::RB) + (1u << (G::RB - PS)));
+  else return (t << G::RB) + ((t << G::RB) >> PS);  // register part below bit PS: no carry
 }
 template <typename R, int T, int A>
 __device__ constexpr uint32_t loff(int j) {
@@ -867,6 +869,192 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
   }
 }
 
+// ============================================================== whole state in registers
+
+// The same evaluation as k_small for a state of exactly 2^T amplitudes (T = 12, 13), held in
+// registers as one tile (TileCfg<T>: 256 threads, 2^(T-8) amplitudes each): a layer is the
+// phase multiply in the current register assignment and three register stages joined by two
+// LDS exchanges, instead of one LDS pass per qubit. Layers alternate the stage order (H, M, L
+// then L, M, H) so the next layer starts in the assignment the last one ended in; the reverse
+// sweep undoes each layer in the opposite order, taking the X-pair terms of each group of
+// bits before rotating it (weighted by the rotations of the layer done so far, as in the tile
+// passes). Scalars, flips and the FP64 sums as in k_small.
+
+// cost-table index of tile element e (the stored vector is flipped by F)
+template <typename TT>
+__device__ __forceinline__ uint32_t widx(const unsigned char *tab, uint32_t e, uint32_t F) {
+  return (uint32_t)((const TT *)tab)[e ^ F];
+}
+
+template <typename R, int T, typename TT, int A, int NV>
+__device__ __forceinline__ void w_phase(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
+                                        const unsigned char *tab, const typename Cplx<R>::T2 *lut,
+                                        uint32_t F, uint32_t t) {
+  using T2 = typename Cplx<R>::T2;
+#pragma unroll
+  for (int j = 0; j < TileCfg<T>::RN; j++) {
+    const T2 L = lut[widx<TT>(tab, elem<A, T>(t, j), F)];
+    phi[j] = cmul<T2, R>(phi[j], L);
+    if constexpr (NV == 2) lam[j] = cmul<T2, R>(lam[j], L);
+  }
+}
+
+// <C> and norm partial sums, then lam = (C - c0) phi
+template <typename R, int T, typename TT, int A>
+__device__ __forceinline__ void w_end(const typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
+                                      const unsigned char *tab, const double *dval, double c0, uint32_t F,
+                                      uint32_t t, double &e, double &nr) {
+#pragma unroll
+  for (int j = 0; j < TileCfg<T>::RN; j++) {
+    const double c = dval[widx<TT>(tab, elem<A, T>(t, j), F)];
+    const double pr = (double)phi[j].x * phi[j].x + (double)phi[j].y * phi[j].y;
+    e += pr * c;
+    nr += pr;
+    const R kf = (R)(c - c0);
+    lam[j].x = kf * phi[j].x;
+    lam[j].y = kf * phi[j].y;
+  }
+}
+
+// sum of Im(conj(lam) phi) (C - c0)
+template <typename R, int T, typename TT, int A>
+__device__ __forceinline__ double w_ggamma(const typename Cplx<R>::T2 *phi, const typename Cplx<R>::T2 *lam,
+                                           const unsigned char *tab, const double *dval, double c0, uint32_t F,
+                                           uint32_t t) {
+  double g = 0.0;
+#pragma unroll
+  for (int j = 0; j < TileCfg<T>::RN; j++) {
+    const double c = dval[widx<TT>(tab, elem<A, T>(t, j), F)] - c0;
+    g += (double)fmaR(lam[j].x, phi[j].y, -lam[j].y * phi[j].x) * c;
+  }
+  return g;
+}
+
+// Forward mixer of one layer: stages A0, M, A2 (A0 = H, A2 = L when DOWN).
+template <typename R, int T, bool DOWN>
+__device__ __forceinline__ void w_fwd_mixer(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lds, uint32_t t,
+                                            R tau) {
+  constexpr int A0 = DOWN ? AH : AL, A2 = DOWN ? AL : AH;
+  constexpr uint32_t all = (1u << T) - 1;
+  double w = 1.0, acc = 0.0;
+  stage<R, T, 1, A0, false, false>(phi, phi, all, tau, w, acc);
+  xchg1<R, T, A0, AM>(lds, phi, t);
+  stage<R, T, 1, AM, false, false>(phi, phi, all, tau, w, acc);
+  xchg1<R, T, AM, A2>(lds, phi, t);
+  stage<R, T, 1, A2, false, false>(phi, phi, all, tau, w, acc);
+}
+
+// Reverse of a layer whose forward order was DOWN: undo stages A2, M, A0 on both vectors,
+// X-pair terms first in each; returns the thread's weighted X-pair sum.
+template <typename R, int T, bool DOWN>
+__device__ __forceinline__ double w_rev_mixer(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
+                                              typename Cplx<R>::T2 *lds, uint32_t t, R tau) {
+  constexpr int A0 = DOWN ? AH : AL, A2 = DOWN ? AL : AH;
+  constexpr uint32_t all = (1u << T) - 1;
+  double w = 1.0, acc = 0.0;
+  stage<R, T, 2, A2, true, true>(phi, lam, all, -tau, w, acc);
+  xchg<R, T, 2, A2, AM>(lds, phi, lam, t);
+  stage<R, T, 2, AM, true, true>(phi, lam, all, -tau, w, acc);
+  xchg<R, T, 2, AM, A0>(lds, phi, lam, t);
+  stage<R, T, 2, A0, true, true>(phi, lam, all, -tau, w, acc);
+  return acc;
+}
+
+template <typename R, int T, typename TT>
+__global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ items, const double *__restrict__ angles,
+                                               int p, int grad, int max_lut, double *__restrict__ out) {
+  using G = TileCfg<T>;
+  using T2 = typename Cplx<R>::T2;
+  constexpr int RN = G::RN;
+  constexpr uint32_t N = 1u << T;
+  constexpr uint32_t kSlots = N + (N >> Pad<R>::PS);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2 *lds = (T2 *)smem;
+  T2 *lut = lds + kSlots;
+  double *dval = (double *)(lut + max_lut);
+  unsigned char *tab = (unsigned char *)(dval + max_lut);
+  double *red = (double *)(tab + ((N * sizeof(TT) + 15) & ~15u));
+  const SmallItem it = items[blockIdx.x];
+  const uint32_t t = threadIdx.x;
+  const double *ang = angles + (size_t)it.angle_set * 2 * p;
+
+  for (uint32_t i = t; i < N * sizeof(TT) / 4; i += 256) ((uint32_t *)tab)[i] = ((const uint32_t *)it.table)[i];
+  for (int c = t; c < it.lut_len; c += 256) dval[c] = it.vals[c];
+  uint32_t F = 0;
+  const uint32_t FALL = it.sym ? 0u : N - 1;
+  DC sig{1.0, 0.0};
+  auto build_lut = [&](double gamma, double sign) {
+    __syncthreads();
+    for (int c = t; c < it.lut_len; c += 256) {
+      double sn, co;
+      sincos(sign * gamma * dval[c], &sn, &co);
+      lut[c] = T2{(R)(sig.re * co - sig.im * sn), (R)(sig.re * sn + sig.im * co)};
+    }
+    __syncthreads();
+  };
+
+  T2 phi[RN], lam[RN];
+  const R u0 = (R)(1.0 / sqrt((double)N));
+#pragma unroll
+  for (int j = 0; j < RN; j++) phi[j] = T2{u0, (R)0};
+
+  // ---- forward: layer k starts in H when k is even (H, M, L) and in L when odd (L, M, H)
+  auto fwd_layer = [&](int k, auto down) {
+    constexpr bool D = decltype(down)::value;
+    build_lut(ang[p + k], -1.0);
+    w_phase<R, T, TT, D ? AH : AL, 1>(phi, lam, tab, lut, F, t);
+    sig = DC{1.0, 0.0};
+    R tau;
+    DC f, finv;
+    bool fl;
+    rot_params<R>(ang[k], tau, f, finv, fl);
+    w_fwd_mixer<R, T, D>(phi, lds, t, tau);
+    if (fl) F ^= FALL;
+    for (int qb = 0; qb < T; qb++) sig = dmul(sig, f);
+  };
+  for (int k = 0; k < p; k += 2) {
+    fwd_layer(k, std::true_type{});
+    if (k + 1 < p) fwd_layer(k + 1, std::false_type{});
+  }
+  // ends in L after an odd number of layers, in H after an even number
+  double e = 0.0, nr = 0.0;
+  if (p & 1) w_end<R, T, TT, AL>(phi, lam, tab, dval, it.c0, F, t, e, nr);
+  else w_end<R, T, TT, AH>(phi, lam, tab, dval, it.c0, F, t, e, nr);
+  e = block_sum(e, red);
+  nr = block_sum(nr, red);
+  const double ntrue = (sig.re * sig.re + sig.im * sig.im) * nr;
+  double *o = out + (size_t)it.out_index * (1 + 2 * p);
+  if (t == 0) o[0] = e / nr;
+  if (!grad) return;
+
+  // ---- reverse: layer k was DOWN when k is even; undoing it ends in its first assignment
+  auto rev_layer = [&](int k, auto down) {
+    constexpr bool D = decltype(down)::value;
+    constexpr int A0 = D ? AH : AL;
+    const double wgt = sig.re * sig.re + sig.im * sig.im;
+    R tau;
+    DC f, finv;
+    bool fl;
+    rot_params<R>(ang[k], tau, f, finv, fl);
+    const double gb = block_sum(w_rev_mixer<R, T, D>(phi, lam, lds, t, tau), red);
+    if (t == 0) o[1 + k] = 2.0 * wgt * gb / ntrue;
+    if (fl) F ^= FALL;
+    for (int qb = 0; qb < T; qb++) sig = dmul(sig, finv);
+    const double gg = block_sum(w_ggamma<R, T, TT, A0>(phi, lam, tab, dval, it.c0, F, t), red);
+    const double wg2 = sig.re * sig.re + sig.im * sig.im;
+    if (t == 0) o[1 + p + k] = 2.0 * wg2 * gg / ntrue;
+    if (k > 0) {
+      build_lut(ang[p + k], 1.0);
+      w_phase<R, T, TT, A0, 2>(phi, lam, tab, lut, F, t);
+      sig = DC{1.0, 0.0};
+    }
+  };
+  for (int k = p - 1; k >= 0; k--) {
+    if (k & 1) rev_layer(k, std::false_type{});
+    else rev_layer(k, std::true_type{});
+  }
+}
+
 // ============================================================== launch wrappers
 
 static unsigned grid_for(uint64_t N, unsigned threads) {
@@ -1045,6 +1233,43 @@ hipError_t launch_small(int precision, const SmallItem *items, int n_items, int 
     hipLaunchKernelGGL((k_small<double>), dim3(n_items), dim3(256), lds, s, items, angles, p,
                        grad, max_n, max_tbytes, max_lut, out);
   return hipGetLastError();
+}
+
+template <typename R, int T, typename TT>
+static hipError_t launch_whole_t(const SmallItem *items, int n_items, int max_lut, const double *angles, int p,
+                                 int grad, double *out, hipStream_t s) {
+  using T2 = typename Cplx<R>::T2;
+  constexpr size_t N = size_t(1) << T;
+  const size_t lds = (N + (N >> Pad<R>::PS)) * sizeof(T2) + (size_t)max_lut * (sizeof(T2) + sizeof(double)) +
+                     ((N * sizeof(TT) + 15) & ~size_t(15)) + 64;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_whole<R, T, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_whole<R, T, TT>), dim3(n_items), dim3(256), lds, s, items, angles, p, grad, max_lut, out);
+  return hipGetLastError();
+}
+
+bool whole_supported(int precision, int n) { return precision == 0 ? (n == 12 || n == 13) : n == 12; }
+
+hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items, int n_items, int max_lut,
+                        const double *angles, int p, int grad, double *out, hipStream_t s) {
+  if (precision == 0) {
+    if (n == 12)
+      return tbytes == 1 ? launch_whole_t<float, 12, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s)
+                         : launch_whole_t<float, 12, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s);
+    if (n == 13)
+      return tbytes == 1 ? launch_whole_t<float, 13, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s)
+                         : launch_whole_t<float, 13, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s);
+  } else if (n == 12) {
+    return tbytes == 1 ? launch_whole_t<double, 12, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s)
+                       : launch_whole_t<double, 12, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
