@@ -138,6 +138,32 @@ int qaoa_mixer_ring(qaoa_ctx *ctx, int n, int k, qaoa_mixer **out, void *stream)
 int qaoa_mixer_matrix(qaoa_ctx *ctx, int n, int hamming_k, const double *host_matrix, qaoa_mixer **out,
                       void *stream);
 
+/* Mixers built from products of Pauli X (Sec. 2.1, Eq. (2): a Hadamard on every qubit turns
+ * f(X) into the diagonal f(Z)), for unconstrained problems, n <= 32. Every layer runs as the
+ * cost phase, a Walsh-Hadamard transform, the diagonal e^{-i beta d(y)} and the transform again,
+ * in FP32 or FP64 like the other mixers; the gradient comes from the same reverse sweep.
+ *
+ * qaoa_mixer_x_orders: H_M = sum over k in orders[0..n_orders) of the sum over all k-subsets S
+ * of prod_{i in S} X_i (orders distinct, in [1, n]; {1} is the transverse field). The diagonal
+ * depends on the Hamming weight w of y only: d = sum_k K_k(w), K_k the Krawtchouk polynomial. */
+int qaoa_mixer_x_orders(qaoa_ctx *ctx, int n, const int *orders, int n_orders, qaoa_mixer **out);
+
+/* H_M = sum_t coefs[t] prod_{i: bit i of masks[t] set} X_i, 1 <= n_terms <= 10 (masks nonzero,
+ * below 2^n; coefs finite). d(y) = sum_t coefs[t] (-1)^{popcount(y & masks[t])}. */
+int qaoa_mixer_x_terms(qaoa_ctx *ctx, int n, const uint64_t *masks, const double *coefs, int n_terms,
+                       qaoa_mixer **out);
+
+/* Multi-angle mixer (Sec. 3: several mixers per layer, each with its own angle): layer k applies
+ * prod_q e^{-i beta_{k,q} X_q}. With this mixer an angle set holds p (n + 1) entries,
+ * [beta_{1,0..n-1}, ..., beta_{p,0..n-1}, gamma_1..gamma_p], and the gradient has the same
+ * layout; qaoa_expect, qaoa_expect_grad, qaoa_state and the batched and paired calls accept it
+ * (all mixers of one batched or paired call must take the same number of angles). */
+int qaoa_mixer_x_multiangle(qaoa_ctx *ctx, int n, qaoa_mixer **out);
+
+/* Mixer metadata: qubits, hamming_k (-1: all states), angles per layer of an angle set (2, or
+ * n + 1 for the multi-angle mixer). Any output pointer may be NULL. */
+int qaoa_mixer_info(const qaoa_mixer *mix, int *n, int *hamming_k, int *angles_per_layer);
+
 /* Stored eigendecomposition of a clique, ring or matrix mixer (Sec. 2.1: the decomposition
  * is computed once and stored for re-use): copies the FP64 eigenvectors (column j, the j-th
  * eigenvector, at host_V[j * N .. j * N + N)) and eigenvalues host_D[0..N) to the host. N must
@@ -324,7 +350,8 @@ int qaoa_find_angles_random(const qaoa_problem *prob, const qaoa_mixer *mix, int
 #define QAOA_KC_OTHER 4
 #define QAOA_KC_GROVER 5       /* Grover-mixer rounds on the cost classes */
 #define QAOA_KC_COUNT_STATES 6 /* table-free degeneracy counting */
-#define QAOA_KC_COUNT 7
+#define QAOA_KC_XMIX 7         /* X-product mixers: Walsh-Hadamard passes and diagonals */
+#define QAOA_KC_COUNT 8
 int qaoa_profile_enable(qaoa_ctx *ctx, int enable);
 
 /* Totals of class `kernel_class` since the last enable: launches, summed milliseconds,

@@ -28,10 +28,11 @@ EXPORTED = [
     "qaoa_cost_degeneracies", "qaoa_problem_degeneracies", "qaoa_mixer_ring", "qaoa_mixer_matrix",
     "qaoa_mixer_eigen", "qaoa_mixer_from_eigen", "qaoa_angle_opts_default", "qaoa_minimize",
     "qaoa_basinhopping", "qaoa_find_angles", "qaoa_find_angles_random", "qaoa_find_angles_multi",
-    "qaoa_expect_pairs", "qaoa_expect_grad_pairs",
+    "qaoa_expect_pairs", "qaoa_expect_grad_pairs", "qaoa_mixer_x_orders", "qaoa_mixer_x_terms",
+    "qaoa_mixer_x_multiangle", "qaoa_mixer_info",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
-                  "count_states": 6}
+                  "count_states": 6, "xmix": 7}
 
 
 class qaoa_angle_opts(ctypes.Structure):
@@ -83,6 +84,10 @@ def lib() -> ctypes.CDLL:
     L.qaoa_mixer_clique.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
     L.qaoa_mixer_grover.argtypes = [c_void_p, c_int, c_int, P(c_void_p)]
     L.qaoa_mixer_ring.argtypes = [c_void_p, c_int, c_int, P(c_void_p), c_void_p]
+    L.qaoa_mixer_x_orders.argtypes = [c_void_p, c_int, P(c_int), c_int, P(c_void_p)]
+    L.qaoa_mixer_x_terms.argtypes = [c_void_p, c_int, P(ctypes.c_uint64), P(c_double), c_int, P(c_void_p)]
+    L.qaoa_mixer_x_multiangle.argtypes = [c_void_p, c_int, P(c_void_p)]
+    L.qaoa_mixer_info.argtypes = [c_void_p, P(c_int), P(c_int), P(c_int)]
     L.qaoa_mixer_eigen.argtypes = [c_void_p, P(c_double), P(c_double), c_size_t, c_void_p]
     L.qaoa_mixer_from_eigen.argtypes = [c_void_p, c_int, c_int, P(c_double), P(c_double), P(c_void_p), c_void_p]
     L.qaoa_mixer_matrix.argtypes = [c_void_p, c_int, c_int, P(c_double), P(c_void_p), c_void_p]
@@ -244,6 +249,33 @@ def qaoa_mixer_from_eigen(ctx: int, n: int, hamming_k: int, V, D, stream: int = 
     return out.value
 
 
+def qaoa_mixer_x_orders(ctx: int, n: int, orders) -> int:
+    o = (c_int * len(orders))(*[int(x) for x in orders])
+    out = c_void_p()
+    check(lib().qaoa_mixer_x_orders(ctx, n, o, len(orders), ctypes.byref(out)), "qaoa_mixer_x_orders")
+    return out.value
+
+
+def qaoa_mixer_x_terms(ctx: int, n: int, masks, coefs) -> int:
+    m = (ctypes.c_uint64 * len(masks))(*[int(x) for x in masks])
+    c = (c_double * len(coefs))(*[float(x) for x in coefs])
+    out = c_void_p()
+    check(lib().qaoa_mixer_x_terms(ctx, n, m, c, len(masks), ctypes.byref(out)), "qaoa_mixer_x_terms")
+    return out.value
+
+
+def qaoa_mixer_x_multiangle(ctx: int, n: int) -> int:
+    out = c_void_p()
+    check(lib().qaoa_mixer_x_multiangle(ctx, n, ctypes.byref(out)), "qaoa_mixer_x_multiangle")
+    return out.value
+
+
+def qaoa_mixer_info(mix: int) -> dict:
+    n, k, apl = c_int(), c_int(), c_int()
+    check(lib().qaoa_mixer_info(mix, ctypes.byref(n), ctypes.byref(k), ctypes.byref(apl)), "qaoa_mixer_info")
+    return {"n": n.value, "hamming_k": k.value, "angles_per_layer": apl.value}
+
+
 def qaoa_mixer_grover(ctx: int, n: int, hamming_k: int = -1) -> int:
     out = c_void_p()
     check(lib().qaoa_mixer_grover(ctx, n, hamming_k, ctypes.byref(out)), "qaoa_mixer_grover")
@@ -305,7 +337,7 @@ def qaoa_expect_grad(prob: int, mix: int, p: int, angles, d_psi0: int = 0,
     import numpy as np
     aa, ap = _f64(angles)
     out = c_double()
-    g = np.zeros(2 * p, dtype=np.float64)
+    g = np.zeros(aa.size, dtype=np.float64)
     check(lib().qaoa_expect_grad(prob, mix, p, ap, d_psi0 or None, precision, ctypes.byref(out),
                                  g.ctypes.data_as(P(c_double)), stream), "qaoa_expect_grad")
     return out.value, g
@@ -322,34 +354,38 @@ def _ptrs(handles):
     return arr
 
 
-def qaoa_expect_batched(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+def qaoa_expect_batched(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0,
+                        set_len: int = 0):
     import numpy as np
     aa, ap = _f64(angles)
-    n_sets = aa.size // (2 * p)
+    n_sets = aa.size // (set_len or 2 * p)
     out = np.zeros((len(probs), n_sets), dtype=np.float64)
     check(lib().qaoa_expect_batched(_ptrs(probs), _ptrs(mixers), len(probs), n_sets, p, ap, precision,
                                     out.ctypes.data_as(P(c_double)), stream), "qaoa_expect_batched")
     return out
 
 
-def qaoa_expect_grad_batched(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+def qaoa_expect_grad_batched(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0,
+                             set_len: int = 0):
     import numpy as np
     aa, ap = _f64(angles)
-    n_sets = aa.size // (2 * p)
+    L = set_len or 2 * p
+    n_sets = aa.size // L
     out = np.zeros((len(probs), n_sets), dtype=np.float64)
-    g = np.zeros((len(probs), n_sets, 2 * p), dtype=np.float64)
+    g = np.zeros((len(probs), n_sets, L), dtype=np.float64)
     check(lib().qaoa_expect_grad_batched(_ptrs(probs), _ptrs(mixers), len(probs), n_sets, p, ap, precision,
                                          out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)),
                                          stream), "qaoa_expect_grad_batched")
     return out, g
 
 
-def qaoa_expect_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+def qaoa_expect_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0,
+                      set_len: int = 0):
     """<C> of pair i = (probs[i], mixers[i], angles[i])."""
     import numpy as np
     aa, ap = _f64(angles)
     n = len(probs)
-    if aa.size != n * 2 * p or len(mixers) != n:
+    if aa.size != n * (set_len or 2 * p) or len(mixers) != n:
         raise ValueError("one mixer and 2p angles per pair")
     out = np.zeros(n, dtype=np.float64)
     check(lib().qaoa_expect_pairs(_ptrs(probs), _ptrs(mixers), n, p, ap, precision,
@@ -357,14 +393,16 @@ def qaoa_expect_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32,
     return out
 
 
-def qaoa_expect_grad_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+def qaoa_expect_grad_pairs(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0,
+                           set_len: int = 0):
     import numpy as np
     aa, ap = _f64(angles)
     n = len(probs)
-    if aa.size != n * 2 * p or len(mixers) != n:
+    L = set_len or 2 * p
+    if aa.size != n * L or len(mixers) != n:
         raise ValueError("one mixer and 2p angles per pair")
     out = np.zeros(n, dtype=np.float64)
-    g = np.zeros((n, 2 * p), dtype=np.float64)
+    g = np.zeros((n, L), dtype=np.float64)
     check(lib().qaoa_expect_grad_pairs(_ptrs(probs), _ptrs(mixers), n, p, ap, precision,
                                        out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)), stream),
           "qaoa_expect_grad_pairs")

@@ -111,6 +111,8 @@ class Mixer:
 
     def __init__(self, ctx: Context, handle: int, kind: str, n: int, k: int = -1):
         self.ctx, self.handle, self.kind, self.n, self.k = ctx, handle, kind, n, k
+        # angles per layer of an angle set: beta and gamma, or n betas and gamma (multi-angle)
+        self.angles_per_layer = n + 1 if kind == "x_multiangle" else 2
         ctx._children.add(self)
 
     @classmethod
@@ -137,6 +139,24 @@ class Mixer:
         from math import comb
         N = (1 << self.n) if self.k < 0 else comb(self.n, self.k)
         return _lib.qaoa_mixer_eigen(self.handle, N, _stream(stream))
+
+    @classmethod
+    def x_orders(cls, ctx: Context, n: int, orders):
+        """sum over k in orders of all k-body products of X (Eq. (2)); [1] is the transverse field."""
+        return cls(ctx, _lib.qaoa_mixer_x_orders(ctx.handle, n, list(orders)), "x_orders", n)
+
+    @classmethod
+    def x_terms(cls, ctx: Context, n: int, masks, coefs):
+        """sum_t coefs[t] prod_{i in masks[t]} X_i (at most 10 terms)."""
+        return cls(ctx, _lib.qaoa_mixer_x_terms(ctx.handle, n, list(masks), list(coefs)), "x_terms", n)
+
+    @classmethod
+    def x_multiangle(cls, ctx: Context, n: int):
+        """prod_q e^{-i beta_{k,q} X_q}: angle sets [beta_{1,0..n-1}, ..., beta_{p,0..n-1}, gamma_1..gamma_p]."""
+        return cls(ctx, _lib.qaoa_mixer_x_multiangle(ctx.handle, n), "x_multiangle", n)
+
+    def info(self) -> dict:
+        return _lib.qaoa_mixer_info(self.handle)
 
     @classmethod
     def grover(cls, ctx: Context, n: int, hamming_k: int = -1):
@@ -166,35 +186,37 @@ def _ptr(t):
 
 def expect(problem: Problem, mixer: Mixer, angles, psi0=None, precision: int = QAOA_FP32, stream=None) -> float:
     a = np.asarray(angles, dtype=np.float64).reshape(-1)
-    return _lib.qaoa_expect(problem.handle, mixer.handle, a.size // 2, a, _ptr(psi0), precision, _stream(stream))
+    return _lib.qaoa_expect(problem.handle, mixer.handle, a.size // mixer.angles_per_layer, a, _ptr(psi0), precision,
+                            _stream(stream))
 
 
 def expect_grad(problem: Problem, mixer: Mixer, angles, psi0=None, precision: int = QAOA_FP32, stream=None):
     a = np.asarray(angles, dtype=np.float64).reshape(-1)
-    return _lib.qaoa_expect_grad(problem.handle, mixer.handle, a.size // 2, a, _ptr(psi0), precision,
+    return _lib.qaoa_expect_grad(problem.handle, mixer.handle, a.size // mixer.angles_per_layer, a, _ptr(psi0),
+                                 precision,
                                  _stream(stream))
 
 
 def state(problem: Problem, mixer: Mixer, angles, out, psi0=None, precision: int = QAOA_FP32, stream=None):
     """Write psi_p into the device tensor ``out`` (complex64 / complex128, feasible-set length)."""
     a = np.asarray(angles, dtype=np.float64).reshape(-1)
-    _lib.qaoa_state(problem.handle, mixer.handle, a.size // 2, a, _ptr(out), _ptr(psi0), precision,
+    _lib.qaoa_state(problem.handle, mixer.handle, a.size // mixer.angles_per_layer, a, _ptr(out), _ptr(psi0), precision,
                     _stream(stream))
     return out
 
 
 def expect_batched(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
     a = np.asarray(angles, dtype=np.float64)
-    p = a.shape[-1] // 2
+    p = a.shape[-1] // mixers[0].angles_per_layer
     return _lib.qaoa_expect_batched([x.handle for x in problems], [m.handle for m in mixers], p, a,
-                                    precision, _stream(stream))
+                                    precision, _stream(stream), set_len=a.shape[-1])
 
 
 def expect_grad_batched(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
     a = np.asarray(angles, dtype=np.float64)
-    p = a.shape[-1] // 2
+    p = a.shape[-1] // mixers[0].angles_per_layer
     return _lib.qaoa_expect_grad_batched([x.handle for x in problems], [m.handle for m in mixers], p, a,
-                                         precision, _stream(stream))
+                                         precision, _stream(stream), set_len=a.shape[-1])
 
 
 # ---------------------------------------------------------------- angle finding (Sec. 2.3)
@@ -243,14 +265,16 @@ def find_angles_multi(problems, mixers, p: int, files=None, stream=None, **opts)
 def expect_pairs(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
     """<C> of pair i = (problems[i], mixers[i], angles[i])."""
     a = np.asarray(angles, dtype=np.float64)
-    return _lib.qaoa_expect_pairs([x.handle for x in problems], [m.handle for m in mixers], a.shape[-1] // 2, a,
-                                  precision, _stream(stream))
+    return _lib.qaoa_expect_pairs([x.handle for x in problems], [m.handle for m in mixers],
+                                  a.shape[-1] // mixers[0].angles_per_layer, a, precision, _stream(stream),
+                                  set_len=a.shape[-1])
 
 
 def expect_grad_pairs(problems, mixers, angles, precision: int = QAOA_FP32, stream=None):
     a = np.asarray(angles, dtype=np.float64)
-    return _lib.qaoa_expect_grad_pairs([x.handle for x in problems], [m.handle for m in mixers], a.shape[-1] // 2,
-                                       a, precision, _stream(stream))
+    return _lib.qaoa_expect_grad_pairs([x.handle for x in problems], [m.handle for m in mixers],
+                                       a.shape[-1] // mixers[0].angles_per_layer, a, precision, _stream(stream),
+                                       set_len=a.shape[-1])
 
 
 def find_angles_random(problem: Problem, mixer: Mixer, p: int, restarts: int = 100, stream=None, **opts):

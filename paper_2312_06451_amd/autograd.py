@@ -18,7 +18,7 @@ class QAOAExpectation(torch.autograd.Function):
     @staticmethod
     def forward(ctx, angles: torch.Tensor, problem: Problem, mixer: Mixer, precision: int = QAOA_FP32):
         a = angles.detach().to("cpu", torch.float64).contiguous().numpy()
-        p = a.size // 2
+        p = a.size // mixer.angles_per_layer
         if ctx.needs_input_grad[0]:
             e, g = _lib.qaoa_expect_grad(problem.handle, mixer.handle, p, a, 0, precision, _stream(None))
             ctx.save_for_backward(torch.from_numpy(g).to(angles.device, angles.dtype))

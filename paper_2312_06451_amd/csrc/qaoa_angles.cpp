@@ -119,9 +119,13 @@ struct Objective {
     int64_t big = 1;
     for (int i = 0; i < n_inst; i++) {
       int64_t size = 0;
-      const int rc = qaoa_problem_info(probs[i], nullptr, nullptr, &size, nullptr);
+      int rc = qaoa_problem_info(probs[i], nullptr, nullptr, &size, nullptr);
       if (rc != QAOA_OK) throw Passed{rc};
       big = std::max(big, size);
+      int apl = 0;
+      rc = qaoa_mixer_info(mixes[i], nullptr, nullptr, &apl);
+      if (rc != QAOA_OK) throw Passed{rc};
+      if (apl != 2) throw Fail{QAOA_ERR_UNSUPPORTED, "angle finding takes mixers with one angle per layer"};
     }
     if (o.max_sets_per_call > 0) {
       chunk = o.max_sets_per_call;

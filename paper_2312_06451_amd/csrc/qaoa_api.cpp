@@ -287,10 +287,23 @@ void upload_values(qaoa_problem *prob, hipStream_t st) {
 
 struct qaoa_mixer {
   qaoa_ctx *ctx = nullptr;
-  int kind = 0;  // 0: transverse field, 1: clique, 2: Grover
+  int kind = 0;  // 0: transverse field, 1: clique, 2: Grover, 3: X products, 4: per-qubit angles
   int n = 0, k = -1;
   std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique;
+  // kinds 3 and 4: the mixer's diagonal after the Walsh-Hadamard transform
+  XDiag xd{};
+  double *xvals = nullptr;  // kind 3: diagonal value of each index (xlen entries, device)
+  int xlen = 0;
+  ~qaoa_mixer() {
+    if (xvals) (void)hipFree(xvals);
+  }
 };
+
+namespace {
+// angles per set: [beta_1..beta_p, gamma_1..gamma_p], or with per-qubit angles
+// [beta_{1,0..n-1}, ..., beta_{p,0..n-1}, gamma_1..gamma_p]
+size_t set_len(const qaoa_mixer *mix, int p) { return (size_t)p * (mix->kind == 4 ? mix->n + 1 : 2); }
+}  // namespace
 
 // ---------------------------------------------------------------- plan of the X path
 
@@ -872,7 +885,8 @@ void check_pair(const qaoa_problem *prob, const qaoa_mixer *mix, int precision) 
   REQUIRE(prob->ctx == mix->ctx, "problem and mixer belong to different contexts");
   REQUIRE(precision == QAOA_FP32 || precision == QAOA_FP64, "precision must be QAOA_FP32 or QAOA_FP64");
   REQUIRE(prob->n == mix->n, "mixer and problem have different qubit counts");
-  if (mix->kind == 0) REQUIRE(prob->k < 0, "the transverse-field mixer needs an unconstrained problem");
+  if (mix->kind == 0 || mix->kind == 3 || mix->kind == 4)
+    REQUIRE(prob->k < 0, "X-type mixers need an unconstrained problem");
   else REQUIRE(prob->k == mix->k, "the mixer's Hamming weight differs from the problem's");
   if (mix->kind != 2 && !prob->table)
     throw fail(QAOA_ERR_UNSUPPORTED, "the problem holds degeneracies only: it serves the Grover mixer");
@@ -1546,6 +1560,105 @@ int qaoa_mixer_matrix(qaoa_ctx *ctx, int n, int hamming_k, const double *host_ma
   });
 }
 
+static void xprod_mixer(qaoa_ctx *ctx, int n, int kind, const XDiag &xd, const std::vector<double> &vals,
+                        qaoa_mixer **out) {
+  DeviceGuard g(ctx->device);
+  auto m = std::make_unique<qaoa_mixer>();
+  m->ctx = ctx;
+  m->kind = kind;
+  m->n = n;
+  m->xd = xd;
+  if (!vals.empty()) {
+    m->xlen = (int)vals.size();
+    if (hipMalloc(&m->xvals, vals.size() * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      m->xvals = nullptr;
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "mixer value allocation failed");
+    }
+    HIPCHK(hipMemcpy(m->xvals, vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  ctx->live++;
+  *out = m.release();
+}
+
+int qaoa_mixer_x_orders(qaoa_ctx *ctx, int n, const int *orders, int n_orders, qaoa_mixer **out) {
+  return guarded([&] {
+    REQUIRE(ctx && out && orders, "ctx, orders or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 32, "n must be in [1, 32]");
+    REQUIRE(n_orders >= 1 && n_orders <= n, "n_orders must be in [1, n]");
+    std::vector<bool> seen(n + 1, false);
+    for (int i = 0; i < n_orders; i++) {
+      REQUIRE(orders[i] >= 1 && orders[i] <= n, "orders must be in [1, n]");
+      REQUIRE(!seen[orders[i]], "orders must be distinct");
+      seen[orders[i]] = true;
+    }
+    // d(w) = sum over orders k of the Krawtchouk value K_k(w) = sum_j (-1)^j C(w, j) C(n - w, k - j)
+    std::vector<double> vals(n + 1);
+    for (int w = 0; w <= n; w++) {
+      int64_t d = 0;
+      for (int i = 0; i < n_orders; i++) {
+        const int k = orders[i];
+        for (int j = 0; j <= k && j <= w; j++) {
+          if (k - j > n - w) continue;
+          const int64_t t = binom64(w, j) * binom64(n - w, k - j);
+          d += (j & 1) ? -t : t;
+        }
+      }
+      vals[w] = (double)d;
+    }
+    XDiag xd{};
+    xd.mode = XD_POPCOUNT;
+    xprod_mixer(ctx, n, 3, xd, vals, out);
+  });
+}
+
+int qaoa_mixer_x_terms(qaoa_ctx *ctx, int n, const uint64_t *masks, const double *coefs, int n_terms,
+                       qaoa_mixer **out) {
+  return guarded([&] {
+    REQUIRE(ctx && out && masks && coefs, "ctx, masks, coefs or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 32, "n must be in [1, 32]");
+    REQUIRE(n_terms >= 1 && n_terms <= XD_MAX_TERMS, "n_terms must be in [1, 10]");
+    XDiag xd{};
+    xd.mode = XD_TERMS;
+    xd.nterms = n_terms;
+    for (int t = 0; t < n_terms; t++) {
+      REQUIRE(masks[t] != 0 && (masks[t] >> n) == 0, "term masks must be nonzero and below 2^n");
+      REQUIRE(std::isfinite(coefs[t]), "coefficients must be finite");
+      xd.masks[t] = masks[t];
+    }
+    // index bit t is the parity of y & masks[t]; value = sum_t coefs[t] (1 - 2 bit_t)
+    std::vector<double> vals((size_t)1 << n_terms);
+    for (size_t idx = 0; idx < vals.size(); idx++) {
+      double v = 0.0;
+      for (int t = 0; t < n_terms; t++) v += ((idx >> t) & 1) ? -coefs[t] : coefs[t];
+      vals[idx] = v;
+    }
+    xprod_mixer(ctx, n, 3, xd, vals, out);
+  });
+}
+
+int qaoa_mixer_x_multiangle(qaoa_ctx *ctx, int n, qaoa_mixer **out) {
+  return guarded([&] {
+    REQUIRE(ctx && out, "ctx or out is NULL");
+    *out = nullptr;
+    REQUIRE(n >= 1 && n <= 32, "n must be in [1, 32]");
+    XDiag xd{};
+    xd.mode = XD_QUBIT;
+    xprod_mixer(ctx, n, 4, xd, {}, out);
+  });
+}
+
+int qaoa_mixer_info(const qaoa_mixer *mix, int *n, int *hamming_k, int *angles_per_layer) {
+  return guarded([&] {
+    REQUIRE(mix != nullptr, "mixer is NULL");
+    if (n) *n = mix->n;
+    if (hamming_k) *hamming_k = mix->k;
+    if (angles_per_layer) *angles_per_layer = (int)set_len(mix, 1);
+  });
+}
+
 int qaoa_mixer_from_eigen(qaoa_ctx *ctx, int n, int hamming_k, const double *host_V, const double *host_D,
                           qaoa_mixer **out, void *stream) {
   return guarded([&] {
@@ -1587,6 +1700,113 @@ int qaoa_mixer_destroy(qaoa_mixer *mix) {
   });
 }
 
+// X-product and per-qubit multi-angle mixers: every layer is phase, W, mixer diagonal, W (W the
+// Walsh-Hadamard transform, Eq. (2)); the gradient undoes the layers on the state and the
+// adjoint vector, taking each angle's sum just before its diagonal is undone.
+static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, const double *angles, int nsets,
+                           const void *d_psi0, int precision, int grad, double *out_expect, double *out_grad,
+                           void *d_state, hipStream_t st) {
+  qaoa_ctx *ctx = prob->ctx;
+  REQUIRE(prob->table != nullptr, "the problem has no value table");
+  const int n = prob->n;
+  const uint64_t N = 1ull << n;
+  const size_t esz = precision == QAOA_FP32 ? 8 : 16;
+  const bool qb = mix->kind == 4;
+  const int m = qb ? n : 1, slen = p * (m + 1);
+  const int lut_cost = (int)prob->max_value + 1;
+  if (lut_cost > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+  const int bsums = qb ? 33 : 1;  // sums per beta layer: total and per-bit (per-qubit angles) or one
+  const int nout = 2 + p * bsums + p;
+  const unsigned nblk = xdiag_blocks(N);
+  void *phi = ctx->phi.get((size_t)nsets * N * esz);
+  void *lam = grad ? ctx->lam.get((size_t)nsets * N * esz) : nullptr;
+  double *part = (double *)ctx->partials.get((size_t)(qb ? 33 : 2) * nsets * nblk * sizeof(double));
+  const size_t abytes = (size_t)nsets * slen * sizeof(double), aoff = (abytes + 255) & ~size_t(255);
+  unsigned char *dp = (unsigned char *)ctx->params.get(aoff + (size_t)nsets * nout * sizeof(double));
+  double *dang = (double *)dp, *dres = (double *)(dp + aoff);
+  const int lut_max = std::max(std::max(lut_cost, mix->xlen), 1024);
+  void *luts = ctx->luts.get((size_t)nsets * lut_max * esz);
+  unsigned char *h = (unsigned char *)ctx->hparams.get(abytes);
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(h, angles, abytes);
+  HIPCHK(hipMemcpyAsync(dang, h, abytes, hipMemcpyHostToDevice, st));
+  XDiag cost{};
+  cost.mode = XD_TABLE;
+  cost.tbytes = prob->tbytes;
+  cost.table = prob->table;
+  const double c0 = prob->mean;
+  const double vb = (double)N * esz;  // one vector read or written once
+  auto timed = [&](double bytes, auto &&launch) {
+    KTimer kt(ctx, st, QAOA_KC_XMIX, bytes, 0.0);
+    HIPCHK(launch());
+    kt.done();
+  };
+  auto wht = [&](int nv) {
+    timed(2.0 * nv * vb * nsets * xwht_passes(n),
+          [&] { return launch_xwht(precision, nv, phi, lam, n, nsets, st); });
+  };
+  auto cost_diag = [&](int k, double sign, int nv, int gs) {
+    HIPCHK(launch_xlut(precision, prob->dvals, lut_cost, dang, slen, p * m + k, sign, nsets, luts, st));
+    timed((2.0 * nv * vb + (double)N * prob->tbytes) * nsets, [&] {
+      return launch_xdiag(precision, nv, gs, phi, lam, N, cost, luts, lut_cost, prob->dvals, c0, part, nsets, st);
+    });
+  };
+  auto mix_diag = [&](int k, double sign, int nv, int gs) {
+    if (qb) HIPCHK(launch_xlut_q(precision, n, dang, slen, k * n, sign, nsets, luts, st));
+    else HIPCHK(launch_xlut(precision, mix->xvals, mix->xlen, dang, slen, k, sign, nsets, luts, st));
+    timed(2.0 * nv * vb * nsets, [&] {
+      return launch_xdiag(precision, nv, gs, phi, lam, N, mix->xd, luts, mix->xlen, mix->xvals, 0.0, part, nsets, st);
+    });
+  };
+  if (d_psi0) {
+    for (int s = 0; s < nsets; s++)
+      HIPCHK(hipMemcpyAsync((unsigned char *)phi + (size_t)s * N * esz, d_psi0, N * esz, hipMemcpyDeviceToDevice, st));
+  } else {
+    HIPCHK(launch_xfill(precision, phi, (uint64_t)nsets * N, 1.0 / std::sqrt((double)N), st));
+  }
+  for (int k = 0; k < p; k++) {
+    cost_diag(k, 1.0, 1, 0);
+    wht(1);
+    mix_diag(k, 1.0, 1, 0);
+    wht(1);
+  }
+  if (d_state) HIPCHK(hipMemcpyAsync(d_state, phi, N * esz, hipMemcpyDeviceToDevice, st));
+  timed(vb * nsets * (grad ? 2.0 : 1.0) + (double)N * prob->tbytes * nsets, [&] {
+    return launch_xend(precision, phi, lam, N, cost, prob->dvals, lut_cost, c0, part, nsets, st);
+  });
+  HIPCHK(launch_xfinal(part, (int)nblk, 2, nsets, dres, nout, 0, st));
+  if (grad) {
+    for (int k = p - 1; k >= 0; k--) {
+      wht(2);
+      mix_diag(k, -1.0, 2, 1);
+      HIPCHK(launch_xfinal(part, (int)nblk, bsums, nsets, dres, nout, 2 + k * bsums, st));
+      wht(2);
+      cost_diag(k, -1.0, 2, 1);
+      HIPCHK(launch_xfinal(part, (int)nblk, 1, nsets, dres, nout, 2 + p * bsums + k, st));
+    }
+  }
+  std::vector<double> res((size_t)nsets * nout);
+  HIPCHK(hipMemcpyAsync(res.data(), dres, res.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  profile_collect(ctx);
+  for (int s = 0; s < nsets; s++) {
+    const double *r = res.data() + (size_t)s * nout;
+    const double nr = r[1];
+    if (out_expect) out_expect[s] = r[0] / nr;
+    if (grad && out_grad) {
+      double *g = out_grad + (size_t)s * slen;
+      for (int k = 0; k < p; k++) {
+        const double *b = r + 2 + k * bsums;
+        if (qb)
+          for (int q = 0; q < n; q++) g[k * n + q] = 2.0 * (b[0] - 2.0 * b[1 + q]) / nr;
+        else
+          g[k] = 2.0 * b[0] / nr;
+        g[p * m + k] = 2.0 * r[2 + p * bsums + k] / nr;
+      }
+    }
+  }
+}
+
 static void evaluate(const qaoa_problem *cprob, const qaoa_mixer *mix, int p, const double *angles,
                      int nsets, const void *d_psi0, int precision, int grad, double *out_expect,
                      double *out_grad, void *d_state, hipStream_t st) {
@@ -1595,6 +1815,8 @@ static void evaluate(const qaoa_problem *cprob, const qaoa_mixer *mix, int p, co
     evaluate_x(prob, p, angles, nsets, d_psi0, precision, grad, out_expect, out_grad, d_state, st);
   } else if (mix->kind == 2) {
     evaluate_grover(prob, p, angles, nsets, d_psi0, precision, grad, out_expect, out_grad, d_state, st);
+  } else if (mix->kind == 3 || mix->kind == 4) {
+    evaluate_xprod(prob, mix, p, angles, nsets, d_psi0, precision, grad, out_expect, out_grad, d_state, st);
   } else {
     CliqueEval ev;
     ev.table = prob->table;
@@ -1618,7 +1840,7 @@ int qaoa_expect(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const do
                 const void *d_psi0, int precision, double *out_expect, void *stream) {
   return guarded([&] {
     check_pair(prob, mix, precision);
-    check_angles(p, angles, 2 * (size_t)p);
+    check_angles(p, angles, set_len(mix, p));
     REQUIRE(out_expect != nullptr, "out_expect is NULL");
     DeviceGuard g(prob->ctx->device);
     evaluate(prob, mix, p, angles, 1, d_psi0, precision, 0, out_expect, nullptr, nullptr,
@@ -1631,7 +1853,7 @@ int qaoa_expect_grad(const qaoa_problem *prob, const qaoa_mixer *mix, int p, con
                      void *stream) {
   return guarded([&] {
     check_pair(prob, mix, precision);
-    check_angles(p, angles, 2 * (size_t)p);
+    check_angles(p, angles, set_len(mix, p));
     REQUIRE(out_expect && out_grad, "output pointer is NULL");
     DeviceGuard g(prob->ctx->device);
     evaluate(prob, mix, p, angles, 1, d_psi0, precision, 1, out_expect, out_grad, nullptr,
@@ -1643,7 +1865,7 @@ int qaoa_state(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const dou
                const void *d_psi0, int precision, void *d_out, void *stream) {
   return guarded([&] {
     check_pair(prob, mix, precision);
-    check_angles(p, angles, 2 * (size_t)p);
+    check_angles(p, angles, set_len(mix, p));
     REQUIRE(d_out != nullptr, "d_out is NULL");
     DeviceGuard g(prob->ctx->device);
     double e;
@@ -1656,15 +1878,16 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
                     double *out_expect, double *out_grad, hipStream_t st) {
   REQUIRE(probs && mixers, "probs or mixers is NULL");
   REQUIRE(n_probs >= 1 && n_sets >= 1, "n_probs and n_sets must be >= 1");
-  check_angles(p, angles, (size_t)n_sets * 2 * p);
   REQUIRE(out_expect != nullptr && (!grad || out_grad != nullptr), "output pointer is NULL");
   qaoa_ctx *ctx = probs[0] ? probs[0]->ctx : nullptr;
   for (int i = 0; i < n_probs; i++) {
     check_pair(probs[i], mixers[i], precision);
     REQUIRE(probs[i]->ctx == ctx, "all problems must share one context");
+    REQUIRE(set_len(mixers[i], p) == set_len(mixers[0], p), "all mixers must take the same number of angles");
   }
+  const int g2p = (int)set_len(mixers[0], p);
+  check_angles(p, angles, (size_t)n_sets * g2p);
   DeviceGuard g(ctx->device);
-  const int g2p = 2 * p;
   // whole-state items first (one launch), then the larger problems one by one
   std::vector<SmallItem> items;
   std::vector<int> small_probs;
@@ -1724,15 +1947,16 @@ static void paired(const qaoa_problem *const *probs, const qaoa_mixer *const *mi
                    hipStream_t st) {
   REQUIRE(probs && mixers, "probs or mixers is NULL");
   REQUIRE(n_pairs >= 1, "n_pairs must be >= 1");
-  check_angles(p, angles, (size_t)n_pairs * 2 * p);
   REQUIRE(out_expect != nullptr && (!grad || out_grad != nullptr), "output pointer is NULL");
   qaoa_ctx *ctx = probs[0] ? probs[0]->ctx : nullptr;
   for (int i = 0; i < n_pairs; i++) {
     check_pair(probs[i], mixers[i], precision);
     REQUIRE(probs[i]->ctx == ctx, "all problems must share one context");
+    REQUIRE(set_len(mixers[i], p) == set_len(mixers[0], p), "all mixers must take the same number of angles");
   }
+  const int g2p = (int)set_len(mixers[0], p);
+  check_angles(p, angles, (size_t)n_pairs * g2p);
   DeviceGuard g(ctx->device);
-  const int g2p = 2 * p;
   auto scatter = [&](const double *r, int i) {
     out_expect[i] = r[0];
     if (grad) std::memcpy(out_grad + (size_t)i * g2p, r + 1, g2p * sizeof(double));

@@ -155,6 +155,33 @@ hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int
 hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
                         int max_tbytes, int max_lut, const double *angles, int p, int grad,
                         double *out, hipStream_t s);
+// Diagonal of a step of the X-product / multi-angle path: where the value index of basis
+// state y comes from.
+enum { XD_TABLE = 0, XD_POPCOUNT = 1, XD_TERMS = 2, XD_QUBIT = 3 };
+constexpr int XD_MAX_TERMS = 10;
+struct XDiag {
+  int mode;             // XD_*
+  int tbytes;           // XD_TABLE: 1 or 2
+  const void *table;    // XD_TABLE: index table (2^n entries)
+  int nterms;           // XD_TERMS: index bit t = parity of (y & masks[t])
+  uint64_t masks[XD_MAX_TERMS];
+};
+unsigned xdiag_blocks(uint64_t N);
+int xwht_passes(int n);
+hipError_t launch_xlut(int precision, const double *vals, int len, const double *angles, int stride, int off,
+                       double sign, int nsets, void *out, hipStream_t s);
+hipError_t launch_xlut_q(int precision, int n, const double *angles, int stride, int off, double sign, int nsets,
+                         void *out, hipStream_t s);
+hipError_t launch_xdiag(int precision, int nv, int gsums, void *phi, void *lam, uint64_t N, const XDiag &d,
+                        const void *luts, int lut_len, const double *gv, double gshift, double *partials,
+                        int nsets, hipStream_t s);
+hipError_t launch_xend(int precision, const void *phi, void *lam, uint64_t N, const XDiag &d, const double *vals,
+                       int lut_len, double c0, double *partials, int nsets, hipStream_t s);
+hipError_t launch_xfill(int precision, void *v, uint64_t total, double u0, hipStream_t s);
+hipError_t launch_xfinal(const double *partials, int nblk, int nsums, int nsets, double *out, int ostride, int ooff,
+                         hipStream_t s);
+hipError_t launch_xwht(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s);
+
 // Whole-state evaluation with the state in registers, for n = 12, 13 (FP32) or n = 12 (FP64):
 // every item must have that n and table width.
 bool whole_supported(int precision, int n);

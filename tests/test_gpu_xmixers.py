@@ -1,0 +1,150 @@
+"""GPU parity of mixers built from Pauli-X products (Eq. (2)) and of per-qubit multi-angle
+mixers against the FP64 oracle (``oracle.xmixers``): symmetric k-body sums, term lists,
+per-qubit angles; one and several transform passes (n <= 12 and n > 12); FP32 (1e-5) and FP64
+(1e-10), relative to max|C| for <C> and to max|g| for the gradient. At n = 24 the transverse
+field written as the order-1 sum is compared with the rotation kernels, an independent path."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import xmixers as X
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-5, 1: 1e-10}
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2312_06451_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def _check(q, P, M, n, t, angles, d=None, multi=False, precisions=(0, 1)):
+    scale = float(np.max(np.abs(t)))
+    for prec in precisions:
+        for a in angles:
+            E, Nr, g0 = X.grad(n, t, a, d=d, multiangle=multi)
+            e, g = q.expect_grad(P, M, a, precision=prec)
+            assert abs(e - E / Nr) <= TOL[prec] * scale, (prec, e, E / Nr)
+            assert g.shape == g0.shape
+            assert np.max(np.abs(g - g0 / Nr)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3), (prec, g, g0)
+            assert abs(q.expect(P, M, a, precision=prec) - e) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,orders,p", [(8, [1], 3), (10, [2], 2), (12, [1, 3], 2), (14, [2], 2), (17, [1, 2, 5], 2)])
+def test_orders_vs_oracle(q, ctx, n, orders, p):
+    g = workloads.erdos_renyi(n, 2800 + n, 0.5, (1, 3))
+    t = oracle.graph_table(g)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x_orders(ctx, n, orders)
+    _check(q, P, M, n, t, workloads.random_angles(p, 2, 2801 + n), d=X.diag_orders(n, orders))
+
+
+@pytest.mark.parametrize("n,masks,coefs", [(9, [0b1, 0b110, 0b101010101], [1.0, -0.5, 2.0]),
+                                            (13, [0b1111111111111, 0b11, 0b1000000000001, 0b1010], [0.3, 1.0, -1.2, 0.8])])
+def test_terms_vs_oracle(q, ctx, n, masks, coefs):
+    rng = np.random.default_rng(2810 + n)
+    vals = rng.normal(0.0, 2.0, 60)[rng.integers(0, 60, 1 << n)]
+    P, M = q.Problem.from_values(ctx, n, vals), q.Mixer.x_terms(ctx, n, masks, coefs)
+    _check(q, P, M, n, vals, workloads.random_angles(3, 2, 2811), d=X.diag_terms(n, masks, coefs))
+
+
+@pytest.mark.parametrize("n,p", [(6, 2), (11, 3), (15, 2)])
+def test_multiangle_vs_oracle(q, ctx, n, p):
+    g = workloads.erdos_renyi(n, 2820 + n, 0.5, (1, 3))
+    t = oracle.graph_table(g)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x_multiangle(ctx, n)
+    assert M.info()["angles_per_layer"] == n + 1
+    rng = np.random.default_rng(2821 + n)
+    _check(q, P, M, n, t, rng.uniform(0, np.pi, (2, p * (n + 1))), multi=True)
+
+
+def test_multiangle_equal_angles_is_the_transverse_field(q, ctx):
+    n, p = 16, 3
+    g = workloads.erdos_renyi(n, 2830, 0.5, (1, 3))
+    P, Mx, Mm = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n), q.Mixer.x_multiangle(ctx, n)
+    a = workloads.random_angles(p, 1, 2831)[0]
+    ma = np.concatenate([np.repeat(a[:p], n), a[p:]])
+    for prec in (0, 1):
+        e0, g0 = q.expect_grad(P, Mx, a, precision=prec)
+        e1, g1 = q.expect_grad(P, Mm, ma, precision=prec)
+        assert abs(e0 - e1) <= TOL[prec] * 40
+        assert np.allclose(g1[:p * n].reshape(p, n).sum(axis=1), g0[:p], atol=TOL[prec] * 40 * n)
+        assert np.allclose(g1[p * n:], g0[p:], atol=TOL[prec] * 40)
+
+
+def test_order_one_at_n24_matches_rotation_kernels(q, ctx):
+    n, p = 24, 2
+    g = workloads.random_regular_graph(n, 3, 2840)
+    P, Mx, Mo = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n), q.Mixer.x_orders(ctx, n, [1])
+    a = workloads.random_angles(p, 2, 2841)
+    for prec in (0, 1):
+        e0, g0 = q.expect_grad_batched([P], [Mx], a, precision=prec)
+        e1, g1 = q.expect_grad_batched([P], [Mo], a, precision=prec)
+        assert np.max(np.abs(e0 - e1)) <= TOL[prec] * 36
+        assert np.max(np.abs(g0 - g1)) <= TOL[prec] * np.max(np.abs(g0))
+
+
+def test_batched_and_paired_equal_single_calls(q, ctx):
+    n = 13
+    gs = [workloads.erdos_renyi(n, 2850 + i, 0.5, (1, 3)) for i in range(2)]
+    P = [q.Problem.from_graph(ctx, g) for g in gs]
+    Mo, Mt = q.Mixer.x_orders(ctx, n, [2, 3]), q.Mixer.x_terms(ctx, n, [0b111, 0b1000000000001], [1.0, -2.0])
+    a = workloads.random_angles(3, 3, 2851)
+    e, g = q.expect_grad_batched(P, [Mo, Mt], a)
+    for i, M in enumerate((Mo, Mt)):
+        for s in range(3):
+            e1, g1 = q.expect_grad(P[i], M, a[s])
+            assert e[i, s] == e1 and np.array_equal(g[i, s], g1)
+    Mm = q.Mixer.x_multiangle(ctx, n)
+    am = np.random.default_rng(2852).uniform(0, np.pi, (3, 2 * (n + 1)))
+    ep, gp = q.expect_grad_pairs([P[0], P[1], P[0]], [Mm] * 3, am)
+    for j, i in enumerate((0, 1, 0)):
+        e1, g1 = q.expect_grad(P[i], Mm, am[j])
+        assert ep[j] == e1 and np.array_equal(gp[j], g1)
+
+
+def test_state_output(q, ctx):
+    import torch
+    n, p = 14, 2
+    g = workloads.erdos_renyi(n, 2860, 0.5, (1, 3))
+    t = oracle.graph_table(g)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x_orders(ctx, n, [1, 2])
+    a = workloads.random_angles(p, 1, 2861)[0]
+    out = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
+    q.state(P, M, a, out, precision=1)
+    psi = out.cpu().numpy()
+    d = X.diag_orders(n, [1, 2])
+    want = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    for k in range(p):
+        want = X._mixer(np.exp(-1j * a[p + k] * t) * want, a[k], d)
+    assert np.max(np.abs(psi - want)) <= 1e-12
+
+
+def test_errors(q, ctx):
+    n = 8
+    with pytest.raises(q.QAOAError):
+        q.Mixer.x_orders(ctx, n, [1, 1])
+    with pytest.raises(q.QAOAError):
+        q.Mixer.x_orders(ctx, n, [9])
+    with pytest.raises(q.QAOAError):
+        q.Mixer.x_terms(ctx, n, [1 << 8], [1.0])
+    with pytest.raises(q.QAOAError):
+        q.Mixer.x_terms(ctx, n, list(range(1, 12)), [1.0] * 11)
+    g = workloads.erdos_renyi(n, 2870, 0.5)
+    Pk = q.Problem.from_graph(ctx, g, hamming_k=4)
+    with pytest.raises(q.QAOAError):
+        q.expect(Pk, q.Mixer.x_orders(ctx, n, [1]), [0.1, 0.2])
+    P = q.Problem.from_graph(ctx, g)
+    Mm, Mx = q.Mixer.x_multiangle(ctx, n), q.Mixer.x(ctx, n)
+    with pytest.raises(q.QAOAError):
+        q.expect_batched([P, P], [Mm, Mx], np.zeros((1, 9)))
+    with pytest.raises(q.QAOAError):
+        q.find_angles(P, Mm, 1)
