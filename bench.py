@@ -17,6 +17,8 @@ Other workloads (--workload):
                            value in states/s
   angles_er_n12_p10        angle finding: one step = iterative basinhopping rounds 1..10 for 50
                            G(12,1/2) MaxCut instances at once; value in evals/s inside the loop
+  xorders_maxcut3reg_n24_p4  mixer of all 1- and 2-body X products (Walsh-Hadamard path), n=24,
+                           p=4, 16 angle sets per batched call
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
@@ -87,6 +89,8 @@ class Runner:
         self.problems = [q.Problem.from_graph(self.ctx, g, hamming_k=k) for g in W.graphs]
         if W.mixer == "clique":
             self.mixers = [q.Mixer.clique(self.ctx, g.n, k) for g in W.graphs]
+        elif W.mixer == "x_orders":
+            self.mixers = [q.Mixer.x_orders(self.ctx, g.n, W.extra["orders"]) for g in W.graphs]
         else:
             self.mixers = [q.Mixer.x(self.ctx, g.n) for g in W.graphs]
         self.batched = len(W.graphs) > 1 or W.angles.shape[0] > 1
@@ -131,6 +135,24 @@ def cpu_baseline(W, sample):
                           f"{dt:.1f} s, scaled x{W.p} to one p={W.p} evaluation"}, {}
     if W.name == "maxcut3reg_n32_p16":
         return None, {}
+    if W.mixer == "x_orders":
+        # one fwd+adjoint evaluation with p=1 at the full n (one of the p layers), scaled by p
+        # one fwd+adjoint evaluation with p=1 on a 3-regular graph of n - 2 vertices, scaled by 4 n / (n - 2)
+        # (transform work per amplitude grows with n) and by p
+        from oracle import xmixers as X
+        n = W.graphs[0].n
+        gs = workloads_mod().random_regular_graph(n - 2, 3, 8124)
+        table = oracle.graph_table(gs)
+        d = X.diag_orders(n - 2, W.extra["orders"])
+        a1 = np.array([W.angles[0][0], W.angles[0][W.p]])
+        t0 = time.perf_counter()
+        X.grad(n - 2, table, a1, d=d)
+        dt = time.perf_counter() - t0
+        scale = 4.0 * n / (n - 2) * W.p
+        return {"value": 1.0 / (dt * scale), "unit": "evals/s", "cores": 1, "kind": "oracle",
+                "sample": f"one fwd+adjoint evaluation with p=1 at n={n - 2} (numpy, one thread), {dt:.1f} s, "
+                          f"scaled x{scale:.2f} (4 n/(n-2) for the size, x{W.p} for the layers) to one n={n}, "
+                          f"p={W.p} evaluation"}, {}
     tables = [oracle.graph_table(g, k) for g in W.graphs]
     res = {}
     t0 = time.perf_counter()
@@ -180,19 +202,20 @@ def traffic_from_profile(workload, cls):
     return None
 
 
-KERNEL_NAMES = {"fwd_pass": "k_pass<float,13,1,uint8> (tile pass, one vector)",
+KERNEL_NAMES = {"xmix": "k_xwht / k_xdiag (Walsh-Hadamard passes and diagonals of X-product mixers)",
+                "fwd_pass": "k_pass<float,13,1,uint8> (tile pass, one vector)",
                 "rev_pass": "k_pass<float,13,2|3,uint8> (tile pass, state and adjoint vector)",
                 "small": "k_small<float> (whole state in one workgroup)",
                 "dense": "hipBLASLt GEMM f16 x f16 -> f32 (split eigenbasis product, 2 calls)"}
 
 
 def roofline(prof, workload):
-    cls = max(("fwd_pass", "rev_pass", "small", "dense"), key=lambda k: prof[k]["ms"])
+    cls = max(("fwd_pass", "rev_pass", "small", "dense", "xmix"), key=lambda k: prof[k]["ms"])
     d = prof[cls]
     L = max(d["launches"], 1)
     mean_ms = d["ms"] / L
     base = {"kernel": KERNEL_NAMES[cls], "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
-    if cls in ("fwd_pass", "rev_pass"):
+    if cls in ("fwd_pass", "rev_pass", "xmix"):
         bpl = d["bytes"] / L
         a = bpl / (mean_ms * 1e-3) / 1e9
         return dict({"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -1742,7 +1742,7 @@ static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, con
     kt.done();
   };
   auto wht = [&](int nv) {
-    timed(2.0 * nv * vb * nsets * xwht_passes(n),
+    timed(2.0 * nv * vb * nsets * xwht_passes(n, precision),
           [&] { return launch_xwht(precision, nv, phi, lam, n, nsets, st); });
   };
   auto cost_diag = [&](int k, double sign, int nv, int gs) {

@@ -167,7 +167,7 @@ struct XDiag {
   uint64_t masks[XD_MAX_TERMS];
 };
 unsigned xdiag_blocks(uint64_t N);
-int xwht_passes(int n);
+int xwht_passes(int n, int precision);
 hipError_t launch_xlut(int precision, const double *vals, int len, const double *angles, int stride, int off,
                        double sign, int nsets, void *out, hipStream_t s);
 hipError_t launch_xlut_q(int precision, int n, const double *angles, int stride, int off, double sign, int nsets,
@@ -181,6 +181,11 @@ hipError_t launch_xfill(int precision, void *v, uint64_t total, double u0, hipSt
 hipError_t launch_xfinal(const double *partials, int nblk, int nsums, int nsets, double *out, int ostride, int ooff,
                          hipStream_t s);
 hipError_t launch_xwht(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s);
+// Walsh-Hadamard transform with register tiles of 2^13 (complex64) or 2^12 (complex128)
+// amplitudes, for n >= wht_min_bits(precision).
+hipError_t launch_wht_tiles(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s);
+int wht_tile_passes(int n, int precision);
+int wht_min_bits(int precision);
 
 // Whole-state evaluation with the state in registers, for n = 12, 13 (FP32) or n = 12 (FP64):
 // every item must have that n and table width.

@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
+#include <vector>
 #include <cstdint>
 #include "qaoa_internal.h"
 
@@ -1054,6 +1056,122 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
     else rev_layer(k, std::true_type{});
   }
 }
+
+// ============================================================== Walsh-Hadamard tile pass
+
+// Hadamards on the tile bits in `mask` held in the registers of assignment A.
+template <typename R, int T, int A>
+__device__ __forceinline__ void hstage(typename Cplx<R>::T2 *v, uint32_t mask) {
+  using G = TileCfg<T>;
+  const R h = (R)0.70710678118654752440;
+#pragma unroll
+  for (int b = 0; b < G::RB; b++) {
+    constexpr uint32_t grp = group<A, T>();
+    const int tb = regbit<A, T>(b);
+    if (((grp & mask) >> tb) & 1u) {  // uniform
+#pragma unroll
+      for (int j = 0; j < G::RN; j++)
+        if (!(j & (1 << b))) {
+          const typename Cplx<R>::T2 a = v[j], c = v[j | (1 << b)];
+          v[j] = typename Cplx<R>::T2{(a.x + c.x) * h, (a.y + c.y) * h};
+          v[j | (1 << b)] = typename Cplx<R>::T2{(a.x - c.x) * h, (a.y - c.y) * h};
+        }
+    }
+  }
+}
+
+// One pass of the Walsh-Hadamard transform over tiles of 2^T amplitudes held in registers
+// (T = 13 for complex64, 12 for complex128): tile bits [0, c) are contiguous index bits (rows),
+// tile bits [c, T) are the transformed index bits [b0, b0 + T - c) (c = 0 and b0 = 0 for the
+// first pass). Stages H, then M and L as far as the transformed bits reach, with LDS
+// exchanges between them; loads and stores in assignment H (lanes over the low tile bits).
+template <typename R, int T, int NV>
+__global__ __launch_bounds__(256) void k_wht(typename Cplx<R>::T2 *__restrict__ phi,
+                                             typename Cplx<R>::T2 *__restrict__ lam, uint64_t N, int b0, int c) {
+  using G = TileCfg<T>;
+  using T2 = typename Cplx<R>::T2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2 *lds = (T2 *)smem;
+  const uint32_t t = threadIdx.x;
+  const uint64_t r = blockIdx.x;
+  const int B = T - c, lo_w = b0 - c;
+  const uint64_t base = ((r & ((1ull << lo_w) - 1)) << c) | ((r >> lo_w) << (b0 + B));
+  const uint32_t cmask = (1u << c) - 1;
+  const uint32_t mask = ((1u << T) - 1) & ~cmask;
+  auto addr = [&](uint32_t e) -> uint64_t { return base | (e & cmask) | ((uint64_t)(e >> c) << b0); };
+  T2 v[G::RN];
+  for (int k = 0; k < NV; k++) {
+    T2 *vec = (k == 0 ? phi : lam) + (size_t)blockIdx.y * N;
+#pragma unroll
+    for (int j = 0; j < G::RN; j++) v[j] = vec[addr(elem<AH, T>(t, j))];
+    hstage<R, T, AH>(v, mask);
+    if (mask & group<AM, T>()) {
+      xchg1<R, T, AH, AM>(lds, v, t);
+      hstage<R, T, AM>(v, mask);
+      if (mask & group<AL, T>()) {
+        xchg1<R, T, AM, AL>(lds, v, t);
+        hstage<R, T, AL>(v, mask);
+        xchg1<R, T, AL, AH>(lds, v, t);
+      } else {
+        xchg1<R, T, AM, AH>(lds, v, t);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < G::RN; j++) vec[addr(elem<AH, T>(t, j))] = v[j];
+  }
+}
+
+static int wht_tile_bits(int precision) { return precision == 0 ? 13 : 12; }
+
+// Transformed bits of pass k of an n-qubit transform: the first pass takes the low T bits, the
+// others T - 5 bits at a time (rows of 2^5 amplitudes), the last one the remaining B bits with
+// T - B contiguous row bits.
+static void wht_schedule(int n, int T, std::vector<std::pair<int, int>> &out) {
+  int b = 0;
+  while (b < n) {
+    const int B = b == 0 ? T : (n - b < T - 5 ? n - b : T - 5);
+    out.emplace_back(b, b == 0 ? 0 : T - B);
+    b += B;
+  }
+}
+
+template <typename R, int T>
+static hipError_t wht_t(int nv, void *phi, void *lam, int n, int nsets, hipStream_t s) {
+  using T2 = typename Cplx<R>::T2;
+  const uint64_t N = 1ull << n;
+  const size_t lds = (size_t)((1u << T) + ((1u << T) >> Pad<R>::PS)) * sizeof(T2);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_wht<R, T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       96 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  std::vector<std::pair<int, int>> sched;
+  wht_schedule(n, T, sched);
+  const dim3 g((unsigned)(1ull << (n - T)), nsets);
+  // one vector per launch: the single-vector kernel keeps two waves per SIMD
+  for (int k = 0; k < nv; k++)
+    for (auto &bc : sched) {
+      k_wht<R, T, 1><<<g, 256, lds, s>>>((T2 *)(k == 0 ? phi : lam), nullptr, N, bc.first, bc.second);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+hipError_t launch_wht_tiles(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s) {
+  if (n < wht_tile_bits(precision)) return hipErrorInvalidValue;
+  return precision == 0 ? wht_t<float, 13>(nv, phi, lam, n, nsets, s) : wht_t<double, 12>(nv, phi, lam, n, nsets, s);
+}
+
+int wht_tile_passes(int n, int precision) {
+  std::vector<std::pair<int, int>> sched;
+  wht_schedule(n, wht_tile_bits(precision), sched);
+  return (int)sched.size();
+}
+
+int wht_min_bits(int precision) { return wht_tile_bits(precision); }
 
 // ============================================================== launch wrappers
 

@@ -3,11 +3,10 @@
 // qubit), the mixer's diagonal e^{-i beta d(y)} and W again, since W e^{-i beta f(Z)} W =
 // e^{-i beta f(X)}. Every step is unitary, so no scalar bookkeeping is needed.
 //
-// W runs as tile passes: a workgroup loads 2^(B + c) amplitudes of one vector into LDS (c
-// contiguous low index bits for coalesced rows, B transformed bits from b0 up), applies the B
-// butterfly rounds there and stores them back; passes over bits [0, 12), then [12, 19), ...
-// cover every qubit. Diagonals run elementwise; the index of the diagonal value comes from
-// the cost table, from the popcount of y (symmetric k-body mixers), from the parities of y
+// W runs as tile passes. For n >= 13 (complex64) or 12 (complex128) the passes hold tiles of
+// 2^13 or 2^12 amplitudes in registers (k_wht, next to the other register-tile kernels); below that a workgroup loads the whole
+// state into LDS (k_xwht below) and applies the n butterfly rounds there. Diagonals run
+// elementwise; the index of the diagonal value comes from the cost table, from the popcount of y (symmetric k-body mixers), from the parities of y
 // against up to 10 term masks (general term lists), or, per qubit, as a product of up to four
 // 256-entry factor tables over 8-bit slices of y. Gradient sums are taken in the same sweep as
 // the undoing of a diagonal, before it is undone: sum_y v(y) Im(conj(lam_y) phi_y), or for
@@ -342,6 +341,7 @@ hipError_t launch_xfinal(const double *partials, int nblk, int nsums, int nsets,
 }
 
 hipError_t launch_xwht(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s) {
+  if (n >= wht_min_bits(precision)) return launch_wht_tiles(precision, nv, phi, lam, n, nsets, s);
   const uint64_t N = 1ull << n;
   int b = 0;
   while (b < n) {
@@ -375,7 +375,8 @@ hipError_t launch_xwht(int precision, int nv, void *phi, void *lam, int n, int n
   return hipSuccess;
 }
 
-int xwht_passes(int n) {
+int xwht_passes(int n, int precision) {
+  if (n >= wht_min_bits(precision)) return wht_tile_passes(n, precision);
   int b = 0, k = 0;
   while (b < n) {
     const int c = b == 0 ? 0 : (b < 5 ? b : 5);

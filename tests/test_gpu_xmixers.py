@@ -148,3 +148,21 @@ def test_errors(q, ctx):
         q.expect_batched([P, P], [Mm, Mx], np.zeros((1, 9)))
     with pytest.raises(q.QAOAError):
         q.find_angles(P, Mm, 1)
+
+
+def test_full_size_against_stored_oracle_values(q, ctx):
+    """The benchmark's workload and launch configuration (16 angle sets per batched call) at
+    n = 24: set 0 against the FP64 oracle values stored by tests/golden/make_golden.py."""
+    import json
+    import os
+    W = workloads.workload("xorders_maxcut3reg_n24_p4")
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "xorders_maxcut3reg_n24_p4.json")))
+    rec = G["sets"][0]
+    assert np.array_equal(np.array(rec["angles"]), W.angles[0])
+    g = W.graphs[0]
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x_orders(ctx, g.n, W.extra["orders"])
+    for prec in (0, 1):
+        e, gr = q.expect_grad_batched([P], [M], W.angles, precision=prec)
+        assert abs(e[0, 0] - rec["expect"]) <= TOL[prec] * G["table_max"]
+        g0 = np.array(rec["grad"])
+        assert np.max(np.abs(gr[0, 0] - g0)) <= TOL[prec] * np.max(np.abs(g0))

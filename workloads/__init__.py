@@ -165,6 +165,13 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
         graphs = [erdos_renyi(12, 7000 + i, 0.5) for i in range(50 if n_sets is None else n_sets)]
         return Workload(name, "angle finding: 50 MaxCut G(12,1/2) instances, iterative basinhopping to p=10",
                         graphs, 10, np.zeros((0, 20)), extra={"seed": 7100, "n_chains": 8, "n_hops": 10})
+    if name == "xorders_maxcut3reg_n24_p4":
+        # mixer sum_i X_i + sum_{i<j} X_i X_j (orders 1 and 2, Eq. (2)), 16 angle sets per call
+        g, _ = _maxcut_3reg(24, 4, 8024)
+        ns = 16 if n_sets is None else n_sets
+        return Workload(name, "MaxCut, random 3-regular n=24, mixer of all 1- and 2-body X products, p=4, "
+                              "16 sets", [g], 4, random_angles(4, ns, 8025), mixer="x_orders",
+                        extra={"orders": [1, 2]})
     if name == "maxcut3reg_n32_p16":
         g, a = _maxcut_3reg(32, 16, 5032)
         return Workload(name, "MaxCut, random 3-regular n=32, X mixer, p=16, fwd+grad",
@@ -173,4 +180,5 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
 
 
 WORKLOADS = ["maxcut3reg_n10_p3", "maxcut3reg_n28_p8", "batched_er_n12to20_p10",
-             "bisection_g16_k8_p6", "maxcut3reg_n32_p16", "grover_maxcut3reg_n40_p16", "angles_er_n12_p10"]
+             "bisection_g16_k8_p6", "maxcut3reg_n32_p16", "grover_maxcut3reg_n40_p16", "angles_er_n12_p10",
+             "xorders_maxcut3reg_n24_p4"]
