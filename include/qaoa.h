@@ -286,7 +286,7 @@ void qaoa_angle_opts_default(qaoa_angle_opts *opts);
  * optimum): BFGS in inverse-Hessian form, started from the identity and rescaled after the
  * first step, with a backtracking line search that accepts on sufficient decrease or on the
  * approximate Wolfe conditions (a slope test that still works where single-precision
- * rounding hides the change of <C>). angles: host double [n_starts][2p], in:
+ * rounding hides the change of <C>); a trial step moves no angle by more than one radian. angles: host double [n_starts][2p], in:
  * starting points, out: the optima found; out_values: host double [n_starts], <C> there;
  * out_iters (NULL allowed): accepted steps taken. Starts are batched max_sets_per_call at a
  * time (automatic: as many as keep 2 x sets x states x 16 bytes under 4 GiB). Stops on

@@ -12,8 +12,9 @@ numpy FP64, on the oracle's <C> and adjoint gradient:
   Eq. 6.20), an update skipped when s.y <= 1e-10 |s| |y|; backtracking line search by halving
   (their Alg. 3.1), at most 20 halvings, accepting a step on sufficient decrease (c1 = 1e-4)
   or on the approximate Wolfe conditions of Hager and Zhang (SIAM J. Optim. 16, 170 (2005);
-  sigma = 0.9, delta = 0.1, eps = 1e-6); first trial step 1, except while H = I, where it is
-  min(1, 1 / max|g|); converged when max|g| <= gtol max(1, |f|).
+  sigma = 0.9, delta = 0.1, eps = 1e-6); first trial step min(1, 1 / max|d|) along the
+  search direction d (no angle moves more than one radian in a trial); converged when
+  max|g| <= gtol max(1, |f|).
 * Basinhopping (Wales and Doye, J. Phys. Chem. A 101, 5111 (1997)): local minimisation,
   uniform perturbation in [-step, step] per angle, local minimisation, Metropolis acceptance
   with probability exp(-(f_new - f_cur) / T).
@@ -105,7 +106,7 @@ def bfgs(fun, x0, gtol=1e-5, max_iter=100):
             gd = g @ d
             if not gd < 0:
                 break
-        alpha = min(1.0, 1.0 / np.max(np.abs(g))) if unscaled else 1.0
+        alpha = min(1.0, 1.0 / np.max(np.abs(d)))         # no angle moves more than one radian
         accepted = False
         for _ in range(MAX_HALVINGS + 1):
             xt = x + alpha * d

@@ -10,8 +10,9 @@
 //    Eq. 6.17), H_0 = I rescaled to (s.y / y.y) I before the first update (their Eq. 6.20),
 //    updates skipped when s.y <= 1e-10 |s| |y|; backtracking line search by halving (their
 //    Alg. 3.1) that accepts on sufficient decrease (c1 = 1e-4) or on the approximate Wolfe
-//    conditions (sigma = 0.9, delta = 0.1, eps = 1e-6); first trial step 1 except while
-//    H = I, where it is min(1, 1 / max|g|) so no angle moves more than one radian; 20
+//    conditions (sigma = 0.9, delta = 0.1, eps = 1e-6); first trial step min(1, 1 / max|d|)
+//    along the direction d, so no angle moves more than one radian in a trial (the landscape
+//    repeats, and an uncapped quasi-Newton step can jump by thousands of radians); 20
 //    halvings without acceptance end the minimisation; converged when
 //    max|g| <= gtol max(1, |f|).
 //  * Basinhopping (Wales and Doye, J. Phys. Chem. A 101, 5111 (1997)): minimise, perturb every
@@ -230,8 +231,7 @@ void new_direction(Run &r, int D) {
       return;
     }
   }
-  const double gmax = maxabs(r.g.data(), D);
-  r.alpha = r.unscaled ? std::min(1.0, 1.0 / gmax) : 1.0;
+  r.alpha = std::min(1.0, 1.0 / maxabs(r.d.data(), D));  // no angle moves more than one radian
   r.halvings = 0;
   for (int i = 0; i < D; i++) r.xt[i] = r.x[i] + r.alpha * r.d[i];
 }
