@@ -191,6 +191,7 @@ struct TileCfg {
   static constexpr int RN = 1 << RB;           // amplitudes per thread per vector
   static constexpr int MLO = T - 2 * RB;       // assignment M holds tile bits [MLO, MLO+RB)
   static_assert(MLO >= 0 && 3 * RB >= T, "tile shape");
+  static_assert(((1u << T) / 16) % 256 == 0, "table tile: whole 16-byte chunks per thread");
 };
 
 // Tile index of register j of thread t in assignment A.
@@ -533,6 +534,17 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   T2 phi[RN];
   T2 lam[NV == 2 ? RN : 1];
 
+  // ---- this tile's table bytes, loaded into registers ahead of the state so that writing
+  // them to LDS later waits only for these loads
+  constexpr bool need_tab = SHAPE != 0;
+  constexpr uint32_t kTabChunks = need_tab ? ((1u << T) * sizeof(TT)) / 16 / 256 : 1;  // 16 B per thread each
+  uint4 tpre[kTabChunks];
+  if constexpr (need_tab) {
+    const uint4 *tsrc = (const uint4 *)((const unsigned char *)(sp.tflip ? a.table_rev : a.table) +
+                                        (uint64_t)r * ((1ull << T) * sizeof(TT)));
+#pragma unroll
+    for (uint32_t k = 0; k < kTabChunks; k++) tpre[k] = tsrc[t + 256 * k];
+  }
   // ---- load (assignment H: lanes run over contiguous address bits)
   {
     const uint64_t src = (f & PF_LOAD_PSI0) ? (uint64_t)a.psi0 + base * sizeof(T2) : (uint64_t)a.phi + vs;
@@ -560,12 +572,12 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
     }
   }
   // ---- stage this tile's table entries and the set's LUT in LDS
-  constexpr bool need_tab = SHAPE != 0;
   if constexpr (need_tab) {
-    constexpr uint32_t nchunk = ((1u << T) * sizeof(TT)) / 16;
-    const uint4 *src = (const uint4 *)((const unsigned char *)(sp.tflip ? a.table_rev : a.table) +
-                                       (uint64_t)r * ((1ull << T) * sizeof(TT)));
-    for (uint32_t i = t; i < nchunk; i += 256) *(uint4 *)(ltab + i * 16 + ((i >> 4) << 4)) = src[i];
+#pragma unroll
+    for (uint32_t k = 0; k < kTabChunks; k++) {
+      const uint32_t i = t + 256 * k;
+      *(uint4 *)(ltab + i * 16 + ((i >> 4) << 4)) = tpre[k];
+    }
     if (sp.lut >= 0) {
       const T2 *lsrc = (const T2 *)a.luts + (size_t)sp.lut * a.lut_len;
       for (int i = t; i < a.lut_len; i += 256) llut[i] = lsrc[i];
