@@ -47,3 +47,42 @@ def test_no_oracle_on_product_path():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "liboracle" not in text, f
+
+
+def test_angle_finding_defaults_and_null_args():
+    """Host-side part of the angle-finding entry points: documented defaults, and NULL or
+    out-of-range arguments rejected before any device work."""
+    import ctypes
+    import paper_2312_06451_amd._lib as L
+    lib = L.lib()
+    o = L.qaoa_angle_opts_default()
+    assert (o.maximize, o.precision, o.max_iter, o.n_chains, o.n_hops, o.seed, o.max_sets_per_call) == \
+        (1, L.QAOA_FP32, 100, 8, 10, 0, 0)
+    assert (o.gtol, o.step, o.temperature) == (1e-5, 0.5, 1.0)
+    d = ctypes.c_double(1.0)
+    ang = (ctypes.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    out = (ctypes.c_double * 4)()
+    assert lib.qaoa_find_angles(None, None, 2, ctypes.byref(o), None, out, out, None) == L.QAOA_ERR_INVALID_ARG
+    assert lib.qaoa_minimize(None, None, 1, 2, ang, out, None, ctypes.byref(o), None) == L.QAOA_ERR_INVALID_ARG
+    bad = L.qaoa_angle_opts_default()
+    bad.n_chains = 0
+    assert lib.qaoa_basinhopping(None, None, 1, ang, ctypes.byref(bad), out, ctypes.byref(d), None) == \
+        L.QAOA_ERR_INVALID_ARG
+    assert b"n_chains" in lib.qaoa_last_error()
+    assert lib.qaoa_find_angles_random(None, None, 1, 0, ctypes.byref(o), out, ctypes.byref(d), None, None) == \
+        L.QAOA_ERR_INVALID_ARG
+    assert lib.qaoa_expect_pairs(None, None, 1, 1, ang, 0, out, None) == L.QAOA_ERR_INVALID_ARG
+
+
+def test_x_product_mixers_null_args():
+    import ctypes
+    import paper_2312_06451_amd._lib as L
+    lib = L.lib()
+    out = ctypes.c_void_p()
+    orders = (ctypes.c_int * 1)(1)
+    assert lib.qaoa_mixer_x_orders(None, 4, orders, 1, ctypes.byref(out)) == L.QAOA_ERR_INVALID_ARG
+    masks = (ctypes.c_uint64 * 1)(1)
+    coefs = (ctypes.c_double * 1)(1.0)
+    assert lib.qaoa_mixer_x_terms(None, 4, masks, coefs, 1, ctypes.byref(out)) == L.QAOA_ERR_INVALID_ARG
+    assert lib.qaoa_mixer_x_multiangle(None, 4, ctypes.byref(out)) == L.QAOA_ERR_INVALID_ARG
+    assert lib.qaoa_mixer_info(None, None, None, None) == L.QAOA_ERR_INVALID_ARG
