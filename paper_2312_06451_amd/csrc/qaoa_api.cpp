@@ -1764,11 +1764,15 @@ static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, con
   } else {
     HIPCHK(launch_xfill(precision, phi, (uint64_t)nsets * N, 1.0 / std::sqrt((double)N), st));
   }
+  // forward: each diagonal is applied by the first pass of the transform that follows it
   for (int k = 0; k < p; k++) {
-    cost_diag(k, 1.0, 1, 0);
-    wht(1);
-    mix_diag(k, 1.0, 1, 0);
-    wht(1);
+    HIPCHK(launch_xlut(precision, prob->dvals, lut_cost, dang, slen, p * m + k, 1.0, nsets, luts, st));
+    timed((2.0 * vb * xwht_passes(n, precision) + (double)N * prob->tbytes) * nsets,
+          [&] { return launch_xwht_pre(precision, phi, n, nsets, cost, luts, lut_cost, st); });
+    if (qb) HIPCHK(launch_xlut_q(precision, n, dang, slen, k * n, 1.0, nsets, luts, st));
+    else HIPCHK(launch_xlut(precision, mix->xvals, mix->xlen, dang, slen, k, 1.0, nsets, luts, st));
+    timed(2.0 * vb * xwht_passes(n, precision) * nsets,
+          [&] { return launch_xwht_pre(precision, phi, n, nsets, mix->xd, luts, mix->xlen, st); });
   }
   if (d_state) HIPCHK(hipMemcpyAsync(d_state, phi, N * esz, hipMemcpyDeviceToDevice, st));
   timed(vb * nsets * (grad ? 2.0 : 1.0) + (double)N * prob->tbytes * nsets, [&] {

@@ -166,6 +166,29 @@ struct XDiag {
   int nterms;           // XD_TERMS: index bit t = parity of (y & masks[t])
   uint64_t masks[XD_MAX_TERMS];
 };
+// Index of the diagonal value of basis state y (XD_TABLE, XD_POPCOUNT, XD_TERMS).
+__device__ __forceinline__ uint32_t xdiag_index(const XDiag &d, uint64_t y) {
+  if (d.mode == XD_TABLE)
+    return d.tbytes == 1 ? (uint32_t)((const uint8_t *)d.table)[y] : (uint32_t)((const uint16_t *)d.table)[y];
+  if (d.mode == XD_POPCOUNT) return (uint32_t)__popcll(y);
+  uint32_t idx = 0;
+  for (int t = 0; t < d.nterms; t++) idx |= (uint32_t)(__popcll(y & d.masks[t]) & 1) << t;
+  return idx;
+}
+// Diagonal entry of basis state y from a set's table: lut[index] (L = table length), or for
+// XD_QUBIT the product of the four 256-entry factor tables over the 8-bit slices of y.
+template <typename T2>
+__device__ __forceinline__ T2 xdiag_value(const XDiag &d, const T2 *lut, uint64_t y, uint64_t N) {
+  if (d.mode != XD_QUBIT) return lut[xdiag_index(d, y)];
+  T2 D = lut[y & 255];
+  for (int h = 1; h < 4; h++) {
+    if (N <= (1ull << (8 * h))) break;
+    const T2 f = lut[256 * h + ((y >> (8 * h)) & 255)];
+    const T2 o{D.x * f.x - D.y * f.y, D.x * f.y + D.y * f.x};
+    D = o;
+  }
+  return D;
+}
 unsigned xdiag_blocks(uint64_t N);
 int xwht_passes(int n, int precision);
 hipError_t launch_xlut(int precision, const double *vals, int len, const double *angles, int stride, int off,
@@ -183,7 +206,12 @@ hipError_t launch_xfinal(const double *partials, int nblk, int nsums, int nsets,
 hipError_t launch_xwht(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s);
 // Walsh-Hadamard transform with register tiles of 2^13 (complex64) or 2^12 (complex128)
 // amplitudes, for n >= wht_min_bits(precision).
-hipError_t launch_wht_tiles(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s);
+hipError_t launch_wht_tiles(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s,
+                            const XDiag *pre = nullptr, const void *luts = nullptr, int lut_len = 0);
+// W applied to one vector after multiplying it by a diagonal (forward steps of the X-product
+// path); the multiply is fused into the first transform pass when the register tiles apply.
+hipError_t launch_xwht_pre(int precision, void *phi, int n, int nsets, const XDiag &d, const void *luts, int lut_len,
+                           hipStream_t s);
 int wht_tile_passes(int n, int precision);
 int wht_min_bits(int precision);
 

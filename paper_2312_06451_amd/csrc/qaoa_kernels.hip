@@ -1097,9 +1097,10 @@ __device__ __forceinline__ void hstage(typename Cplx<R>::T2 *v, uint32_t mask) {
 // tile bits [c, T) are the transformed index bits [b0, b0 + T - c) (c = 0 and b0 = 0 for the
 // first pass). Stages H, then M and L as far as the transformed bits reach, with LDS
 // exchanges between them; loads and stores in assignment H (lanes over the low tile bits).
-template <typename R, int T, int NV>
+template <typename R, int T, int NV, bool PRE>
 __global__ __launch_bounds__(256) void k_wht(typename Cplx<R>::T2 *__restrict__ phi,
-                                             typename Cplx<R>::T2 *__restrict__ lam, uint64_t N, int b0, int c) {
+                                             typename Cplx<R>::T2 *__restrict__ lam, uint64_t N, int b0, int c,
+                                             XDiag pre, const typename Cplx<R>::T2 *__restrict__ luts, int lut_len) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1116,6 +1117,11 @@ __global__ __launch_bounds__(256) void k_wht(typename Cplx<R>::T2 *__restrict__ 
     T2 *vec = (k == 0 ? phi : lam) + (size_t)blockIdx.y * N;
 #pragma unroll
     for (int j = 0; j < G::RN; j++) v[j] = vec[addr(elem<AH, T>(t, j))];
+    if constexpr (PRE) {  // the diagonal that precedes this transform, applied on load
+      const T2 *lut = luts + (size_t)blockIdx.y * (pre.mode == XD_QUBIT ? 1024 : lut_len);
+#pragma unroll
+      for (int j = 0; j < G::RN; j++) v[j] = cmul<T2, R>(v[j], xdiag_value(pre, lut, addr(elem<AH, T>(t, j)), N));
+    }
     hstage<R, T, AH>(v, mask);
     if (mask & group<AM, T>()) {
       xchg1<R, T, AH, AM>(lds, v, t);
@@ -1148,33 +1154,45 @@ static void wht_schedule(int n, int T, std::vector<std::pair<int, int>> &out) {
 }
 
 template <typename R, int T>
-static hipError_t wht_t(int nv, void *phi, void *lam, int n, int nsets, hipStream_t s) {
+static hipError_t wht_t(int nv, void *phi, void *lam, int n, int nsets, hipStream_t s, const XDiag *pre,
+                        const void *luts, int lut_len) {
   using T2 = typename Cplx<R>::T2;
   const uint64_t N = 1ull << n;
   const size_t lds = (size_t)((1u << T) + ((1u << T) >> Pad<R>::PS)) * sizeof(T2);
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_wht<R, T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)k_wht<R, T, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        96 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_wht<R, T, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              96 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
   std::vector<std::pair<int, int>> sched;
   wht_schedule(n, T, sched);
   const dim3 g((unsigned)(1ull << (n - T)), nsets);
+  const XDiag none{};
   // one vector per launch: the single-vector kernel keeps two waves per SIMD
   for (int k = 0; k < nv; k++)
-    for (auto &bc : sched) {
-      k_wht<R, T, 1><<<g, 256, lds, s>>>((T2 *)(k == 0 ? phi : lam), nullptr, N, bc.first, bc.second);
+    for (size_t i = 0; i < sched.size(); i++) {
+      T2 *v = (T2 *)(k == 0 ? phi : lam);
+      if (i == 0 && k == 0 && pre)
+        k_wht<R, T, 1, true><<<g, 256, lds, s>>>(v, nullptr, N, sched[i].first, sched[i].second, *pre,
+                                                 (const T2 *)luts, lut_len);
+      else
+        k_wht<R, T, 1, false><<<g, 256, lds, s>>>(v, nullptr, N, sched[i].first, sched[i].second, none, nullptr, 0);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
   return hipSuccess;
 }
 
-hipError_t launch_wht_tiles(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s) {
+hipError_t launch_wht_tiles(int precision, int nv, void *phi, void *lam, int n, int nsets, hipStream_t s,
+                            const XDiag *pre, const void *luts, int lut_len) {
   if (n < wht_tile_bits(precision)) return hipErrorInvalidValue;
-  return precision == 0 ? wht_t<float, 13>(nv, phi, lam, n, nsets, s) : wht_t<double, 12>(nv, phi, lam, n, nsets, s);
+  return precision == 0 ? wht_t<float, 13>(nv, phi, lam, n, nsets, s, pre, luts, lut_len)
+                        : wht_t<double, 12>(nv, phi, lam, n, nsets, s, pre, luts, lut_len);
 }
 
 int wht_tile_passes(int n, int precision) {

@@ -86,16 +86,6 @@ __device__ __forceinline__ void block_partials(const double *v, double *red, dou
 
 // ---------------------------------------------------------------- diagonals
 
-// Index of the diagonal value of basis state y.
-__device__ __forceinline__ uint32_t xindex(const XDiag &d, uint64_t y) {
-  if (d.mode == XD_TABLE)
-    return d.tbytes == 1 ? (uint32_t)((const uint8_t *)d.table)[y] : (uint32_t)((const uint16_t *)d.table)[y];
-  if (d.mode == XD_POPCOUNT) return (uint32_t)__popcll(y);
-  uint32_t idx = 0;
-  for (int t = 0; t < d.nterms; t++) idx |= (uint32_t)(__popcll(y & d.masks[t]) & 1) << t;
-  return idx;
-}
-
 // v <- D v for NV vectors, D from the staged LUT (modes TABLE, POPCOUNT, TERMS) or the per-qubit
 // factor tables (mode QUBIT). GS: first add sum_y g(y) Im(conj(lam) phi) into the partials, with
 // g(y) = gv[index] - gshift, or (QUBIT) the total and the per-bit sums.
@@ -131,7 +121,7 @@ __global__ __launch_bounds__(256) void k_xdiag(typename XC<R>::T2 *__restrict__ 
       if (N > 65536) D = xmul(D, lut[512 + ((y >> 16) & 255)]);
       if (N > 16777216) D = xmul(D, lut[768 + ((y >> 24) & 255)]);
     }
-    const uint32_t idx = QUBIT ? 0u : xindex(d, y);
+    const uint32_t idx = QUBIT ? 0u : xdiag_index(d, y);
     if constexpr (!QUBIT) D = lut[idx];
     T2 a = ph[y];
     if constexpr (NV == 2) {
@@ -176,7 +166,7 @@ __global__ __launch_bounds__(256) void k_xend(const typename XC<R>::T2 *__restri
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   for (uint64_t y = (uint64_t)blockIdx.x * 256 + t; y < N; y += stride) {
     const T2 a = ph[y];
-    const double c = lv[xindex(d, y)];
+    const double c = lv[xdiag_index(d, y)];
     const double pr = (double)a.x * a.x + (double)a.y * a.y;
     acc[0] += pr * c;
     acc[1] += pr;
@@ -373,6 +363,15 @@ hipError_t launch_xwht(int precision, int nv, void *phi, void *lam, int n, int n
     b += B;
   }
   return hipSuccess;
+}
+
+hipError_t launch_xwht_pre(int precision, void *phi, int n, int nsets, const XDiag &d, const void *luts, int lut_len,
+                           hipStream_t s) {
+  if (n >= wht_min_bits(precision)) return launch_wht_tiles(precision, 1, phi, nullptr, n, nsets, s, &d, luts, lut_len);
+  hipError_t e = launch_xdiag(precision, 1, 0, phi, nullptr, 1ull << n, d, luts, lut_len, nullptr, 0.0, nullptr,
+                              nsets, s);
+  if (e != hipSuccess) return e;
+  return launch_xwht(precision, 1, phi, nullptr, n, nsets, s);
 }
 
 int xwht_passes(int n, int precision) {
