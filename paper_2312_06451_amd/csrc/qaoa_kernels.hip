@@ -976,7 +976,7 @@ __device__ __forceinline__ double w_rev_mixer(typename Cplx<R>::T2 *phi, typenam
 
 template <typename R, int T, typename TT>
 __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ items, const double *__restrict__ angles,
-                                               int p, int grad, int max_lut, double *__restrict__ out) {
+                                               int p, int grad, int max_lut, int pre, double *__restrict__ out) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
   constexpr int RN = G::RN;
@@ -988,6 +988,11 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
   double *dval = (double *)(lut + max_lut);
   unsigned char *tab = (unsigned char *)(dval + max_lut);
   double *red = (double *)(tab + ((N * sizeof(TT) + 15) & ~15u));
+  // pre != 0: every layer's phase table computed once (forward tables, then reverse ones),
+  // per-layer scalars, and the per-wave partial gradient sums, reduced after the sweep
+  T2 *plut = (T2 *)(red + 4);
+  double *scal = (double *)(plut + (size_t)(pre ? 2 * p * max_lut : 0));  // 6 per layer
+  double *gsum = scal + (pre ? 6 * p : 0);                                // 8 per layer
   const SmallItem it = items[blockIdx.x];
   const uint32_t t = threadIdx.x;
   const double *ang = angles + (size_t)it.angle_set * 2 * p;
@@ -997,15 +1002,53 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
   uint32_t F = 0;
   const uint32_t FALL = it.sym ? 0u : N - 1;
   DC sig{1.0, 0.0};
+  auto lut_entry = [&](const DC &sc, double gamma, double sign, int c) -> T2 {
+    double sn, co;
+    sincos(sign * gamma * dval[c], &sn, &co);
+    return T2{(R)(sc.re * co - sc.im * sn), (R)(sc.re * sn + sc.im * co)};
+  };
   auto build_lut = [&](double gamma, double sign) {
     __syncthreads();
-    for (int c = t; c < it.lut_len; c += 256) {
-      double sn, co;
-      sincos(sign * gamma * dval[c], &sn, &co);
-      lut[c] = T2{(R)(sig.re * co - sig.im * sn), (R)(sig.re * sn + sig.im * co)};
-    }
+    for (int c = t; c < it.lut_len; c += 256) lut[c] = lut_entry(sig, gamma, sign, c);
     __syncthreads();
   };
+  if (pre) {
+    __syncthreads();  // dval staged
+    // scalars of layer k, in the order the sweeps accumulate them: forward table scale
+    // (f_{k-1}^T, 1 for k = 0), reverse table scale and weights before and after undoing
+    // layer k (the last layer starts from the forward's final scalar)
+    for (int k = t; k < p; k += 256) {
+      R tau;
+      DC f, finv, sf{1.0, 0.0}, before{1.0, 0.0};
+      bool fl;
+      if (k > 0) {
+        rot_params<R>(ang[k - 1], tau, f, finv, fl);
+        for (int qb = 0; qb < T; qb++) sf = dmul(sf, f);
+      }
+      rot_params<R>(ang[k], tau, f, finv, fl);
+      if (k == p - 1)
+        for (int qb = 0; qb < T; qb++) before = dmul(before, f);
+      DC after = before;
+      for (int qb = 0; qb < T; qb++) after = dmul(after, finv);
+      double *sk = scal + 6 * k;
+      sk[0] = sf.re;
+      sk[1] = sf.im;
+      sk[2] = after.re;
+      sk[3] = after.im;
+      sk[4] = before.re * before.re + before.im * before.im;
+      sk[5] = after.re * after.re + after.im * after.im;
+    }
+    __syncthreads();
+    for (int i = t; i < 2 * p * it.lut_len; i += 256) {
+      const int kk = i / it.lut_len, c = i - kk * it.lut_len;
+      const bool rev = kk >= p;
+      const int k = rev ? kk - p : kk;
+      const double *sk = scal + 6 * k;
+      const DC sc = rev ? DC{sk[2], sk[3]} : DC{sk[0], sk[1]};
+      plut[(size_t)kk * max_lut + c] = lut_entry(sc, ang[p + k], rev ? 1.0 : -1.0, c);
+    }
+    __syncthreads();
+  }
 
   T2 phi[RN], lam[RN];
   const R u0 = (R)(1.0 / sqrt((double)N));
@@ -1015,8 +1058,10 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
   // ---- forward: layer k starts in H when k is even (H, M, L) and in L when odd (L, M, H)
   auto fwd_layer = [&](int k, auto down) {
     constexpr bool D = decltype(down)::value;
-    build_lut(ang[p + k], -1.0);
-    w_phase<R, T, TT, D ? AH : AL, 1>(phi, lam, tab, lut, F, t);
+    const T2 *lk = lut;
+    if (pre) lk = plut + (size_t)k * max_lut;
+    else build_lut(ang[p + k], -1.0);
+    w_phase<R, T, TT, D ? AH : AL, 1>(phi, lam, tab, lk, F, t);
     sig = DC{1.0, 0.0};
     R tau;
     DC f, finv;
@@ -1041,6 +1086,11 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
   if (t == 0) o[0] = e / nr;
   if (!grad) return;
 
+  // wave sums (the first half of block_sum); with pre they are kept per layer and wave
+  auto wave_sum = [&](double v) -> double {
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+  };
   // ---- reverse: layer k was DOWN when k is even; undoing it ends in its first assignment
   auto rev_layer = [&](int k, auto down) {
     constexpr bool D = decltype(down)::value;
@@ -1050,22 +1100,44 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
     DC f, finv;
     bool fl;
     rot_params<R>(ang[k], tau, f, finv, fl);
-    const double gb = block_sum(w_rev_mixer<R, T, D>(phi, lam, lds, t, tau), red);
-    if (t == 0) o[1 + k] = 2.0 * wgt * gb / ntrue;
+    const double xb = w_rev_mixer<R, T, D>(phi, lam, lds, t, tau);
+    if (pre) {
+      const double v = wave_sum(xb);
+      if ((t & 63) == 0) gsum[8 * k + (t >> 6)] = v;
+    } else {
+      const double gb = block_sum(xb, red);
+      if (t == 0) o[1 + k] = 2.0 * wgt * gb / ntrue;
+    }
     if (fl) F ^= FALL;
     for (int qb = 0; qb < T; qb++) sig = dmul(sig, finv);
-    const double gg = block_sum(w_ggamma<R, T, TT, A0>(phi, lam, tab, dval, it.c0, F, t), red);
-    const double wg2 = sig.re * sig.re + sig.im * sig.im;
-    if (t == 0) o[1 + p + k] = 2.0 * wg2 * gg / ntrue;
+    const double xg = w_ggamma<R, T, TT, A0>(phi, lam, tab, dval, it.c0, F, t);
+    if (pre) {
+      const double v = wave_sum(xg);
+      if ((t & 63) == 0) gsum[8 * k + 4 + (t >> 6)] = v;
+    } else {
+      const double gg = block_sum(xg, red);
+      const double wg2 = sig.re * sig.re + sig.im * sig.im;
+      if (t == 0) o[1 + p + k] = 2.0 * wg2 * gg / ntrue;
+    }
     if (k > 0) {
-      build_lut(ang[p + k], 1.0);
-      w_phase<R, T, TT, A0, 2>(phi, lam, tab, lut, F, t);
+      const T2 *lk = lut;
+      if (pre) lk = plut + (size_t)(p + k) * max_lut;
+      else build_lut(ang[p + k], 1.0);
+      w_phase<R, T, TT, A0, 2>(phi, lam, tab, lk, F, t);
       sig = DC{1.0, 0.0};
     }
   };
   for (int k = p - 1; k >= 0; k--) {
     if (k & 1) rev_layer(k, std::false_type{});
     else rev_layer(k, std::true_type{});
+  }
+  if (pre) {  // the block sums, in block_sum's order, and the layer weights
+    __syncthreads();
+    for (int k = t; k < p; k += 256) {
+      const double *gk = gsum + 8 * k, *sk = scal + 6 * k;
+      o[1 + k] = 2.0 * sk[4] * ((gk[0] + gk[1]) + (gk[2] + gk[3])) / ntrue;
+      o[1 + p + k] = 2.0 * sk[5] * ((gk[4] + gk[5]) + (gk[6] + gk[7])) / ntrue;
+    }
   }
 }
 
@@ -1388,8 +1460,14 @@ static hipError_t launch_whole_t(const SmallItem *items, int n_items, int max_lu
                                  int grad, double *out, hipStream_t s) {
   using T2 = typename Cplx<R>::T2;
   constexpr size_t N = size_t(1) << T;
-  const size_t lds = (N + (N >> Pad<R>::PS)) * sizeof(T2) + (size_t)max_lut * (sizeof(T2) + sizeof(double)) +
-                     ((N * sizeof(TT) + 15) & ~size_t(15)) + 64;
+  const size_t base = (N + (N >> Pad<R>::PS)) * sizeof(T2) + (size_t)max_lut * (sizeof(T2) + sizeof(double)) +
+                      ((N * sizeof(TT) + 15) & ~size_t(15)) + 4 * sizeof(double);
+  // precomputed phase tables and deferred sums when they fit without lowering occupancy:
+  // complex64 at n = 12 keeps two workgroups per CU below 80 KB
+  const size_t with_pre = base + (size_t)2 * p * max_lut * sizeof(T2) + (size_t)14 * p * sizeof(double);
+  const size_t cap = (sizeof(R) == 4 && T == 12) ? 80 * 1024 : 160 * 1024;
+  const int pre = grad && with_pre <= cap ? 1 : 0;
+  const size_t lds = pre ? with_pre : base + 64;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)k_whole<R, T, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1398,7 +1476,7 @@ static hipError_t launch_whole_t(const SmallItem *items, int n_items, int max_lu
     attr_set = true;
   }
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_whole<R, T, TT>), dim3(n_items), dim3(256), lds, s, items, angles, p, grad, max_lut, out);
+  hipLaunchKernelGGL((k_whole<R, T, TT>), dim3(n_items), dim3(256), lds, s, items, angles, p, grad, max_lut, pre, out);
   return hipGetLastError();
 }
 
