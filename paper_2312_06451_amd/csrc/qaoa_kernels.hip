@@ -286,6 +286,69 @@ __device__ __forceinline__ void xchg1(typename Cplx<R>::T2 *lds, typename Cplx<R
   from_lds<R, T, TO>(lds, v, t);
 }
 
+// Exchange through a half-size buffer in two rounds, split on tile bit T - 1 (register bit
+// RB - 1 in assignment H, thread bit 7 in M and L): round h moves the amplitudes whose tile
+// bit T - 1 is h. A thread that must read before it has written all of its own registers
+// parks the values in `tmp` (register-to-thread moves at h = 0), or all threads read the
+// first half into `tmp` (thread-to-register moves), so nothing is overwritten unsent.
+template <typename R, int T, int FROM, int TO, int HB>
+__device__ __forceinline__ void xchgh_round(typename Cplx<R>::T2 *lds, typename Cplx<R>::T2 *v,
+                                            typename Cplx<R>::T2 *tmp, uint32_t t, uint32_t tb) {
+  using G = TileCfg<T>;
+  constexpr int RN = G::RN, HN = RN / 2;
+  constexpr uint32_t D = HB ? (1u << (T - 1)) + (1u << (T - 1 - Pad<R>::PS)) : 0u;  // slots of the lower half
+  __syncthreads();
+  typename Cplx<R>::T2 *pf = lds + lbase<R, T, FROM>(t) - D;
+  if constexpr (FROM == AH) {
+#pragma unroll
+    for (int j = 0; j < RN; j++)
+      if (((j >> (G::RB - 1)) & 1) == HB) pf[loff<R, T, FROM>(j)] = v[j];
+  } else {
+    if (tb == (uint32_t)HB) {
+#pragma unroll
+      for (int j = 0; j < RN; j++) pf[loff<R, T, FROM>(j)] = v[j];
+    }
+  }
+  __syncthreads();
+  const typename Cplx<R>::T2 *pt = lds + lbase<R, T, TO>(t) - D;
+  if constexpr (TO == AH) {
+#pragma unroll
+    for (int j = 0; j < RN; j++)
+      if (((j >> (G::RB - 1)) & 1) == HB) {
+        if (HB == 0) tmp[j] = pt[loff<R, T, TO>(j)];
+        else v[j] = pt[loff<R, T, TO>(j)];
+      }
+  } else {
+    if (tb == (uint32_t)HB) {
+#pragma unroll
+      for (int j = 0; j < RN; j++) {
+        if (FROM == AH && HB == 0 && j >= HN) tmp[j - HN] = pt[loff<R, T, TO>(j)];
+        else v[j] = pt[loff<R, T, TO>(j)];
+      }
+    }
+  }
+}
+template <typename R, int T, int FROM, int TO>
+__device__ __forceinline__ void xchg1h(typename Cplx<R>::T2 *lds, typename Cplx<R>::T2 *v, uint32_t t) {
+  if constexpr (FROM != TO) {
+    using G = TileCfg<T>;
+    constexpr int HN = G::RN / 2;
+    typename Cplx<R>::T2 tmp[HN];
+    const uint32_t tb = (t >> 7) & 1u;  // tile bit T - 1 in assignments M and L
+    xchgh_round<R, T, FROM, TO, 0>(lds, v, tmp, t, tb);
+    xchgh_round<R, T, FROM, TO, 1>(lds, v, tmp, t, tb);
+    if constexpr (TO == AH) {
+#pragma unroll
+      for (int j = 0; j < HN; j++) v[j] = tmp[j];
+    } else if constexpr (FROM == AH) {
+      if (tb == 0) {
+#pragma unroll
+        for (int j = 0; j < HN; j++) v[HN + j] = tmp[j];
+      }
+    }
+  }
+}
+
 // (a, b) <- (a - i tau b, b - i tau a)
 template <typename T2, typename R>
 __device__ __forceinline__ void bfly(T2 &a, T2 &b, R tau) {
@@ -474,6 +537,29 @@ __device__ __forceinline__ void xchg(typename Cplx<R>::T2 *lds, typename Cplx<R>
   }
 }
 
+// Tile passes over one vector that do more than one register block (or start a sweep) use
+// the half-size exchange: half the LDS, so three workgroups fit on a CU and one workgroup's
+// loads overlap another's stages. The single-block forward pass keeps the full exchange
+// (fewer barriers; it already streams at the copy rate), and so do the two-vector passes
+// (their registers would not leave room for three workgroups); passes whose stages stay in
+// assignment H exchange nothing.
+template <int KIND, int S1, int S2>
+constexpr bool pass_half_xchg() { return KIND == 1 && !(S1 == 7 && S2 == 0) && ((S1 | S2) & 6) != 0; }
+
+template <typename R, int T, int FROM, int TO, bool HALF>
+__device__ __forceinline__ void xchg1p(typename Cplx<R>::T2 *lds, typename Cplx<R>::T2 *v, uint32_t t) {
+  if constexpr (HALF) xchg1h<R, T, FROM, TO>(lds, v, t);
+  else xchg1<R, T, FROM, TO>(lds, v, t);
+}
+template <typename R, int T, int NV, int FROM, int TO, bool HALF>
+__device__ __forceinline__ void xchgp(typename Cplx<R>::T2 *lds, typename Cplx<R>::T2 *phi,
+                                      typename Cplx<R>::T2 *lam, uint32_t t) {
+  if constexpr (FROM != TO) {
+    xchg1p<R, T, FROM, TO, HALF>(lds, phi, t);
+    if constexpr (NV == 2) xchg1p<R, T, FROM, TO, HALF>(lds, lam, t);
+  }
+}
+
 // Register assignment after the stages of set S (bit 0: H, bit 1: M, bit 2: L) visited in the
 // order H, M, L (DOWN) or L, M, H (UP), starting from assignment START.
 template <int S, bool DOWN, int START>
@@ -488,13 +574,14 @@ constexpr int after_stages() {
 // sweep on phi (part 1), <C> and lam = rho (C - c0) phi (middle), then the reverse sweep's
 // first block on both (part 2). S1 / S2: register stages of part 1 / part 2.
 template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT>
-__global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
+__global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void k_pass(const PassArgs<R> a) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
   constexpr int NV = KIND == 1 ? 1 : 2;
   constexpr int RN = G::RN;
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr uint32_t kStateSlots = (1u << T) + ((1u << T) >> (sizeof(R) == 4 ? 5 : 4));
+  constexpr bool HALF = pass_half_xchg<KIND, S1, S2>();
+  constexpr uint32_t kStateSlots = ((1u << T) >> (HALF ? 1 : 0)) + (((1u << T) >> (HALF ? 1 : 0)) >> Pad<R>::PS);
   constexpr uint32_t kTabBytes = ((1u << T) * sizeof(TT)) + (((1u << T) * sizeof(TT)) >> 8) * 16;
   T2 *lds = (T2 *)smem;
   unsigned char *ltab = smem + kStateSlots * sizeof(T2);
@@ -595,11 +682,11 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   const uint32_t m1 = a.mask1;
   if constexpr (S1 & 1) stage<R, T, NV, AH, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
   if constexpr (S1 & 2) {
-    xchg<R, T, NV, AH, AM>(lds, phi, lam, t);
+    xchgp<R, T, NV, AH, AM, HALF>(lds, phi, lam, t);
     stage<R, T, NV, AM, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
   }
   if constexpr (S1 & 4) {
-    xchg<R, T, NV, (S1 & 2) ? AM : AH, AL>(lds, phi, lam, t);
+    xchgp<R, T, NV, (S1 & 2) ? AM : AH, AL, HALF>(lds, phi, lam, t);
     stage<R, T, NV, AL, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
   }
   constexpr int CM = after_stages<S1, true, AH>();
@@ -619,22 +706,22 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   constexpr bool RL2 = KIND != 1, XT2 = KIND != 1;
   const uint32_t m2 = a.mask2;
   if constexpr (S2 & 4) {
-    xchg<R, T, NV, CM, AL>(lds, phi, lam, t);
+    xchgp<R, T, NV, CM, AL, HALF>(lds, phi, lam, t);
     stage<R, T, NV, AL, RL2, XT2>(phi, lam, m2, sp.tau2, w, acc[SL_C]);
   }
   if constexpr (S2 & 2) {
-    xchg<R, T, NV, (S2 & 4) ? AL : CM, AM>(lds, phi, lam, t);
+    xchgp<R, T, NV, (S2 & 4) ? AL : CM, AM, HALF>(lds, phi, lam, t);
     stage<R, T, NV, AM, RL2, XT2>(phi, lam, m2, sp.tau2, w, acc[SL_C]);
   }
   if constexpr (S2 & 1) {
-    xchg<R, T, NV, (S2 & 2) ? AM : ((S2 & 4) ? AL : CM), AH>(lds, phi, lam, t);
+    xchgp<R, T, NV, (S2 & 2) ? AM : ((S2 & 4) ? AL : CM), AH, HALF>(lds, phi, lam, t);
     stage<R, T, NV, AH, RL2, XT2>(phi, lam, m2, sp.tau2, w, acc[SL_C]);
   }
   constexpr int CE = after_stages<S2, false, CM>();
   // ---- store (assignment H)
   if constexpr (KIND != 3) {
     if (f & PF_STORE_PHI) {
-      xchg1<R, T, CE, AH>(lds, phi, t);
+      xchg1p<R, T, CE, AH, HALF>(lds, phi, t);
       const uint64_t dst = (uint64_t)a.phi_out + vs;
 #pragma unroll
       for (int j = 0; j < RN; j++) st(dst, j, phi[j]);
@@ -642,7 +729,7 @@ __global__ __launch_bounds__(256, 2) void k_pass(const PassArgs<R> a) {
   }
   if constexpr (KIND != 1) {
     if (f & PF_STORE_LAM) {
-      xchg1<R, T, CE, AH>(lds, lam, t);
+      xchg1p<R, T, CE, AH, HALF>(lds, lam, t);
       const uint64_t dl = (uint64_t)a.lam + vs;
 #pragma unroll
       for (int j = 0; j < RN; j++) st(dl, j, lam[j]);
@@ -1354,8 +1441,9 @@ hipError_t launch_table_values(const void *table, int tbytes, const double *vals
 }
 
 template <typename R, int T>
-static size_t lds_for(int tbytes, int lut_len) {
-  size_t st = ((1u << T) + ((1u << T) >> (sizeof(R) == 4 ? 5 : 4))) * 2 * sizeof(R);
+static size_t lds_for(int tbytes, int lut_len, bool half = false) {
+  const size_t slots = (size_t)1 << (half ? T - 1 : T);
+  size_t st = (slots + (slots >> (sizeof(R) == 4 ? 5 : 4))) * 2 * sizeof(R);
   size_t tb = ((size_t)(1u << T) * tbytes);
   tb += (tb >> 8) * 16;
   return st + tb + (size_t)lut_len * 3 * sizeof(R);
@@ -1368,7 +1456,7 @@ size_t pass_lds_bytes(int precision, int tbytes, int lut_len) {
 
 template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT>
 static hipError_t launch_pass_t(const PassArgs<R> &a, hipStream_t s) {
-  size_t lds = lds_for<R, T>((int)sizeof(TT), a.lut_len);
+  size_t lds = lds_for<R, T>((int)sizeof(TT), a.lut_len, pass_half_xchg<KIND, S1, S2>());
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)k_pass<R, T, KIND, S1, S2, SHAPE, TT>,
