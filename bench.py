@@ -204,7 +204,7 @@ def traffic_from_profile(workload, cls):
 
 KERNEL_NAMES = {"xmix": "k_xwht / k_xdiag (Walsh-Hadamard passes and diagonals of X-product mixers)",
                 "fwd_pass": "k_pass<float,13,1,uint8> (tile pass, one vector)",
-                "rev_pass": "k_pass<float,13,2|3,uint8> (tile pass, state and adjoint vector)",
+                "rev_pass": "k_pass<float,13,2|3|4,uint8> (tile pass, state and adjoint vector)",
                 "small": "k_small<float> (whole state in one workgroup)",
                 "dense": "hipBLASLt GEMM f16 x f16 -> f32 (split eigenbasis product, 2 calls)"}
 

@@ -176,6 +176,7 @@ double dot(const double *a, const double *b, int D) {
 
 struct Run {
   std::vector<double> x, g, H, d, xt;
+  std::vector<double> s, y, Hy;  // scratch of the update, allocated once per run
   double f = 0.0, gd = 0.0, alpha = 1.0;
   int iters = 0, halvings = 0, owner = 0;
   bool unscaled = true;  // H = I, not yet rescaled by a first update
@@ -201,6 +202,9 @@ void start_run(Run &r, int owner, const double *x0, int D) {
   r.d.assign(D, 0.0);
   r.H.assign((size_t)D * D, 0.0);
   r.xt.assign(x0, x0 + D);
+  r.s.assign(D, 0.0);
+  r.y.assign(D, 0.0);
+  r.Hy.assign(D, 0.0);
   r.f = r.gd = 0.0;
   r.alpha = 1.0;
   r.iters = r.halvings = 0;
@@ -249,9 +253,9 @@ void bfgs_update(Run &r, const double *s, const double *y, int D) {
   }
   // H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T, expanded with Hy = H y (H symmetric)
   const double rho = 1.0 / sy;
-  std::vector<double> Hy(D);
+  double *Hy = r.Hy.data();
   for (int i = 0; i < D; i++) Hy[i] = dot(&r.H[(size_t)i * D], y, D);
-  const double yHy = dot(y, Hy.data(), D);
+  const double yHy = dot(y, Hy, D);
   const double c = rho * rho * yHy + rho;
   for (int i = 0; i < D; i++)
     for (int j = 0; j < D; j++)
@@ -266,9 +270,9 @@ void bfgs_update(Run &r, const double *s, const double *y, int D) {
 void advance(Run &r, double ft, const double *gt, int D, const qaoa_angle_opts &o) {
   if (r.init) {
     r.init = false;
-    r.x = r.xt;
+    std::copy(r.xt.begin(), r.xt.end(), r.x.begin());
     r.f = ft;
-    r.g.assign(gt, gt + D);
+    std::copy(gt, gt + D, r.g.begin());
     if (!std::isfinite(r.f) || converged(r, o, D) || o.max_iter <= 0) r.done = true;
     else new_direction(r, D);
     return;
@@ -280,15 +284,15 @@ void advance(Run &r, double ft, const double *gt, int D, const qaoa_angle_opts &
              (ft <= r.f + kEps * std::fabs(r.f) && slope >= kSigma * r.gd && slope <= (2.0 * kDelta - 1.0) * r.gd);
   }
   if (accept) {
-    std::vector<double> s(D), y(D);
+    double *s = r.s.data(), *y = r.y.data();
     for (int j = 0; j < D; j++) {
       s[j] = r.xt[j] - r.x[j];
       y[j] = gt[j] - r.g[j];
     }
-    bfgs_update(r, s.data(), y.data(), D);
-    r.x = r.xt;
+    bfgs_update(r, s, y, D);
+    std::copy(r.xt.begin(), r.xt.end(), r.x.begin());
     r.f = ft;
-    r.g.assign(gt, gt + D);
+    std::copy(gt, gt + D, r.g.begin());
     r.iters++;
     if (converged(r, o, D) || r.iters >= o.max_iter) r.done = true;
     else new_direction(r, D);

@@ -721,7 +721,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         }
         sps.push_back(q);
       }
-      add_pass(a, 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile);
+      // with checkpoints phi is read and never stored: the kind that compiles its store out
+      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile);
     }
   }
 

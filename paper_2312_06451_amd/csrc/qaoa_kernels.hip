@@ -570,9 +570,11 @@ constexpr int after_stages() {
 
 // One tile pass. KIND 1: forward over phi. KIND 2: reverse sweep over (phi, lam): part 1 undoes
 // the forward pass's last rotation block (X-pair terms first), the middle reads the gamma
-// gradient and undoes the phase, part 2 undoes the first block. KIND 3: end of the forward
-// sweep on phi (part 1), <C> and lam = rho (C - c0) phi (middle), then the reverse sweep's
-// first block on both (part 2). S1 / S2: register stages of part 1 / part 2.
+// gradient and undoes the phase, part 2 undoes the first block. KIND 4: KIND 2 reading phi
+// from a forward checkpoint and never storing it, so the last stage's rotation of phi is dead
+// code and compiled out. KIND 3: end of the forward sweep on phi (part 1), <C> and
+// lam = rho (C - c0) phi (middle), then the reverse sweep's first block on both (part 2).
+// S1 / S2: register stages of part 1 / part 2.
 template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT>
 __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void k_pass(const PassArgs<R> a) {
   using G = TileCfg<T>;
@@ -649,7 +651,7 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
     }
   }
   if constexpr (NV == 2) {
-    if (KIND == 2) {
+    if (KIND == 2 || KIND == 4) {
       const uint64_t src = (uint64_t)a.lam + vs;
 #pragma unroll
       for (int j = 0; j < RN; j++) lam[j] = ld(src, j);
@@ -678,7 +680,7 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   double acc[NSLOT] = {0.0, 0.0, 0.0};
   double w = sp.w1;
   // ---- part 1: stages H, M, L
-  constexpr bool RL1 = KIND == 2, XT1 = KIND == 2;
+  constexpr bool RL1 = KIND == 2 || KIND == 4, XT1 = RL1;
   const uint32_t m1 = a.mask1;
   if constexpr (S1 & 1) stage<R, T, NV, AH, RL1, XT1>(phi, lam, m1, sp.tau1, w, acc[SL_A]);
   if constexpr (S1 & 2) {
@@ -696,7 +698,7 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
       SHAPE == 0 ? 0u
       : SHAPE == 3 ? (KIND == 1 ? (uint32_t)PF_EXPECT : (uint32_t)PF_GGAMMA)
       : (KIND == 1 ? (uint32_t)PF_PHASE
-                   : (KIND == 2 ? (uint32_t)(PF_GGAMMA | PF_PHASE) : (uint32_t)(PF_EXPECT | PF_LAMBDA)));
+                   : (KIND == 3 ? (uint32_t)(PF_EXPECT | PF_LAMBDA) : (uint32_t)(PF_GGAMMA | PF_PHASE)));
   if constexpr (MID != 0) {
     __syncthreads();
     middle<R, T, NV, TT, CM, MID>(a, sp, phi, lam, ltab, llut, lval, t, w, acc);
@@ -719,7 +721,7 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   }
   constexpr int CE = after_stages<S2, false, CM>();
   // ---- store (assignment H)
-  if constexpr (KIND != 3) {
+  if constexpr (KIND == 1 || KIND == 2) {
     if (f & PF_STORE_PHI) {
       xchg1p<R, T, CE, AH, HALF>(lds, phi, t);
       const uint64_t dst = (uint64_t)a.phi_out + vs;
@@ -1497,6 +1499,7 @@ template <typename R, int T, typename TT>
 static hipError_t launch_kind(const PassArgs<R> &a, int kind, int sx, int shape, hipStream_t s) {
   if (kind == 1) return launch_sx<R, T, 1, TT>(a, sx, shape, s);
   if (kind == 2) return launch_sx<R, T, 2, TT>(a, sx, shape, s);
+  if (kind == 4) return launch_sx<R, T, 4, TT>(a, sx, shape, s);
   return launch_sx<R, T, 3, TT>(a, sx, shape, s);
 }
 
