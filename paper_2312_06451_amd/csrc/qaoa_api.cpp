@@ -670,7 +670,19 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       // the state after forward pass j: its checkpoint, or the vector undone in place
       a.phi = ckpt ? fwd_out(j) : dphi;
       a.phi_out = a.phi;
-      uint32_t f = PF_LOAD_PHI | PF_LOAD_LAM | (ckpt ? (uint32_t)PF_LOAD_SCALE : 0u);
+      // A checkpoint carries the forward sweep's scalar sig_fwd, lam the reverse sweep's sb.
+      // When their ratio kappa is real and positive for every set (always, by the choice of
+      // the reverse phase tables' scalars below), phi is used as stored and kappa goes into
+      // the inner-product weights; otherwise phi is rescaled by kappa on load.
+      bool kappa_real = ckpt;
+      std::vector<double> kap(nsets, 1.0);
+      if (ckpt)
+        for (int s = 0; s < nsets; s++) {
+          const cd kappa = sig_fwd[(size_t)j * nsets + s] / sb[s];
+          kap[s] = kappa.real();
+          if (!(kappa.real() > 0.0) || std::fabs(kappa.imag()) > 1e-12 * kappa.real()) kappa_real = false;
+        }
+      uint32_t f = PF_LOAD_PHI | PF_LOAD_LAM | ((ckpt && !kappa_real) ? (uint32_t)PF_LOAD_SCALE : 0u);
       const bool last = (j == 0);
       // part 1 undoes the forward pass's last rotation block
       int l1 = fp.post >= 0 ? fp.post : fp.pre;
@@ -698,24 +710,32 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         q.lut = -1;
         q.lam_rho = (R)1;
         if (fp.ph >= 0) q.tflip = tflip(s, fp.ph);
-        if (ckpt) {
-          // the checkpoint carries the forward sweep's scalar; rescale it to the reverse
-          // sweep's so that phi and lam share one scalar (real inner-product weights)
+        double wk = 1.0;  // kappa, when it is a weight
+        if (ckpt && !kappa_real) {
+          // rescale the checkpoint to the reverse sweep's scalar (phi and lam share one)
           const cd kappa = sig_fwd[(size_t)j * nsets + s] / sb[s];
           q.out_re = (R)kappa.real();
           q.out_im = (R)kappa.imag();
+        } else if (ckpt) {
+          wk = kap[s];
         }
-        q.w1 = std::norm(sb[s]);
+        q.w1 = std::norm(sb[s]) * wk;
         q.tau1 = -tau[s * p + l1];
         sb[s] *= cpow_int(fi[s * p + l1], rotbits(fp.tile));
         q.w2 = 1.0;
         if (fp.ph >= 0 && !last) {
+          // the table takes sb / t and lam leaves the phase with scalar t; with checkpoints
+          // t is chosen so that lam reaches the next checkpoint with its scalar, which makes
+          // the next pass's kappa exactly 1
+          cd t(1.0, 0.0);
+          if (ckpt && has2) t = sig_fwd[(size_t)(j - 1) * nsets + s] / cpow_int(fi[s * p + fp.pre], rotbits(fp.tile));
+          const cd fold = sb[s] / t;
           q.lut = (int)jobs.size();
-          jobs.push_back(LutJob{gam(s, fp.ph), sb[s].real(), sb[s].imag(), 1.0});
-          sb[s] = cd(1.0, 0.0);
+          jobs.push_back(LutJob{gam(s, fp.ph), fold.real(), fold.imag(), 1.0});
+          sb[s] = t;
         }
         if (has2) {
-          q.w2 = std::norm(sb[s]);
+          q.w2 = std::norm(sb[s]) * wk;
           q.tau2 = -tau[s * p + fp.pre];
           sb[s] *= cpow_int(fi[s * p + fp.pre], rotbits(fp.tile));
         }

@@ -141,7 +141,8 @@ hipError_t launch_table_reverse(const void *src, void *dst, int tbytes, uint64_t
 // dst[x] = vals[table[x]]
 hipError_t launch_table_values(const void *table, int tbytes, const double *vals, double *dst, uint64_t N,
                                hipStream_t s);
-// kind: 1 = forward pass (phi), 2 = reverse-sweep pass (phi, lam), 3 = fused end of the
+// kind: 1 = forward pass (phi), 2 = reverse-sweep pass (phi, lam), 4 = reverse-sweep pass reading
+// phi from a checkpoint (phi never stored), 3 = fused end of the
 // forward sweep and start of the reverse sweep. sx: register stages holding the tile's
 // rotated bits (bit 0: H, bit 1: M, bit 2: L; 7, 5, 3 or 1). shape: 0 = part 1 only,
 // 1 = both parts with the kind's elementwise steps between them, 2 = phase then part 2

@@ -59,6 +59,12 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// A uniform value the compiler must treat as new: values derived from it are recomputed
+// rather than kept live (in scalar registers, or spilled to vector lanes) from an earlier use.
+__device__ __forceinline__ uint32_t fresh_s(uint32_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
 
 // ============================================================== (a) cost table
 
@@ -617,7 +623,17 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   using gV2 = __attribute__((address_space(1))) V2;
   auto at = [&](uint64_t vb, int j) -> gV2 * { return (gV2 *)((gbyte *)uniform64(vb + jbyte(j)) + tbyte); };
   auto ld = [&](uint64_t vb, int j) -> T2 { V2 v = *at(vb, j); return T2{v.x, v.y}; };
-  auto st = [&](uint64_t vb, int j, const T2 &x) { V2 v; v.x = x.x; v.y = x.y; *at(vb, j) = v; };
+  // stores recompute the per-register offsets (from fresh copies of the geometry) instead of
+  // keeping the loads' 32 64-bit offsets live across the whole pass
+  auto st = [&](uint64_t vb, int j, const T2 &x) {
+    const uint32_t cs = fresh_s((uint32_t)a.c), hs = fresh_s((uint32_t)a.h0);
+    const uint64_t e = (uint64_t)j << G::TB;
+    const uint64_t jb = ((e & ((1ull << cs) - 1)) | ((e >> cs) << hs)) * sizeof(T2);
+    V2 v;
+    v.x = x.x;
+    v.y = x.y;
+    *(gV2 *)((gbyte *)uniform64(vb + jb) + tbyte) = v;
+  };
   const uint64_t vs = ((uint64_t)q * a.vstride + base) * sizeof(T2);
 
   T2 phi[RN];
