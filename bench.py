@@ -190,9 +190,11 @@ def traffic_from_profile(workload, cls):
     if not os.path.exists(tpath):
         return None
     txt = open(tpath).read()
-    ksrc = os.path.join(ROOT, "paper_2312_06451_amd", "csrc", "qaoa_kernels.hip")
-    cur = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()
-    if f"kernel_source_sha256 = {cur}" not in txt:
+    csrc = os.path.join(ROOT, "paper_2312_06451_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("qaoa_tile.h", "qaoa_kernels.hip", "qaoa_xpass.hip"):  # the pass kernel and its launchers
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    if f"kernel_source_sha256 = {h.hexdigest()}" not in txt:
         return None
     for line in txt.splitlines():
         if line.startswith("traffic_bytes_per_launch "):
@@ -202,9 +204,10 @@ def traffic_from_profile(workload, cls):
     return None
 
 
-KERNEL_NAMES = {"xmix": "k_xwht / k_xdiag (Walsh-Hadamard passes and diagonals of X-product mixers)",
-                "fwd_pass": "k_pass<float,13,1,uint8> (tile pass, one vector)",
-                "rev_pass": "k_pass<float,13,2|3|4,uint8> (tile pass, state and adjoint vector)",
+KERNEL_NAMES = {"xmix": "k_pass<float,13,1|3|4,uint8,1|2> (tile passes with Y rotations: basis change and "
+                        "diagonals of X-product mixers)",
+                "fwd_pass": "k_pass<float,13,1,uint8,0> (tile pass, one vector)",
+                "rev_pass": "k_pass<float,13,2|3|4,uint8,0> (tile pass, state and adjoint vector)",
                 "small": "k_small<float> (whole state in one workgroup)",
                 "dense": "hipBLASLt GEMM f16 x f16 -> f32 (split eigenbasis product, 2 calls)"}
 

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa.so")
-SOURCES = ["qaoa_kernels.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_xmix.hip", "qaoa_api.cpp",
-           "qaoa_angles.cpp"]
+SOURCES = ["qaoa_kernels.hip", "qaoa_xpass.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_xmix.hip",
+           "qaoa_api.cpp", "qaoa_angles.cpp"]
 HOST_ONLY = {"qaoa_angles.cpp"}  # plain C++ above the C ABI: no device code
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP source of this library.

@@ -148,7 +148,8 @@ struct qaoa_ctx {
   int device = 0;
   int64_t live = 0;          // problems and mixers created on this context and not yet destroyed
   int checkpoint_mode = -1;  // -1: when memory allows, 0: never, 1: always
-  DevBuf phi, lam, ckpt, partials, params, luts, results, cnt, items, gitems, gamps;
+  int xprod_tiles = 1;       // X-product mixers on Hadamard tile passes when they apply
+  DevBuf phi, lam, ckpt, partials, params, luts, luts2, results, cnt, items, gitems, gamps;
   HostBuf hparams, hresults;
   // kernel timing
   bool profiling = false;
@@ -293,9 +294,11 @@ struct qaoa_mixer {
   // kinds 3 and 4: the mixer's diagonal after the Walsh-Hadamard transform
   XDiag xd{};
   double *xvals = nullptr;  // kind 3: diagonal value of each index (xlen entries, device)
+  float *xvals_f = nullptr;  // the same in FP32
   int xlen = 0;
   ~qaoa_mixer() {
     if (xvals) (void)hipFree(xvals);
+    if (xvals_f) (void)hipFree(xvals_f);
   }
 };
 
@@ -406,9 +409,38 @@ struct OutMap {
   int gg(int k) const { return 2 + p + k; }
 };
 
+// Tile-major copy of the cost table for tile geometry (T, c, h0), built once per problem and
+// geometry (the natural table for a contiguous tile).
+const void *tile_table(qaoa_problem *prob, int T, int c, int h0, hipStream_t st) {
+  if (c == T) return prob->table;
+  auto key = std::make_tuple(T, c, h0);
+  auto it = prob->layouts.find(key);
+  if (it != prob->layouts.end()) return it->second;
+  void *d = nullptr;
+  if (hipMalloc(&d, prob->N * prob->tbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw fail(QAOA_ERR_OUT_OF_MEMORY, "table layout allocation failed");
+  }
+  hipError_t e = launch_table_relayout(prob->table, d, prob->tbytes, prob->n, T, c, h0, st);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    throw fail(QAOA_ERR_HIP, std::string("table relayout: ") + hipGetErrorString(e));
+  }
+  prob->layouts[key] = d;
+  return d;
+}
+
+// The tile-pass path. xm == nullptr: transverse-field mixer, layer k = phase, then a rotation
+// e^{-i beta_k X} of every qubit. xm = an X-product mixer with a diagonal by Hamming weight:
+// 2p half-layers, each a diagonal (even: the cost phase of layer h / 2, odd: the mixer diagonal
+// of layer (h - 1) / 2) followed by the basis change V^dag (even) or V (odd), V = R_y(pi/2) on
+// every qubit, applied as Y rotations with tau = -1 or +1 (scalar cos(pi/4) per qubit); no
+// X-pair terms, the beta gradient is taken at the mixer diagonal like the gamma gradient at
+// the phase.
 template <typename R>
 void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
-                int grad, double *out_expect, double *out_grad, void *d_state_out, hipStream_t st) {
+                int grad, double *out_expect, double *out_grad, void *d_state_out, hipStream_t st,
+                const qaoa_mixer *xm = nullptr) {
   qaoa_ctx *ctx = prob->ctx;
   const int prec = sizeof(R) == 4 ? QAOA_FP32 : QAOA_FP64;
   const int T = prec == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
@@ -416,33 +448,18 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const int n = prob->n;
   const std::vector<TileGeo> tiles = make_tiles(n, T, cmin);
   const int K = (int)tiles.size();
-  const std::vector<FwdPass> fwd = make_forward(K, p);
+  const int L = xm ? 2 * p : p;  // layers of the pass plan
+  const std::vector<FwdPass> fwd = make_forward(K, L);
   const uint32_t nwg = 1u << (n - T);
   const uint64_t N = 1ull << n;
   const size_t esz = 2 * sizeof(R);
   const int lut_len = (int)prob->max_value + 1;
   if (lut_len > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+  const int lut_mix = xm ? xm->xlen : 0;
+  if (lut_mix > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "mixer diagonal exceeds the LUT limit");
 
   // tile-major table copies for every geometry that reads the table
-  auto table_for = [&](int tile) -> const void * {
-    const TileGeo &g = tiles[tile];
-    if (g.c == T) return prob->table;  // contiguous tile: natural layout
-    auto key = std::make_tuple(T, g.c, g.h0);
-    auto it = prob->layouts.find(key);
-    if (it != prob->layouts.end()) return it->second;
-    void *d = nullptr;
-    if (hipMalloc(&d, N * prob->tbytes) != hipSuccess) {
-      (void)hipGetLastError();
-      throw fail(QAOA_ERR_OUT_OF_MEMORY, "table layout allocation failed");
-    }
-    hipError_t e = launch_table_relayout(prob->table, d, prob->tbytes, n, T, g.c, g.h0, st);
-    if (e != hipSuccess) {
-      (void)hipFree(d);
-      throw fail(QAOA_ERR_HIP, std::string("table relayout: ") + hipGetErrorString(e));
-    }
-    prob->layouts[key] = d;
-    return d;
-  };
+  auto table_for = [&](int tile) -> const void * { return tile_table(prob, T, tiles[tile].c, tiles[tile].h0, st); };
   // the same layouts for C(~x): the whole array reversed (complementing x complements the
   // tile index and the element index); the table itself when C(~x) = C(x)
   auto table_rev_for = [&](int tile) -> const void * {
@@ -471,7 +488,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   // (checkpoints) and the reverse sweep reads the state from them instead of undoing and
   // rewriting it: 24 instead of 32 bytes per amplitude in each reverse pass.
   const size_t vbytes = (size_t)nsets * N * esz;
-  const int npf_est = 1 + p * ((int)tiles.size() - 1);
+  const int npf_est = 1 + L * ((int)tiles.size() - 1);
   bool ckpt = false;
   if (grad && ctx->checkpoint_mode != 0) {
     size_t fr = 0, tot = 0;
@@ -482,6 +499,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       if (need > have) ckpt = false;
     }
   }
+  if (xm && grad && !ckpt) throw fail(QAOA_ERR_HIP, "internal: X-product tile passes need checkpoints");
   void *dphi = ckpt ? nullptr : ctx->phi.get(vbytes);
   unsigned char *dck = ckpt ? (unsigned char *)ctx->ckpt.get((size_t)npf_est * vbytes) : nullptr;
   // forward pass j writes checkpoint j (or the single in-place buffer)
@@ -495,30 +513,56 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   double *dpart = (double *)ctx->partials.get(part_elems * sizeof(double));
 
   // angle-derived parameters per set and layer
-  std::vector<R> tau((size_t)nsets * p);
-  std::vector<int> swp((size_t)nsets * p);
-  std::vector<cd> ff((size_t)nsets * p), fi((size_t)nsets * p);
+  std::vector<R> tau((size_t)nsets * L);
+  std::vector<int> swp((size_t)nsets * L);
+  std::vector<cd> ff((size_t)nsets * L), fi((size_t)nsets * L);
   for (int s = 0; s < nsets; s++)
-    for (int k = 0; k < p; k++) {
+    for (int k = 0; k < L; k++) {
+      if (xm) {  // V^dag after an even half-layer's diagonal, V after an odd one's
+        tau[s * L + k] = (R)((k % 2 == 0) ? -1.0 : 1.0);
+        swp[s * L + k] = 0;
+        ff[s * L + k] = fi[s * L + k] = cd(std::sqrt(0.5), 0.0);
+        continue;
+      }
       double beta = angles[(size_t)s * 2 * p + k];
-      rot_params<R>(beta, tau[s * p + k], swp[s * p + k], ff[s * p + k], fi[s * p + k]);
+      rot_params<R>(beta, tau[s * L + k], swp[s * L + k], ff[s * L + k], fi[s * L + k]);
     }
   // flip state of set s's stored vector after `layers` complete rounds (all bits or none):
   // 1 when an odd number of them used the tau = -cot form; only an asymmetric table cares
   auto tflip = [&](int s, int layers) {
     if (prob->sym) return 0;
     int f = 0;
-    for (int k = 0; k < layers; k++) f ^= swp[s * p + k];
+    for (int k = 0; k < layers; k++) f ^= swp[s * L + k];
     return f;
   };
-  auto gam = [&](int s, int k) { return angles[(size_t)s * 2 * p + p + k]; };
+  // angle of the diagonal of layer k: gamma_k; with X products gamma_{k/2} (even k) or
+  // beta_{(k-1)/2} (odd k, the mixer diagonal)
+  auto gam = [&](int s, int k) {
+    if (!xm) return angles[(size_t)s * 2 * p + p + k];
+    return (k % 2 == 0) ? angles[(size_t)s * 2 * p + p + k / 2] : angles[(size_t)s * 2 * p + (k - 1) / 2];
+  };
+  auto is_mix = [&](int k) { return xm != nullptr && k % 2 == 1; };
+  // output slot of the derivative taken at the diagonal of layer k
+  auto diag_out = [&](int k) { return !xm ? om.gg(k) : (k % 2 == 0 ? om.gg(k / 2) : om.gb((k - 1) / 2)); };
 
   std::vector<PassArgs<R>> passes;
   std::vector<int> nvs;     // kernel kind: 1 forward, 2 reverse, 3 fused
   std::vector<int> shapes;  // 0: part 1 only, 1: both parts, 2: part 2 only
   std::vector<int> sxs;     // register stages holding the tile's rotated bits
+  std::vector<int> mixlut;  // 1: the pass's diagonal is the mixer's (LUTs in jobs_m)
   std::vector<SetParams<R>> sps;
-  std::vector<LutJob> jobs;
+  std::vector<LutJob> jobs, jobs_m;
+  auto push_job = [&](int k, const LutJob &jb) -> int {
+    std::vector<LutJob> &J = is_mix(k) ? jobs_m : jobs;
+    J.push_back(jb);
+    return (int)J.size() - 1;
+  };
+  // a pass whose diagonal is the mixer's: value index = Hamming weight, the mixer's values
+  auto mix_diag = [&](PassArgs<R> &a) {
+    a.vals = sizeof(R) == 4 ? (const void *)xm->xvals_f : (const void *)xm->xvals;
+    a.lut_len = lut_mix;
+    a.lam_c0 = (R)0;
+  };
   std::vector<int> cnt(nout, 0);
   auto slot_for = [&](int o) -> int64_t {
     int c = cnt[o]++;
@@ -563,11 +607,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (sx != 7 && sx != 5 && sx != 3 && sx != 1) throw fail(QAOA_ERR_HIP, "internal: unsupported tile stage set");
     return sx;
   };
-  auto add_pass = [&](const PassArgs<R> &a, int kind, int shape, int tile) {
+  auto add_pass = [&](const PassArgs<R> &a, int kind, int shape, int tile, int mixd = 0) {
     passes.push_back(a);
     nvs.push_back(kind);
     shapes.push_back(shape);
     sxs.push_back(stage_set(tile));
+    mixlut.push_back(mixd);
   };
   const int npf = (int)fwd.size();
 
@@ -585,8 +630,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (fp.pre >= 0) a.mask1 = tiles[fp.tile].rot;
     if (fp.ph >= 0) {
       f |= PF_PHASE;
-      a.table = table_for(fp.tile);
-      a.table_rev = table_rev_for(fp.tile);
+      if (is_mix(fp.ph)) {
+        mix_diag(a);
+      } else {
+        a.table = table_for(fp.tile);
+        a.table_rev = xm ? a.table : table_rev_for(fp.tile);
+      }
     }
     if (fp.post >= 0) a.mask2 = tiles[fp.tile].rot;
     a.flags = f;
@@ -597,22 +646,21 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       q.w1 = q.w2 = 1.0;
       q.lam_rho = (R)1;
       if (fp.pre >= 0) {
-        q.tau1 = tau[s * p + fp.pre];
-        sig[s] *= cpow_int(ff[s * p + fp.pre], rotbits(fp.tile));
+        q.tau1 = tau[s * L + fp.pre];
+        sig[s] *= cpow_int(ff[s * L + fp.pre], rotbits(fp.tile));
       }
       if (fp.ph >= 0) {
-        q.lut = (int)jobs.size();
         q.tflip = tflip(s, fp.ph);
-        jobs.push_back(LutJob{gam(s, fp.ph), sig[s].real(), sig[s].imag(), -1.0});
+        q.lut = push_job(fp.ph, LutJob{gam(s, fp.ph), sig[s].real(), sig[s].imag(), -1.0});
         sig[s] = cd(1.0, 0.0);
       }
       if (fp.post >= 0) {
-        q.tau2 = tau[s * p + fp.post];
-        sig[s] *= cpow_int(ff[s * p + fp.post], rotbits(fp.tile));
+        q.tau2 = tau[s * L + fp.post];
+        sig[s] *= cpow_int(ff[s * L + fp.post], rotbits(fp.tile));
       }
       sps.push_back(q);
     }
-    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile);
+    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph));
     sig_fwd.insert(sig_fwd.end(), sig.begin(), sig.end());
   }
 
@@ -629,7 +677,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     // a single-pass plan would need the phase too; K >= 2 always gives >= 2 passes
     a.mask1 = tiles[lp.tile].rot;
     a.table = table_for(lp.tile);
-    a.table_rev = table_rev_for(lp.tile);
+    a.table_rev = xm ? a.table : table_rev_for(lp.tile);
     f |= PF_EXPECT;
     a.slot_off[SL_A] = slot_for(om.E());
     a.slot_off[SL_B] = slot_for(om.Nr());
@@ -637,16 +685,16 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (grad) {
       f |= PF_LAMBDA | PF_XT2 | PF_ROT2_BOTH | PF_STORE_LAM;
       a.mask2 = tiles[lp.tile].rot;
-      a.slot_off[SL_C] = slot_for(om.gb(lp.pre));
+      if (!xm) a.slot_off[SL_C] = slot_for(om.gb(lp.pre));
     }
     a.flags = f;
     for (int s = 0; s < nsets; s++) {
       SetParams<R> q;
       std::memset(&q, 0, sizeof(q));
       q.lut = -1;
-      q.tflip = tflip(s, p);
-      q.tau1 = tau[s * p + lp.pre];
-      sig[s] *= cpow_int(ff[s * p + lp.pre], rotbits(lp.tile));
+      q.tflip = tflip(s, L);
+      q.tau1 = tau[s * L + lp.pre];
+      sig[s] *= cpow_int(ff[s * L + lp.pre], rotbits(lp.tile));
       sig_p[s] = sig[s];
       double t = (double)q.tau1;
       rho[s] = std::pow(1.0 / (1.0 + t * t), rotbits(lp.tile));
@@ -688,19 +736,23 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       int l1 = fp.post >= 0 ? fp.post : fp.pre;
       a.mask1 = tiles[fp.tile].rot;
       f |= PF_XT1 | PF_ROT1_BOTH;
-      a.slot_off[SL_A] = slot_for(om.gb(l1));
+      if (!xm) a.slot_off[SL_A] = slot_for(om.gb(l1));
       if (fp.ph >= 0) {
         f |= PF_GGAMMA;
-        a.table = table_for(fp.tile);
-        a.table_rev = table_rev_for(fp.tile);
-        a.slot_off[SL_B] = slot_for(om.gg(fp.ph));
+        if (is_mix(fp.ph)) {
+          mix_diag(a);
+        } else {
+          a.table = table_for(fp.tile);
+          a.table_rev = xm ? a.table : table_rev_for(fp.tile);
+        }
+        a.slot_off[SL_B] = slot_for(diag_out(fp.ph));
         if (!last) f |= PF_PHASE | PF_PHASE_BOTH;
       }
       const bool has2 = (fp.post >= 0 && fp.pre >= 0);
       if (has2) {
         a.mask2 = tiles[fp.tile].rot;
         f |= PF_XT2 | PF_ROT2_BOTH;
-        a.slot_off[SL_C] = slot_for(om.gb(fp.pre));
+        if (!xm) a.slot_off[SL_C] = slot_for(om.gb(fp.pre));
       }
       if (!last) f |= (ckpt ? 0u : (uint32_t)PF_STORE_PHI) | PF_STORE_LAM;
       a.flags = f;
@@ -720,44 +772,45 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
           wk = kap[s];
         }
         q.w1 = std::norm(sb[s]) * wk;
-        q.tau1 = -tau[s * p + l1];
-        sb[s] *= cpow_int(fi[s * p + l1], rotbits(fp.tile));
+        q.tau1 = -tau[s * L + l1];
+        sb[s] *= cpow_int(fi[s * L + l1], rotbits(fp.tile));
         q.w2 = 1.0;
         if (fp.ph >= 0 && !last) {
           // the table takes sb / t and lam leaves the phase with scalar t; with checkpoints
           // t is chosen so that lam reaches the next checkpoint with its scalar, which makes
           // the next pass's kappa exactly 1
           cd t(1.0, 0.0);
-          if (ckpt && has2) t = sig_fwd[(size_t)(j - 1) * nsets + s] / cpow_int(fi[s * p + fp.pre], rotbits(fp.tile));
+          if (ckpt && has2) t = sig_fwd[(size_t)(j - 1) * nsets + s] / cpow_int(fi[s * L + fp.pre], rotbits(fp.tile));
           const cd fold = sb[s] / t;
-          q.lut = (int)jobs.size();
-          jobs.push_back(LutJob{gam(s, fp.ph), fold.real(), fold.imag(), 1.0});
+          q.lut = push_job(fp.ph, LutJob{gam(s, fp.ph), fold.real(), fold.imag(), 1.0});
           sb[s] = t;
         }
         if (has2) {
           q.w2 = std::norm(sb[s]) * wk;
-          q.tau2 = -tau[s * p + fp.pre];
-          sb[s] *= cpow_int(fi[s * p + fp.pre], rotbits(fp.tile));
+          q.tau2 = -tau[s * L + fp.pre];
+          sb[s] *= cpow_int(fi[s * L + fp.pre], rotbits(fp.tile));
         }
         sps.push_back(q);
       }
       // with checkpoints phi is read and never stored: the kind that compiles its store out
-      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile);
+      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph));
     }
   }
 
   // ---------------- upload parameters (one copy), LUTs on the device
   const size_t sp_bytes = sps.size() * sizeof(SetParams<R>);
-  const size_t job_bytes = jobs.size() * sizeof(LutJob);
+  const size_t job_bytes = jobs.size() * sizeof(LutJob), jobm_bytes = jobs_m.size() * sizeof(LutJob);
   const size_t cnt_bytes = nout * sizeof(int);
   const size_t off_jobs = (sp_bytes + 255) & ~size_t(255);
-  const size_t off_cnt = (off_jobs + job_bytes + 255) & ~size_t(255);
+  const size_t off_jobm = (off_jobs + job_bytes + 255) & ~size_t(255);
+  const size_t off_cnt = (off_jobm + jobm_bytes + 255) & ~size_t(255);
   const size_t total = off_cnt + cnt_bytes;
   unsigned char *h = (unsigned char *)ctx->hparams.get(total);
   // the previous call may still read the pinned staging buffer through its async copy
   HIPCHK(hipStreamSynchronize(st));
   std::memcpy(h, sps.data(), sp_bytes);
   if (job_bytes) std::memcpy(h + off_jobs, jobs.data(), job_bytes);
+  if (jobm_bytes) std::memcpy(h + off_jobm, jobs_m.data(), jobm_bytes);
   std::memcpy(h + off_cnt, cnt.data(), cnt_bytes);
   unsigned char *d = (unsigned char *)ctx->params.get(total);
   HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
@@ -766,23 +819,33 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     dluts = ctx->luts.get(jobs.size() * (size_t)lut_len * esz);
     HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobs), (int)jobs.size(), lut_len, prob->dvals, dluts, st));
   }
+  void *dluts_m = nullptr;
+  if (!jobs_m.empty()) {
+    dluts_m = ctx->luts2.get(jobs_m.size() * (size_t)lut_mix * esz);
+    HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobm), (int)jobs_m.size(), lut_mix, xm->xvals, dluts_m, st));
+  }
   // ---------------- passes
   for (size_t i = 0; i < passes.size(); i++) {
     PassArgs<R> &a = passes[i];
     a.sp = (const SetParams<R> *)(d + i * nsets * sizeof(SetParams<R>));
-    a.luts = dluts;
+    a.luts = mixlut[i] ? dluts_m : dluts;
     const uint32_t fl = a.flags;
     double by = 0;
     if (fl & (PF_LOAD_PHI | PF_LOAD_PSI0)) by += (double)N * esz;
     if (fl & PF_LOAD_LAM) by += (double)N * esz;
     if (fl & PF_STORE_PHI) by += (double)N * esz;
     if (fl & PF_STORE_LAM) by += (double)N * esz;
-    if (fl & (PF_EXPECT | PF_LAMBDA | PF_GGAMMA | PF_PHASE)) by += (double)N * prob->tbytes;
+    if ((fl & (PF_EXPECT | PF_LAMBDA | PF_GGAMMA | PF_PHASE)) && !mixlut[i]) by += (double)N * prob->tbytes;
     by *= nsets;
-    KTimer kt(ctx, st, nvs[i] >= 2 ? QAOA_KC_REV_PASS : QAOA_KC_FWD_PASS, by, 0.0);
+    KTimer kt(ctx, st, xm ? QAOA_KC_XMIX : (nvs[i] >= 2 ? QAOA_KC_REV_PASS : QAOA_KC_FWD_PASS), by, 0.0);
     hipError_t e;
-    if constexpr (sizeof(R) == 4) e = launch_pass_f32(a, nvs[i], sxs[i], shapes[i], prob->tbytes, st);
-    else e = launch_pass_f64(a, nvs[i], sxs[i], shapes[i], prob->tbytes, st);
+    if (xm) {
+      if constexpr (sizeof(R) == 4) e = launch_hpass_f32(a, nvs[i], sxs[i], shapes[i], prob->tbytes, mixlut[i], st);
+      else e = launch_hpass_f64(a, nvs[i], sxs[i], shapes[i], prob->tbytes, mixlut[i], st);
+    } else {
+      if constexpr (sizeof(R) == 4) e = launch_pass_f32(a, nvs[i], sxs[i], shapes[i], prob->tbytes, st);
+      else e = launch_pass_f64(a, nvs[i], sxs[i], shapes[i], prob->tbytes, st);
+    }
     if (e != hipSuccess) throw fail(QAOA_ERR_HIP, std::string("pass launch: ") + hipGetErrorString(e));
     kt.done();
   }
@@ -1078,6 +1141,7 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
     // QAOA_GRAD_CHECKPOINT: "0" never keep forward checkpoints, "1" always, unset: when the
     // free device memory allows
     if (const char *e = std::getenv("QAOA_GRAD_CHECKPOINT")) c->checkpoint_mode = std::atoi(e) ? 1 : 0;
+    if (const char *e = std::getenv("QAOA_XPROD_TILES")) c->xprod_tiles = std::atoi(e) ? 1 : 0;
     *out = c.release();
   });
 }
@@ -1597,6 +1661,13 @@ static void xprod_mixer(qaoa_ctx *ctx, int n, int kind, const XDiag &xd, const s
       throw fail(QAOA_ERR_OUT_OF_MEMORY, "mixer value allocation failed");
     }
     HIPCHK(hipMemcpy(m->xvals, vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<float> vf(vals.begin(), vals.end());
+    if (hipMalloc(&m->xvals_f, vf.size() * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      m->xvals_f = nullptr;
+      throw fail(QAOA_ERR_OUT_OF_MEMORY, "mixer value allocation failed");
+    }
+    HIPCHK(hipMemcpy(m->xvals_f, vf.data(), vf.size() * sizeof(float), hipMemcpyHostToDevice));
   }
   ctx->live++;
   *out = m.release();
@@ -1736,6 +1807,28 @@ static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, con
   const int m = qb ? n : 1, slen = p * (m + 1);
   const int lut_cost = (int)prob->max_value + 1;
   if (lut_cost > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+  // Tile passes (Y-rotation basis change): mixers with a diagonal by Hamming weight (sums of
+  // k-body X products), states larger than one tile, the gradient's checkpoints within half
+  // the free memory (the rule of the transverse-field path)
+  if (ctx->xprod_tiles && !qb && !d_state && mix->xd.mode == XD_POPCOUNT &&
+      n > (precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64) && lut_cost <= MAX_LUT && mix->xlen <= MAX_LUT) {
+    bool fits = true;
+    if (grad) {
+      const int T = precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
+      const int K = (int)make_tiles(n, T, precision == QAOA_FP32 ? MIN_CONTIG_F32 : MIN_CONTIG_F64).size();
+      const size_t vbytes = (size_t)nsets * N * esz, need = (size_t)(1 + 2 * p * (K - 1)) * vbytes;
+      size_t fr = 0, tot = 0;
+      fits = ctx->checkpoint_mode != 0 && hipMemGetInfo(&fr, &tot) == hipSuccess &&
+             (ctx->checkpoint_mode == 1 || need + vbytes <= (fr + ctx->ckpt.cap) / 2) && need <= fr + ctx->ckpt.cap;
+    }
+    if (fits) {
+      if (precision == QAOA_FP32)
+        run_x_path<float>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, nullptr, st, mix);
+      else
+        run_x_path<double>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, nullptr, st, mix);
+      return;
+    }
+  }
   const int bsums = qb ? 33 : 1;  // sums per beta layer: total and per-bit (per-qubit angles) or one
   const int nout = 2 + p * bsums + p;
   const unsigned nblk = xdiag_blocks(N);

@@ -46,6 +46,18 @@ enum : uint32_t {
   PF_LOAD_SCALE = 1u << 16,  // phi *= (out_re + i out_im) right after loading
 };
 
+// Diagonal of a step of the X-product / multi-angle path: where the value index of basis
+// state y comes from.
+enum { XD_TABLE = 0, XD_POPCOUNT = 1, XD_TERMS = 2, XD_QUBIT = 3 };
+constexpr int XD_MAX_TERMS = 10;
+struct XDiag {
+  int mode;             // XD_*
+  int tbytes;           // XD_TABLE: 1 or 2
+  const void *table;    // XD_TABLE: index table (2^n entries)
+  int nterms;           // XD_TERMS: index bit t = parity of (y & masks[t])
+  uint64_t masks[XD_MAX_TERMS];
+};
+
 // Partial-sum slots of one pass.
 enum { SL_A = 0, SL_B = 1, SL_C = 2, NSLOT = 3 };
 
@@ -151,22 +163,18 @@ hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape
                            hipStream_t s);
 hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
                            hipStream_t s);
+// The same passes with Y rotations and no X-pair terms (X-product mixers, qaoa_xpass.hip):
+// kinds 1 (shapes 0, 1, 2, 3), 3 (shape 1) and 4 (shapes 0, 1, 3); mixd: the diagonal of a kind 1
+// or 4 pass of shape 1 is the mixer's, indexed by the Hamming weight of the state index.
+hipError_t launch_hpass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes, bool mixd,
+                           hipStream_t s);
+hipError_t launch_hpass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes, bool mixd,
+                           hipStream_t s);
 hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
                            int64_t nwg, int nout, double *out, hipStream_t s);
 hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
                         int max_tbytes, int max_lut, const double *angles, int p, int grad,
                         double *out, hipStream_t s);
-// Diagonal of a step of the X-product / multi-angle path: where the value index of basis
-// state y comes from.
-enum { XD_TABLE = 0, XD_POPCOUNT = 1, XD_TERMS = 2, XD_QUBIT = 3 };
-constexpr int XD_MAX_TERMS = 10;
-struct XDiag {
-  int mode;             // XD_*
-  int tbytes;           // XD_TABLE: 1 or 2
-  const void *table;    // XD_TABLE: index table (2^n entries)
-  int nterms;           // XD_TERMS: index bit t = parity of (y & masks[t])
-  uint64_t masks[XD_MAX_TERMS];
-};
 // Index of the diagonal value of basis state y (XD_TABLE, XD_POPCOUNT, XD_TERMS).
 __device__ __forceinline__ uint32_t xdiag_index(const XDiag &d, uint64_t y) {
   if (d.mode == XD_TABLE)

@@ -166,3 +166,55 @@ def test_full_size_against_stored_oracle_values(q, ctx):
         assert abs(e[0, 0] - rec["expect"]) <= TOL[prec] * G["table_max"]
         g0 = np.array(rec["grad"])
         assert np.max(np.abs(gr[0, 0] - g0)) <= TOL[prec] * np.max(np.abs(g0))
+
+
+@pytest.mark.parametrize("n,orders,p", [(13, [2], 2), (16, [1, 2], 3), (23, [1, 2], 2)])
+def test_tile_passes_match_transform_passes(q, monkeypatch, n, orders, p):
+    """Mixers diagonal by Hamming weight run on the tile passes (basis change by Y rotations,
+    the transform's boundary passes shared with the diagonals) for n above the tile bits (13
+    complex64, 12 complex128); with QAOA_XPROD_TILES=0 the same calls take the separate
+    Walsh-Hadamard and diagonal kernels. Both against each other for several angle sets and an
+    initial state, and the first set against the FP64 oracle where it finishes quickly."""
+    g = workloads.erdos_renyi(n, 2870 + n, 0.3, (1, 2))
+    t = oracle.graph_table(g)
+    A = workloads.random_angles(p, 3, 2871 + n)
+    rng = np.random.default_rng(2872 + n)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    res = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("QAOA_XPROD_TILES", mode)
+        c = q.Context(0)
+        try:
+            P, M = q.Problem.from_graph(c, g), q.Mixer.x_orders(c, n, orders)
+            out = []
+            for prec in (0, 1):
+                e, gr = q.expect_grad_batched([P], [M], A, precision=prec)
+                import torch
+                dt = torch.complex64 if prec == 0 else torch.complex128
+                s0 = torch.tensor(psi0, dtype=dt, device="cuda")
+                e0, g0 = q.expect_grad(P, M, A[0], psi0=s0, precision=prec)
+                out.append((e[0], gr[0], e0, g0))
+            res[mode] = out
+        finally:
+            c.close()
+    scale = float(np.max(np.abs(t)))
+    for prec in (0, 1):
+        e1, g1, e1s, g1s = res["1"][prec]
+        e0, g0, e0s, g0s = res["0"][prec]
+        assert np.max(np.abs(e1 - e0)) <= TOL[prec] * scale
+        assert np.max(np.abs(g1 - g0)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3)
+        assert abs(e1s - e0s) <= TOL[prec] * scale
+    # From a random initial state the gradient is far below the cost scale (cancellation over
+    # the whole state), while the rounding of each term scales with the costs: each path's
+    # FP32 gradient against its own FP64 one, with the error floor at 1e-3 of the cost scale.
+    for mode in ("1", "0"):
+        g32, g64 = res[mode][0][3], res[mode][1][3]
+        assert np.max(np.abs(g32 - g64)) <= TOL[0] * max(np.max(np.abs(g64)), 1e-3 * scale), mode
+    assert np.max(np.abs(res["1"][1][3] - res["0"][1][3])) <= TOL[1] * max(np.max(np.abs(res["0"][1][3])), 1e-3)
+    if n <= 16:
+        E, Nr, gref = X.grad(n, t, A[0], d=X.diag_orders(n, orders))
+        for prec in (0, 1):
+            e1, g1 = res["1"][prec][0], res["1"][prec][1]
+            assert abs(e1[0] - E / Nr) <= TOL[prec] * scale
+            assert np.max(np.abs(g1[0] - gref / Nr)) <= TOL[prec] * max(np.max(np.abs(gref)), 1e-3)
