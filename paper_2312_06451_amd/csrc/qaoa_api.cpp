@@ -431,7 +431,7 @@ const void *tile_table(qaoa_problem *prob, int T, int c, int h0, hipStream_t st)
 }
 
 // The tile-pass path. xm == nullptr: transverse-field mixer, layer k = phase, then a rotation
-// e^{-i beta_k X} of every qubit. xm = an X-product mixer with a diagonal by Hamming weight:
+// e^{-i beta_k X} of every qubit. xm = a single-angle X-product mixer:
 // 2p half-layers, each a diagonal (even: the cost phase of layer h / 2, odd: the mixer diagonal
 // of layer (h - 1) / 2) followed by the basis change V^dag (even) or V (odd), V = R_y(pi/2) on
 // every qubit, applied as Y rotations with tau = -1 or +1 (scalar cos(pi/4) per qubit); no
@@ -549,7 +549,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   std::vector<int> nvs;     // kernel kind: 1 forward, 2 reverse, 3 fused
   std::vector<int> shapes;  // 0: part 1 only, 1: both parts, 2: part 2 only
   std::vector<int> sxs;     // register stages holding the tile's rotated bits
-  std::vector<int> mixlut;  // 1: the pass's diagonal is the mixer's (LUTs in jobs_m)
+  std::vector<int> mixlut;  // XD_POPCOUNT / XD_TERMS: the pass's diagonal is the mixer's (LUTs in jobs_m)
   std::vector<SetParams<R>> sps;
   std::vector<LutJob> jobs, jobs_m;
   auto push_job = [&](int k, const LutJob &jb) -> int {
@@ -557,11 +557,31 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     J.push_back(jb);
     return (int)J.size() - 1;
   };
-  // a pass whose diagonal is the mixer's: value index = Hamming weight, the mixer's values
-  auto mix_diag = [&](PassArgs<R> &a) {
+  // a pass whose diagonal is the mixer's: the mixer's values, indexed by the Hamming weight of
+  // y, or by its parities against the term masks (then the register parts' indices in the
+  // middle's register assignment go with the pass: register j holds tile element j << sh)
+  auto mix_diag = [&](PassArgs<R> &a, int tile) {
     a.vals = sizeof(R) == 4 ? (const void *)xm->xvals_f : (const void *)xm->xvals;
     a.lut_len = lut_mix;
     a.lam_c0 = (R)0;
+    if (xm->xd.mode != XD_TERMS) return;
+    a.xnterms = xm->xd.nterms;
+    for (int k = 0; k < XD_MAX_TERMS; k++) a.xmasks[k] = k < xm->xd.nterms ? xm->xd.masks[k] : 0;
+    const uint32_t rot = tiles[tile].rot;
+    const int RB = T - 8, MLO = T - 2 * RB;
+    const bool Lg = rot & ((1u << RB) - 1), Mg = rot & (((1u << 8) - 1) & ~((1u << RB) - 1));
+    const int sh = Lg ? 0 : (Mg ? MLO : 8);  // assignment after part 1 (stages H, M, L in order)
+    const uint64_t cmask = (1ull << a.c) - 1;
+    for (int j = 0; j < 32; j++) {
+      if (j >= (1 << RB)) {
+        a.xreg[j] = 0;
+        continue;
+      }
+      const uint64_t e = (uint64_t)j << sh, y = (e & cmask) | ((e >> a.c) << a.h0);
+      uint32_t idx = 0;
+      for (int k = 0; k < xm->xd.nterms; k++) idx |= (uint32_t)(__builtin_popcountll(y & xm->xd.masks[k]) & 1) << k;
+      a.xreg[j] = (uint16_t)idx;
+    }
   };
   std::vector<int> cnt(nout, 0);
   auto slot_for = [&](int o) -> int64_t {
@@ -631,7 +651,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (fp.ph >= 0) {
       f |= PF_PHASE;
       if (is_mix(fp.ph)) {
-        mix_diag(a);
+        mix_diag(a, fp.tile);
       } else {
         a.table = table_for(fp.tile);
         a.table_rev = xm ? a.table : table_rev_for(fp.tile);
@@ -660,7 +680,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       }
       sps.push_back(q);
     }
-    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph));
+    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph) ? xm->xd.mode : 0);
     sig_fwd.insert(sig_fwd.end(), sig.begin(), sig.end());
   }
 
@@ -740,7 +760,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       if (fp.ph >= 0) {
         f |= PF_GGAMMA;
         if (is_mix(fp.ph)) {
-          mix_diag(a);
+          mix_diag(a, fp.tile);
         } else {
           a.table = table_for(fp.tile);
           a.table_rev = xm ? a.table : table_rev_for(fp.tile);
@@ -793,7 +813,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         sps.push_back(q);
       }
       // with checkpoints phi is read and never stored: the kind that compiles its store out
-      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph));
+      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph) ? xm->xd.mode : 0);
     }
   }
 
@@ -1807,10 +1827,10 @@ static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, con
   const int m = qb ? n : 1, slen = p * (m + 1);
   const int lut_cost = (int)prob->max_value + 1;
   if (lut_cost > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
-  // Tile passes (Y-rotation basis change): mixers with a diagonal by Hamming weight (sums of
-  // k-body X products), states larger than one tile, the gradient's checkpoints within half
-  // the free memory (the rule of the transverse-field path)
-  if (ctx->xprod_tiles && !qb && !d_state && mix->xd.mode == XD_POPCOUNT &&
+  // Tile passes (Y-rotation basis change): single-angle mixers (diagonal by Hamming weight or
+  // by parities against term masks), states larger than one tile, the gradient's checkpoints
+  // within half the free memory (the rule of the transverse-field path)
+  if (ctx->xprod_tiles && !qb && !d_state && (mix->xd.mode == XD_POPCOUNT || mix->xd.mode == XD_TERMS) &&
       n > (precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64) && lut_cost <= MAX_LUT && mix->xlen <= MAX_LUT) {
     bool fits = true;
     if (grad) {

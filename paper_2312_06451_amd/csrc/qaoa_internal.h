@@ -98,6 +98,11 @@ struct PassArgs {
   const SetParams<R> *sp;  // [nsets]
   double *partials;        // slot s of set q, tile b: partials[slot_off[s] + q * nwg + b]
   int64_t slot_off[NSLOT]; // -1: slot unused
+  // X-product passes whose middle is a parity-mask diagonal: index bit k = parity(y & xmasks[k]);
+  // xreg[j] = the index of register j's part of y in the middle's register assignment
+  uint64_t xmasks[XD_MAX_TERMS];
+  int xnterms;
+  uint16_t xreg[32];
 };
 
 // LUT construction job: luts[i][c] = scale_i * exp(sign_i * i * gamma_i * vals[c]),
@@ -164,11 +169,12 @@ hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape
 hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
                            hipStream_t s);
 // The same passes with Y rotations and no X-pair terms (X-product mixers, qaoa_xpass.hip):
-// kinds 1 (shapes 0, 1, 2, 3), 3 (shape 1) and 4 (shapes 0, 1, 3); mixd: the diagonal of a kind 1
-// or 4 pass of shape 1 is the mixer's, indexed by the Hamming weight of the state index.
-hipError_t launch_hpass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes, bool mixd,
+// kinds 1 (shapes 0, 1, 2, 3), 3 (shape 1) and 4 (shapes 0, 1, 3); mixd (kind 1 or 4, shape 1):
+// 0 = the middle's diagonal is the cost's, XD_POPCOUNT / XD_TERMS = the mixer's, indexed by the
+// Hamming weight of the state index / by its parities against PassArgs::xmasks.
+hipError_t launch_hpass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes, int mixd,
                            hipStream_t s);
-hipError_t launch_hpass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes, bool mixd,
+hipError_t launch_hpass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes, int mixd,
                            hipStream_t s);
 hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
                            int64_t nwg, int nout, double *out, hipStream_t s);

@@ -349,6 +349,14 @@ struct PopIdx {
   }
 };
 
+// Parity-mask index: the thread part's index XOR register j's (a per-pass constant table).
+template <typename P>
+struct TermsIdx {
+  uint32_t i0;
+  const P *a;
+  __device__ __forceinline__ uint32_t operator()(int j) const { return i0 ^ (uint32_t)a->xreg[j]; }
+};
+
 template <typename T2, typename R>
 __device__ __forceinline__ T2 cmul(const T2 &v, const T2 &L) {
   T2 o;
@@ -468,7 +476,8 @@ constexpr int after_stages() {
 // (transverse-field mixer); OP 1 and 2: about Y, which with tau = +-1 applies the basis change
 // of the X-product mixers (Eq. (2) with R_y(pi/2) in place of the Hadamard: both map Z to X),
 // with no X-pair terms; OP 1 indexes the middle's diagonal by the cost table, OP 2 by the
-// Hamming weight of the state index (the mixer's diagonal; no table is read).
+// Hamming weight of the state index, OP 3 by its parities against a set of masks (OP 2 and 3:
+// the mixer's diagonal; no table is read).
 template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT, int OP = 0>
 __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void k_pass(const PassArgs<R> a) {
   using G = TileCfg<T>;
@@ -529,7 +538,7 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
 
   // ---- this tile's table bytes, loaded into registers ahead of the state so that writing
   // them to LDS later waits only for these loads
-  constexpr bool need_tab = SHAPE != 0 && OP != 2;
+  constexpr bool need_tab = SHAPE != 0 && OP < 2;
   constexpr uint32_t kTabChunks = need_tab ? ((1u << T) * sizeof(TT)) / 16 / 256 : 1;  // 16 B per thread each
   uint4 tpre[kTabChunks];
   if constexpr (need_tab) {
@@ -615,6 +624,14 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
       // the mixer's diagonal, indexed by the Hamming weight of the state index
       const uint64_t y0 = base | off(elem<CM, T>(t, 0u));
       middle<R, T, NV, CM, MID>(a, sp, phi, lam, llut, lval, PopIdx<T, CM>{(uint32_t)__popcll(y0)}, w, acc);
+    } else if constexpr (OP == 3) {
+      // the mixer's diagonal, indexed by the parities of the state index against the masks
+      const uint64_t y0 = base | off(elem<CM, T>(t, 0u));
+      uint32_t i0 = 0;
+#pragma unroll
+      for (int k = 0; k < XD_MAX_TERMS; k++)
+        if (k < a.xnterms) i0 |= (uint32_t)(__popcll(y0 & a.xmasks[k]) & 1) << k;
+      middle<R, T, NV, CM, MID>(a, sp, phi, lam, llut, lval, TermsIdx<PassArgs<R>>{i0, &a}, w, acc);
     } else {
       const TabIdx<TT, T, CM> tix{ltab + tbase<T, CM, (int)sizeof(TT)>(t)};
       middle<R, T, NV, CM, MID>(a, sp, phi, lam, llut, lval, tix, w, acc);

@@ -16,7 +16,7 @@ namespace qaoa {
 namespace {
 
 template <typename R, int T, int KIND, typename TT, int SX>
-hipError_t hpass_shape(const PassArgs<R> &a, int shape, bool mixd, hipStream_t s) {
+hipError_t hpass_shape(const PassArgs<R> &a, int shape, int mixd, hipStream_t s) {
   if constexpr (KIND == 3) return launch_pass_t<R, T, 3, SX, SX, 1, TT, 1>(a, s);
   else {
     if (shape == 0) return launch_pass_t<R, T, KIND, SX, 0, 0, TT, 1>(a, s);
@@ -24,7 +24,9 @@ hipError_t hpass_shape(const PassArgs<R> &a, int shape, bool mixd, hipStream_t s
       if (shape == 2) return launch_pass_t<R, T, 1, 0, SX, 2, TT, 1>(a, s);
     if (shape == 3) return launch_pass_t<R, T, KIND, SX, 0, 3, TT, 1>(a, s);
     if (shape == 1) {
-      if (mixd) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 2>(a, s);
+      if (mixd == XD_POPCOUNT) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 2>(a, s);
+      if (mixd == XD_TERMS) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 3>(a, s);
+      if (mixd != 0) return hipErrorInvalidValue;
       return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 1>(a, s);
     }
     return hipErrorInvalidValue;
@@ -32,7 +34,7 @@ hipError_t hpass_shape(const PassArgs<R> &a, int shape, bool mixd, hipStream_t s
 }
 
 template <typename R, int T, int KIND, typename TT>
-hipError_t hpass_sx(const PassArgs<R> &a, int sx, int shape, bool mixd, hipStream_t s) {
+hipError_t hpass_sx(const PassArgs<R> &a, int sx, int shape, int mixd, hipStream_t s) {
   if (sx == 7) return hpass_shape<R, T, KIND, TT, 7>(a, shape, mixd, s);
   if (sx == 5) return hpass_shape<R, T, KIND, TT, 5>(a, shape, mixd, s);
   if (sx == 3) return hpass_shape<R, T, KIND, TT, 3>(a, shape, mixd, s);
@@ -41,7 +43,7 @@ hipError_t hpass_sx(const PassArgs<R> &a, int sx, int shape, bool mixd, hipStrea
 }
 
 template <typename R, int T, typename TT>
-hipError_t hpass_kind(const PassArgs<R> &a, int kind, int sx, int shape, bool mixd, hipStream_t s) {
+hipError_t hpass_kind(const PassArgs<R> &a, int kind, int sx, int shape, int mixd, hipStream_t s) {
   if (kind == 1) return hpass_sx<R, T, 1, TT>(a, sx, shape, mixd, s);
   if (kind == 3) return hpass_sx<R, T, 3, TT>(a, sx, shape, mixd, s);
   if (kind == 4) return hpass_sx<R, T, 4, TT>(a, sx, shape, mixd, s);
@@ -50,13 +52,13 @@ hipError_t hpass_kind(const PassArgs<R> &a, int kind, int sx, int shape, bool mi
 
 }  // namespace
 
-hipError_t launch_hpass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes, bool mixd,
+hipError_t launch_hpass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes, int mixd,
                            hipStream_t s) {
   return tbytes == 1 ? hpass_kind<float, TILE_BITS_F32, uint8_t>(a, kind, sx, shape, mixd, s)
                      : hpass_kind<float, TILE_BITS_F32, uint16_t>(a, kind, sx, shape, mixd, s);
 }
 
-hipError_t launch_hpass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes, bool mixd,
+hipError_t launch_hpass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes, int mixd,
                            hipStream_t s) {
   return tbytes == 1 ? hpass_kind<double, TILE_BITS_F64, uint8_t>(a, kind, sx, shape, mixd, s)
                      : hpass_kind<double, TILE_BITS_F64, uint16_t>(a, kind, sx, shape, mixd, s);

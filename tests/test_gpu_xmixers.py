@@ -218,3 +218,34 @@ def test_tile_passes_match_transform_passes(q, monkeypatch, n, orders, p):
             e1, g1 = res["1"][prec][0], res["1"][prec][1]
             assert abs(e1[0] - E / Nr) <= TOL[prec] * scale
             assert np.max(np.abs(g1[0] - gref / Nr)) <= TOL[prec] * max(np.max(np.abs(gref)), 1e-3)
+
+
+@pytest.mark.parametrize("n,masks,coefs", [(15, [0b11, 0b101000000000001, 0b111111100000000, 0b1010], [1.0, -0.7, 0.4, 1.3]),
+                                            (22, [(1 << 22) - 1, 0b11 << 20, 0b1001, 1 << 17], [0.2, 1.0, -1.5, 0.6])])
+def test_terms_on_tile_passes(q, monkeypatch, n, masks, coefs):
+    """Term-list mixers (index = parities of y against the masks) on the tile passes against the
+    separate transform and diagonal kernels (QAOA_XPROD_TILES=0), FP32 and FP64, and against
+    the FP64 oracle at n = 15. The masks span the tiles' contiguous, strided and register bits."""
+    rng = np.random.default_rng(2890 + n)
+    vals = rng.integers(0, 40, 1 << n).astype(np.float64)
+    A = workloads.random_angles(2, 2, 2891 + n)
+    res = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("QAOA_XPROD_TILES", mode)
+        c = q.Context(0)
+        try:
+            P, M = q.Problem.from_values(c, n, vals), q.Mixer.x_terms(c, n, masks, coefs)
+            res[mode] = [q.expect_grad_batched([P], [M], A, precision=prec) for prec in (0, 1)]
+        finally:
+            c.close()
+    scale = float(np.max(np.abs(vals)))
+    for prec in (0, 1):
+        (e1, g1), (e0, g0) = res["1"][prec], res["0"][prec]
+        assert np.max(np.abs(e1 - e0)) <= TOL[prec] * scale
+        assert np.max(np.abs(g1 - g0)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3)
+    if n <= 16:
+        E, Nr, gref = X.grad(n, vals, A[0], d=X.diag_terms(n, masks, coefs))
+        for prec in (0, 1):
+            e1, g1 = res["1"][prec]
+            assert abs(e1[0, 0] - E / Nr) <= TOL[prec] * scale
+            assert np.max(np.abs(g1[0, 0] - gref / Nr)) <= TOL[prec] * max(np.max(np.abs(gref)), 1e-3)
