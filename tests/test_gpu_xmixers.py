@@ -249,3 +249,30 @@ def test_terms_on_tile_passes(q, monkeypatch, n, masks, coefs):
             e1, g1 = res["1"][prec]
             assert abs(e1[0, 0] - E / Nr) <= TOL[prec] * scale
             assert np.max(np.abs(g1[0, 0] - gref / Nr)) <= TOL[prec] * max(np.max(np.abs(gref)), 1e-3)
+
+
+@pytest.mark.parametrize("n,p,nsets,distinct", [(14, 1, 1, 300), (19, 1, 5, 30), (20, 3, 2, 700)])
+def test_tile_passes_edge_cases(q, monkeypatch, n, p, nsets, distinct):
+    """Edge cases of the X-product tile passes against the transform path: one layer (the plan
+    is then the first pass, the fused end-of-sweep pass and their reverses), one angle set,
+    cost tables of 16-bit indices (more than 255 distinct values), k-body sums and term lists."""
+    rng = np.random.default_rng(2900 + n)
+    vals = rng.normal(0.0, 3.0, distinct)[rng.integers(0, distinct, 1 << n)]
+    A = workloads.random_angles(p, nsets, 2901 + n)
+    res = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("QAOA_XPROD_TILES", mode)
+        c = q.Context(0)
+        try:
+            P = q.Problem.from_values(c, n, vals)
+            Ms = [q.Mixer.x_orders(c, n, [1, 3]), q.Mixer.x_terms(c, n, [0b111, 1 << (n - 1), (1 << n) - 1], [0.5, -1.0, 0.25])]
+            res[mode] = [[q.expect_grad_batched([P], [M], A, precision=prec) for prec in (0, 1)] for M in Ms]
+        finally:
+            c.close()
+    scale = float(np.max(np.abs(vals)))
+    for m in range(2):
+        for prec in (0, 1):
+            (e1, g1), (e0, g0) = res["1"][m][prec], res["0"][m][prec]
+            assert e1.shape == (1, nsets) and g1.shape == (1, nsets, 2 * p)
+            assert np.max(np.abs(e1 - e0)) <= TOL[prec] * scale, (m, prec)
+            assert np.max(np.abs(g1 - g0)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3 * scale), (m, prec)
