@@ -8,6 +8,10 @@
   per-qubit loop or Taylor series).
 * ``johnson_spectrum``: closed-form eigenvalues of the clique mixer on weight-k strings
   (Johnson-scheme adjacency times 2).
+* ``cycle_edge``: per-edge cut probability of p-round QAOA on a cycle of at least 2p + 3
+  vertices, from the light cone (Farhi, Goldstone and Gutmann, arXiv:1411.4028): the middle
+  edge of the path of 2p + 2 vertices, by dense matrix exponentials, and its gradient by
+  central differences.
 """
 from __future__ import annotations
 
@@ -100,3 +104,25 @@ def dense_ring_hamiltonian(n):
     for i, j in edges:
         H += _op_on(n, {i: X, j: X}) + _op_on(n, {i: Y, j: Y})
     return H
+
+
+def cycle_edge(p, angles, h=1e-5):
+    """(value, gradient) of the cut probability of one edge of a cycle C_n, n >= 2p + 3, after
+    p rounds at `angles` ([beta_1..p, gamma_1..p]): after p rounds the edge term involves only
+    the qubits within distance p of the edge and the edges touching qubits within distance
+    p - 1, i.e. the path of 2p + 2 vertices with the edge in the middle."""
+    m = 2 * p + 2
+    xs = np.arange(1 << m)
+    bit = lambda q: (xs >> q) & 1
+    path_cost = sum(bit(i) ^ bit(i + 1) for i in range(m - 1)).astype(np.float64)
+    mid_cut = (bit(p) ^ bit(p + 1)).astype(np.float64)
+    H = dense_x_mixer_hamiltonian(m)
+    psi0 = np.full(1 << m, 2.0 ** (-m / 2), dtype=np.complex128)
+
+    def value(a):
+        psi = dense_evolve(H, path_cost, a, psi0)
+        return float(np.sum(np.abs(psi) ** 2 * mid_cut))
+
+    a = np.asarray(angles, dtype=np.float64)
+    g = np.array([(value(a + h * e) - value(a - h * e)) / (2 * h) for e in np.eye(2 * p)])
+    return value(a), g

@@ -243,6 +243,26 @@ def test_full_size_n28_identities(q, c2):
     assert np.max(np.abs(g1 + g2)) < 2e-5 * np.max(np.abs(g1))
 
 
+def test_full_size_cycle_light_cone(q, ctx):
+    """MaxCut on the cycle C_28 at p = 3 in the n = 28 launch configuration of the benchmark
+    (tile passes, complex64 and complex128) against a property that holds at any size: by the
+    light cone, <C> = 28 times the middle-edge cut probability of the path of 8 vertices, and
+    the same for the gradient (dense matrices on 8 qubits, no oracle)."""
+    from tests import pins
+    n, p = 28, 3
+    u = np.arange(n, dtype=np.int32)
+    v = (u + 1) % n
+    g = workloads.Graph(n, np.minimum(u, v).astype(np.int32), np.maximum(u, v).astype(np.int32), np.ones(n, dtype=np.int32))
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+    for a in workloads.random_angles(p, 2, 4128):
+        ev, eg = pins.cycle_edge(p, a)
+        for prec in (0, 1):
+            e, gr = q.expect_grad(P, M, a, precision=prec)
+            assert _rel(e, n * ev) < TOL[prec][0]
+            # the finite differences of the dense value carry ~1e-10 of their own
+            assert np.max(np.abs(gr - n * eg)) < max(TOL[prec][1], 1e-9) * n * np.max(np.abs(eg))
+
+
 def test_deterministic_repeat(q, c2):
     W, g, P, M = c2
     r1 = q.expect_grad(P, M, W.angles[0], precision=0)

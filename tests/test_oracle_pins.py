@@ -214,25 +214,12 @@ def test_cycle_light_cone_pins_large_n(n, p):
     path of 2p + 2 vertices, so <C>(C_n) = n * P(middle edge cut) on the path P_{2p+2}, the
     latter by dense matrix exponentials on 2p + 2 qubits. Pins the oracle's evolution and its
     adjoint gradient at p >= 2 and n > 8, where no other closed form or brute force reaches."""
-    m = 2 * p + 2
-    xs = np.arange(1 << m)
-    bit = lambda q: (xs >> q) & 1
-    path_cost = sum(bit(i) ^ bit(i + 1) for i in range(m - 1)).astype(np.float64)
-    mid_cut = (bit(p) ^ bit(p + 1)).astype(np.float64)
-    H = pins.dense_x_mixer_hamiltonian(m)
-    psi0 = np.full(1 << m, 2.0 ** (-m / 2), dtype=np.complex128)
-
-    def edge_value(a):
-        psi = pins.dense_evolve(H, path_cost, a, psi0)
-        return float(np.sum(np.abs(psi) ** 2 * mid_cut))
-
     u = np.arange(n)
     t = oracle.cost_table(n, u, (u + 1) % n)
     for a in workloads.random_angles(p, 2, 4100 + n):
         E, Nr, g = oracle.grad(n, t, a)
-        assert abs(E / Nr - n * edge_value(a)) < 1e-11 * n
-        h = 1e-5
-        fd = np.array([(edge_value(a + h * e) - edge_value(a - h * e)) / (2 * h) for e in np.eye(2 * p)])
+        ev, fd = pins.cycle_edge(p, a)
+        assert abs(E / Nr - n * ev) < 1e-11 * n
         assert np.max(np.abs(g / Nr - n * fd)) < 1e-7 * n
 
 
