@@ -208,7 +208,7 @@ KERNEL_NAMES = {"xmix": "k_pass<float,13,1|3|4,uint8,1|2> (tile passes with Y ro
                         "diagonals of X-product mixers)",
                 "fwd_pass": "k_pass<float,13,1,uint8,0> (tile pass, one vector)",
                 "rev_pass": "k_pass<float,13,2|3|4,uint8,0> (tile pass, state and adjoint vector)",
-                "small": "k_small<float> (whole state in one workgroup)",
+                "small": "k_whole / k_small<float> (whole state in one workgroup)",
                 "dense": "hipBLASLt GEMM f16 x f16 -> f32 (split eigenbasis product, 2 calls)"}
 
 

@@ -117,6 +117,35 @@ struct HostBuf {
   }
 };
 
+// Host memory the device writes directly (fine-grained, coherent, mapped): small result
+// arrays that the host reads after synchronising the stream, with no device-to-host copy.
+struct MappedBuf {
+  void *h = nullptr, *d = nullptr;
+  size_t cap = 0;
+  void get(size_t bytes) {
+    if (bytes <= cap && h) return;
+    if (h) (void)hipHostFree(h);
+    h = d = nullptr;
+    cap = 0;
+    const size_t want = bytes < 4096 ? 4096 : bytes;
+    if (hipHostMalloc(&h, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      h = nullptr;
+      (void)hipGetLastError();
+      throw Err{QAOA_ERR_OUT_OF_MEMORY, "hipHostMalloc (mapped) failed"};
+    }
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipHostFree(h);
+      h = d = nullptr;
+      (void)hipGetLastError();
+      throw Err{QAOA_ERR_HIP, "hipHostGetDevicePointer failed"};
+    }
+    cap = want;
+  }
+  ~MappedBuf() {
+    if (h) (void)hipHostFree(h);
+  }
+};
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -151,6 +180,7 @@ struct qaoa_ctx {
   int xprod_tiles = 1;       // X-product mixers on Hadamard tile passes when they apply
   DevBuf phi, lam, ckpt, partials, params, luts, luts2, results, cnt, items, gitems, gamps;
   HostBuf hparams, hresults;
+  MappedBuf small_out;  // results of the whole-state kernels
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -941,7 +971,9 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
   HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
   int nrow = 0;
   for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
-  double *dres = (double *)ctx->results.get((size_t)nrow * rowlen * sizeof(double));
+  // the kernels write their result rows straight into mapped host memory
+  ctx->small_out.get((size_t)nrow * rowlen * sizeof(double));
+  double *dres = (double *)ctx->small_out.d;
   const SmallItem *ditems = (const SmallItem *)d;
   const double *dang = (const double *)(d + off_a);
   // algorithmic work per item: the table read once; FP32 flops of the method per amplitude:
@@ -973,8 +1005,8 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
                         grad, dres, st));
     kt.done();
   }
-  HIPCHK(hipMemcpyAsync(hout, dres, (size_t)nrow * rowlen * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(hout, ctx->small_out.h, (size_t)nrow * rowlen * sizeof(double));
   profile_collect(ctx);
 }
 
