@@ -17,8 +17,10 @@ Other workloads (--workload):
                            value in states/s
   angles_er_n12_p10        angle finding: one step = iterative basinhopping rounds 1..10 for 50
                            G(12,1/2) MaxCut instances at once; value in evals/s inside the loop
-  xorders_maxcut3reg_n24_p4  mixer of all 1- and 2-body X products (Walsh-Hadamard path), n=24,
-                           p=4, 16 angle sets per batched call
+  xorders_maxcut3reg_n24_p4  mixer of all 1- and 2-body X products (tile passes with the basis
+                           change as Y rotations), n=24, p=4, 16 angle sets per batched call
+  multiangle_maxcut3reg_n24_p4  per-qubit multi-angle X mixer (Walsh-Hadamard path), n=24, p=4,
+                           16 angle sets per batched call
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
@@ -91,6 +93,8 @@ class Runner:
             self.mixers = [q.Mixer.clique(self.ctx, g.n, k) for g in W.graphs]
         elif W.mixer == "x_orders":
             self.mixers = [q.Mixer.x_orders(self.ctx, g.n, W.extra["orders"]) for g in W.graphs]
+        elif W.mixer == "x_multiangle":
+            self.mixers = [q.Mixer.x_multiangle(self.ctx, g.n) for g in W.graphs]
         else:
             self.mixers = [q.Mixer.x(self.ctx, g.n) for g in W.graphs]
         self.batched = len(W.graphs) > 1 or W.angles.shape[0] > 1
@@ -135,18 +139,19 @@ def cpu_baseline(W, sample):
                           f"{dt:.1f} s, scaled x{W.p} to one p={W.p} evaluation"}, {}
     if W.name == "maxcut3reg_n32_p16":
         return None, {}
-    if W.mixer == "x_orders":
-        # one fwd+adjoint evaluation with p=1 at the full n (one of the p layers), scaled by p
+    if W.mixer in ("x_orders", "x_multiangle"):
         # one fwd+adjoint evaluation with p=1 on a 3-regular graph of n - 2 vertices, scaled by 4 n / (n - 2)
-        # (transform work per amplitude grows with n) and by p
+        # (transform or per-qubit rotation work per amplitude grows with n) and by p
         from oracle import xmixers as X
         n = W.graphs[0].n
         gs = workloads_mod().random_regular_graph(n - 2, 3, 8124)
         table = oracle.graph_table(gs)
-        d = X.diag_orders(n - 2, W.extra["orders"])
-        a1 = np.array([W.angles[0][0], W.angles[0][W.p]])
         t0 = time.perf_counter()
-        X.grad(n - 2, table, a1, d=d)
+        if W.mixer == "x_orders":
+            d = X.diag_orders(n - 2, W.extra["orders"])
+            X.grad(n - 2, table, np.array([W.angles[0][0], W.angles[0][W.p]]), d=d)
+        else:
+            X.grad(n - 2, table, np.concatenate([W.angles[0][:n - 2], [W.angles[0][W.p * n]]]), multiangle=True)
         dt = time.perf_counter() - t0
         scale = 4.0 * n / (n - 2) * W.p
         return {"value": 1.0 / (dt * scale), "unit": "evals/s", "cores": 1, "kind": "oracle",
@@ -217,7 +222,12 @@ def roofline(prof, workload):
     d = prof[cls]
     L = max(d["launches"], 1)
     mean_ms = d["ms"] / L
-    base = {"kernel": KERNEL_NAMES[cls], "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
+    name = KERNEL_NAMES[cls]
+    if cls == "xmix" and workload.startswith("multiangle"):
+        # per-qubit angles take the Walsh-Hadamard path; one timed group is one transform (its
+        # passes) or one two-vector diagonal kernel
+        name = "k_wht / k_xdiag (Walsh-Hadamard passes and per-qubit diagonals)"
+    base = {"kernel": name, "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
     if cls in ("fwd_pass", "rev_pass", "xmix"):
         bpl = d["bytes"] / L
         a = bpl / (mean_ms * 1e-3) / 1e9

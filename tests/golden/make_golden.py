@@ -3,6 +3,7 @@
     python tests/golden/make_golden.py maxcut3reg_n28_p8
     python tests/golden/make_golden.py bisection_g16_k8_p6 2
     python tests/golden/make_golden.py xorders_maxcut3reg_n24_p4
+    python tests/golden/make_golden.py multiangle_maxcut3reg_n24_p4
 
 Each output file records the workload, its graph and angles (so a reader can check the
 inputs are the seeded ones), and the FP64 oracle's <C> (E / Nrm) and adjoint gradient
@@ -35,13 +36,16 @@ def make(name: str, n_sets: int = 1, extra_sets=None):
         if W.mixer == "x_orders":
             from oracle import xmixers
             E, N, gr = xmixers.grad(g.n, table, a, d=xmixers.diag_orders(g.n, W.extra["orders"]))
+        elif W.mixer == "x_multiangle":
+            from oracle import xmixers
+            E, N, gr = xmixers.grad(g.n, table, a, multiangle=True)
         else:
             E, N, gr = oracle.grad(g.n, table, a, W.hamming_k)
         rows.append({"angles": a.tolist(), "expect": E / N, "norm": N, "grad": (gr / N).tolist()})
         print(name, "set done", time.time() - t0, flush=True)
     out = {
         "workload": name,
-        "source": ("FP64 CPU oracle (oracle/xmixers.py), adjoint gradient" if W.mixer == "x_orders"
+        "source": ("FP64 CPU oracle (oracle/xmixers.py), adjoint gradient" if W.mixer in ("x_orders", "x_multiangle")
                    else "FP64 CPU oracle (oracle/qaoa_oracle.c), adjoint gradient"),
         "n": g.n, "p": W.p, "hamming_k": W.hamming_k,
         "edges": [g.u.tolist(), g.v.tolist(), g.w.tolist()],

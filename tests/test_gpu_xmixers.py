@@ -276,3 +276,22 @@ def test_tile_passes_edge_cases(q, monkeypatch, n, p, nsets, distinct):
             assert e1.shape == (1, nsets) and g1.shape == (1, nsets, 2 * p)
             assert np.max(np.abs(e1 - e0)) <= TOL[prec] * scale, (m, prec)
             assert np.max(np.abs(g1 - g0)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3 * scale), (m, prec)
+
+
+def test_multiangle_full_size_against_stored_oracle_values(q, ctx):
+    """The per-qubit multi-angle workload in its benchmark launch configuration (n = 24, p = 4,
+    16 angle sets per batched call): set 0 against the FP64 oracle values stored by
+    tests/golden/make_golden.py."""
+    import json
+    import os
+    W = workloads.workload("multiangle_maxcut3reg_n24_p4")
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "multiangle_maxcut3reg_n24_p4.json")))
+    rec = G["sets"][0]
+    assert np.array_equal(np.array(rec["angles"]), W.angles[0])
+    g = W.graphs[0]
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x_multiangle(ctx, g.n)
+    for prec in (0, 1):
+        e, gr = q.expect_grad_batched([P], [M], W.angles, precision=prec)
+        assert abs(e[0, 0] - rec["expect"]) <= TOL[prec] * G["table_max"]
+        g0 = np.array(rec["grad"])
+        assert np.max(np.abs(gr[0, 0] - g0)) <= TOL[prec] * np.max(np.abs(g0))

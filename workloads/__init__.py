@@ -120,7 +120,7 @@ class Workload:
     graphs: List[Graph]
     p: int
     angles: np.ndarray             # [n_sets, 2p]
-    mixer: str = "x"               # "x" (transverse field), "clique" or "grover"
+    mixer: str = "x"               # "x" (transverse field), "clique", "grover", "x_orders", "x_multiangle"
     hamming_k: int = -1            # feasible subspace weight, -1 = all 2^n states
     extra: dict = field(default_factory=dict)
 
@@ -172,6 +172,14 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
         return Workload(name, "MaxCut, random 3-regular n=24, mixer of all 1- and 2-body X products, p=4, "
                               "16 sets", [g], 4, random_angles(4, ns, 8025), mixer="x_orders",
                         extra={"orders": [1, 2]})
+    if name == "multiangle_maxcut3reg_n24_p4":
+        # per-qubit angles (one beta per qubit and layer), 16 angle sets per call; rows
+        # [beta_{1,0..n-1}, ..., beta_{p,0..n-1}, gamma_1..gamma_p], each ~ U(0, pi)
+        g, _ = _maxcut_3reg(24, 4, 8224)
+        ns = 16 if n_sets is None else n_sets
+        a = np.random.default_rng(8225).uniform(0.0, np.pi, size=(ns, 4 * (24 + 1)))
+        return Workload(name, "MaxCut, random 3-regular n=24, per-qubit multi-angle X mixer, p=4, 16 sets",
+                        [g], 4, a, mixer="x_multiangle")
     if name == "maxcut3reg_n32_p16":
         g, a = _maxcut_3reg(32, 16, 5032)
         return Workload(name, "MaxCut, random 3-regular n=32, X mixer, p=16, fwd+grad",
@@ -181,4 +189,4 @@ def workload(name: str, n_sets: Optional[int] = None) -> Workload:
 
 WORKLOADS = ["maxcut3reg_n10_p3", "maxcut3reg_n28_p8", "batched_er_n12to20_p10",
              "bisection_g16_k8_p6", "maxcut3reg_n32_p16", "grover_maxcut3reg_n40_p16", "angles_er_n12_p10",
-             "xorders_maxcut3reg_n24_p4"]
+             "xorders_maxcut3reg_n24_p4", "multiangle_maxcut3reg_n24_p4"]
