@@ -19,8 +19,8 @@ Other workloads (--workload):
                            G(12,1/2) MaxCut instances at once; value in evals/s inside the loop
   xorders_maxcut3reg_n24_p4  mixer of all 1- and 2-body X products (tile passes with the basis
                            change as Y rotations), n=24, p=4, 16 angle sets per batched call
-  multiangle_maxcut3reg_n24_p4  per-qubit multi-angle X mixer (Walsh-Hadamard path), n=24, p=4,
-                           16 angle sets per batched call
+  multiangle_maxcut3reg_n24_p4  per-qubit multi-angle X mixer (tile passes, per-qubit diagonal),
+                           n=24, p=4, 16 angle sets per batched call
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
@@ -209,7 +209,7 @@ def traffic_from_profile(workload, cls):
     return None
 
 
-KERNEL_NAMES = {"xmix": "k_pass<float,13,1|3|4,uint8,1|2> (tile passes with Y rotations: basis change and "
+KERNEL_NAMES = {"xmix": "k_pass<float,13,1|3|4,uint8,1..4> (tile passes with Y rotations: basis change and "
                         "diagonals of X-product mixers)",
                 "fwd_pass": "k_pass<float,13,1,uint8,0> (tile pass, one vector)",
                 "rev_pass": "k_pass<float,13,2|3|4,uint8,0> (tile pass, state and adjoint vector)",
@@ -222,12 +222,7 @@ def roofline(prof, workload):
     d = prof[cls]
     L = max(d["launches"], 1)
     mean_ms = d["ms"] / L
-    name = KERNEL_NAMES[cls]
-    if cls == "xmix" and workload.startswith("multiangle"):
-        # per-qubit angles take the Walsh-Hadamard path; one timed group is one transform (its
-        # passes) or one two-vector diagonal kernel
-        name = "k_wht / k_xdiag (Walsh-Hadamard passes and per-qubit diagonals)"
-    base = {"kernel": name, "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
+    base = {"kernel": KERNEL_NAMES[cls], "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
     if cls in ("fwd_pass", "rev_pass", "xmix"):
         bpl = d["bytes"] / L
         a = bpl / (mean_ms * 1e-3) / 1e9

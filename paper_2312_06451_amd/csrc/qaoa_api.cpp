@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <array>
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
@@ -433,10 +434,12 @@ cd cpow_int(cd z, int m) {
 
 struct OutMap {
   int nout, p;
+  int m = 1;  // outputs per beta layer: 1, or with per-qubit angles 1 + n (the total, then per qubit)
   int E() const { return 0; }
   int Nr() const { return 1; }
-  int gb(int k) const { return 2 + k; }
-  int gg(int k) const { return 2 + p + k; }
+  int gb(int k) const { return 2 + k * m; }
+  int gbq(int k, int q) const { return 2 + k * m + 1 + q; }
+  int gg(int k) const { return 2 + p * m + k; }
 };
 
 // Tile-major copy of the cost table for tile geometry (T, c, h0), built once per problem and
@@ -479,6 +482,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const std::vector<TileGeo> tiles = make_tiles(n, T, cmin);
   const int K = (int)tiles.size();
   const int L = xm ? 2 * p : p;  // layers of the pass plan
+  const bool ma = xm && xm->kind == 4;      // per-qubit angles
+  const int SL = ma ? p * (n + 1) : 2 * p;  // angles per set
   const std::vector<FwdPass> fwd = make_forward(K, L);
   const uint32_t nwg = 1u << (n - T);
   const uint64_t N = 1ull << n;
@@ -536,7 +541,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   auto fwd_out = [&](int j) -> void * { return ckpt ? (void *)(dck + (size_t)j * vbytes) : dphi; };
   auto fwd_in = [&](int j) -> void * { return j == 0 ? nullptr : fwd_out(j - 1); };
   void *dlam = grad ? ctx->lam.get(vbytes) : nullptr;
-  OutMap om{2 + 2 * p, p};
+  OutMap om{2 + p * (ma ? n + 1 : 1) + p, p, ma ? n + 1 : 1};
   const int nout = om.nout;
   const int maxc = K + 1;
   const size_t part_elems = (size_t)nout * maxc * nsets * nwg;
@@ -554,7 +559,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         ff[s * L + k] = fi[s * L + k] = cd(std::sqrt(0.5), 0.0);
         continue;
       }
-      double beta = angles[(size_t)s * 2 * p + k];
+      double beta = angles[(size_t)s * SL + k];
       rot_params<R>(beta, tau[s * L + k], swp[s * L + k], ff[s * L + k], fi[s * L + k]);
     }
   // flip state of set s's stored vector after `layers` complete rounds (all bits or none):
@@ -568,8 +573,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   // angle of the diagonal of layer k: gamma_k; with X products gamma_{k/2} (even k) or
   // beta_{(k-1)/2} (odd k, the mixer diagonal)
   auto gam = [&](int s, int k) {
-    if (!xm) return angles[(size_t)s * 2 * p + p + k];
-    return (k % 2 == 0) ? angles[(size_t)s * 2 * p + p + k / 2] : angles[(size_t)s * 2 * p + (k - 1) / 2];
+    if (!xm) return angles[(size_t)s * SL + p + k];
+    return (k % 2 == 0) ? angles[(size_t)s * SL + (ma ? p * n : p) + k / 2] : angles[(size_t)s * SL + (k - 1) / 2];
   };
   auto is_mix = [&](int k) { return xm != nullptr && k % 2 == 1; };
   // output slot of the derivative taken at the diagonal of layer k
@@ -590,10 +595,70 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   // a pass whose diagonal is the mixer's: the mixer's values, indexed by the Hamming weight of
   // y, or by its parities against the term masks (then the register parts' indices in the
   // middle's register assignment go with the pass: register j holds tile element j << sh)
+  // per-qubit angles: for pass i and set s, the register parts' factors (RN complex, staged as
+  // the pass's LUT) and the constant and per-qubit factors (33 complex doubles, read by each
+  // thread once); filled per pass as the plan is built, uploaded with the parameters
+  const int RBq = T - 8, RNq = 1 << RBq;
+  std::vector<std::complex<R>> ma_lut;
+  std::vector<cd> ma_bf;
+  std::vector<int> ma_block;                 // per pass: block index into the tables, or -1
+  std::vector<std::array<uint64_t, 32>> ma_yreg;  // per block: the address bits of register j
+  // register assignment of the middle (after part 1's stages H, M, L in order)
+  auto middle_shift = [&](int tile) {
+    const uint32_t rot = tiles[tile].rot;
+    const bool Lg = rot & ((1u << RBq) - 1), Mg = rot & (((1u << 8) - 1) & ~((1u << RBq) - 1));
+    return Lg ? 0 : (Mg ? T - 2 * RBq : 8);
+  };
+  auto ma_fill = [&](int block, int s, int layer, cd scale, double sgn) {
+    // D(y) = e^{-i sum_q b_q} prod_{q in y} e^{2i b_q} (forward, sgn = 1); the inverse with sgn = -1
+    const double *b = angles + (size_t)s * SL + (size_t)layer * n;
+    double B = 0.0;
+    for (int qq = 0; qq < n; qq++) B += b[qq];
+    cd *bf = &ma_bf[((size_t)block * nsets + s) * 33];
+    bf[0] = scale * std::polar(1.0, -sgn * B);
+    for (int qq = 0; qq < 32; qq++) bf[1 + qq] = qq < n ? std::polar(1.0, 2.0 * sgn * b[qq]) : cd(1.0, 0.0);
+    std::complex<R> *L = &ma_lut[((size_t)block * nsets + s) * RNq];
+    for (int jj = 0; jj < RNq; jj++) {
+      cd v(1.0, 0.0);
+      for (int qq = 0; qq < n; qq++)
+        if ((ma_yreg[block][jj] >> qq) & 1) v *= bf[1 + qq];
+      L[jj] = std::complex<R>((R)v.real(), (R)v.imag());
+    }
+  };
+  auto ma_new_block = [&](PassArgs<R> &a, int tile) -> int {
+    const int block = (int)ma_yreg.size();
+    std::array<uint64_t, 32> yr{};
+    const int sh = middle_shift(tile);
+    const uint64_t cmask = (1ull << a.c) - 1;
+    for (int jj = 0; jj < RNq; jj++) {
+      const uint64_t e = (uint64_t)jj << sh;
+      yr[jj] = (e & cmask) | ((e >> a.c) << a.h0);
+    }
+    ma_yreg.push_back(yr);
+    ma_lut.resize((size_t)(block + 1) * nsets * RNq);
+    ma_bf.resize((size_t)(block + 1) * nsets * 33);
+    // where each qubit sits in the middle's register assignment
+    const int MLO = T - 2 * RBq;
+    for (int qq = 0; qq < 32; qq++) {
+      int tb = -1;
+      if (qq < a.c) tb = qq;
+      else if (qq >= a.h0 && qq < a.h0 + T - a.c) tb = a.c + (qq - a.h0);
+      int src = 16;
+      if (tb >= 0) {
+        if (sh == 8) src = tb >= 8 ? tb - 8 : 8 + tb;
+        else if (sh == 0) src = tb < RBq ? tb : 8 + (tb - RBq);
+        else src = (tb >= MLO && tb < MLO + RBq) ? tb - MLO : (tb < MLO ? 8 + tb : 8 + (tb - RBq));
+      }
+      a.ma_src[qq] = (int8_t)(qq < n ? src : 16);
+    }
+    a.lut_len = RNq;
+    return block;
+  };
   auto mix_diag = [&](PassArgs<R> &a, int tile) {
     a.vals = sizeof(R) == 4 ? (const void *)xm->xvals_f : (const void *)xm->xvals;
     a.lut_len = lut_mix;
     a.lam_c0 = (R)0;
+    if (ma) return;
     if (xm->xd.mode != XD_TERMS) return;
     a.xnterms = xm->xd.nterms;
     for (int k = 0; k < XD_MAX_TERMS; k++) a.xmasks[k] = k < xm->xd.nterms ? xm->xd.masks[k] : 0;
@@ -657,12 +722,13 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (sx != 7 && sx != 5 && sx != 3 && sx != 1) throw fail(QAOA_ERR_HIP, "internal: unsupported tile stage set");
     return sx;
   };
-  auto add_pass = [&](const PassArgs<R> &a, int kind, int shape, int tile, int mixd = 0) {
+  auto add_pass = [&](const PassArgs<R> &a, int kind, int shape, int tile, int mixd = 0, int mblock = -1) {
     passes.push_back(a);
     nvs.push_back(kind);
     shapes.push_back(shape);
     sxs.push_back(stage_set(tile));
     mixlut.push_back(mixd);
+    ma_block.push_back(mblock);
   };
   const int npf = (int)fwd.size();
 
@@ -678,10 +744,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     else f |= PF_LOAD_PHI;
     f |= PF_STORE_PHI;
     if (fp.pre >= 0) a.mask1 = tiles[fp.tile].rot;
+    int mblock = -1;
     if (fp.ph >= 0) {
       f |= PF_PHASE;
       if (is_mix(fp.ph)) {
         mix_diag(a, fp.tile);
+        if (ma) mblock = ma_new_block(a, fp.tile);
       } else {
         a.table = table_for(fp.tile);
         a.table_rev = xm ? a.table : table_rev_for(fp.tile);
@@ -701,7 +769,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       }
       if (fp.ph >= 0) {
         q.tflip = tflip(s, fp.ph);
-        q.lut = push_job(fp.ph, LutJob{gam(s, fp.ph), sig[s].real(), sig[s].imag(), -1.0});
+        if (mblock >= 0) {
+          ma_fill(mblock, s, (fp.ph - 1) / 2, sig[s], 1.0);
+          q.lut = s;
+        } else {
+          q.lut = push_job(fp.ph, LutJob{gam(s, fp.ph), sig[s].real(), sig[s].imag(), -1.0});
+        }
         sig[s] = cd(1.0, 0.0);
       }
       if (fp.post >= 0) {
@@ -710,7 +783,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       }
       sps.push_back(q);
     }
-    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph) ? xm->xd.mode : 0);
+    add_pass(a, 1, fp.pre < 0 ? 2 : (fp.post >= 0 ? 1 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph) ? xm->xd.mode : 0,
+             mblock);
     sig_fwd.insert(sig_fwd.end(), sig.begin(), sig.end());
   }
 
@@ -787,15 +861,28 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       a.mask1 = tiles[fp.tile].rot;
       f |= PF_XT1 | PF_ROT1_BOTH;
       if (!xm) a.slot_off[SL_A] = slot_for(om.gb(l1));
+      int mblock = -1;
       if (fp.ph >= 0) {
         f |= PF_GGAMMA;
         if (is_mix(fp.ph)) {
           mix_diag(a, fp.tile);
+          if (ma) mblock = ma_new_block(a, fp.tile);
         } else {
           a.table = table_for(fp.tile);
           a.table_rev = xm ? a.table : table_rev_for(fp.tile);
         }
-        a.slot_off[SL_B] = slot_for(diag_out(fp.ph));
+        if (mblock >= 0) {
+          // the total and the per-qubit sums of layer k: consecutive outputs, one contribution each
+          const int k = (fp.ph - 1) / 2;
+          a.ma_total = slot_for(om.gb(k));
+          a.ma_slot = slot_for(om.gbq(k, 0));
+          a.ma_stride = (int64_t)maxc * nsets * (int64_t)nwg;
+          for (int qq = 1; qq < n; qq++)
+            if (slot_for(om.gbq(k, qq)) != a.ma_slot + qq * a.ma_stride)
+              throw fail(QAOA_ERR_HIP, "internal: per-qubit slots");
+        } else {
+          a.slot_off[SL_B] = slot_for(diag_out(fp.ph));
+        }
         if (!last) f |= PF_PHASE | PF_PHASE_BOTH;
       }
       const bool has2 = (fp.post >= 0 && fp.pre >= 0);
@@ -832,7 +919,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
           cd t(1.0, 0.0);
           if (ckpt && has2) t = sig_fwd[(size_t)(j - 1) * nsets + s] / cpow_int(fi[s * L + fp.pre], rotbits(fp.tile));
           const cd fold = sb[s] / t;
-          q.lut = push_job(fp.ph, LutJob{gam(s, fp.ph), fold.real(), fold.imag(), 1.0});
+          if (mblock >= 0) {
+            ma_fill(mblock, s, (fp.ph - 1) / 2, fold, -1.0);
+            q.lut = s;
+          } else {
+            q.lut = push_job(fp.ph, LutJob{gam(s, fp.ph), fold.real(), fold.imag(), 1.0});
+          }
           sb[s] = t;
         }
         if (has2) {
@@ -843,7 +935,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
         sps.push_back(q);
       }
       // with checkpoints phi is read and never stored: the kind that compiles its store out
-      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph) ? xm->xd.mode : 0);
+      add_pass(a, ckpt ? 4 : 2, has2 ? 1 : (fp.ph >= 0 ? 3 : 0), fp.tile, fp.ph >= 0 && is_mix(fp.ph) ? xm->xd.mode : 0,
+               mblock);
     }
   }
 
@@ -851,10 +944,13 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const size_t sp_bytes = sps.size() * sizeof(SetParams<R>);
   const size_t job_bytes = jobs.size() * sizeof(LutJob), jobm_bytes = jobs_m.size() * sizeof(LutJob);
   const size_t cnt_bytes = nout * sizeof(int);
+  const size_t mal_bytes = ma_lut.size() * sizeof(std::complex<R>), mab_bytes = ma_bf.size() * sizeof(cd);
   const size_t off_jobs = (sp_bytes + 255) & ~size_t(255);
   const size_t off_jobm = (off_jobs + job_bytes + 255) & ~size_t(255);
   const size_t off_cnt = (off_jobm + jobm_bytes + 255) & ~size_t(255);
-  const size_t total = off_cnt + cnt_bytes;
+  const size_t off_mal = (off_cnt + cnt_bytes + 255) & ~size_t(255);
+  const size_t off_mab = (off_mal + mal_bytes + 255) & ~size_t(255);
+  const size_t total = off_mab + mab_bytes;
   unsigned char *h = (unsigned char *)ctx->hparams.get(total);
   // the previous call may still read the pinned staging buffer through its async copy
   HIPCHK(hipStreamSynchronize(st));
@@ -862,6 +958,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   if (job_bytes) std::memcpy(h + off_jobs, jobs.data(), job_bytes);
   if (jobm_bytes) std::memcpy(h + off_jobm, jobs_m.data(), jobm_bytes);
   std::memcpy(h + off_cnt, cnt.data(), cnt_bytes);
+  if (mal_bytes) std::memcpy(h + off_mal, ma_lut.data(), mal_bytes);
+  if (mab_bytes) std::memcpy(h + off_mab, ma_bf.data(), mab_bytes);
   unsigned char *d = (unsigned char *)ctx->params.get(total);
   HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
   void *dluts = nullptr;
@@ -879,6 +977,10 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     PassArgs<R> &a = passes[i];
     a.sp = (const SetParams<R> *)(d + i * nsets * sizeof(SetParams<R>));
     a.luts = mixlut[i] ? dluts_m : dluts;
+    if (ma_block[i] >= 0) {
+      a.luts = d + off_mal + (size_t)ma_block[i] * nsets * RNq * sizeof(std::complex<R>);
+      a.vals = d + off_mab + (size_t)ma_block[i] * nsets * 33 * sizeof(cd);
+    }
     const uint32_t fl = a.flags;
     double by = 0;
     if (fl & (PF_LOAD_PHI | PF_LOAD_PSI0)) by += (double)N * esz;
@@ -926,8 +1028,14 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     if (grad && out_grad) {
       const double ntrue = std::norm(sig_p[s]) * Nr;
       for (int k = 0; k < p; k++) {
-        out_grad[(size_t)s * 2 * p + k] = 2.0 * r[om.gb(k)] / ntrue;
-        out_grad[(size_t)s * 2 * p + p + k] = 2.0 * r[om.gg(k)] / ntrue;
+        if (ma) {  // g_q = 2 (S - 2 S_q): S over all states, S_q over those with bit q set
+          for (int qq = 0; qq < n; qq++)
+            out_grad[(size_t)s * SL + (size_t)k * n + qq] = 2.0 * (r[om.gb(k)] - 2.0 * r[om.gbq(k, qq)]) / ntrue;
+          out_grad[(size_t)s * SL + (size_t)p * n + k] = 2.0 * r[om.gg(k)] / ntrue;
+          continue;
+        }
+        out_grad[(size_t)s * SL + k] = 2.0 * r[om.gb(k)] / ntrue;
+        out_grad[(size_t)s * SL + p + k] = 2.0 * r[om.gg(k)] / ntrue;
       }
     }
   }
@@ -1862,7 +1970,7 @@ static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, con
   // Tile passes (Y-rotation basis change): single-angle mixers (diagonal by Hamming weight or
   // by parities against term masks), states larger than one tile, the gradient's checkpoints
   // within half the free memory (the rule of the transverse-field path)
-  if (ctx->xprod_tiles && !qb && !d_state && (mix->xd.mode == XD_POPCOUNT || mix->xd.mode == XD_TERMS) &&
+  if (ctx->xprod_tiles && !d_state && (mix->xd.mode == XD_POPCOUNT || mix->xd.mode == XD_TERMS || qb) &&
       n > (precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64) && lut_cost <= MAX_LUT && mix->xlen <= MAX_LUT) {
     bool fits = true;
     if (grad) {

@@ -103,6 +103,14 @@ struct PassArgs {
   uint64_t xmasks[XD_MAX_TERMS];
   int xnterms;
   uint16_t xreg[32];
+  // Per-qubit multi-angle passes: vals holds, per angle set, 33 complex doubles (the constant
+  // factor, then e^{+-2i beta_q} per qubit q); the LUT holds the register parts' factors. In
+  // the reverse sweep the sum over all states goes to slot ma_total and the sum over the states
+  // with bit q set to slot ma_slot + q * ma_stride; ma_src[q] says where bit q sits in the
+  // middle's register assignment: register bit b (0..7), thread bit i (8 + i), or the tile
+  // index (16).
+  int64_t ma_total, ma_slot, ma_stride;
+  int8_t ma_src[32];
 };
 
 // LUT construction job: luts[i][c] = scale_i * exp(sign_i * i * gamma_i * vals[c]),

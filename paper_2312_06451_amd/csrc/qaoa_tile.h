@@ -365,6 +365,54 @@ __device__ __forceinline__ T2 cmul(const T2 &v, const T2 &L) {
   return o;
 }
 
+// Middle of a per-qubit multi-angle pass (the mixer diagonal e^{-i sum_q beta_q (-1)^{y_q}} in
+// the basis of V): the diagonal of state y = y0 | (register j's part) is F(y0) L[j], F(y0) the
+// set's constant factor times e^{2i beta_q} over the bits q of y0 (FP64 product, once per
+// thread), L[j] the register part's factor from the staged LUT. With GS, first the weighted
+// sums of Im(conj(lam) phi): over all of the thread's states (mt) and over those with register
+// bit b set (mu[b]); per-thread sums of the 2^RB terms in FP32, then FP64.
+template <typename R, int T, int NV, bool GS>
+__device__ __forceinline__ void middle_ma(typename Cplx<R>::T2 *phi, typename Cplx<R>::T2 *lam,
+                                          const typename Cplx<R>::T2 *llut, const double2 *bf, uint64_t y0,
+                                          double w, double &mt, double *mu) {
+  using G = TileCfg<T>;
+  using T2 = typename Cplx<R>::T2;
+  if constexpr (NV == 2 && GS) {
+    R st = 0, su[G::RB];
+#pragma unroll
+    for (int b = 0; b < G::RB; b++) su[b] = 0;
+#pragma unroll
+    for (int j = 0; j < G::RN; j++) {
+      const R im = fmaR(lam[j].x, phi[j].y, -lam[j].y * phi[j].x);
+      st += im;
+#pragma unroll
+      for (int b = 0; b < G::RB; b++)
+        if (j & (1 << b)) su[b] += im;
+    }
+    pin(st);
+    mt = w * (double)st;
+#pragma unroll
+    for (int b = 0; b < G::RB; b++) {
+      pin(su[b]);
+      mu[b] = w * (double)su[b];
+    }
+  }
+  double fr = bf[0].x, fi = bf[0].y;
+  for (uint64_t yy = y0; yy; yy &= yy - 1) {
+    const double2 f = bf[1 + __builtin_ctzll(yy)];
+    const double nr = fr * f.x - fi * f.y;
+    fi = fr * f.y + fi * f.x;
+    fr = nr;
+  }
+  const T2 F{(R)fr, (R)fi};
+#pragma unroll
+  for (int j = 0; j < G::RN; j++) {
+    const T2 D = cmul<T2, R>(F, llut[j]);
+    phi[j] = cmul<T2, R>(phi[j], D);
+    if constexpr (NV == 2) lam[j] = cmul<T2, R>(lam[j], D);
+  }
+}
+
 // Elementwise steps in assignment A, each step in its own loop (no per-element branching).
 // MID != 0 fixes the steps at compile time (flag bits of the PF_ set); MID == 0 reads them
 // from the pass flags.
@@ -476,8 +524,8 @@ constexpr int after_stages() {
 // (transverse-field mixer); OP 1 and 2: about Y, which with tau = +-1 applies the basis change
 // of the X-product mixers (Eq. (2) with R_y(pi/2) in place of the Hadamard: both map Z to X),
 // with no X-pair terms; OP 1 indexes the middle's diagonal by the cost table, OP 2 by the
-// Hamming weight of the state index, OP 3 by its parities against a set of masks (OP 2 and 3:
-// the mixer's diagonal; no table is read).
+// Hamming weight of the state index, OP 3 by its parities against a set of masks, OP 4 is the
+// per-qubit multi-angle diagonal (OP 2 to 4: the mixer's diagonal; no table is read).
 template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT, int OP = 0>
 __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void k_pass(const PassArgs<R> a) {
   using G = TileCfg<T>;
@@ -624,6 +672,42 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
       // the mixer's diagonal, indexed by the Hamming weight of the state index
       const uint64_t y0 = base | off(elem<CM, T>(t, 0u));
       middle<R, T, NV, CM, MID>(a, sp, phi, lam, llut, lval, PopIdx<T, CM>{(uint32_t)__popcll(y0)}, w, acc);
+    } else if constexpr (OP == 4) {
+      // the per-qubit multi-angle diagonal (shape 1, kinds 1 and 4)
+      const uint64_t y0 = base | off(elem<CM, T>(t, 0u));
+      double ma_t = 0.0, ma_u[G::RB];
+      middle_ma<R, T, NV, KIND == 4>(phi, lam, llut, (const double2 *)a.vals + (size_t)q * 33, y0, w, ma_t, ma_u);
+      if constexpr (KIND == 4) {
+        // per-qubit sums, reduced here (the table area of LDS is free in these passes): the
+        // total, the register-bit sums, and the thread-bit sums (thread bit i: the total of
+        // the threads with bit i set), one at a time in a fixed order; a qubit on the tile
+        // index takes the total or zero
+        constexpr int NS = 1 + G::RB + 8;
+        double *red = (double *)ltab;
+#pragma unroll
+        for (int k = 0; k < NS; k++) {
+          double v = k == 0 ? ma_t : (k <= G::RB ? ma_u[k - 1] : (((t >> (k - 1 - G::RB)) & 1u) ? ma_t : 0.0));
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          if ((t & 63) == 0) red[(t >> 6) * NS + k] = v;
+        }
+        __syncthreads();
+        if (t <= (uint32_t)a.n) {
+          auto tot = [&](int k) { return (red[k] + red[NS + k]) + (red[2 * NS + k] + red[3 * NS + k]); };
+          double val;
+          int64_t slot;
+          if (t == (uint32_t)a.n) {
+            val = tot(0);
+            slot = a.ma_total;
+          } else {
+            const int src = a.ma_src[t];
+            if (src < 8) val = tot(1 + src);
+            else if (src < 16) val = tot(1 + G::RB + (src - 8));
+            else val = ((base >> t) & 1ull) ? tot(0) : 0.0;
+            slot = a.ma_slot + (int64_t)t * a.ma_stride;
+          }
+          a.partials[slot + (int64_t)q * a.nwg + b] = val;
+        }
+      }
     } else if constexpr (OP == 3) {
       // the mixer's diagonal, indexed by the parities of the state index against the masks
       const uint64_t y0 = base | off(elem<CM, T>(t, 0u));

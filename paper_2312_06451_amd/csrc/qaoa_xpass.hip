@@ -26,6 +26,7 @@ hipError_t hpass_shape(const PassArgs<R> &a, int shape, int mixd, hipStream_t s)
     if (shape == 1) {
       if (mixd == XD_POPCOUNT) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 2>(a, s);
       if (mixd == XD_TERMS) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 3>(a, s);
+      if (mixd == XD_QUBIT) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 4>(a, s);
       if (mixd != 0) return hipErrorInvalidValue;
       return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 1>(a, s);
     }

@@ -295,3 +295,34 @@ def test_multiangle_full_size_against_stored_oracle_values(q, ctx):
         assert abs(e[0, 0] - rec["expect"]) <= TOL[prec] * G["table_max"]
         g0 = np.array(rec["grad"])
         assert np.max(np.abs(gr[0, 0] - g0)) <= TOL[prec] * np.max(np.abs(g0))
+
+
+@pytest.mark.parametrize("n,p,nsets", [(13, 2, 2), (14, 2, 3), (23, 2, 2)])
+def test_multiangle_on_tile_passes(q, monkeypatch, n, p, nsets):
+    """Per-qubit multi-angle mixers on the tile passes (diagonal factored into a per-thread and
+    a per-register part, n + 1 gradient sums per layer) against the transform path
+    (QAOA_XPROD_TILES=0), complex64 and complex128, and against the FP64 oracle at n <= 14."""
+    g = workloads.erdos_renyi(n, 2920 + n, 0.3, (1, 3))
+    t = oracle.graph_table(g)
+    A = np.random.default_rng(2921 + n).uniform(0.0, np.pi, size=(nsets, p * (n + 1)))
+    res = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("QAOA_XPROD_TILES", mode)
+        c = q.Context(0)
+        try:
+            P, M = q.Problem.from_graph(c, g), q.Mixer.x_multiangle(c, n)
+            res[mode] = [q.expect_grad_batched([P], [M], A, precision=prec) for prec in (0, 1)]
+        finally:
+            c.close()
+    scale = float(np.max(np.abs(t)))
+    for prec in (0, 1):
+        (e1, g1), (e0, g0) = res["1"][prec], res["0"][prec]
+        assert g1.shape == (1, nsets, p * (n + 1))
+        assert np.max(np.abs(e1 - e0)) <= TOL[prec] * scale, prec
+        assert np.max(np.abs(g1 - g0)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3), prec
+    if n <= 14:
+        E, Nr, gref = X.grad(n, t, A[0], multiangle=True)
+        for prec in (0, 1):
+            e1, g1 = res["1"][prec]
+            assert abs(e1[0, 0] - E / Nr) <= TOL[prec] * scale
+            assert np.max(np.abs(g1[0, 0] - gref / Nr)) <= TOL[prec] * max(np.max(np.abs(gref)), 1e-3)
