@@ -534,7 +534,6 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       if (need > have) ckpt = false;
     }
   }
-  if (xm && grad && !ckpt) throw fail(QAOA_ERR_HIP, "internal: X-product tile passes need checkpoints");
   void *dphi = ckpt ? nullptr : ctx->phi.get(vbytes);
   unsigned char *dck = ckpt ? (unsigned char *)ctx->ckpt.get((size_t)npf_est * vbytes) : nullptr;
   // forward pass j writes checkpoint j (or the single in-place buffer)
@@ -1967,27 +1966,16 @@ static void evaluate_xprod(qaoa_problem *prob, const qaoa_mixer *mix, int p, con
   const int m = qb ? n : 1, slen = p * (m + 1);
   const int lut_cost = (int)prob->max_value + 1;
   if (lut_cost > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
-  // Tile passes (Y-rotation basis change): single-angle mixers (diagonal by Hamming weight or
-  // by parities against term masks), states larger than one tile, the gradient's checkpoints
-  // within half the free memory (the rule of the transverse-field path)
+  // Tile passes (Y-rotation basis change) for states larger than one tile: the gradient reads
+  // the forward checkpoints when they fit (the rule of the transverse-field path), else undoes
+  // the state in place
   if (ctx->xprod_tiles && !d_state && (mix->xd.mode == XD_POPCOUNT || mix->xd.mode == XD_TERMS || qb) &&
       n > (precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64) && lut_cost <= MAX_LUT && mix->xlen <= MAX_LUT) {
-    bool fits = true;
-    if (grad) {
-      const int T = precision == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
-      const int K = (int)make_tiles(n, T, precision == QAOA_FP32 ? MIN_CONTIG_F32 : MIN_CONTIG_F64).size();
-      const size_t vbytes = (size_t)nsets * N * esz, need = (size_t)(1 + 2 * p * (K - 1)) * vbytes;
-      size_t fr = 0, tot = 0;
-      fits = ctx->checkpoint_mode != 0 && hipMemGetInfo(&fr, &tot) == hipSuccess &&
-             (ctx->checkpoint_mode == 1 || need + vbytes <= (fr + ctx->ckpt.cap) / 2) && need <= fr + ctx->ckpt.cap;
-    }
-    if (fits) {
-      if (precision == QAOA_FP32)
-        run_x_path<float>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, nullptr, st, mix);
-      else
-        run_x_path<double>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, nullptr, st, mix);
-      return;
-    }
+    if (precision == QAOA_FP32)
+      run_x_path<float>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, nullptr, st, mix);
+    else
+      run_x_path<double>(prob, p, angles, nsets, d_psi0, grad, out_expect, out_grad, nullptr, st, mix);
+    return;
   }
   const int bsums = qb ? 33 : 1;  // sums per beta layer: total and per-bit (per-qubit angles) or one
   const int nout = 2 + p * bsums + p;

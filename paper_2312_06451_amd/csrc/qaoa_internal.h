@@ -177,7 +177,7 @@ hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape
 hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
                            hipStream_t s);
 // The same passes with Y rotations and no X-pair terms (X-product mixers, qaoa_xpass.hip):
-// kinds 1 (shapes 0, 1, 2, 3), 3 (shape 1) and 4 (shapes 0, 1, 3); mixd (kind 1 or 4, shape 1):
+// kinds 1 (shapes 0, 1, 2, 3), 3 (shape 1), 2 and 4 (shapes 0, 1, 3); mixd (kinds 1, 2, 4, shape 1):
 // 0 = the middle's diagonal is the cost's, XD_POPCOUNT / XD_TERMS = the mixer's, indexed by the
 // Hamming weight of the state index / by its parities against PassArgs::xmasks.
 hipError_t launch_hpass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes, int mixd,

@@ -676,8 +676,9 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
       // the per-qubit multi-angle diagonal (shape 1, kinds 1 and 4)
       const uint64_t y0 = base | off(elem<CM, T>(t, 0u));
       double ma_t = 0.0, ma_u[G::RB];
-      middle_ma<R, T, NV, KIND == 4>(phi, lam, llut, (const double2 *)a.vals + (size_t)q * 33, y0, w, ma_t, ma_u);
-      if constexpr (KIND == 4) {
+      middle_ma<R, T, NV, KIND == 2 || KIND == 4>(phi, lam, llut, (const double2 *)a.vals + (size_t)q * 33, y0, w,
+                                                   ma_t, ma_u);
+      if constexpr (KIND == 2 || KIND == 4) {
         // per-qubit sums, reduced here (the table area of LDS is free in these passes): the
         // total, the register-bit sums, and the thread-bit sums (thread bit i: the total of
         // the threads with bit i set), one at a time in a fixed order; a qubit on the tile

@@ -46,6 +46,7 @@ hipError_t hpass_sx(const PassArgs<R> &a, int sx, int shape, int mixd, hipStream
 template <typename R, int T, typename TT>
 hipError_t hpass_kind(const PassArgs<R> &a, int kind, int sx, int shape, int mixd, hipStream_t s) {
   if (kind == 1) return hpass_sx<R, T, 1, TT>(a, sx, shape, mixd, s);
+  if (kind == 2) return hpass_sx<R, T, 2, TT>(a, sx, shape, mixd, s);
   if (kind == 3) return hpass_sx<R, T, 3, TT>(a, sx, shape, mixd, s);
   if (kind == 4) return hpass_sx<R, T, 4, TT>(a, sx, shape, mixd, s);
   return hipErrorInvalidValue;

@@ -326,3 +326,39 @@ def test_multiangle_on_tile_passes(q, monkeypatch, n, p, nsets):
             e1, g1 = res["1"][prec]
             assert abs(e1[0, 0] - E / Nr) <= TOL[prec] * scale
             assert np.max(np.abs(g1[0, 0] - gref / Nr)) <= TOL[prec] * max(np.max(np.abs(gref)), 1e-3)
+
+
+@pytest.mark.parametrize("kind", ["orders", "terms", "multiangle"])
+def test_tile_passes_in_place_sweep(q, monkeypatch, kind):
+    """The X-product tile passes' gradient with the reverse sweep undoing the state in place
+    (QAOA_GRAD_CHECKPOINT=0, the fallback when the forward checkpoints do not fit) against the
+    sweep that reads the checkpoints and against the transform path, both precisions."""
+    n, p = 15, 2
+    g = workloads.erdos_renyi(n, 2950, 0.3, (1, 2))
+    t = oracle.graph_table(g)
+    width = p * (n + 1) if kind == "multiangle" else 2 * p
+    A = np.random.default_rng(2951).uniform(0.0, np.pi, size=(2, width))
+
+    def mixer(c):
+        if kind == "orders":
+            return q.Mixer.x_orders(c, n, [1, 2])
+        if kind == "terms":
+            return q.Mixer.x_terms(c, n, [0b111, 1 << 14, (1 << 15) - 1], [0.5, -1.0, 0.25])
+        return q.Mixer.x_multiangle(c, n)
+
+    res = {}
+    for tiles, ckpt in (("1", "0"), ("1", "1"), ("0", "1")):
+        monkeypatch.setenv("QAOA_XPROD_TILES", tiles)
+        monkeypatch.setenv("QAOA_GRAD_CHECKPOINT", ckpt)
+        c = q.Context(0)
+        try:
+            P, M = q.Problem.from_graph(c, g), mixer(c)
+            res[(tiles, ckpt)] = [q.expect_grad_batched([P], [M], A, precision=prec) for prec in (0, 1)]
+        finally:
+            c.close()
+    scale = float(np.max(np.abs(t)))
+    for ref in (("1", "1"), ("0", "1")):
+        for prec in (0, 1):
+            (e1, g1), (e0, g0) = res[("1", "0")][prec], res[ref][prec]
+            assert np.max(np.abs(e1 - e0)) <= TOL[prec] * scale, (ref, prec)
+            assert np.max(np.abs(g1 - g0)) <= TOL[prec] * max(np.max(np.abs(g0)), 1e-3), (ref, prec)
