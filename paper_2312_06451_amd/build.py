@@ -29,8 +29,9 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".cpp") and src not in HOST_ONLY else []
-        cmd = [HIPCC] + FLAGS + lang + ["-I", os.path.join(ROOT, "include"), "-c",
-                                        os.path.join(CSRC, src), "-o", obj]
+        omp = ["-fopenmp"] if src in HOST_ONLY else []  # the optimiser's per-run updates
+        cmd = [HIPCC] + FLAGS + lang + omp + ["-I", os.path.join(ROOT, "include"), "-c",
+                                              os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -48,8 +49,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     if failed:
         raise RuntimeError("compilation failed: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + \
-          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lhipblaslt"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-fopenmp", "-o", tmp] + objs + \
+          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lhipblaslt", "-Wl,-rpath,/opt/rocm/llvm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

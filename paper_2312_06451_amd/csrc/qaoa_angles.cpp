@@ -319,6 +319,8 @@ struct Stepper {
       own[a] = live[a]->owner;
     }
     obj.eval(L, own.data(), pts.data(), fv.data(), gv.data());
+    // the runs are independent: their O(D^2) updates on the host cores
+#pragma omp parallel for schedule(static) if (L >= 32)
     for (int a = 0; a < L; a++) advance(*live[a], fv[a], &gv[(size_t)a * D], D, o);
   }
 };
