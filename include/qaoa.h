@@ -59,10 +59,15 @@ extern "C" {
 
 typedef struct qaoa_ctx qaoa_ctx;         /* one HIP device + reusable scratch         */
 typedef struct qaoa_problem qaoa_problem; /* cost diagonal C(x) over the feasible set   */
-typedef struct qaoa_mixer qaoa_mixer;     /* H_M: transverse field or clique            */
+typedef struct qaoa_mixer qaoa_mixer;     /* H_M: transverse field, eigenbasis mixers (clique, ring, matrix), Grover, X products */
 
 /* Create a context on HIP device `hip_device` (>= 0). *out receives the handle.
- * INVALID_ARG for a bad device index or out == NULL; HIP on runtime failure. */
+ * INVALID_ARG for a bad device index or out == NULL; HIP on runtime failure.
+ * Read once here from the environment (both optional, for tests and memory-limited runs):
+ * QAOA_GRAD_CHECKPOINT = "0" never keep the forward passes' outputs for the gradient's
+ * reverse sweep (undo the state in place), "1" always keep them; unset: keep them when they
+ * fit in half the free device memory. QAOA_XPROD_TILES = "0" runs X-product and per-qubit
+ * mixers on separate Walsh-Hadamard and diagonal kernels instead of the tile passes. */
 int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
 
 /* Destroy a context and free its scratch. Problems and mixers created on it must be
