@@ -11,6 +11,7 @@
 // of that qubit's edges) or over the weight-k states (Gosper's order, Sec. 2.4).
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 #include "qaoa_internal.h"
 
@@ -60,11 +61,10 @@ __global__ __launch_bounds__(256) void k_hist_table(const TT *__restrict__ t, ui
 // wave-uniform data. With NW > 0 they are neighbour bitmasks, one per distinct edge weight w_j
 // (masks[q * NW + j], classes beyond the graph's padded with empty masks), and the cut changes
 // by (x_q ? -1 : 1) sum_j w_j (deg_j(q) - 2 popcount(mask_j(q) & x)) (an edge of q is cut after
-// the flip iff its endpoints agree before it). The walk is unrolled by 16: within a block of
-// 16 steps the first 15 flip qubits 0..3, whose masks are loaded once; only every 16th step
-// reads the masks of a higher qubit. With NW == 0, q's adjacency list (neighbour << 16 |
-// weight, CSR) is walked instead. The histogram lives in LDS; with PRIV each thread owns a
-// column of it.
+// the flip iff its endpoints agree before it). For 2^lo >= 64 the walk runs in blocks of 32
+// steps (below); shorter walks take the flips one by one. With NW == 0, q's adjacency list
+// (neighbour << 16 | weight, CSR) is walked instead. The histogram lives in LDS; with PRIV each
+// thread owns a column of it.
 template <int NW>
 struct QMasks {
   uint64_t mk[NW > 0 ? NW : 1];
@@ -116,44 +116,103 @@ __global__ __launch_bounds__(256) void k_enum_full(int n, int m, const int32_t *
         x ^= 1ull << q;
         bump(c);
       };
-      if (lo >= 4) {
-        // Block b covers steps 16b + 1 .. 16b + 15 (qubits 0..3) and the step 16(b + 1). Before
-        // step 16b + r the low four bits of x are G(r - 1) ^ 8 beta, with G(r) = r ^ (r >> 1)
-        // the Gray code and beta = b & 1, and the bits above stay fixed: with H = x & ~15,
-        //   popcount(mask & x) = popcount(mask & H) + popcount(mask & low bits),
-        // so each flip adds s (A_q - 2 K) with A_q = sum_j w_j (deg_j(q) - 2 popcount(mask_j(q)
-        // & H)) per block and lane, and s = (x_q ? -1 : 1), K = sum_j w_j popcount(mask_j(q)
-        // & low bits) wave-uniform.
-        const QMasks<NW> Qs[4] = {load(0), load(1), load(2), load(3)};
-        const uint64_t blocks = steps >> 4;
-        for (uint64_t b = 0; b < blocks; b++) {
-          const uint32_t beta = (uint32_t)(b & 1ull);
-          const uint64_t H = x & ~15ull;
-          int A[4];
+      if (lo >= 6) {
+        // Blocks of 32 steps. Steps 32b + 1 .. 32b + 31 flip qubits 0..4; before step 32b + r the
+        // low five bits of x are G(r - 1) ^ 16 beta (G(r) = r ^ (r >> 1), beta = b & 1) and the
+        // bits above, H, stay fixed. With popcount(mask & x) = popcount(mask & H) +
+        // popcount(mask & low bits), step r changes the cut by s A_q + u_r, where
+        //   A_q = sum_j w_j (deg_j(q) - 2 popcount(mask_j(q) & H))        (per lane),
+        //   u_r = -2 s sum_j w_j popcount(mask_j(q) & low bits)            (wave-uniform),
+        // s = +1 when bit q is 0 before the step. Blocks run in pairs (beta = 0, 1), so q, s and
+        // the low bits are compile-time and one step is one add of three terms plus one LDS
+        // atomic. The cut is carried as its LDS byte offset, cut * SC + the thread's column.
+        // Step 32(b + 1) flips a qubit Q >= 5 of H: its own cut change takes full popcounts,
+        // and A_q moves by -/+ 2 sum_j w_j [Q in mask_j(q)] as H gains or loses bit Q. Lane i
+        // of the wave holds qubit i's masks, read by Q with readlane (every lane is active on
+        // this path: the launch has a multiple of 64 threads).
+        constexpr uint32_t SC = PRIV ? 1024u : 4u;
+        const uint32_t col = PRIV ? threadIdx.x * 4u : 0u;
+        const int lane = threadIdx.x & 63;
+        uint32_t lmlo[NW], lmhi[NW];
+        int ldg[NW];
 #pragma unroll
-          for (int q = 0; q < 4; q++) {
-            int a = 0;
+        for (int j = 0; j < NW; j++) {
+          const uint64_t mk = lane < n ? masks[lane * NW + j] : 0ull;
+          lmlo[j] = (uint32_t)mk;
+          lmhi[j] = (uint32_t)(mk >> 32);
+          ldg[j] = lane < n ? mdeg[lane * NW + j] : 0;
+        }
+        const QMasks<NW> Qs[5] = {load(0), load(1), load(2), load(3), load(4)};
+        uint32_t U[2][32];
 #pragma unroll
-            for (int j = 0; j < NW; j++)
-              a += __mul24(w[j], __mul24(-2, (int)__builtin_popcountll(Qs[q].mk[j] & H)) + Qs[q].dg[j]);
-            A[q] = a;
-          }
+        for (int bt = 0; bt < 2; bt++)
 #pragma unroll
-          for (int r = 1; r < 16; r++) {
+          for (int r = 1; r < 32; r++) {
             const int q = __builtin_ctz(r);
-            const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (beta << 3);
+            const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (uint32_t)(bt << 4);
             int K = 0;
 #pragma unroll
             for (int j = 0; j < NW; j++) K += w[j] * __builtin_popcount((uint32_t)Qs[q].mk[j] & low);
-            const int t = A[q] - 2 * K;
-            c += ((low >> q) & 1u) ? -t : t;
-            bump(c);
+            U[bt][r] = ((low >> q) & 1u) ? (uint32_t)(2 * K) * SC : (uint32_t)(-2 * K) * SC;
+            asm volatile("" : "+s"(U[bt][r]));  // opaque: keeps u_r an added operand, not a subtraction
           }
-          x = H | (uint64_t)(8u ^ (beta << 3));  // low bits G(15) ^ 8 beta
-          if (b + 1 < blocks) {
-            const int q = __builtin_ctzll((b + 1) << 4);
-            flip(q, load(q));
+        uint64_t H = x;  // low five bits are 0 at the start
+        uint32_t A[5], nA[5];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+          int a = 0;
+#pragma unroll
+          for (int j = 0; j < NW; j++) a += w[j] * (Qs[q].dg[j] - 2 * (int)__builtin_popcountll(Qs[q].mk[j] & H));
+          A[q] = (uint32_t)a * SC;
+          nA[q] = 0u - A[q];
+        }
+        // cs is the LDS address itself (the histogram's base included), so a step's atomic takes it
+        // as is
+        typedef __attribute__((address_space(3))) unsigned int lds_u32;
+        uint32_t cs = (uint32_t)(size_t)(lds_u32 *)hist + (uint32_t)c * SC + col;
+        auto at = [&](uint32_t a) { __atomic_fetch_add((lds_u32 *)(size_t)a, 1u, __ATOMIC_RELAXED); };
+        auto block = [&](auto beta_c) {
+          constexpr uint32_t bt = decltype(beta_c)::value;
+#pragma unroll
+          for (int r = 1; r < 32; r++) {
+            const int q = __builtin_ctz(r);
+            const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (bt << 4);
+            cs = (cs + (((low >> q) & 1u) ? nA[q] : A[q])) + U[bt][r];
+            at(cs);
           }
+        };
+        // flip of qubit Q >= 5 with the low bits equal to lowx (wave-uniform)
+        auto flip_high = [&](int Q, uint32_t lowx) {
+          const uint32_t bit = (uint32_t)(H >> Q) & 1u;
+          int t = 0;
+#pragma unroll
+          for (int j = 0; j < NW; j++) {
+            const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)lmlo[j], Q);
+            const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)lmhi[j], Q);
+            const int dq = __builtin_amdgcn_readlane(ldg[j], Q);
+            const int pc = (int)(__builtin_popcount(mlo & (uint32_t)H) + __builtin_popcount(mhi & (uint32_t)(H >> 32)) +
+                                 __builtin_popcount(mlo & lowx));
+            t += __mul24(w[j], __mul24(-2, pc) + dq);
+          }
+          const int sgn = bit ? -(int)SC : (int)SC;  // s * SC
+          cs += (uint32_t)__mul24(sgn, t);
+#pragma unroll
+          for (int q = 0; q < 5; q++) {
+            int d = 0;
+#pragma unroll
+            for (int j = 0; j < NW; j++) d += w[j] * (int)((Qs[q].mk[j] >> Q) & 1ull);
+            A[q] += (uint32_t)__mul24(sgn, -2 * d);
+            nA[q] += (uint32_t)__mul24(sgn, 2 * d);
+          }
+          H ^= 1ull << Q;
+          at(cs);
+        };
+        const uint64_t pairs = steps >> 6;
+        for (uint64_t pr = 0; pr < pairs; pr++) {
+          block(std::integral_constant<uint32_t, 0>{});
+          flip_high(5, 16u);
+          block(std::integral_constant<uint32_t, 1>{});
+          if (pr + 1 < pairs) flip_high(__builtin_ctzll(pr + 1) + 6, 0u);
         }
       } else {
         for (uint64_t i = 1; i < steps; i++) {
@@ -369,6 +428,7 @@ hipError_t launch_enum_full(int n, int m, const int32_t *eu, const int32_t *ev, 
   const size_t lds = enum_full_lds(nbins, priv);
   const dim3 blocks((unsigned)((nthreads + 255) / 256));
   if (masks && nw != 1 && nw != 2 && nw != 4 && nw != 8) return hipErrorInvalidValue;
+  if (masks && lo >= 6 && (nthreads & 63)) return hipErrorInvalidValue;  // the block walk reads every lane
   const int k = masks ? nw : 0;
 #define QAOA_ENUM_CASE(P, NW)                                                                                 \
   if (priv == P && k == NW)                                                                                    \

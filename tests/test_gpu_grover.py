@@ -105,6 +105,39 @@ def test_table_free_degeneracies(q, ctx, n, k, wr):
         assert abs(e1 - e2) <= 1e-12 * abs(e2) and np.max(np.abs(g1 - g2)) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("n,kind", [(26, "reg3"), (27, "sparse"), (27, "sparse12")])
+def test_table_free_degeneracies_block_walk(q, ctx, n, kind):
+    # 2^(n-20) states per thread, walked in pairs of 32-step blocks; sparse graphs keep the
+    # histogram in per-thread columns (one or two edge-weight classes)
+    if kind == "reg3":
+        g = workloads.random_regular_graph(n, 3, 970 + n)
+    else:
+        g = workloads.erdos_renyi(n, 975 + n, 0.08, (1, 2) if kind == "sparse12" else None)
+    assert g.w.sum() <= 63
+    Pd = q.Problem.degeneracies_of_graph(ctx, g)
+    vals, cnt = Pd.degeneracies()
+    v0, c0 = oracle.degeneracies(oracle.graph_table(g, -1))
+    assert np.array_equal(vals, v0.astype(np.float64)) and np.array_equal(cnt, c0)
+
+
+@pytest.mark.parametrize("n,kind", [(30, "reg3"), (31, "dense"), (32, "sparse13")])
+def test_table_free_degeneracies_vs_table_histogram(q, ctx, n, kind):
+    # larger walks (2^10 .. 2^12 states per thread: every high-qubit flip of the block walk)
+    # against the histogram of the stored cost table, itself checked against the oracle above
+    if kind == "reg3":
+        g = workloads.random_regular_graph(n, 3, 980 + n)
+    elif kind == "dense":
+        g = workloads.erdos_renyi(n, 980 + n, 0.5, (1, 4))
+    else:
+        g = workloads.erdos_renyi(n, 980 + n, 0.07, (1, 3))
+    vals, cnt = q.Problem.degeneracies_of_graph(ctx, g).degeneracies()
+    Pt = q.Problem.from_graph(ctx, g)
+    vt, ct = Pt.degeneracies()
+    Pt.close()
+    assert np.array_equal(vals, vt) and np.array_equal(cnt, ct)
+    assert int(cnt.sum()) == 2 ** n
+
+
 def test_table_free_degeneracies_n34_moments(q, ctx):
     # over all 2^n strings the cut indicators of the edges are pairwise independent fair bits:
     # sum_c m_c = 2^n, sum_c c m_c = W 2^(n-1), sum_c (2c - W)^2 m_c = 2^n sum_e w_e^2
