@@ -182,6 +182,7 @@ struct qaoa_ctx {
   DevBuf phi, lam, ckpt, partials, params, luts, luts2, results, cnt, items, gitems, gamps;
   HostBuf hparams, hresults;
   MappedBuf small_out;  // results of the whole-state kernels
+  MappedBuf small_params;  // items and angles of the whole-state kernels, read by them in place
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -1070,12 +1071,25 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
   size_t ab = (size_t)nsets * 2 * p * sizeof(double);
   size_t off_a = (ib + 255) & ~size_t(255);
   size_t total = off_a + ab;
-  unsigned char *h = (unsigned char *)ctx->hparams.get(total);
+  // With p <= 1024 the angle set fits in LDS beside the state: the kernels copy it in at the
+  // start, so items and angles stay in mapped host memory and no copy precedes the launch (the
+  // previous call's kernels have finished: every call synchronises its stream before returning).
+  const int stage = p <= 1024 ? 1 : 0;
   HIPCHK(hipStreamSynchronize(st));
-  std::memcpy(h, items.data(), ib);
-  std::memcpy(h + off_a, angles, ab);
-  unsigned char *d = (unsigned char *)ctx->items.get(total);
-  HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
+  unsigned char *d;
+  if (stage) {
+    ctx->small_params.get(total);
+    unsigned char *h = (unsigned char *)ctx->small_params.h;
+    std::memcpy(h, items.data(), ib);
+    std::memcpy(h + off_a, angles, ab);
+    d = (unsigned char *)ctx->small_params.d;
+  } else {
+    unsigned char *h = (unsigned char *)ctx->hparams.get(total);
+    std::memcpy(h, items.data(), ib);
+    std::memcpy(h + off_a, angles, ab);
+    d = (unsigned char *)ctx->items.get(total);
+    HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
+  }
   int nrow = 0;
   for (auto &it : items) nrow = std::max(nrow, it.out_index + 1);
   // the kernels write their result rows straight into mapped host memory
@@ -1101,7 +1115,7 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
     work(std::get<2>(g), std::get<3>(g), by, fl);
     KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
     HIPCHK(launch_whole(precision, std::get<0>(g), std::get<1>(g), ditems + std::get<2>(g), (int)std::get<3>(g),
-                        max_lut, dang, p, grad, dres, st));
+                        max_lut, dang, p, grad, dres, st, stage));
     kt.done();
   }
   if (items.size() > nwhole) {
@@ -1109,7 +1123,7 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
     work(nwhole, items.size() - nwhole, by, fl);
     KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
     HIPCHK(launch_small(precision, ditems + nwhole, (int)(items.size() - nwhole), max_n, max_tb, max_lut, dang, p,
-                        grad, dres, st));
+                        grad, dres, st, stage));
     kt.done();
   }
   HIPCHK(hipStreamSynchronize(st));

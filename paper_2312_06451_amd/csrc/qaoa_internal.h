@@ -186,9 +186,11 @@ hipError_t launch_hpass_f64(const PassArgs<double> &a, int kind, int sx, int sha
                            hipStream_t s);
 hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
                            int64_t nwg, int nout, double *out, hipStream_t s);
+// stage != 0 (launch_small, launch_whole): each workgroup first copies its angle set into LDS, so
+// items and angles may sit in mapped host memory (read once per workgroup, no copy beforehand).
 hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
                         int max_tbytes, int max_lut, const double *angles, int p, int grad,
-                        double *out, hipStream_t s);
+                        double *out, hipStream_t s, int stage = 0);
 // Index of the diagonal value of basis state y (XD_TABLE, XD_POPCOUNT, XD_TERMS).
 __device__ __forceinline__ uint32_t xdiag_index(const XDiag &d, uint64_t y) {
   if (d.mode == XD_TABLE)
@@ -242,7 +244,7 @@ int wht_min_bits(int precision);
 // every item must have that n and table width.
 bool whole_supported(int precision, int n);
 hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items, int n_items, int max_lut,
-                        const double *angles, int p, int grad, double *out, hipStream_t s);
+                        const double *angles, int p, int grad, double *out, hipStream_t s, int stage = 0);
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
                              double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);

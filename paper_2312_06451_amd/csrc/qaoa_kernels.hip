@@ -242,7 +242,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ items,
                                                const double *__restrict__ angles, int p, int grad,
                                                int max_n, int max_tb, int max_lut,
-                                               double *__restrict__ out) {
+                                               double *__restrict__ out, int stage) {
   using T2 = typename Cplx<R>::T2;
   extern __shared__ __align__(16) unsigned char smem[];
   const SmallItem it = items[blockIdx.x];
@@ -255,6 +255,13 @@ __global__ __launch_bounds__(256) void k_small(const SmallItem *__restrict__ ite
   double *red = (double *)(tab + ((((size_t)max_tb << max_n) + 15) & ~(size_t)15));
   const int tid = threadIdx.x;
   const double *ang = angles + (size_t)it.angle_set * 2 * p;
+  if (stage) {
+    // the angle set is read once into LDS (the caller may pass it in host memory)
+    double *sang = red + 8;
+    for (int i = tid; i < 2 * p; i += 256) sang[i] = ang[i];
+    __syncthreads();
+    ang = sang;
+  }
 
   for (uint32_t x = tid; x < N; x += 256) {
     if (it.tbytes == 1) ((unsigned char *)tab)[x] = ((const unsigned char *)it.table)[x];
@@ -466,7 +473,8 @@ __device__ __forceinline__ double w_rev_mixer(typename Cplx<R>::T2 *phi, typenam
 
 template <typename R, int T, typename TT>
 __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ items, const double *__restrict__ angles,
-                                               int p, int grad, int max_lut, int pre, double *__restrict__ out) {
+                                               int p, int grad, int max_lut, int pre, double *__restrict__ out,
+                                               int stage) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
   constexpr int RN = G::RN;
@@ -486,6 +494,13 @@ __global__ __launch_bounds__(256) void k_whole(const SmallItem *__restrict__ ite
   const SmallItem it = items[blockIdx.x];
   const uint32_t t = threadIdx.x;
   const double *ang = angles + (size_t)it.angle_set * 2 * p;
+  if (stage) {
+    // the angle set is read once into LDS (the caller may pass it in host memory)
+    double *sang = gsum + (pre ? 8 * p : 0);
+    for (int i = t; i < 2 * p; i += 256) sang[i] = ang[i];
+    __syncthreads();
+    ang = sang;
+  }
 
   for (uint32_t i = t; i < N * sizeof(TT) / 4; i += 256) ((uint32_t *)tab)[i] = ((const uint32_t *)it.table)[i];
   for (int c = t; c < it.lut_len; c += 256) dval[c] = it.vals[c];
@@ -901,10 +916,15 @@ hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int
 
 hipError_t launch_small(int precision, const SmallItem *items, int n_items, int max_n,
                         int max_tbytes, int max_lut, const double *angles, int p, int grad,
-                        double *out, hipStream_t s) {
+                        double *out, hipStream_t s, int stage) {
   size_t esz = precision == 0 ? 8 : 16;
   size_t lds = (2ull << max_n) * esz + (size_t)max_lut * esz +
                ((((size_t)max_tbytes << max_n) + 15) & ~(size_t)15) + 64;
+  // a staged angle set that does not fit is read in place instead
+  const size_t angb = (size_t)2 * p * sizeof(double);
+  if (stage && lds + angb > 160 * 1024) stage = 0;
+  if (stage) lds += angb;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)k_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -916,16 +936,16 @@ hipError_t launch_small(int precision, const SmallItem *items, int n_items, int 
   }
   if (precision == 0)
     hipLaunchKernelGGL((k_small<float>), dim3(n_items), dim3(256), lds, s, items, angles, p, grad,
-                       max_n, max_tbytes, max_lut, out);
+                       max_n, max_tbytes, max_lut, out, stage);
   else
     hipLaunchKernelGGL((k_small<double>), dim3(n_items), dim3(256), lds, s, items, angles, p,
-                       grad, max_n, max_tbytes, max_lut, out);
+                       grad, max_n, max_tbytes, max_lut, out, stage);
   return hipGetLastError();
 }
 
 template <typename R, int T, typename TT>
 static hipError_t launch_whole_t(const SmallItem *items, int n_items, int max_lut, const double *angles, int p,
-                                 int grad, double *out, hipStream_t s) {
+                                 int grad, double *out, hipStream_t s, int stage) {
   using T2 = typename Cplx<R>::T2;
   constexpr size_t N = size_t(1) << T;
   const size_t base = (N + (N >> Pad<R>::PS)) * sizeof(T2) + (size_t)max_lut * (sizeof(T2) + sizeof(double)) +
@@ -934,8 +954,11 @@ static hipError_t launch_whole_t(const SmallItem *items, int n_items, int max_lu
   // complex64 at n = 12 keeps two workgroups per CU below 80 KB
   const size_t with_pre = base + (size_t)2 * p * max_lut * sizeof(T2) + (size_t)14 * p * sizeof(double);
   const size_t cap = (sizeof(R) == 4 && T == 12) ? 80 * 1024 : 160 * 1024;
-  const int pre = grad && with_pre <= cap ? 1 : 0;
-  const size_t lds = pre ? with_pre : base + 64;
+  // the staged angle set sits after everything else; one that does not fit is read in place
+  if (stage && base + 64 + (size_t)2 * p * sizeof(double) > 160 * 1024) stage = 0;
+  const size_t angb = stage ? (size_t)2 * p * sizeof(double) : 0;
+  const int pre = grad && with_pre + angb <= cap ? 1 : 0;
+  const size_t lds = (pre ? with_pre : base + 64) + angb;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)k_whole<R, T, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -944,24 +967,25 @@ static hipError_t launch_whole_t(const SmallItem *items, int n_items, int max_lu
     attr_set = true;
   }
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_whole<R, T, TT>), dim3(n_items), dim3(256), lds, s, items, angles, p, grad, max_lut, pre, out);
+  hipLaunchKernelGGL((k_whole<R, T, TT>), dim3(n_items), dim3(256), lds, s, items, angles, p, grad, max_lut, pre, out,
+                     stage);
   return hipGetLastError();
 }
 
 bool whole_supported(int precision, int n) { return precision == 0 ? (n == 12 || n == 13) : n == 12; }
 
 hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items, int n_items, int max_lut,
-                        const double *angles, int p, int grad, double *out, hipStream_t s) {
+                        const double *angles, int p, int grad, double *out, hipStream_t s, int stage) {
   if (precision == 0) {
     if (n == 12)
-      return tbytes == 1 ? launch_whole_t<float, 12, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s)
-                         : launch_whole_t<float, 12, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s);
+      return tbytes == 1 ? launch_whole_t<float, 12, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s, stage)
+                         : launch_whole_t<float, 12, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s, stage);
     if (n == 13)
-      return tbytes == 1 ? launch_whole_t<float, 13, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s)
-                         : launch_whole_t<float, 13, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s);
+      return tbytes == 1 ? launch_whole_t<float, 13, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s, stage)
+                         : launch_whole_t<float, 13, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s, stage);
   } else if (n == 12) {
-    return tbytes == 1 ? launch_whole_t<double, 12, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s)
-                       : launch_whole_t<double, 12, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s);
+    return tbytes == 1 ? launch_whole_t<double, 12, uint8_t>(items, n_items, max_lut, angles, p, grad, out, s, stage)
+                       : launch_whole_t<double, 12, uint16_t>(items, n_items, max_lut, angles, p, grad, out, s, stage);
   }
   return hipErrorInvalidValue;
 }
