@@ -117,6 +117,25 @@ def test_small_edges(q, ctx, n, prec):
     assert np.max(np.abs(gr - g0 / N0)) <= TOL[prec][1] * max(1.0, np.max(np.abs(g0)))
 
 
+@pytest.mark.parametrize("n,p,prec", [(10, 1024, 0), (10, 1025, 1), (12, 1024, 0), (12, 1025, 0), (12, 1024, 1),
+                                      (13, 1024, 0)])
+def test_small_parameter_staging_boundary(q, ctx, n, p, prec):
+    # p <= 1024: the whole-state kernels read their items and angle sets from host memory
+    # (the angle set staged in LDS); p > 1024: both are copied to device memory first. FP32
+    # bound: each of the p layers adds at most ~1.2e-7 relative rounding to the amplitudes,
+    # so 2e-4 at p = 1024 (the usual 1e-5 is for p <= 100); FP64 keeps its bounds.
+    g = workloads.erdos_renyi(n, 60 + n, 0.4)
+    t = oracle.graph_table(g)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+    a = np.random.default_rng(90 + p + n).uniform(0.0, np.pi, 2 * p)
+    E0, N0, g0 = oracle.grad(n, t, a)
+    e, gr = q.expect_grad(P, M, a, precision=prec)
+    te, tg = TOL[prec] if prec == 1 else (2e-4, 2e-4)
+    assert _rel(e, E0 / N0) < te
+    assert _gerr(gr, g0 / N0) < tg
+    assert _rel(q.expect(P, M, a, precision=prec), E0 / N0) < te
+
+
 # ---------------------------------------------------------------- tile path (n > 13)
 
 TILE_CASES = [(14, 1, 0), (14, 2, 1), (16, 3, 0), (17, 2, 1), (20, 4, 0), (21, 3, 0), (22, 2, 0),
