@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_hist_table(const TT *__restrict__ t, ui
 // (masks[q * NW + j], classes beyond the graph's padded with empty masks), and the cut changes
 // by (x_q ? -1 : 1) sum_j w_j (deg_j(q) - 2 popcount(mask_j(q) & x)) (an edge of q is cut after
 // the flip iff its endpoints agree before it). For 2^lo >= 64 the walk runs in blocks of 32
-// steps (below); shorter walks take the flips one by one. With NW == 0, q's adjacency list
+// or 64 steps (walk_blocks); shorter walks take the flips one by one. With NW == 0, q's adjacency list
 // (neighbour << 16 | weight, CSR) is walked instead. The histogram lives in LDS; with PRIV each
 // thread owns a column of it.
 template <int NW>
@@ -70,6 +70,119 @@ struct QMasks {
   uint64_t mk[NW > 0 ? NW : 1];
   int dg[NW > 0 ? NW : 1];
 };
+
+// Walk of the 2^lo states from x (low bits zero, cut c) in blocks of 2^LB steps. Steps
+// 2^LB b + 1 .. 2^LB b + 2^LB - 1 flip qubits 0..LB-1; before step 2^LB b + r the low LB bits of
+// x are G(r - 1) ^ 2^(LB-1) beta (G(r) = r ^ (r >> 1), beta = b & 1) and the bits above, H, stay
+// fixed. With popcount(mask & x) = popcount(mask & H) + popcount(mask & low bits), step r
+// changes the cut by s A_q + u_r, where
+//   A_q = sum_j w_j (deg_j(q) - 2 popcount(mask_j(q) & H))        (per lane),
+//   u_r = -2 s sum_j w_j popcount(mask_j(q) & low bits)            (wave-uniform),
+// s = +1 when bit q is 0 before the step. Blocks run in pairs (beta = 0, 1), so q, s and the
+// low bits are compile-time and one step is one add of three terms plus one LDS atomic. The
+// cut is carried as its LDS byte address, cut * SC + the thread's column. Step 2^LB (b + 1)
+// flips a qubit Q >= LB of H: its own cut change takes full popcounts, and A_q moves by
+// -/+ 2 sum_j w_j [Q in mask_j(q)] as H gains or loses bit Q. Lane i of the wave holds qubit
+// i's masks, read by Q with readlane (every lane is active: the launch has a multiple of 64
+// threads). The u_r live in scalar registers for LB = 5 and in vector registers for LB = 6.
+template <int LB, bool PRIV, int NW>
+__device__ __forceinline__ void walk_blocks(uint64_t x, int c, uint64_t steps, int n, const uint64_t *__restrict__ masks,
+                                            const int32_t *__restrict__ mdeg, const int *w, unsigned int *hist) {
+  constexpr int BS = 1 << LB;
+  constexpr uint32_t SC = PRIV ? 1024u : 4u;
+  const uint32_t col = PRIV ? threadIdx.x * 4u : 0u;
+  const int lane = threadIdx.x & 63;
+  uint32_t lmlo[NW], lmhi[NW];
+  int ldg[NW];
+#pragma unroll
+  for (int j = 0; j < NW; j++) {
+    const uint64_t mk = lane < n ? masks[lane * NW + j] : 0ull;
+    lmlo[j] = (uint32_t)mk;
+    lmhi[j] = (uint32_t)(mk >> 32);
+    ldg[j] = lane < n ? mdeg[lane * NW + j] : 0;
+  }
+  QMasks<NW> Qs[LB];
+#pragma unroll
+  for (int q = 0; q < LB; q++)
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+      Qs[q].mk[j] = masks[q * NW + j];
+      Qs[q].dg[j] = mdeg[q * NW + j];
+    }
+  uint32_t U[2][BS];
+#pragma unroll
+  for (int bt = 0; bt < 2; bt++)
+#pragma unroll
+    for (int r = 1; r < BS; r++) {
+      const int q = __builtin_ctz(r);
+      const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (uint32_t)(bt << (LB - 1));
+      int K = 0;
+#pragma unroll
+      for (int j = 0; j < NW; j++) K += w[j] * __builtin_popcount((uint32_t)Qs[q].mk[j] & low);
+      U[bt][r] = ((low >> q) & 1u) ? (uint32_t)(2 * K) * SC : (uint32_t)(-2 * K) * SC;
+      // opaque: keeps u_r an added operand, not a subtraction, in the register file chosen
+      if constexpr (LB <= 5) asm volatile("" : "+s"(U[bt][r]));
+      else asm volatile("" : "+v"(U[bt][r]));
+    }
+  uint64_t H = x;  // low LB bits are 0 at the start
+  uint32_t A[LB], nA[LB];
+#pragma unroll
+  for (int q = 0; q < LB; q++) {
+    int a = 0;
+#pragma unroll
+    for (int j = 0; j < NW; j++) a += w[j] * (Qs[q].dg[j] - 2 * (int)__builtin_popcountll(Qs[q].mk[j] & H));
+    A[q] = (uint32_t)a * SC;
+    nA[q] = 0u - A[q];
+  }
+  // cs is the LDS address itself (the histogram's base included), so a step's atomic takes it
+  // as is
+  typedef __attribute__((address_space(3))) unsigned int lds_u32;
+  uint32_t cs = (uint32_t)(size_t)(lds_u32 *)hist + (uint32_t)c * SC + col;
+  auto at = [&](uint32_t a) { __atomic_fetch_add((lds_u32 *)(size_t)a, 1u, __ATOMIC_RELAXED); };
+  auto block = [&](auto beta_c) {
+    constexpr uint32_t bt = decltype(beta_c)::value;
+#pragma unroll
+    for (int r = 1; r < BS; r++) {
+      const int q = __builtin_ctz(r);
+      const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (bt << (LB - 1));
+      cs = (cs + (((low >> q) & 1u) ? nA[q] : A[q])) + U[bt][r];
+      at(cs);
+    }
+  };
+  // flip of qubit Q >= LB with the low bits equal to lowx (wave-uniform)
+  auto flip_high = [&](int Q, uint32_t lowx) {
+    const uint32_t bit = (uint32_t)(H >> Q) & 1u;
+    int t = 0;
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+      const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)lmlo[j], Q);
+      const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)lmhi[j], Q);
+      const int dq = __builtin_amdgcn_readlane(ldg[j], Q);
+      const int pc = (int)(__builtin_popcount(mlo & (uint32_t)H) + __builtin_popcount(mhi & (uint32_t)(H >> 32)) +
+                           __builtin_popcount(mlo & lowx));
+      t += __mul24(w[j], __mul24(-2, pc) + dq);
+    }
+    const int sgn = bit ? -(int)SC : (int)SC;  // s * SC
+    cs += (uint32_t)__mul24(sgn, t);
+#pragma unroll
+    for (int q = 0; q < LB; q++) {
+      int d = 0;
+#pragma unroll
+      for (int j = 0; j < NW; j++) d += w[j] * (int)((Qs[q].mk[j] >> Q) & 1ull);
+      A[q] += (uint32_t)__mul24(sgn, -2 * d);
+      nA[q] += (uint32_t)__mul24(sgn, 2 * d);
+    }
+    H ^= 1ull << Q;
+    at(cs);
+  };
+  const uint64_t pairs = steps >> (LB + 1);
+  for (uint64_t pr = 0; pr < pairs; pr++) {
+    block(std::integral_constant<uint32_t, 0>{});
+    flip_high(LB, 1u << (LB - 1));  // low bits after a beta = 0 block: G(2^LB - 1) = 2^(LB-1)
+    block(std::integral_constant<uint32_t, 1>{});
+    if (pr + 1 < pairs) flip_high(__builtin_ctzll(pr + 1) + LB + 1, 0u);
+  }
+}
 
 template <bool PRIV, int NW>
 __global__ __launch_bounds__(256) void k_enum_full(int n, int m, const int32_t *__restrict__ eu,
@@ -116,104 +229,10 @@ __global__ __launch_bounds__(256) void k_enum_full(int n, int m, const int32_t *
         x ^= 1ull << q;
         bump(c);
       };
-      if (lo >= 6) {
-        // Blocks of 32 steps. Steps 32b + 1 .. 32b + 31 flip qubits 0..4; before step 32b + r the
-        // low five bits of x are G(r - 1) ^ 16 beta (G(r) = r ^ (r >> 1), beta = b & 1) and the
-        // bits above, H, stay fixed. With popcount(mask & x) = popcount(mask & H) +
-        // popcount(mask & low bits), step r changes the cut by s A_q + u_r, where
-        //   A_q = sum_j w_j (deg_j(q) - 2 popcount(mask_j(q) & H))        (per lane),
-        //   u_r = -2 s sum_j w_j popcount(mask_j(q) & low bits)            (wave-uniform),
-        // s = +1 when bit q is 0 before the step. Blocks run in pairs (beta = 0, 1), so q, s and
-        // the low bits are compile-time and one step is one add of three terms plus one LDS
-        // atomic. The cut is carried as its LDS byte offset, cut * SC + the thread's column.
-        // Step 32(b + 1) flips a qubit Q >= 5 of H: its own cut change takes full popcounts,
-        // and A_q moves by -/+ 2 sum_j w_j [Q in mask_j(q)] as H gains or loses bit Q. Lane i
-        // of the wave holds qubit i's masks, read by Q with readlane (every lane is active on
-        // this path: the launch has a multiple of 64 threads).
-        constexpr uint32_t SC = PRIV ? 1024u : 4u;
-        const uint32_t col = PRIV ? threadIdx.x * 4u : 0u;
-        const int lane = threadIdx.x & 63;
-        uint32_t lmlo[NW], lmhi[NW];
-        int ldg[NW];
-#pragma unroll
-        for (int j = 0; j < NW; j++) {
-          const uint64_t mk = lane < n ? masks[lane * NW + j] : 0ull;
-          lmlo[j] = (uint32_t)mk;
-          lmhi[j] = (uint32_t)(mk >> 32);
-          ldg[j] = lane < n ? mdeg[lane * NW + j] : 0;
-        }
-        const QMasks<NW> Qs[5] = {load(0), load(1), load(2), load(3), load(4)};
-        uint32_t U[2][32];
-#pragma unroll
-        for (int bt = 0; bt < 2; bt++)
-#pragma unroll
-          for (int r = 1; r < 32; r++) {
-            const int q = __builtin_ctz(r);
-            const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (uint32_t)(bt << 4);
-            int K = 0;
-#pragma unroll
-            for (int j = 0; j < NW; j++) K += w[j] * __builtin_popcount((uint32_t)Qs[q].mk[j] & low);
-            U[bt][r] = ((low >> q) & 1u) ? (uint32_t)(2 * K) * SC : (uint32_t)(-2 * K) * SC;
-            asm volatile("" : "+s"(U[bt][r]));  // opaque: keeps u_r an added operand, not a subtraction
-          }
-        uint64_t H = x;  // low five bits are 0 at the start
-        uint32_t A[5], nA[5];
-#pragma unroll
-        for (int q = 0; q < 5; q++) {
-          int a = 0;
-#pragma unroll
-          for (int j = 0; j < NW; j++) a += w[j] * (Qs[q].dg[j] - 2 * (int)__builtin_popcountll(Qs[q].mk[j] & H));
-          A[q] = (uint32_t)a * SC;
-          nA[q] = 0u - A[q];
-        }
-        // cs is the LDS address itself (the histogram's base included), so a step's atomic takes it
-        // as is
-        typedef __attribute__((address_space(3))) unsigned int lds_u32;
-        uint32_t cs = (uint32_t)(size_t)(lds_u32 *)hist + (uint32_t)c * SC + col;
-        auto at = [&](uint32_t a) { __atomic_fetch_add((lds_u32 *)(size_t)a, 1u, __ATOMIC_RELAXED); };
-        auto block = [&](auto beta_c) {
-          constexpr uint32_t bt = decltype(beta_c)::value;
-#pragma unroll
-          for (int r = 1; r < 32; r++) {
-            const int q = __builtin_ctz(r);
-            const uint32_t low = (uint32_t)((r - 1) ^ ((r - 1) >> 1)) ^ (bt << 4);
-            cs = (cs + (((low >> q) & 1u) ? nA[q] : A[q])) + U[bt][r];
-            at(cs);
-          }
-        };
-        // flip of qubit Q >= 5 with the low bits equal to lowx (wave-uniform)
-        auto flip_high = [&](int Q, uint32_t lowx) {
-          const uint32_t bit = (uint32_t)(H >> Q) & 1u;
-          int t = 0;
-#pragma unroll
-          for (int j = 0; j < NW; j++) {
-            const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)lmlo[j], Q);
-            const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)lmhi[j], Q);
-            const int dq = __builtin_amdgcn_readlane(ldg[j], Q);
-            const int pc = (int)(__builtin_popcount(mlo & (uint32_t)H) + __builtin_popcount(mhi & (uint32_t)(H >> 32)) +
-                                 __builtin_popcount(mlo & lowx));
-            t += __mul24(w[j], __mul24(-2, pc) + dq);
-          }
-          const int sgn = bit ? -(int)SC : (int)SC;  // s * SC
-          cs += (uint32_t)__mul24(sgn, t);
-#pragma unroll
-          for (int q = 0; q < 5; q++) {
-            int d = 0;
-#pragma unroll
-            for (int j = 0; j < NW; j++) d += w[j] * (int)((Qs[q].mk[j] >> Q) & 1ull);
-            A[q] += (uint32_t)__mul24(sgn, -2 * d);
-            nA[q] += (uint32_t)__mul24(sgn, 2 * d);
-          }
-          H ^= 1ull << Q;
-          at(cs);
-        };
-        const uint64_t pairs = steps >> 6;
-        for (uint64_t pr = 0; pr < pairs; pr++) {
-          block(std::integral_constant<uint32_t, 0>{});
-          flip_high(5, 16u);
-          block(std::integral_constant<uint32_t, 1>{});
-          if (pr + 1 < pairs) flip_high(__builtin_ctzll(pr + 1) + 6, 0u);
-        }
+      if (lo >= 7) {
+        walk_blocks<6, PRIV, NW>(x, c, steps, n, masks, mdeg, w, hist);
+      } else if (lo >= 6) {
+        walk_blocks<5, PRIV, NW>(x, c, steps, n, masks, mdeg, w, hist);
       } else {
         for (uint64_t i = 1; i < steps; i++) {
           const int q = __builtin_ctzll(i);
