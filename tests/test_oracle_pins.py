@@ -223,6 +223,22 @@ def test_cycle_light_cone_pins_large_n(n, p):
         assert np.max(np.abs(g / Nr - n * fd)) < 1e-7 * n
 
 
+def test_light_cone_pins_weighted_regular_graph_p2():
+    """The same light cone on a graph that is not a cycle: a weighted random 3-regular graph
+    on 20 vertices at p = 2, where each edge's ball holds at most 14 qubits. Every edge term is
+    evolved on its ball with scipy's expm_multiply on the sparse sum of X; their weighted sum
+    pins the oracle's <C> and its adjoint gradient (central differences of the sum)."""
+    g = workloads.random_regular_graph(20, 3, 4200)
+    w = np.random.default_rng(4201).integers(1, 4, g.u.size).astype(np.int32)
+    t = oracle.cost_table(20, g.u, g.v, w)
+    for a in workloads.random_angles(2, 1, 4202):
+        E, Nr, gr = oracle.grad(20, t, a)
+        ev, fd = pins.light_cone_expect(20, g.u, g.v, w, 2, a)
+        scale = float(w.sum())
+        assert abs(E / Nr - ev) < 1e-10 * scale
+        assert np.max(np.abs(gr / Nr - fd)) < 1e-7 * scale
+
+
 # ---------------------------------------------------------------- clique mixer
 
 @pytest.mark.parametrize("n,k", [(4, 2), (6, 3), (7, 2)])
