@@ -141,12 +141,13 @@ def sparse_x_mixer_hamiltonian(m):
     return sp.csr_matrix((np.ones(N * m), (rows, cols)), shape=(N, N))
 
 
-def light_cone_expect(n, u, v, w, p, angles, h=1e-5):
+def light_cone_expect(n, u, v, w, p, angles, h=1e-5, components=None):
     """(<C>, gradient) of p-round QAOA for C = sum_e w_e [x_u != x_v] on the graph (u, v, w) at
     `angles` ([beta_1..p, gamma_1..p]). After p rounds the term of edge e involves only the
     qubits within distance p of e, and the phase terms of edges outside that ball commute with
     it, so each term is evolved on the subgraph induced by its ball (<= 2 + 4 + ... qubits on a
-    3-regular graph) from the uniform superposition."""
+    3-regular graph) from the uniform superposition. `components` limits the central
+    differences to those gradient entries (all by default; the others are returned as NaN)."""
     from scipy.sparse.linalg import expm_multiply
     u = np.asarray(u); v = np.asarray(v); w = np.asarray(w, dtype=np.float64)
     adj = [[] for _ in range(n)]
@@ -187,5 +188,8 @@ def light_cone_expect(n, u, v, w, p, angles, h=1e-5):
         return tot
 
     a = np.asarray(angles, dtype=np.float64)
-    g = np.array([(value(a + h * e) - value(a - h * e)) / (2 * h) for e in np.eye(2 * p)])
+    g = np.full(2 * p, np.nan)
+    for i in (range(2 * p) if components is None else components):
+        e = np.eye(2 * p)[i]
+        g[i] = (value(a + h * e) - value(a - h * e)) / (2 * h)
     return value(a), g

@@ -239,6 +239,26 @@ def test_light_cone_pins_weighted_regular_graph_p2():
         assert np.max(np.abs(gr / Nr - fd)) < 1e-7 * scale
 
 
+def test_light_cone_pins_circular_ladder_p3():
+    """p = 3 on a graph that is not a cycle: the circular ladder (prism) on 2 x 10 vertices,
+    3-regular with weights 1..3, where the ball of radius 3 around any edge holds 14 qubits
+    (8 consecutive rungs' worth, no wrap-around). <C> and the d/dbeta_1 entry of the gradient
+    from the light-cone sum."""
+    L = 10
+    u = [i for i in range(L)] + [i for i in range(L)] + [L + i for i in range(L)]
+    v = [(i + 1) % L for i in range(L)] + [L + i for i in range(L)] + [L + (i + 1) % L for i in range(L)]
+    u, v = np.array([min(a, b) for a, b in zip(u, v)]), np.array([max(a, b) for a, b in zip(u, v)])
+    w = np.random.default_rng(4301).integers(1, 4, u.size).astype(np.int32)
+    n = 2 * L
+    t = oracle.cost_table(n, u, v, w)
+    a = workloads.random_angles(3, 1, 4302)[0]
+    E, Nr, gr = oracle.grad(n, t, a)
+    ev, fd = pins.light_cone_expect(n, u, v, w, 3, a, components=[0])
+    scale = float(w.sum())
+    assert abs(E / Nr - ev) < 1e-10 * scale
+    assert abs(gr[0] / Nr - fd[0]) < 1e-7 * scale
+
+
 # ---------------------------------------------------------------- clique mixer
 
 @pytest.mark.parametrize("n,k", [(4, 2), (6, 3), (7, 2)])
