@@ -282,6 +282,31 @@ def test_full_size_cycle_light_cone(q, ctx):
             assert np.max(np.abs(gr - n * eg)) < max(TOL[prec][1], 1e-9) * n * np.max(np.abs(eg))
 
 
+def test_full_size_weighted_ladder_light_cone(q, ctx):
+    """Weighted MaxCut on the circular ladder with 2 x 14 = 28 vertices (3-regular, weights
+    1..3) at p = 3, in the n = 28 launch configuration of the benchmark, against the light-cone
+    sum: every edge term evolved on its ball of 14 qubits with scipy's expm_multiply (no
+    oracle). <C> in both precisions, and d/dbeta_1 against central differences of the sum."""
+    from tests import pins
+    L, p = 14, 3
+    ed = sorted({(min(a, b), max(a, b)) for i in range(L)
+                 for a, b in ((i, (i + 1) % L), (i, L + i), (L + i, L + (i + 1) % L))})
+    u = np.array([e[0] for e in ed], dtype=np.int32)
+    v = np.array([e[1] for e in ed], dtype=np.int32)
+    w = np.random.default_rng(4401).integers(1, 4, u.size).astype(np.int32)
+    n = 2 * L
+    g = workloads.Graph(n, u, v, w)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+    a = workloads.random_angles(p, 1, 4402)[0]
+    ev, eg = pins.light_cone_expect(n, u, v, w, p, a, components=[0])
+    for prec in (0, 1):
+        assert _rel(q.expect(P, M, a, precision=prec), ev) < TOL[prec][0]
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        assert _rel(e, ev) < TOL[prec][0]
+        # the central differences carry ~1e-9 of their own
+        assert abs(gr[0] - eg[0]) < max(TOL[prec][1] * np.max(np.abs(gr)), 1e-7 * float(w.sum()))
+
+
 def test_deterministic_repeat(q, c2):
     W, g, P, M = c2
     r1 = q.expect_grad(P, M, W.angles[0], precision=0)
