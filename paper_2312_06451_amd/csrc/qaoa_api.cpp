@@ -1075,7 +1075,6 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
   // start, so items and angles stay in mapped host memory and no copy precedes the launch (the
   // previous call's kernels have finished: every call synchronises its stream before returning).
   const int stage = p <= 1024 ? 1 : 0;
-  HIPCHK(hipStreamSynchronize(st));
   unsigned char *d;
   if (stage) {
     ctx->small_params.get(total);
@@ -1084,6 +1083,8 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
     std::memcpy(h + off_a, angles, ab);
     d = (unsigned char *)ctx->small_params.d;
   } else {
+    // the pinned staging buffer is shared with other calls' uploads: wait for them first
+    HIPCHK(hipStreamSynchronize(st));
     unsigned char *h = (unsigned char *)ctx->hparams.get(total);
     std::memcpy(h, items.data(), ib);
     std::memcpy(h + off_a, angles, ab);
