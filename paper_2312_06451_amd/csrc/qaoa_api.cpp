@@ -1690,7 +1690,9 @@ int qaoa_cost_degeneracies(qaoa_ctx *ctx, int n, int n_edges, const int32_t *u, 
     if (hamming_k < 0) {
       const int lo = std::max(0, std::min(24, n - 20));
       const uint64_t T = 1ull << (n - lo);
-      const bool priv = nbins <= 64;
+      // a private histogram column per thread while it fits in LDS (160 bins: one workgroup
+      // per CU above 80): contention-free atomics beat a shared histogram by 5-10x
+      const bool priv = nbins <= 160;
       for (uint64_t b0 = 0; b0 < T; b0 += LAUNCH)
         HIPCHK(launch_enum_full(n, n_edges, eu, ev, ew, d_off, d_adj, d_mask, d_mdeg, d_wv, nw, lo, b0,
                                 std::min(LAUNCH, T - b0), nbins, priv, d_cnt, st));

@@ -120,14 +120,19 @@ def test_table_free_degeneracies_block_walk(q, ctx, n, kind):
     assert np.array_equal(vals, v0.astype(np.float64)) and np.array_equal(cnt, c0)
 
 
-@pytest.mark.parametrize("n,kind", [(30, "reg3"), (31, "dense"), (32, "sparse13")])
+@pytest.mark.parametrize("n,kind", [(30, "reg3"), (31, "dense"), (32, "sparse13"), (30, "sparse14")])
 def test_table_free_degeneracies_vs_table_histogram(q, ctx, n, kind):
     # larger walks (2^10 .. 2^12 states per thread: every high-qubit flip of the block walk)
-    # against the histogram of the stored cost table, itself checked against the oracle above
+    # against the histogram of the stored cost table, itself checked against the oracle above;
+    # sparse13 (67 bins) and sparse14 (109 bins: one workgroup per CU) keep per-thread columns,
+    # dense (585 bins) the shared histogram
     if kind == "reg3":
         g = workloads.random_regular_graph(n, 3, 980 + n)
     elif kind == "dense":
         g = workloads.erdos_renyi(n, 980 + n, 0.5, (1, 4))
+    elif kind == "sparse14":
+        g = workloads.erdos_renyi(n, 950 + n, 0.09, (1, 4))
+        assert 80 < g.w.sum() + 1 <= 160
     else:
         g = workloads.erdos_renyi(n, 980 + n, 0.07, (1, 3))
     vals, cnt = q.Problem.degeneracies_of_graph(ctx, g).degeneracies()
