@@ -16,6 +16,11 @@
   evaluated on the vertices within distance p of its edge (the same light cone), with the
   mixer applied by ``scipy.sparse.linalg.expm_multiply`` on the sparse sum of X built entry
   by entry (not the oracle's qubit-by-qubit rotations); the gradient by central differences.
+* ``cycle_edge_blocks``: the cycle's edge term of ``cycle_edge`` at any depth (the path of
+  2p + 2 vertices: 18 qubits at p = 8, beyond dense 2^m x 2^m matrices), with the mixer
+  applied block by block: the X_q commute, so e^{-i b sum_q X_q} is the product over blocks
+  of at most 6 qubits of the dense matrix exponential of that block's sum of X (built from
+  Pauli Kronecker products), each applied to the state reshaped so the block is one axis.
 """
 from __future__ import annotations
 
@@ -186,6 +191,49 @@ def light_cone_expect(n, u, v, w, p, angles, h=1e-5, components=None):
                 psi = expm_multiply((-1j * a[k]) * H, psi)
             tot += float(np.sum(np.abs(psi) ** 2 * cut))
         return tot
+
+    a = np.asarray(angles, dtype=np.float64)
+    g = np.full(2 * p, np.nan)
+    for i in (range(2 * p) if components is None else components):
+        e = np.eye(2 * p)[i]
+        g[i] = (value(a + h * e) - value(a - h * e)) / (2 * h)
+    return value(a), g
+
+
+def _block_mixers(m, beta, block=6):
+    """[(lo, hi, expm(-i beta sum_{lo <= q < hi} X_q))] covering qubits 0..m-1."""
+    out = []
+    for lo in range(0, m, block):
+        hi = min(m, lo + block)
+        out.append((lo, hi, scipy.linalg.expm(-1j * beta * dense_x_mixer_hamiltonian(hi - lo))))
+    return out
+
+
+def _apply_block(psi, m, lo, hi, U):
+    """psi <- (I (x) U (x) I) psi with U on qubits lo..hi-1 (qubit q = bit q of the index)."""
+    t = psi.reshape(1 << (m - hi), 1 << (hi - lo), 1 << lo)
+    return np.einsum("ij,ajb->aib", U, t).reshape(-1)
+
+
+def cycle_edge_blocks(p, angles, h=1e-5, components=None, block=6):
+    """(value, gradient) of the cut probability of one edge of a cycle C_n, n >= 2p + 3, after
+    p rounds (the light cone of ``cycle_edge``: the middle edge of the path of 2p + 2
+    vertices), for any p. The mixer of each round is the product over qubit blocks of dense
+    block exponentials (``_block_mixers``). `components` limits the central differences to
+    those gradient entries (all by default; the others are NaN)."""
+    m = 2 * p + 2
+    xs = np.arange(1 << m)
+    bit = lambda q: (xs >> q) & 1
+    path_cost = sum(bit(i) ^ bit(i + 1) for i in range(m - 1)).astype(np.float64)
+    mid_cut = (bit(p) ^ bit(p + 1)).astype(np.float64)
+
+    def value(a):
+        psi = np.full(1 << m, 2.0 ** (-m / 2), dtype=np.complex128)
+        for r in range(p):
+            psi = np.exp(-1j * a[p + r] * path_cost) * psi
+            for lo, hi, U in _block_mixers(m, a[r], block):
+                psi = _apply_block(psi, m, lo, hi, U)
+        return float(np.sum(np.abs(psi) ** 2 * mid_cut))
 
     a = np.asarray(angles, dtype=np.float64)
     g = np.full(2 * p, np.nan)

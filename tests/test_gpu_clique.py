@@ -1,9 +1,10 @@
 """GPU parity of the constrained path: clique mixer on the Hamming-weight-k subspace,
 eigenbasis products (FP16-split MFMA products in the FP32 form, DGEMM in the FP64 form).
 
-Tolerances: FP32 form <C> 1e-5 relative and gradient 1e-5 of max|g|; FP64 form 1e-10
-(the eigendecomposition itself carries ~1e-13 relative error per eigenpair, which the 2p
-products compound)."""
+Tolerances: FP32 form <C> 1e-5 relative and gradient 1e-5 of max|g|; FP64 form 1e-12 for
+both (the eigendecomposition carries ~1e-13 relative error per eigenpair, which the 2p to
+4p products of an evaluation compound; measured at N = 12870: 1e-16 in <C>, 7e-13 in the
+gradient)."""
 import json
 import os
 from math import comb
@@ -16,7 +17,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-TOL = {0: 1e-5, 1: 1e-10}
+TOL = {0: 1e-5, 1: 1e-12}
 
 
 @pytest.fixture(scope="module")
@@ -56,7 +57,7 @@ def test_clique_state_and_initial_state(q, ctx):
     P, M = q.Problem.from_graph(ctx, g, hamming_k=k), q.Mixer.clique(ctx, n, k)
     a = workloads.random_angles(p, 1, 78)[0]
     want = oracle.state(n, t, a, k=k)
-    for prec, dt, tol in ((0, torch.complex64, 1e-5), (1, torch.complex128, 1e-10)):
+    for prec, dt, tol in ((0, torch.complex64, 1e-5), (1, torch.complex128, 1e-12)):
         out = torch.empty(comb(n, k), dtype=dt, device="cuda")
         q.state(P, M, a, out, precision=prec)
         torch.cuda.synchronize()

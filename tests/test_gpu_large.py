@@ -2,7 +2,8 @@
 workload, MaxCut on a random 3-regular graph. The host oracle cannot hold the state (64 GiB
 per FP64 vector), so parity here rests on properties that hold at any size: the p=1
 closed form and its derivative, the beta = 0 identities, the FP64 GPU path (compared
-component by component with the FP32 path at p=16), and sampled table entries."""
+component by component with the FP32 path at p=16), and the table against the oracle's
+definition at sampled strings plus its sum identity."""
 import numpy as np
 import pytest
 
@@ -24,8 +25,23 @@ def c5():
 
 
 def test_n32_table_sampled(c5):
+    """The 2^32-entry table (64-bit indexing) copied back whole: sampled entries on both sides
+    of 2^31 equal the oracle's definition evaluated at those strings, the complement pairs
+    agree, and the sum is the identity sum_x C(x) = W 2^(n-1)."""
     q, ctx, W, g, P, M = c5
     assert P.size == 1 << 32 and P.max_value <= g.m
+    t = P.table()
+    rng = np.random.default_rng(5100)
+    xs = np.concatenate([np.arange(0, 1 << 32, 1000003, dtype=np.uint64),
+                         rng.integers(1 << 31, 1 << 32, 20000, dtype=np.uint64),
+                         np.array([0, (1 << 31) - 1, 1 << 31, (1 << 32) - 1], dtype=np.uint64)])
+    want = oracle.cost_values(g.n, g.u, g.v, g.w, xs)
+    assert np.array_equal(t[xs.astype(np.int64)], want)
+    comp = (xs ^ np.uint64((1 << 32) - 1)).astype(np.int64)
+    assert np.array_equal(t[comp], want)
+    assert int(t.sum(dtype=np.int64)) == g.total_weight * 2 ** (g.n - 1)
+    assert int(t.max()) == P.max_value
+    del t
 
 
 def test_n32_p1_closed_form(c5):

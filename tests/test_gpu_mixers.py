@@ -1,7 +1,7 @@
 """GPU parity of the ring mixer and of mixers handed over as matrices (Sec. 2.1: mixers applied
 through a stored eigendecomposition), against the FP64 oracle (sparse Taylor series for the
 ring, dense expm for matrices). Tolerances as for the clique mixer: FP32 form 1e-5, FP64 form
-1e-10 (relative to max|C| for <C>, to max|g| for the gradient)."""
+1e-12 (relative to max|C| for <C>, to max|g| for the gradient)."""
 from math import comb
 
 import numpy as np
@@ -12,7 +12,7 @@ import workloads
 from tests import pins
 
 pytestmark = pytest.mark.gpu
-TOL = {0: 1e-5, 1: 1e-10}
+TOL = {0: 1e-5, 1: 1e-12}
 
 
 @pytest.fixture(scope="module")
@@ -147,8 +147,8 @@ def test_eigen_import_full_space_and_errors(q, ctx):
     for a in workloads.random_angles(2, 2, 1061):
         E0, N0, g0 = oracle.dense_mixer_grad(vals, a, H)
         e, gr = q.expect_grad(P, M, a, precision=1)
-        assert abs(e - E0 / N0) <= 1e-10 * np.max(np.abs(vals))
-        assert np.max(np.abs(gr - g0 / N0)) <= 1e-10 * np.max(np.abs(g0 / N0))
+        assert abs(e - E0 / N0) <= 1e-12 * np.max(np.abs(vals))
+        assert np.max(np.abs(gr - g0 / N0)) <= 1e-12 * np.max(np.abs(g0 / N0))
     with pytest.raises(q.QAOAError):
         q.Mixer.from_eigen(ctx, n, 2.0 * V, D)          # columns not of unit length
     with pytest.raises(q.QAOAError):

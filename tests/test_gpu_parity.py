@@ -282,6 +282,32 @@ def test_full_size_cycle_light_cone(q, ctx):
             assert np.max(np.abs(gr - n * eg)) < max(TOL[prec][1], 1e-9) * n * np.max(np.abs(eg))
 
 
+def test_full_size_cycle_light_cone_p8(q, ctx):
+    """MaxCut on the cycle C_28 at the benchmark's depth p = 8 and in its launch configuration
+    (n = 28 tile passes with the checkpoint-reading reverse sweep, complex64 and complex128)
+    against the light cone: <C> = 28 times the middle-edge cut probability of the path of 18
+    vertices (block-exponential mixer on 2^18 amplitudes, no oracle), and three gradient
+    entries against central differences of that value."""
+    from tests import pins
+    n, p = 28, 8
+    u = np.arange(n, dtype=np.int32)
+    v = (u + 1) % n
+    g = workloads.Graph(n, np.minimum(u, v).astype(np.int32), np.maximum(u, v).astype(np.int32),
+                        np.ones(n, dtype=np.int32))
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+    a = workloads.random_angles(p, 1, 4800)[0]
+    comps = [0, p - 1, p]
+    ev, eg = pins.cycle_edge_blocks(p, a, components=comps)
+    for prec in (0, 1):
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        assert _rel(e, n * ev) < TOL[prec][0]
+        scale = n * np.nanmax(np.abs(eg))
+        for i in comps:
+            # the central differences carry ~1e-10 of their own
+            assert abs(gr[i] - n * eg[i]) < max(TOL[prec][1], 1e-9) * scale
+    P.close(); M.close()
+
+
 def test_full_size_weighted_ladder_light_cone(q, ctx):
     """Weighted MaxCut on the circular ladder with 2 x 14 = 28 vertices (3-regular, weights
     1..3) at p = 3, in the n = 28 launch configuration of the benchmark, against the light-cone

@@ -259,6 +259,26 @@ def test_light_cone_pins_circular_ladder_p3():
     assert abs(gr[0] / Nr - fd[0]) < 1e-7 * scale
 
 
+def test_cycle_light_cone_pins_headline_depth():
+    """The light cone at the benchmark's depth p = 8: on the cycles C_20 and C_24 (both
+    >= 2p + 3) <C> is n times the middle-edge cut probability of the path of 18 vertices,
+    evolved with the mixer as a product of dense exponentials over blocks of qubits
+    (``pins.cycle_edge_blocks``; 2^18 amplitudes, no oracle code). Pins the oracle's <C> and
+    three entries of its adjoint gradient (d/dbeta_1, d/dbeta_8, d/dgamma_1; central
+    differences of the light-cone value) at the p of the headline workload."""
+    p = 8
+    a = workloads.random_angles(p, 1, 4800)[0]
+    comps = [0, p - 1, p]
+    ev, fd = pins.cycle_edge_blocks(p, a, components=comps)
+    for n in (20, 24):
+        u = np.arange(n)
+        t = oracle.cost_table(n, u, (u + 1) % n)
+        E, Nr, g = oracle.grad(n, t, a)
+        assert abs(E / Nr - n * ev) < 1e-10 * n
+        for i in comps:
+            assert abs(g[i] / Nr - n * fd[i]) < 1e-7 * n
+
+
 # ---------------------------------------------------------------- clique mixer
 
 @pytest.mark.parametrize("n,k", [(4, 2), (6, 3), (7, 2)])
