@@ -24,9 +24,11 @@ Other workloads (--workload):
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value            FP32-state evaluations per second (whole job, one GPU)
-  roofline         dominant kernel class: algorithmic bytes (or flops) per launch / mean launch
-                   time (HIP events on the launch stream, during the timed region) vs the
-                   MI355X peak (8 TB/s HBM; 2.5 PFLOP/s dense FP16 MFMA; 157.3 TFLOP/s FP32)
+  roofline         dominant kernel class: algorithmic bytes (the method's one-pass-per-round
+                   traffic) or flops per launch / mean launch time (HIP events on the launch
+                   stream, during the timed region) vs the MI355X peak (8 TB/s HBM; 2.5 PFLOP/s
+                   dense FP16 MFMA; 157.3 TFLOP/s FP32); the bytes the tile plan moves beside it
+  copy_roof        the library's streaming copy kernel over 2 GiB (the practical HBM roof)
   cpu_baseline     the FP64 CPU oracle on a bounded sample of the same workload
   fp64             the same kernels with a complex128 state (the plain FP64 GPU path)
   error            FP32 result vs FP64 oracle values
@@ -64,30 +66,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def copy_roof(torch, nbytes=2 << 30, reps=5):
-    """Measured device-to-device copy rate (read + write) of a 2 GiB buffer: the achievable
-    HBM rate of a streaming kernel, and the calibration kernel of the traffic counters."""
+def copy_roof(torch, q, _lib, nbytes=2 << 30, reps=20, warm=20):
+    """Measured rate (read + write) of the library's own streaming copy kernel
+    (``qaoa_stream_copy``: 16-byte non-temporal loads and stores, each byte read and written
+    once) over a 2 GiB buffer, timed with HIP events on the stream it is launched on: the HBM
+    rate a streaming kernel reaches on this device, and the calibration kernel of the traffic
+    counters."""
+    ctx = q.Context(0)
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    st = int(torch.cuda.current_stream().cuda_stream)
+    for _ in range(warm):                                # clocks settle before the timed copies
+        _lib.qaoa_stream_copy(ctx.handle, a.data_ptr(), b.data_ptr(), nbytes, st)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        _lib.qaoa_stream_copy(ctx.handle, a.data_ptr(), b.data_ptr(), nbytes, st)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a, b))
     del a, b
     torch.cuda.empty_cache()
-    return {"GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_read": nbytes, "bytes_written": nbytes, "ms": ms}
+    ctx.close()
+    return {"kernel": "k_stream_copy (qaoa_stream_copy)", "GBps": 2 * nbytes / (ms * 1e-3) / 1e9,
+            "frac_of_peak": 2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_read": nbytes,
+            "bytes_written": nbytes, "ms": ms, "copy_exact": ok}
 
 
 class Runner:
     """One workload on one context: single evaluations or one batched call per step."""
 
     def __init__(self, q, W):
+        import torch
+        from paper_2312_06451_amd.autograd import qaoa_expectation
         self.q, self.W = q, W
+        self.torch, self.qaoa_expectation = torch, qaoa_expectation
         self.ctx = q.Context(0)
         k = W.hamming_k
         self.problems = [q.Problem.from_graph(self.ctx, g, hamming_k=k) for g in W.graphs]
@@ -109,7 +124,11 @@ class Runner:
                 return q.expect_grad_batched(self.problems, self.mixers, W.angles, precision=prec)
             return q.expect_batched(self.problems, self.mixers, W.angles, precision=prec), None
         if grad:
-            return q.expect_grad(self.problems[0], self.mixers[0], W.angles[0], precision=prec)
+            # the torch.autograd.Function path: forward <C>, then backward() for the gradient
+            ang = self.torch.tensor(W.angles[0], dtype=self.torch.float64, requires_grad=True)
+            e = self.qaoa_expectation(ang, self.problems[0], self.mixers[0], prec)
+            e.backward()
+            return float(e), ang.grad.numpy()
         return q.expect(self.problems[0], self.mixers[0], W.angles[0], precision=prec), None
 
     def time(self, prec, grad, steps, warmup, torch):
@@ -219,25 +238,61 @@ KERNEL_NAMES = {"xmix": "k_pass<float,13,1|3|4,uint8,1..4> (tile passes with Y r
                 "dense": "hipBLASLt GEMM f16 x f16 -> f32 (split eigenbasis product, 2 calls)"}
 
 
-def roofline(prof, workload):
+def algorithmic_bytes(R, steps):
+    """SURVEY-model algorithmic HBM bytes of the timed region per kernel class: every round
+    moves each vector it touches once (one pass per round, the lower bound of the method), and
+    reads the cost table once per phase. Per amplitude, angle set and fwd+grad evaluation of a
+    tile-path instance (n above the whole-state kernels' 13 qubits): forward side
+    16p + (p + 1) tb, reverse side (state and adjoint vector) 32p + (p + 1) tb, tb = bytes per
+    table entry; for the X-product mixers each round is two half-rounds (diagonal + basis
+    change), so both sides double their vector bytes (one class covers both)."""
+    W, p = R.W, R.W.p
+    sets = W.angles.shape[0] if R.batched else 1
+    out = {"fwd_pass": 0.0, "rev_pass": 0.0, "xmix": 0.0}
+    for P in R.problems:
+        if P.n <= 13:
+            continue
+        tb = 1 if P.max_value <= 255 else 2
+        amps = float(sets) * 2.0 ** P.n * steps
+        if W.mixer in ("x_orders", "x_multiangle"):
+            out["xmix"] += amps * (2 * 16 * p + 2 * 32 * p + 2 * (p + 1) * tb)
+        else:
+            out["fwd_pass"] += amps * (16 * p + (p + 1) * tb)
+            out["rev_pass"] += amps * (32 * p + (p + 1) * tb)
+    return out
+
+
+def roofline(prof, workload, alg_bytes):
+    """Dominant kernel class of the timed region against its roof. HBM classes: `achieved` =
+    the class's algorithmic bytes (``algorithmic_bytes``) per launch / mean launch time (HIP
+    events on the launch stream), so `frac` is the fraction of the 8 TB/s peak at which the
+    method's lower-bound traffic would move; `moved_*` is the same time against the bytes the
+    tile plan actually moves (two passes per round at n = 28). MFMA class: algorithmic flops
+    of one FP32-accurate real product (2 N^2 x columns) per launch; the split form issues three
+    FP16 products per launch (`mfma_issued_*`)."""
     cls = max(("fwd_pass", "rev_pass", "small", "dense", "xmix"), key=lambda k: prof[k]["ms"])
     d = prof[cls]
     L = max(d["launches"], 1)
     mean_ms = d["ms"] / L
     base = {"kernel": KERNEL_NAMES[cls], "class": cls, "launches": d["launches"], "mean_ms": round(mean_ms, 4)}
     if cls in ("fwd_pass", "rev_pass", "xmix"):
-        bpl = d["bytes"] / L
-        a = bpl / (mean_ms * 1e-3) / 1e9
+        apl = alg_bytes[cls] / L
+        a = apl / (mean_ms * 1e-3) / 1e9
+        mpl = d["bytes"] / L
+        m = mpl / (mean_ms * 1e-3) / 1e9
         return dict({"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(a / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(workload, cls),
-                     "bytes_per_launch": bpl}, **base)
+                     "bytes_per_launch": apl, "bytes_model": "one pass per round (16p / 32p B per amplitude "
+                     "+ (p + 1) table reads per sweep)",
+                     "moved_bytes_per_launch": mpl, "moved_GBps": round(m, 1),
+                     "moved_frac": round(m / HBM_PEAK_GBS, 4)}, **base)
     if cls == "dense":
-        # one product = three FP16 MFMA products (hi*hi, hi*lo, lo*hi) of 2*N*N*cols flops each
-        fpl = 3.0 * d["flops"] / L
+        fpl = d["flops"] / L
         a = fpl / (mean_ms * 1e-3) / 1e12
         return dict({"bound": "mfma", "achieved": round(a, 1), "peak": MFMA_F16_PEAK_TFS, "unit": "TFLOP/s",
                      "frac": round(a / MFMA_F16_PEAK_TFS, 4), "traffic": None, "flops_per_launch": fpl,
-                     "fp32_equivalent_TFLOPs": round(a / 3.0, 1)}, **base)
+                     "mfma_issued_TFLOPs": round(3 * a, 1), "mfma_issued_frac": round(3 * a / MFMA_F16_PEAK_TFS, 4)},
+                    **base)
     return dict({"bound": "alu", "achieved": None, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
                  "frac": None, "traffic": None}, **base)
 
@@ -463,7 +518,7 @@ def main():
     warmup = min(args.warmup, 1) if W.name == "maxcut3reg_n32_p16" else args.warmup
     grad = W.name != "maxcut3reg_n10_p3"
 
-    roof_copy = copy_roof(torch)
+    roof_copy = copy_roof(torch, q, _lib)
     log(f"copy roof: {roof_copy['GBps']:.0f} GB/s")
     R = Runner(q, W)
     h = R.ctx.handle
@@ -540,7 +595,7 @@ def main():
                "fp64_expect_rel": max(ee64) if ee64 else None, "fp64_grad_inf_rel": max(ge64) if ge64 else None,
                "reference": f"FP64 CPU oracle, {len(ref)} evaluation(s)"}
 
-    roof = roofline(prof, W.name)
+    roof = roofline(prof, W.name, algorithmic_bytes(R, steps))
     path = None
     if W.mixer == "x" and len(W.graphs) == 1:
         g = W.graphs[0]

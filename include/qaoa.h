@@ -364,6 +364,15 @@ int qaoa_profile_enable(qaoa_ctx *ctx, int enable);
 int qaoa_profile_read(const qaoa_ctx *ctx, int kernel_class, int64_t *launches, double *ms,
                       double *bytes, double *flops);
 
+/* Measurement aid, not a step of the method: copies `bytes` from device buffer d_src to
+ * device buffer d_dst (both caller-owned, on the context's device, 16-byte aligned, not
+ * overlapping; bytes a multiple of 16, else INVALID_ARG) with the library's plain streaming
+ * kernel (each byte read once and written once: one 16-byte non-temporal load and store per
+ * thread). Its rate is the HBM roof a streaming kernel reaches on the device, and the
+ * calibration of the traffic counters.
+ * Enqueued on `stream`; does not synchronise. */
+int qaoa_stream_copy(qaoa_ctx *ctx, const void *d_src, void *d_dst, size_t bytes, void *stream);
+
 /* Static text for a status code. */
 const char *qaoa_status_string(int status);
 

@@ -29,7 +29,7 @@ EXPORTED = [
     "qaoa_mixer_eigen", "qaoa_mixer_from_eigen", "qaoa_angle_opts_default", "qaoa_minimize",
     "qaoa_basinhopping", "qaoa_find_angles", "qaoa_find_angles_random", "qaoa_find_angles_multi",
     "qaoa_expect_pairs", "qaoa_expect_grad_pairs", "qaoa_mixer_x_orders", "qaoa_mixer_x_terms",
-    "qaoa_mixer_x_multiangle", "qaoa_mixer_info",
+    "qaoa_mixer_x_multiangle", "qaoa_mixer_info", "qaoa_stream_copy",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
                   "count_states": 6, "xmix": 7}
@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
                                            c_int, P(c_double), P(c_double), c_void_p]
     L.qaoa_profile_enable.argtypes = [c_void_p, c_int]
     L.qaoa_profile_read.argtypes = [c_void_p, c_int, P(c_int64), P(c_double), P(c_double), P(c_double)]
+    L.qaoa_stream_copy.argtypes = [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     opts_p = P(qaoa_angle_opts)
     L.qaoa_angle_opts_default.argtypes = [opts_p]
     L.qaoa_minimize.argtypes = [c_void_p, c_void_p, c_int, c_int, P(c_double), P(c_double), P(c_int), opts_p,
@@ -418,6 +419,10 @@ def qaoa_profile_read(ctx: int, kernel_class: int) -> dict:
     check(lib().qaoa_profile_read(ctx, kernel_class, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
                                   ctypes.byref(fl)), "qaoa_profile_read")
     return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+
+def qaoa_stream_copy(ctx: int, src: int, dst: int, nbytes: int, stream: int = 0) -> None:
+    check(lib().qaoa_stream_copy(ctx, src, dst, nbytes, stream), "qaoa_stream_copy")
 
 
 # ---------------------------------------------------------------- angle finding

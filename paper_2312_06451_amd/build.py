@@ -19,8 +19,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source to an object (in parallel), then link the shared library."""
+def _stale(obj: str, src: str) -> bool:
+    """True when the object is missing or older than its source or any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "qaoa.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, jobs: int = 4, force: bool = True) -> str:
+    """Compile every source to an object (in parallel; with force=False only the objects older
+    than their sources or headers), then link the shared library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
@@ -28,6 +39,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
+        if not force and not _stale(obj, src):
+            continue
         lang = ["-x", "hip"] if src.endswith(".cpp") and src not in HOST_ONLY else []
         omp = ["-fopenmp"] if src in HOST_ONLY else []  # the optimiser's per-run updates
         cmd = [HIPCC] + FLAGS + lang + omp + ["-I", os.path.join(ROOT, "include"), "-c",
@@ -57,4 +70,4 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--changed" not in sys.argv))

@@ -1341,6 +1341,17 @@ int qaoa_profile_read(const qaoa_ctx *ctx, int kernel_class, int64_t *launches, 
   });
 }
 
+int qaoa_stream_copy(qaoa_ctx *ctx, const void *d_src, void *d_dst, size_t bytes, void *stream) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr, "ctx is NULL");
+    REQUIRE(d_src && d_dst, "source or destination is NULL");
+    REQUIRE(bytes % 16 == 0, "bytes must be a multiple of 16");
+    REQUIRE(((uintptr_t)d_src | (uintptr_t)d_dst) % 16 == 0, "buffers must be 16-byte aligned");
+    DeviceGuard g(ctx->device);
+    HIPCHK(launch_stream_copy(d_src, d_dst, bytes, (hipStream_t)stream));
+  });
+}
+
 int qaoa_ctx_destroy(qaoa_ctx *ctx) {
   return guarded([&] {
     if (!ctx) return;

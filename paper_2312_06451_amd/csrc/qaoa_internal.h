@@ -248,6 +248,8 @@ hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
                              double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
+// dst <- src, bytes a multiple of 16, both 16-byte aligned (the HBM copy roof).
+hipError_t launch_stream_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 // Grover path (qaoa_grover.hip)
 hipError_t launch_hist_table(const void *table, int tbytes, uint64_t N, int nbins, unsigned long long *counts,
                              hipStream_t s);

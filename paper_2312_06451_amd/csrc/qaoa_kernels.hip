@@ -1000,4 +1000,22 @@ hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t
   return hipGetLastError();
 }
 
+// Streaming copy (the measured HBM roof of a kernel that reads and writes every byte once):
+// one 16-byte word per thread, consecutive threads consecutive words, non-temporal loads and
+// stores (the data is touched once, so it should not displace other lines from the caches).
+typedef unsigned int copy_word __attribute__((ext_vector_type(4)));
+__global__ void k_stream_copy(const copy_word *__restrict__ src, copy_word *__restrict__ dst, uint64_t nwords) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nwords) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s) {
+  const uint64_t nwords = bytes / 16;
+  if (nwords == 0) return hipSuccess;
+  const uint64_t blocks = (nwords + 255) / 256;
+  if (blocks > 0xffffffffull) return hipErrorInvalidValue;
+  k_stream_copy<<<(unsigned)blocks, 256, 0, s>>>((const copy_word *)src, (copy_word *)dst, nwords);
+  return hipGetLastError();
+}
+
 }  // namespace qaoa
