@@ -265,6 +265,20 @@ int qaoa_expect_grad_pairs(const qaoa_problem *const *probs, const qaoa_mixer *c
                            const double *angles, int precision, double *out_expect, double *out_grad,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): qaoa_expect_grad_pairs restricted to pairs whose
+ * state fits one workgroup (transverse-field mixer, n <= 13 for QAOA_FP32, n <= 12 for
+ * QAOA_FP64), with the same arguments, kernels and results. The items, angle sets and result
+ * rows of a call live in a 4 MiB device array that the library holds per GPU from load to
+ * process end; the call makes no device allocation (the problems' tables were built when
+ * they were created). A call needs 56 n_pairs + 8 n_pairs (4p + 1) bytes plus alignment:
+ * beyond 4 MiB it returns QAOA_ERR_INVALID_ARG; other pairs give QAOA_ERR_UNSUPPORTED.
+ * Every call on one GPU shares that array (and a host staging array): calls that overlap in
+ * time, on any stream or thread, race. Synchronises `stream`. */
+int qaoa_expect_grad_pairs_noalloc(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs,
+                                   int p, const double *angles, int precision, double *out_expect, double *out_grad,
+                                   void *stream);
+
 /* ---------------------------------------------------------------- angle finding (Sec. 2.3)
  *
  * Host-side outer loop over the paired evaluation: every objective value and gradient comes

@@ -30,6 +30,7 @@ EXPORTED = [
     "qaoa_basinhopping", "qaoa_find_angles", "qaoa_find_angles_random", "qaoa_find_angles_multi",
     "qaoa_expect_pairs", "qaoa_expect_grad_pairs", "qaoa_mixer_x_orders", "qaoa_mixer_x_terms",
     "qaoa_mixer_x_multiangle", "qaoa_mixer_info", "qaoa_stream_copy",
+    "qaoa_expect_grad_pairs_noalloc",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
                   "count_states": 6, "xmix": 7}
@@ -119,6 +120,8 @@ def lib() -> ctypes.CDLL:
                                     c_void_p]
     L.qaoa_expect_grad_pairs.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, P(c_double), c_int,
                                          P(c_double), P(c_double), c_void_p]
+    L.qaoa_expect_grad_pairs_noalloc.argtypes = [P(c_void_p), P(c_void_p), c_int, c_int, P(c_double), c_int,
+                                                 P(c_double), P(c_double), c_void_p]
     L.qaoa_find_angles_random.argtypes = [c_void_p, c_void_p, c_int, c_int, opts_p, P(c_double), P(c_double),
                                           P(c_double), c_void_p]
     L.qaoa_status_string.argtypes = [c_int]
@@ -407,6 +410,21 @@ def qaoa_expect_grad_pairs(probs, mixers, p: int, angles, precision: int = QAOA_
     check(lib().qaoa_expect_grad_pairs(_ptrs(probs), _ptrs(mixers), n, p, ap, precision,
                                        out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)), stream),
           "qaoa_expect_grad_pairs")
+    return out, g
+
+
+def qaoa_expect_grad_pairs_noalloc(probs, mixers, p: int, angles, precision: int = QAOA_FP32, stream: int = 0):
+    """The allocation-free paired fwd+grad (whole-state transverse-field pairs only)."""
+    import numpy as np
+    aa, ap = _f64(angles)
+    n = len(probs)
+    if aa.size != n * 2 * p or len(mixers) != n:
+        raise ValueError("one mixer and 2p angles per pair")
+    out = np.zeros(n, dtype=np.float64)
+    g = np.zeros((n, 2 * p), dtype=np.float64)
+    check(lib().qaoa_expect_grad_pairs_noalloc(_ptrs(probs), _ptrs(mixers), n, p, ap, precision,
+                                               out.ctypes.data_as(P(c_double)), g.ctypes.data_as(P(c_double)),
+                                               stream), "qaoa_expect_grad_pairs_noalloc")
     return out, g
 
 

@@ -14,6 +14,7 @@
 #include <string>
 #include <tuple>
 #include <vector>
+#include <mutex>
 
 #include "../../include/qaoa.h"
 #include "qaoa_internal.h"
@@ -183,6 +184,7 @@ struct qaoa_ctx {
   HostBuf hparams, hresults;
   MappedBuf small_out;  // results of the whole-state kernels
   MappedBuf small_params;  // items and angles of the whole-state kernels, read by them in place
+  unsigned char *scratch = nullptr;  // this device's copy of the allocation-free entry point's array
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -1287,6 +1289,35 @@ void evaluate_x(qaoa_problem *prob, int p, const double *angles, int nsets, cons
 
 // ---------------------------------------------------------------- C ABI
 
+// ---------------------------------------------------------------- allocation-free scratch
+
+// Device memory of qaoa_expect_grad_pairs_noalloc: the whole-state items, the angle sets and
+// the result rows of one call. A file-scope device array, so each GPU the library runs on holds
+// its own copy from load to process end and no call allocates it. In host code the name is a
+// host-side stand-in, never a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (kept per device in g_scratch_dev).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static unsigned char *g_scratch_dev[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+// Host staging of the items of one call (static, no heap): calls that overlap race on it as
+// they race on the device array.
+static SmallItem g_noalloc_items[NOALLOC_SCRATCH_BYTES / sizeof(SmallItem)];
+
+// Address of this device's scratch array; `dev` must be the current device.
+static unsigned char *scratch_address(int dev) {
+  REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = (unsigned char *)ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
 extern "C" {
 
 const char *qaoa_status_string(int status) {
@@ -1316,6 +1347,7 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
     // free device memory allows
     if (const char *e = std::getenv("QAOA_GRAD_CHECKPOINT")) c->checkpoint_mode = std::atoi(e) ? 1 : 0;
     if (const char *e = std::getenv("QAOA_XPROD_TILES")) c->xprod_tiles = std::atoi(e) ? 1 : 0;
+    c->scratch = scratch_address(hip_device);
     *out = c.release();
   });
 }
@@ -2321,6 +2353,82 @@ int qaoa_expect_grad_pairs(const qaoa_problem *const *probs, const qaoa_mixer *c
                            void *stream) {
   return guarded([&] {
     paired(probs, mixers, n_pairs, p, angles, precision, 1, out_expect, out_grad, (hipStream_t)stream);
+  });
+}
+
+int qaoa_expect_grad_pairs_noalloc(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers, int n_pairs,
+                                   int p, const double *angles, int precision, double *out_expect, double *out_grad,
+                                   void *stream) {
+  return guarded([&] {
+    hipStream_t st = (hipStream_t)stream;
+    REQUIRE(probs && mixers, "probs or mixers is NULL");
+    REQUIRE(n_pairs >= 1, "n_pairs must be >= 1");
+    REQUIRE(out_expect && out_grad, "output pointer is NULL");
+    qaoa_ctx *ctx = probs[0] ? probs[0]->ctx : nullptr;
+    for (int i = 0; i < n_pairs; i++) {
+      check_pair(probs[i], mixers[i], precision);
+      REQUIRE(probs[i]->ctx == ctx, "all problems must share one context");
+      if (mixers[i]->kind != 0 || !small_path(probs[i], precision))
+        throw fail(QAOA_ERR_UNSUPPORTED, "the allocation-free call takes transverse-field pairs whose state fits "
+                                         "one workgroup (n <= 13 for QAOA_FP32, n <= 12 for QAOA_FP64)");
+      if (probs[i]->max_value + 1 > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+    }
+    check_angles(p, angles, (size_t)n_pairs * 2 * p);
+    // layout of the scratch array: items | angle sets | result rows, each 256-byte aligned
+    const int rowlen = 1 + 2 * p;
+    const size_t ib = (size_t)n_pairs * sizeof(SmallItem);
+    const size_t off_a = (ib + 255) & ~size_t(255);
+    const size_t ab = (size_t)n_pairs * 2 * p * sizeof(double);
+    const size_t off_r = (off_a + ab + 255) & ~size_t(255);
+    const size_t total = off_r + (size_t)n_pairs * rowlen * sizeof(double);
+    if (total > NOALLOC_SCRATCH_BYTES)
+      throw fail(QAOA_ERR_INVALID_ARG, "n_pairs x p needs " + std::to_string(total) + " bytes of scratch, more than the " +
+                                           std::to_string(NOALLOC_SCRATCH_BYTES) + " the allocation-free call holds");
+    DeviceGuard g(ctx->device);
+    unsigned char *d = ctx->scratch;
+    REQUIRE(d == scratch_address(ctx->device), "scratch address differs from the context's device");
+    // items grouped as the whole-state path groups them: register-resident kernel by
+    // (n, table width), then the LDS kernel; row i of the results is pair i
+    struct Group { int n, tb; size_t first, count; };
+    Group groups[4];
+    int ng = 0;
+    size_t m = 0;
+    for (int n : {12, 13})
+      for (int tb : {1, 2}) {
+        if (!whole_supported(precision, n)) continue;
+        const size_t first = m;
+        for (int i = 0; i < n_pairs; i++)
+          if (probs[i]->n == n && probs[i]->tbytes == tb) g_noalloc_items[m++] = small_item(probs[i], i, i);
+        if (m > first) groups[ng++] = Group{n, tb, first, m - first};
+      }
+    const size_t nwhole = m;
+    int max_n = 1, max_tb = 1, max_lut = 1;
+    for (int i = 0; i < n_pairs; i++) {
+      max_lut = std::max(max_lut, (int)probs[i]->max_value + 1);
+      if (whole_supported(precision, probs[i]->n)) continue;
+      g_noalloc_items[m++] = small_item(probs[i], i, i);
+      max_n = std::max(max_n, probs[i]->n);
+      max_tb = std::max(max_tb, probs[i]->tbytes);
+    }
+    max_lut = (max_lut + 15) & ~15;
+    HIPCHK(hipMemcpyAsync(d, g_noalloc_items, ib, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d + off_a, angles, ab, hipMemcpyHostToDevice, st));
+    const SmallItem *ditems = (const SmallItem *)d;
+    const double *dang = (const double *)(d + off_a);
+    double *dres = (double *)(d + off_r);
+    for (int j = 0; j < ng; j++)
+      HIPCHK(launch_whole(precision, groups[j].n, groups[j].tb, ditems + groups[j].first, (int)groups[j].count,
+                          max_lut, dang, p, 1, dres, st, 0));
+    if ((size_t)n_pairs > nwhole)
+      HIPCHK(launch_small(precision, ditems + nwhole, (int)(n_pairs - nwhole), max_n, max_tb, max_lut, dang, p, 1,
+                          dres, st, 0));
+    // row i = [<C>, gradient]: the first column to out_expect, the rest to out_grad
+    const size_t pitch = (size_t)rowlen * sizeof(double);
+    HIPCHK(hipMemcpy2DAsync(out_expect, sizeof(double), dres, pitch, sizeof(double), n_pairs,
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpy2DAsync(out_grad, 2 * p * sizeof(double), dres + 1, pitch, 2 * p * sizeof(double), n_pairs,
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
   });
 }
 
