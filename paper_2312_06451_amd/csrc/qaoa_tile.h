@@ -567,7 +567,8 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   using gbyte = __attribute__((address_space(1))) unsigned char;
   using gV2 = __attribute__((address_space(1))) V2;
   auto at = [&](uint64_t vb, int j) -> gV2 * { return (gV2 *)((gbyte *)uniform64(vb + jbyte(j)) + tbyte); };
-  auto ld = [&](uint64_t vb, int j) -> T2 { V2 v = *at(vb, j); return T2{v.x, v.y}; };
+  // the state streams through once per pass: non-temporal loads and stores
+  auto ld = [&](uint64_t vb, int j) -> T2 { V2 v = __builtin_nontemporal_load(at(vb, j)); return T2{v.x, v.y}; };
   // stores recompute the per-register offsets (from fresh copies of the geometry) instead of
   // keeping the loads' 32 64-bit offsets live across the whole pass
   auto st = [&](uint64_t vb, int j, const T2 &x) {
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
     V2 v;
     v.x = x.x;
     v.y = x.y;
-    *(gV2 *)((gbyte *)uniform64(vb + jb) + tbyte) = v;
+    __builtin_nontemporal_store(v, (gV2 *)((gbyte *)uniform64(vb + jb) + tbyte));
   };
   const uint64_t vs = ((uint64_t)q * a.vstride + base) * sizeof(T2);
 
