@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa.so")
 SOURCES = ["qaoa_kernels.hip", "qaoa_xpass.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_xmix.hip",
-           "qaoa_api.cpp", "qaoa_angles.cpp"]
+           "qaoa_gemm.hip", "qaoa_api.cpp", "qaoa_angles.cpp"]
 HOST_ONLY = {"qaoa_angles.cpp"}  # plain C++ above the C ABI: no device code
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP source of this library.
@@ -63,7 +63,7 @@ def build(verbose: bool = False, jobs: int = 4, force: bool = True) -> str:
         raise RuntimeError("compilation failed: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-fopenmp", "-o", tmp] + objs + \
-          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lhipblaslt", "-Wl,-rpath,/opt/rocm/llvm/lib"]
+          ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/llvm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

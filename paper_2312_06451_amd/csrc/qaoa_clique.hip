@@ -8,13 +8,16 @@
 // i.e. two dense products per round, for all angle sets at once: the state of S angle sets is
 // an N x 2S real matrix (real and imaginary parts as separate columns).
 //
-// FP32 form: each product is formed from FP16 halves with FP32 accumulation (MFMA GEMMs of
-// hipBLASLt; for each product shape the fastest of the library's candidate algorithms is
-// timed and kept on first use, rocBLAS when none runs): with x = x_hi + 2^-11 x_lo
-// (x_hi = fp16(x), x_lo = fp16(2^11 (x - x_hi))),
-//     V B ~ V_hi B_hi + 2^-11 (V_hi B_lo + V_lo B_hi),
-// two GEMM calls (K = N, then K = 2N on the stacked halves); the dropped V_lo B_lo term is
-// 2^-22 relative. FP64 form: DGEMM on the FP64 eigenbasis.
+// FP32 form: each product is formed from FP16 halves with FP32 accumulation on the matrix
+// cores, by the hand-written split-FP16 MFMA kernel of qaoa_gemm.hip: with
+// x = x_hi + 2^-11 x_lo (x_hi = fp16(x), x_lo = fp16(2^11 (x - x_hi))),
+//     V B ~ V_hi B_hi + 2^-11 (V_hi B_lo + V_lo B_hi)
+// in one launch; the dropped V_lo B_lo term is 2^-22 relative. FP64 form: DGEMM on the FP64
+// eigenbasis (rocBLAS).
+//
+// In the FP32 form every elementwise step (e^{-i beta D}, the next phase, <C>, lambda and the
+// gradient sums) runs in the epilogue of the product that precedes it, on the product's tile
+// in registers, and writes the next product's FP16 input directly (qaoa_gemm.hip).
 //
 // Gradient: the reverse sweep of the X path with H_M = V D V^T. The forward sweep keeps, per
 // round, the phased state (before V^T) and its eigen-coefficients after exp(-i beta D); then
@@ -23,7 +26,6 @@
 //   lam = V lam~;    g_gamma = 2 sum_x (C - c0) Im(conj(lam) phi);  lam *= exp(+i gamma C).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
-#include <hipblaslt/hipblaslt.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -66,10 +68,6 @@ struct Buf {
 void hipchk(hipError_t e, const char *what) {
   if (e != hipSuccess) throw CliqueError{QAOA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
-void ltchk(hipblasStatus_t s, const char *what) {
-  if (s != HIPBLAS_STATUS_SUCCESS)
-    throw CliqueError{QAOA_ERR_HIP, std::string(what) + ": hipBLASLt status " + std::to_string((int)s)};
-}
 void blaschk(rocblas_status s, const char *what) {
   if (s != rocblas_status_success)
     throw CliqueError{QAOA_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(s)};
@@ -86,36 +84,20 @@ constexpr int RB_ROWS = 1024;  // rows per block in the elementwise kernels (4 p
 
 }  // namespace
 
-// One FP16 x FP16 -> FP32 GEMM shape of the split products with its selected algorithm.
-struct LtGemm {
-  hipblasLtMatmulDesc_t desc = nullptr;
-  hipblasLtMatrixLayout_t a = nullptr, b = nullptr, c = nullptr;
-  hipblasLtMatmulAlgo_t algo{};
-  size_t ws = 0;
-  bool ok = false;  // false: no hipBLASLt algorithm ran, use rocBLAS
-  ~LtGemm() {
-    if (a) (void)hipblasLtMatrixLayoutDestroy(a);
-    if (b) (void)hipblasLtMatrixLayoutDestroy(b);
-    if (c) (void)hipblasLtMatrixLayoutDestroy(c);
-    if (desc) (void)hipblasLtMatmulDescDestroy(desc);
-  }
-};
-
 struct CliqueMixer {
   int n = 0, k = 0;
   int64_t N = 0;
+  int64_t Mp = 0, Kp = 0;  // rows / K of the padded FP16 planes (multiples of 128 / 32)
   rocblas_handle blas = nullptr;
-  hipblasLtHandle_t lt = nullptr;
-  std::map<std::tuple<int, int, int>, std::unique_ptr<LtGemm>> gemms;  // (transpose, K/N, cols)
-  Buf ltws;                                                               // hipBLASLt workspace
-  Buf V, D, Vcols, Vrows;  // FP64 eigenbasis (N x N col-major, column j = eigenvector j),
-                           // eigenvalues, FP16 halves [V_hi | V_lo] (N x 2N) and [V_hi; V_lo] (2N x N)
-  Buf X, Y, B, ckP, ckT, partials, params, luts, results, hres_dev;
+  Buf V, D, V16;  // FP64 eigenbasis (N x N col-major, column j = eigenvector j), eigenvalues,
+                  // FP16 planes [VT_hi, VT_lo, VN_hi, VN_lo], each Mp x Kp: row r of VT is
+                  // eigenvector r (the V^T product), row x of VN is row x of V (the V product)
+  Buf X, Y, B, B16, ckP, ckT, partials, params, luts, results, hres_dev;  // B: FP64 form's product input,
+                                                                          // B16: FP32 form's (FP16 planes)
+  size_t b_zeroed = 0;  // bytes of B16 cleared since its allocation (its padding must stay zero)
   std::vector<double> hres;
   CliqueTimer timer;
   ~CliqueMixer() {
-    gemms.clear();
-    if (lt) (void)hipblasLtDestroy(lt);
     if (blas) (void)rocblas_destroy_handle(blas);
   }
 };
@@ -172,19 +154,20 @@ __global__ void k_clique_matrix(int n, int k, int ring, int64_t N, const int64_t
   }
 }
 
-// FP16 halves of V: hi = fp16(v), lo = fp16(2^11 (v - hi)).
-__global__ void k_split_v(const double *__restrict__ V, int64_t N, __half *__restrict__ Vcols,
-                          __half *__restrict__ Vrows) {
-  const int64_t total = N * N, stride = (int64_t)gridDim.x * blockDim.x;
+// FP16 halves of V: hi = fp16(v), lo = fp16(2^11 (v - hi)), into the zero-padded blocked
+// planes of the split products (VT: row r = eigenvector r; VN: row x = row x of V; rows of Kp).
+__global__ void k_split_v(const double *__restrict__ V, int64_t N, int64_t Mp, int64_t Kp, __half *__restrict__ P) {
+  const int64_t total = N * N, stride = (int64_t)gridDim.x * blockDim.x, plane = Mp * Kp;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int64_t row = i % N, col = i / N;
+    const int64_t x = i % N, r = i / N;  // V[x][r]: component x of eigenvector r
     const double v = V[i];
     const __half hi = __float2half((float)v);
     const __half lo = __float2half((float)((v - (double)__half2float(hi)) * 2048.0));
-    Vcols[row + col * N] = hi;
-    Vcols[row + (col + N) * N] = lo;
-    Vrows[row + col * 2 * N] = hi;
-    Vrows[row + N + col * 2 * N] = lo;
+    const int64_t t = split_plane_offset(r, x, Kp), n = split_plane_offset(x, r, Kp);
+    P[t] = hi;
+    P[plane + t] = lo;
+    P[2 * plane + n] = hi;
+    P[3 * plane + n] = lo;
   }
 }
 
@@ -192,22 +175,23 @@ template <typename R> struct CT;
 template <> struct CT<float> { using T2 = float2; };
 template <> struct CT<double> { using T2 = double2; };
 
-// Write the complex value v of row x, set s as the next product's input: FP16 halves in the
-// stacked layout [lo; hi] (2N rows) for the FP32 form, the value itself for the FP64 form.
+// Write the complex value v of row x, set s as the next product's input. FP32 form: FP16
+// halves in two blocked planes (lo plane at B, hi plane at B + plane halves; state column c is
+// row c of the plane, rows of ldb halves); FP64 form: the value itself, column c at c * ldb.
 template <typename R>
-__device__ __forceinline__ void emit(void *B, int64_t N, int64_t x, int s, R re, R im) {
+__device__ __forceinline__ void emit(void *B, int64_t ldb, int64_t plane, int64_t x, int s, R re, R im) {
   if constexpr (sizeof(R) == 4) {
     __half *b = (__half *)B;
     const __half hr = __float2half(re), hi = __float2half(im);
-    const int64_t c0 = (int64_t)(2 * s) * 2 * N, c1 = (int64_t)(2 * s + 1) * 2 * N;
-    b[c0 + N + x] = hr;
-    b[c0 + x] = __float2half((re - __half2float(hr)) * 2048.0f);
-    b[c1 + N + x] = hi;
-    b[c1 + x] = __float2half((im - __half2float(hi)) * 2048.0f);
+    const int64_t c0 = split_plane_offset(2 * s, x, ldb), c1 = split_plane_offset(2 * s + 1, x, ldb);
+    b[plane + c0] = hr;
+    b[c0] = __float2half((re - __half2float(hr)) * 2048.0f);
+    b[plane + c1] = hi;
+    b[c1] = __float2half((im - __half2float(hi)) * 2048.0f);
   } else {
     R *b = (R *)B;
-    b[(int64_t)(2 * s) * N + x] = re;
-    b[(int64_t)(2 * s + 1) * N + x] = im;
+    b[(int64_t)(2 * s) * ldb + x] = re;
+    b[(int64_t)(2 * s + 1) * ldb + x] = im;
   }
 }
 
@@ -255,7 +239,8 @@ __global__ void k_init(R *__restrict__ X, int64_t N, const void *psi0) {
 // psi(x, s) *= LUT_s[C(x)]; keep the result (ck) and emit it for V^T.
 template <typename R, typename TT>
 __global__ void k_phase(const R *__restrict__ X, int64_t N, const void *table,
-                        const typename CT<R>::T2 *__restrict__ luts, int lut_len, R *ck, void *B) {
+                        const typename CT<R>::T2 *__restrict__ luts, int lut_len, R *ck, void *B, int64_t ldb,
+                        int64_t plane) {
   const int s = blockIdx.y;
   const typename CT<R>::T2 *L = luts + (int64_t)s * lut_len;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
@@ -266,7 +251,7 @@ __global__ void k_phase(const R *__restrict__ X, int64_t N, const void *table,
       ck[(int64_t)(2 * s) * N + x] = re;
       ck[(int64_t)(2 * s + 1) * N + x] = im;
     }
-    emit<R>(B, N, x, s, re, im);
+    emit<R>(B, ldb, plane, x, s, re, im);
   }
 }
 
@@ -275,7 +260,8 @@ __global__ void k_phase(const R *__restrict__ X, int64_t N, const void *table,
 template <typename R>
 __global__ __launch_bounds__(256) void k_eig(const R *__restrict__ Y, int64_t N, const double *__restrict__ D,
                                              const double *__restrict__ betas, double sign,
-                                             const R *tref, R *ck, void *B, double *gpart, int nblk) {
+                                             const R *tref, R *ck, void *B, int64_t ldb, int64_t plane,
+                                             double *gpart, int nblk) {
   const int s = blockIdx.y;
   const double beta = betas[s];
   double acc = 0.0;
@@ -294,7 +280,7 @@ __global__ __launch_bounds__(256) void k_eig(const R *__restrict__ Y, int64_t N,
       ck[(int64_t)(2 * s) * N + r] = re;
       ck[(int64_t)(2 * s + 1) * N + r] = im;
     }
-    emit<R>(B, N, r, s, re, im);
+    emit<R>(B, ldb, plane, r, s, re, im);
   }
   if (gpart) block_sum2(acc, 0.0, gpart + (int64_t)s * nblk + blockIdx.x, nullptr);
 }
@@ -319,11 +305,11 @@ __global__ __launch_bounds__(256) void k_expect(const R *__restrict__ X, int64_t
 // lam = (C - c0) psi_p, emitted for V^T.
 template <typename R, typename TT>
 __global__ void k_lambda(const R *__restrict__ X, int64_t N, const void *table, const double *__restrict__ vals,
-                         double c0, void *B) {
+                         double c0, void *B, int64_t ldb, int64_t plane) {
   const int s = blockIdx.y;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
     const R k = (R)(vals[cval<TT>(table, x)] - c0);
-    emit<R>(B, N, x, s, k * X[(int64_t)(2 * s) * N + x], k * X[(int64_t)(2 * s + 1) * N + x]);
+    emit<R>(B, ldb, plane, x, s, k * X[(int64_t)(2 * s) * N + x], k * X[(int64_t)(2 * s + 1) * N + x]);
   }
 }
 
@@ -333,7 +319,7 @@ template <typename R, typename TT>
 __global__ __launch_bounds__(256) void k_gamma(const R *__restrict__ L, int64_t N, const void *table,
                                                const double *__restrict__ vals, double c0, const R *__restrict__ phi,
                                                const typename CT<R>::T2 *luts, int lut_len, void *B,
-                                               double *gpart, int nblk) {
+                                               int64_t ldb, int64_t plane, double *gpart, int nblk) {
   const int s = blockIdx.y;
   double acc = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * RB_ROWS;
@@ -344,7 +330,7 @@ __global__ __launch_bounds__(256) void k_gamma(const R *__restrict__ L, int64_t 
     acc += (vals[c] - c0) * ((double)a * pb - (double)b * pa);
     if (B) {
       const typename CT<R>::T2 l = luts[(int64_t)s * lut_len + c];
-      emit<R>(B, N, x, s, a * l.x - b * l.y, a * l.y + b * l.x);
+      emit<R>(B, ldb, plane, x, s, a * l.x - b * l.y, a * l.y + b * l.x);
     }
   }
   block_sum2(acc, 0.0, gpart + (int64_t)s * nblk + blockIdx.x, nullptr);
@@ -398,10 +384,13 @@ std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, 
     hipchk(hipStreamSynchronize(st), "eigendecomposition");
     if (hinfo != 0) throw CliqueError{QAOA_ERR_HIP, "eigendecomposition did not converge"};
   }
-  // FP16 halves for the FP32 form
-  __half *Vc = (__half *)m->Vcols.get((size_t)2 * N * N * sizeof(__half));
-  __half *Vr = (__half *)m->Vrows.get((size_t)2 * N * N * sizeof(__half));
-  k_split_v<<<4096, 256, 0, st>>>(H, N, Vc, Vr);
+  // FP16 halves for the FP32 form, in zero-padded planes
+  m->Mp = (N + SPLIT_TILE - 1) / SPLIT_TILE * SPLIT_TILE;
+  m->Kp = (N + SPLIT_KTILE - 1) / SPLIT_KTILE * SPLIT_KTILE;
+  const size_t vbytes = (size_t)4 * m->Mp * m->Kp * sizeof(__half);
+  __half *P16 = (__half *)m->V16.get(vbytes);
+  hipchk(hipMemsetAsync(P16, 0, vbytes, st), "clear FP16 planes");
+  k_split_v<<<4096, 256, 0, st>>>(H, N, m->Mp, m->Kp, P16);
   hipchk(hipGetLastError(), "k_split_v");
   hipchk(hipStreamSynchronize(st), "split V");
   return m;
@@ -420,131 +409,36 @@ int64_t clique_size(const CliqueMixer &m) { return m.N; }
 
 namespace {
 
-constexpr size_t LT_WORKSPACE = 64ull << 20;
-
-// Creates the descriptors of one split-product GEMM (D = alpha op(A) B + beta D, A the FP16
-// eigenbasis halves, B the FP16 state halves with leading dimension 2N, D FP32 N x cols) and
-// times the library's candidate algorithms on the given operands; keeps the fastest.
-// Overwrites out (the caller recomputes it afterwards).
-void lt_select(CliqueMixer &m, LtGemm &g, bool transpose, int kmul, int cols, const void *A, const void *B,
-               float *out, hipStream_t st) {
-  const int64_t N = m.N, K = kmul * N;
-  ltchk(hipblasLtMatmulDescCreate(&g.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F), "matmul desc");
-  const int32_t opA = transpose ? HIPBLAS_OP_T : HIPBLAS_OP_N, opB = HIPBLAS_OP_N;
-  ltchk(hipblasLtMatmulDescSetAttribute(g.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &opA, sizeof(opA)), "transA");
-  ltchk(hipblasLtMatmulDescSetAttribute(g.desc, HIPBLASLT_MATMUL_DESC_TRANSB, &opB, sizeof(opB)), "transB");
-  if (transpose) ltchk(hipblasLtMatrixLayoutCreate(&g.a, HIP_R_16F, K, N, 2 * N), "layout A");
-  else ltchk(hipblasLtMatrixLayoutCreate(&g.a, HIP_R_16F, N, K, N), "layout A");
-  ltchk(hipblasLtMatrixLayoutCreate(&g.b, HIP_R_16F, K, cols, 2 * N), "layout B");
-  ltchk(hipblasLtMatrixLayoutCreate(&g.c, HIP_R_32F, N, cols, N), "layout C");
-  hipblasLtMatmulPreference_t pref = nullptr;
-  ltchk(hipblasLtMatmulPreferenceCreate(&pref), "preference");
-  const uint64_t wmax = LT_WORKSPACE;
-  (void)hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wmax, sizeof(wmax));
-  hipblasLtMatmulHeuristicResult_t res[16];
-  int found = 0;
-  hipblasStatus_t hs = hipblasLtMatmulAlgoGetHeuristic(m.lt, g.desc, g.a, g.b, g.c, g.c, pref, 16, res, &found);
-  (void)hipblasLtMatmulPreferenceDestroy(pref);
-  if (hs != HIPBLAS_STATUS_SUCCESS || found <= 0) return;
-  void *ws = m.ltws.get(LT_WORKSPACE);
-  hipEvent_t e0, e1;
-  hipchk(hipEventCreate(&e0), "event");
-  hipchk(hipEventCreate(&e1), "event");
-  const float one = 1.0f;
-  float best = 1e30f;
-  for (int i = 0; i < found; i++) {
-    if (res[i].state != HIPBLAS_STATUS_SUCCESS || res[i].workspaceSize > LT_WORKSPACE) continue;
-    bool good = true;
-    for (int r = 0; r < 4 && good; r++) {
-      if (r == 1) (void)hipEventRecord(e0, st);
-      good = hipblasLtMatmul(m.lt, g.desc, &one, A, g.a, B, g.b, &one, out, g.c, out, g.c, &res[i].algo, ws,
-                             res[i].workspaceSize, st) == HIPBLAS_STATUS_SUCCESS;
-    }
-    (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) good = false;
-    float ms = 0.f;
-    if (good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
-      best = ms;
-      g.algo = res[i].algo;
-      g.ws = res[i].workspaceSize;
-      g.ok = true;
-    }
-  }
-  (void)hipGetLastError();
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-}
-
 template <typename R>
 struct Dense {
   CliqueMixer &m;
   hipStream_t st;
   int64_t N;
-  int cols;  // 2S
+  int cols;       // 2S
+  int64_t ldb;    // column stride of the product input B (Kp halves for FP32, N for FP64)
+  int64_t plane;  // FP32: halves between the lo and hi planes of B
 
-  LtGemm *gemm(bool transpose, int kmul, const void *A, const void *B, float *out) {
-    auto key = std::make_tuple(transpose ? 1 : 0, kmul, cols);
-    auto it = m.gemms.find(key);
-    if (it != m.gemms.end()) return it->second.get();
-    auto g = std::make_unique<LtGemm>();
-    lt_select(m, *g, transpose, kmul, cols, A, B, out, st);
-    LtGemm *p = g.get();
-    m.gemms[key] = std::move(g);
-    return p;
-  }
-
-  // out (N x cols) = op(V) in (next-product input B), op = V^T (transpose) or V
+  // out (N x cols, ld N) = op(V) in (the product input B), op = V^T (transpose) or V
   void product(bool transpose, const void *B, R *out) {
-    const rocblas_int n = (rocblas_int)N, c = cols;
-    blaschk(rocblas_set_stream(m.blas, st), "rocblas_set_stream");
-    LtGemm *l1 = nullptr, *l2 = nullptr;
-    if constexpr (sizeof(R) == 4) {
-      // algorithm selection runs before the timed product (it overwrites out)
-      const __half *A = transpose ? (const __half *)m.Vrows.p : (const __half *)m.Vcols.p;
-      if (!m.lt) ltchk(hipblasLtCreate(&m.lt), "hipblasLtCreate");
-      l1 = gemm(transpose, 1, A, (const __half *)B + N, (float *)out);
-      l2 = gemm(transpose, 2, A, B, (float *)out);
-    }
     if (m.timer.begin) m.timer.begin(m.timer.ctx, st);
-    double flops;
     if constexpr (sizeof(R) == 4) {
-      const float one = 1.0f, zero = 0.0f, s11 = 1.0f / 2048.0f;
-      const __half *b = (const __half *)B;
-      const rocblas_operation op = transpose ? rocblas_operation_transpose : rocblas_operation_none;
-      const __half *A = transpose ? (const __half *)m.Vrows.p : (const __half *)m.Vcols.p;
-      const rocblas_int lda = transpose ? 2 * n : n;
-      void *ws = m.ltws.p;
-      if (l1->ok)
-        ltchk(hipblasLtMatmul(m.lt, l1->desc, &one, A, l1->a, b + N, l1->b, &zero, out, l1->c, out, l1->c,
-                              &l1->algo, ws, l1->ws, st),
-              "hipblasLtMatmul (hi x hi)");
-      else
-        blaschk(rocblas_gemm_ex(m.blas, op, rocblas_operation_none, n, c, n, &one, A, rocblas_datatype_f16_r, lda,
-                                b + N, rocblas_datatype_f16_r, 2 * n, &zero, out, rocblas_datatype_f32_r, n, out,
-                                rocblas_datatype_f32_r, n, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0),
-                "rocblas_gemm_ex (hi x hi)");
-      if (l2->ok)
-        ltchk(hipblasLtMatmul(m.lt, l2->desc, &s11, A, l2->a, b, l2->b, &one, out, l2->c, out, l2->c, &l2->algo,
-                              ws, l2->ws, st),
-              "hipblasLtMatmul (hi x lo + lo x hi)");
-      else
-        blaschk(rocblas_gemm_ex(m.blas, op, rocblas_operation_none, n, c, 2 * n, &s11, A, rocblas_datatype_f16_r,
-                                lda, b, rocblas_datatype_f16_r, 2 * n, &one, out, rocblas_datatype_f32_r, n, out,
-                                rocblas_datatype_f32_r, n, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0),
-                "rocblas_gemm_ex (hi x lo + lo x hi)");
-      flops = 3.0 * 2.0 * (double)N * N * cols;
+      const __half *P = (const __half *)m.V16.p;
+      const int64_t vp = m.Mp * m.Kp;
+      const __half *mh = transpose ? P : P + 2 * vp, *ml = mh + vp;
+      const __half *bl = (const __half *)B, *bh = bl + plane;
+      hipchk(launch_split_gemm(bh, bl, mh, ml, m.Kp, (int)N, cols, (float *)out, N, st), "split-FP16 product");
     } else {
+      const rocblas_int n = (rocblas_int)N, c = cols;
       const double one = 1.0, zero = 0.0;
+      blaschk(rocblas_set_stream(m.blas, st), "rocblas_set_stream");
       blaschk(rocblas_dgemm(m.blas, transpose ? rocblas_operation_transpose : rocblas_operation_none,
                             rocblas_operation_none, n, c, n, &one, (const double *)m.V.p, n, (const double *)B, n,
                             &zero, out, n),
               "rocblas_dgemm");
-      flops = 2.0 * (double)N * N * cols;
     }
     // algorithmic work of one real N x N x cols product (the three half products are the
     // cost of the FP32 form, not the algorithm)
     if (m.timer.end) m.timer.end(m.timer.ctx, st, QAOA_KC_DENSE, 0.0, 2.0 * (double)N * N * cols);
-    (void)flops;
   }
 };
 
@@ -556,11 +450,27 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
   const int cols = 2 * S;
   const size_t mat = (size_t)N * cols * sizeof(R);
   R *X = (R *)m.X.get(mat);
-  R *Y = (R *)m.Y.get(mat);
-  void *B = m.B.get(sizeof(R) == 4 ? (size_t)2 * N * cols * sizeof(__half) : mat);
+  R *Y = sizeof(R) == 4 ? nullptr : (R *)m.Y.get(mat);  // the FP32 form keeps no product output
+  // product input: FP32 form, lo and hi FP16 planes of Ncp = roundup(cols, 128) columns of Kp
+  // halves (the padding rows and columns stay zero); FP64 form, N x cols doubles
+  const int64_t ncp = ((int64_t)cols + SPLIT_TILE - 1) / SPLIT_TILE * SPLIT_TILE;
+  const int64_t ldb = sizeof(R) == 4 ? m.Kp : N, plane = sizeof(R) == 4 ? ncp * m.Kp : 0;
+  // FP32 form: two sets of planes, the input of the current product and the one its epilogue
+  // writes (ping-pong)
+  const size_t bbytes = sizeof(R) == 4 ? (size_t)2 * 2 * ncp * m.Kp * sizeof(__half) : mat;
+  // the FP16 planes have their own buffer: its padding is written by nothing but this clear
+  Buf &bb = sizeof(R) == 4 ? m.B16 : m.B;
+  const void *bold = bb.p;
+  void *B = bb.get(bbytes);
+  if (sizeof(R) == 4 && (B != bold || m.b_zeroed < bbytes)) {
+    hipchk(hipMemsetAsync(B, 0, bb.cap, st), "clear product input");
+    m.b_zeroed = bb.cap;
+  }
   R *ckP = grad ? (R *)m.ckP.get(mat * p) : nullptr;
   R *ckT = grad ? (R *)m.ckT.get(mat * p) : nullptr;
-  const int nblk = (int)((N + RB_ROWS - 1) / RB_ROWS);
+  // partial sums per block of rows: the elementwise kernels' blocks (FP64 form) or the
+  // product's row tiles (FP32 form: the reductions are fused into the product epilogues)
+  const int nblk = sizeof(R) == 4 ? (int)((N + SPLIT_TILE - 1) / SPLIT_TILE) : (int)((N + RB_ROWS - 1) / RB_ROWS);
   const int nout = 2 + 2 * p;
   double *part = (double *)m.partials.get((size_t)nout * S * nblk * sizeof(double));
   auto pslot = [&](int o) { return part + (size_t)o * S * nblk; };
@@ -592,7 +502,7 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
   auto lut_f = [&](int k) { return dluts + (size_t)k * S * ev.lut_len; };
   auto lut_b = [&](int k) { return dluts + (size_t)(p + k) * S * ev.lut_len; };
 
-  Dense<R> dense{m, st, N, cols};
+  Dense<R> dense{m, st, N, cols, ldb, plane};
   const dim3 eg((unsigned)((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024), (unsigned)S);
   const dim3 rg((unsigned)nblk, (unsigned)S);
   auto launched = [&](const char *w) { hipchk(hipGetLastError(), w); };
@@ -603,49 +513,125 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
     if (m.timer.end) m.timer.end(m.timer.ctx, st, QAOA_KC_OTHER, bytes, 0.0);
   };
 
-  // forward sweep
-  tbegin();
-  k_init<R><<<eg, 256, 0, st>>>(X, N, d_psi0);
-  launched("k_init");
-  tend((double)mat);
-  for (int k = 0; k < p; k++) {
+  if constexpr (sizeof(R) == 4) {
+    // FP32 form: every elementwise step runs in the epilogue of the product before it
+    const int64_t bp = (int64_t)2 * plane;  // halves per set of planes
+    _Float16 *Bset[2] = {(_Float16 *)B, (_Float16 *)B + bp};
+    int cur = 0;
+    const __half *P16 = (const __half *)m.V16.p;
+    const int64_t vp = m.Mp * m.Kp;
+    auto product = [&](bool transpose, int mode, SplitEpi e) {
+      const __half *mh = transpose ? P16 : P16 + 2 * vp, *ml = mh + vp;
+      const _Float16 *bl = Bset[cur], *bh = bl + plane;
+      e.bld = m.Kp;
+      e.bplane = plane;
+      e.ldc = N;
+      e.D = (const double *)m.D.p;
+      e.table = ev.table;
+      e.tbytes = ev.tbytes;
+      e.vals = ev.vals;
+      e.c0 = ev.c0;
+      e.lut_len = ev.lut_len;
+      e.nblk = nblk;
+      if (m.timer.begin) m.timer.begin(m.timer.ctx, st);
+      hipchk(launch_split_gemm_epi(mode, bh, bl, mh, ml, m.Kp, (int)N, cols, e, st), "split-FP16 product");
+      if (m.timer.end) m.timer.end(m.timer.ctx, st, QAOA_KC_DENSE, 0.0, 2.0 * (double)N * N * cols);
+      cur ^= 1;
+    };
     tbegin();
-    k_phase<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, lut_f(k), ev.lut_len, grad ? ckP + (size_t)k * N * cols : nullptr, B);
+    k_init<R><<<eg, 256, 0, st>>>(X, N, d_psi0);
+    launched("k_init");
+    k_phase<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, lut_f(0), ev.lut_len, grad ? ckP : nullptr, Bset[cur], ldb,
+                                        plane);
     launched("k_phase");
-    tend((double)mat * (grad ? 3 : 2));
-    dense.product(true, B, Y);
+    tend((double)mat * (grad ? 4 : 3));
+    for (int k = 0; k < p; k++) {
+      SplitEpi e{};
+      e.bout = Bset[cur ^ 1];
+      e.betas = dbeta + (size_t)k * S;
+      e.ck = grad ? (float *)(ckT + (size_t)k * N * cols) : nullptr;
+      product(true, SE_EIG, e);
+      SplitEpi f{};
+      f.bout = Bset[cur ^ 1];
+      if (k + 1 < p) {
+        f.luts = (const float2 *)lut_f(k + 1);
+        f.ck = grad ? (float *)(ckP + (size_t)(k + 1) * N * cols) : nullptr;
+        product(false, SE_PHASE, f);
+      } else {
+        f.C = (float *)X;
+        f.part0 = pslot(0);
+        f.part1 = pslot(1);
+        if (!grad) f.bout = nullptr;
+        product(false, SE_LAST, f);
+      }
+    }
+    if (d_state) {
+      k_export<R><<<eg.x, 256, 0, st>>>(X, N, (T2 *)d_state);
+      launched("k_export");
+    }
+    if (grad) {
+      // lambda = (C - c0) psi_p was emitted by the last forward product
+      for (int k = p - 1; k >= 0; k--) {
+        SplitEpi e{};
+        e.bout = Bset[cur ^ 1];
+        e.betas = dbeta + (size_t)k * S;
+        e.ckr = (const float *)(ckT + (size_t)k * N * cols);
+        e.part0 = pslot(2 + k);
+        product(true, SE_REIG, e);
+        SplitEpi f{};
+        f.bout = k > 0 ? Bset[cur ^ 1] : nullptr;
+        f.luts = (const float2 *)lut_b(k);
+        f.ckr = (const float *)(ckP + (size_t)k * N * cols);
+        f.part0 = pslot(2 + p + k);
+        product(false, SE_RPHASE, f);
+      }
+    }
+  } else {
+    // forward sweep
     tbegin();
-    k_eig<R><<<rg, 256, 0, st>>>(Y, N, m.D.p ? (const double *)m.D.p : nullptr, dbeta + (size_t)k * S, -1.0, nullptr,
-                                 grad ? ckT + (size_t)k * N * cols : nullptr, B, nullptr, nblk);
-    launched("k_eig");
-    tend((double)mat * (grad ? 3 : 2));
-    dense.product(false, B, X);
-  }
-  tbegin();
-  k_expect<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.vals, pslot(0), pslot(1), nblk);
-  launched("k_expect");
-  tend((double)mat);
-  if (d_state) {
-    k_export<R><<<eg.x, 256, 0, st>>>(X, N, (T2 *)d_state);
-    launched("k_export");
-  }
-  // reverse sweep (only the adjoint vector is multiplied; phi comes from the forward keeps)
-  if (grad) {
-    k_lambda<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, ev.vals, ev.c0, B);
-    launched("k_lambda");
-    for (int k = p - 1; k >= 0; k--) {
+    k_init<R><<<eg, 256, 0, st>>>(X, N, d_psi0);
+    launched("k_init");
+    tend((double)mat);
+    for (int k = 0; k < p; k++) {
+      tbegin();
+      k_phase<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, lut_f(k), ev.lut_len, grad ? ckP + (size_t)k * N * cols : nullptr, B,
+                                          ldb, plane);
+      launched("k_phase");
+      tend((double)mat * (grad ? 3 : 2));
       dense.product(true, B, Y);
       tbegin();
-      k_eig<R><<<rg, 256, 0, st>>>(Y, N, (const double *)m.D.p, dbeta + (size_t)k * S, 1.0,
-                                   ckT + (size_t)k * N * cols, nullptr, B, pslot(2 + k), nblk);
+      k_eig<R><<<rg, 256, 0, st>>>(Y, N, m.D.p ? (const double *)m.D.p : nullptr, dbeta + (size_t)k * S, -1.0, nullptr,
+                                   grad ? ckT + (size_t)k * N * cols : nullptr, B, ldb, plane, nullptr, nblk);
       launched("k_eig");
-      tend((double)mat * 3);
+      tend((double)mat * (grad ? 3 : 2));
       dense.product(false, B, X);
-      tbegin();
-      k_gamma<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.vals, ev.c0, ckP + (size_t)k * N * cols, lut_b(k), ev.lut_len,
-                                         k > 0 ? B : nullptr, pslot(2 + p + k), nblk);
-      launched("k_gamma");
-      tend((double)mat * 3);
+    }
+    tbegin();
+    k_expect<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.vals, pslot(0), pslot(1), nblk);
+    launched("k_expect");
+    tend((double)mat);
+    if (d_state) {
+      k_export<R><<<eg.x, 256, 0, st>>>(X, N, (T2 *)d_state);
+      launched("k_export");
+    }
+    // reverse sweep (only the adjoint vector is multiplied; phi comes from the forward keeps)
+    if (grad) {
+      k_lambda<R, TT><<<eg, 256, 0, st>>>(X, N, ev.table, ev.vals, ev.c0, B, ldb, plane);
+      launched("k_lambda");
+      for (int k = p - 1; k >= 0; k--) {
+        dense.product(true, B, Y);
+        tbegin();
+        k_eig<R><<<rg, 256, 0, st>>>(Y, N, (const double *)m.D.p, dbeta + (size_t)k * S, 1.0,
+                                     ckT + (size_t)k * N * cols, nullptr, B, ldb, plane, pslot(2 + k), nblk);
+        launched("k_eig");
+        tend((double)mat * 3);
+        dense.product(false, B, X);
+        tbegin();
+        k_gamma<R, TT><<<rg, 256, 0, st>>>(X, N, ev.table, ev.vals, ev.c0, ckP + (size_t)k * N * cols, lut_b(k), ev.lut_len,
+                                           k > 0 ? B : nullptr, ldb, plane, pslot(2 + p + k), nblk);
+        launched("k_gamma");
+        tend((double)mat * 3);
+      }
     }
   }
   // fixed-order reduction of the partials: out[s][o]

@@ -248,6 +248,64 @@ hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
                              double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
+// Split-FP16 MFMA product (qaoa_gemm.hip): C[m + n ldc] = sum_k M[m][k] S[n][k] for m < M, n < cols,
+// with every operand given as FP16 hi and 2^11-scaled lo planes of rows of kp halves (kp a
+// multiple of SPLIT_KTILE) in the blocked layout of split_plane_offset; the state planes hold
+// roundup(cols, SPLIT_TILE) rows, the matrix planes roundup(M, SPLIT_TILE), zero-padded.
+constexpr int SPLIT_TILE = 128, SPLIT_KTILE = 32;
+// Offset (in halves) of element (row r, k) of a blocked plane: blocks of SPLIT_TILE rows x
+// SPLIT_KTILE halves, one per (row tile, K tile), K tiles of a row tile consecutive; inside a
+// block row rr holds its four 16-byte chunks in the order c ^ ((rr >> 2) & 3).
+__host__ __device__ inline int64_t split_plane_offset(int64_t r, int64_t k, int64_t kp) {
+  const int64_t rt = r / SPLIT_TILE, kt = k / SPLIT_KTILE, rr = r % SPLIT_TILE, kk = k % SPLIT_KTILE;
+  return (rt * (kp / SPLIT_KTILE) + kt) * (SPLIT_TILE * SPLIT_KTILE) + rr * SPLIT_KTILE +
+         8 * ((kk >> 3) ^ ((rr >> 2) & 3)) + (kk & 7);
+}
+hipError_t launch_split_gemm(const void *st_h, const void *st_l, const void *m_h, const void *m_l, int64_t kp,
+                             int M, int cols, float *C, int64_t ldc, hipStream_t s);
+// Write the complex value (re, im) of row x of angle set s as the next split product's input:
+// FP16 hi and 2^11-scaled lo of the real part (state column 2s) and the imaginary part (column
+// 2s + 1), into the blocked planes lo = B, hi = B + plane (rows of ldb halves).
+__device__ __forceinline__ void split_emit(_Float16 *B, int64_t ldb, int64_t plane, int64_t x, int s, float re,
+                                           float im) {
+  const _Float16 hr = (_Float16)re, hi = (_Float16)im;
+  const int64_t c0 = split_plane_offset(2 * s, x, ldb), c1 = split_plane_offset(2 * s + 1, x, ldb);
+  B[plane + c0] = hr;
+  B[c0] = (_Float16)((re - (float)hr) * 2048.0f);
+  B[plane + c1] = hi;
+  B[c1] = (_Float16)((im - (float)hi) * 2048.0f);
+}
+// Epilogues fused into the split product (the elementwise steps of the eigenbasis mixers,
+// applied to the product's tile while it is in registers). Rows are rows of the product
+// (eigen-index r after V^T, state index x after V), column pairs (2s, 2s + 1) angle set s.
+enum {
+  SE_PLAIN = 0,   // C[m + n ldc] = product
+  SE_EIG = 1,     // t *= e^{-i beta_s D_r}; ck <- t (if ck); emit t
+  SE_PHASE = 2,   // psi *= lut_s[C(x)]; ck <- psi (if ck); emit psi
+  SE_LAST = 3,    // C <- psi; part0 += |psi|^2 C(x), part1 += |psi|^2; emit (C(x) - c0) psi if bout
+  SE_REIG = 4,    // part0 += D_r Im(conj(t) ckr); t *= e^{+i beta_s D_r}; emit t
+  SE_RPHASE = 5,  // part0 += (C(x) - c0) Im(conj(lam) ckr); lam *= lut_s[C(x)]; emit lam if bout
+};
+struct SplitEpi {
+  float *C;                  // SE_PLAIN, SE_LAST: FP32 output, column-major, ld ldc
+  int64_t ldc;
+  _Float16 *bout;            // next product's input planes (lo at bout, hi at bout + bplane)
+  int64_t bld, bplane;
+  float *ck;                 // SE_EIG, SE_PHASE: kept copy (column-major, ld ldc), may be null
+  const float *ckr;          // SE_REIG, SE_RPHASE: the forward sweep's kept copy
+  const double *D;           // eigenvalues
+  const double *betas;       // beta of each set
+  const void *table;         // cost table index per state (tbytes 1 or 2)
+  int tbytes;
+  const double *vals;        // cost value of each table index
+  double c0;
+  const float2 *luts;        // lut_len entries per set
+  int lut_len;
+  double *part0, *part1;     // partial sums [s * nblk + row tile]
+  int nblk;
+};
+hipError_t launch_split_gemm_epi(int mode, const void *st_h, const void *st_l, const void *m_h, const void *m_l,
+                                 int64_t kp, int M, int cols, const SplitEpi &e, hipStream_t s);
 // dst <- src, bytes a multiple of 16, both 16-byte aligned (the HBM copy roof).
 hipError_t launch_stream_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 // Grover path (qaoa_grover.hip)
