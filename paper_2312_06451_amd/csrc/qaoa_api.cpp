@@ -15,6 +15,8 @@
 #include <tuple>
 #include <vector>
 #include <mutex>
+#include <functional>
+#include <atomic>
 
 #include "../../include/qaoa.h"
 #include "qaoa_internal.h"
@@ -185,6 +187,19 @@ struct qaoa_ctx {
   MappedBuf small_out;  // results of the whole-state kernels
   MappedBuf small_params;  // items and angles of the whole-state kernels, read by them in place
   unsigned char *scratch = nullptr;  // this device's copy of the allocation-free entry point's array
+  // batched calls: pinned staging per tile-path instance, and the HIP graphs of their device
+  // work (one per problem set, mixers, p, angle-set count, precision and gradient flag)
+  int batch_graphs = 1;  // QAOA_BATCH_GRAPH = "0": enqueue every call's work eagerly
+  std::vector<std::unique_ptr<HostBuf>> bstage, brstage;
+  struct BGraph {
+    std::vector<uint64_t> key;
+    std::vector<int> ckpt;        // per instance: reverse-sweep mode the work was planned with
+    uint64_t fp = 0;              // fingerprint of the captured work
+    int calls = 0;                // eager calls with this key so far
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<BGraph> bgraphs;
+  hipStream_t gstream = nullptr;  // capture stream when the caller passes the null stream
   // kernel timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -196,6 +211,9 @@ struct qaoa_ctx {
   std::vector<Pending> pending;
   KTotals totals[QAOA_KC_COUNT];
   ~qaoa_ctx() {
+    for (auto &g : bgraphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto &p : pending) {
       (void)hipEventDestroy(p.a);
@@ -272,7 +290,13 @@ static void profile_collect(qaoa_ctx *ctx) {
 
 // The device table holds, per feasible state, an index into the problem's distinct cost
 // values (increasing order); for a graph table the index is the cost itself (values 0..max).
+static uint64_t next_handle_id() {
+  static std::atomic<uint64_t> c{1};
+  return c++;
+}
+
 struct qaoa_problem {
+  uint64_t id = next_handle_id();  // unique for the process (keys of cached graphs)
   qaoa_ctx *ctx = nullptr;
   int n = 0, k = -1;
   uint64_t N = 0;
@@ -321,6 +345,7 @@ void upload_values(qaoa_problem *prob, hipStream_t st) {
 }  // namespace
 
 struct qaoa_mixer {
+  uint64_t id = next_handle_id();
   qaoa_ctx *ctx = nullptr;
   int kind = 0;  // 0: transverse field, 1: clique, 2: Grover, 3: X products, 4: per-qubit angles
   int n = 0, k = -1;
@@ -473,10 +498,35 @@ const void *tile_table(qaoa_problem *prob, int T, int c, int h0, hipStream_t st)
 // every qubit, applied as Y rotations with tau = -1 or +1 (scalar cos(pi/4) per qubit); no
 // X-pair terms, the beta gradient is taken at the mixer diagonal like the gamma gradient at
 // the phase.
+// Deferred evaluation (batched calls): the device work of several instances is enqueued
+// back to back (or captured once as a HIP graph and replayed) and the host reads every
+// result after one synchronisation. Each instance stages its parameters and results in its
+// own pinned buffers.
+struct XDefer {
+  HostBuf *hstage;   // pinned parameter staging of this instance
+  HostBuf *rstage;   // pinned result rows of this instance
+  bool launch;       // false: only write the staging (the device work is a replayed graph)
+  int *ckpt;         // checkpointed reverse sweep: -1 decide and record, else use the record
+  std::vector<std::function<void()>> *finish;  // host work to run after the synchronisation
+  uint64_t *fp;      // fingerprint of every launch and copy the instance makes (FNV-1a)
+};
+
+// FNV-1a over raw bytes (fingerprints of enqueued work: kernel arguments, sizes, pointers).
+inline void fnv(uint64_t *h, const void *p, size_t n) {
+  if (!h) return;
+  const unsigned char *b = (const unsigned char *)p;
+  for (size_t i = 0; i < n; i++) *h = (*h ^ b[i]) * 1099511628211ull;
+}
+template <typename T>
+inline void fnv_v(uint64_t *h, const T &v) {
+  fnv(h, &v, sizeof(T));
+}
+
 template <typename R>
 void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
                 int grad, double *out_expect, double *out_grad, void *d_state_out, hipStream_t st,
-                const qaoa_mixer *xm = nullptr) {
+                const qaoa_mixer *xm = nullptr, const XDefer *df = nullptr) {
+  const bool dev = !df || df->launch;  // enqueue device work
   qaoa_ctx *ctx = prob->ctx;
   const int prec = sizeof(R) == 4 ? QAOA_FP32 : QAOA_FP64;
   const int T = prec == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
@@ -528,7 +578,9 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const size_t vbytes = (size_t)nsets * N * esz;
   const int npf_est = 1 + L * ((int)tiles.size() - 1);
   bool ckpt = false;
-  if (grad && ctx->checkpoint_mode != 0) {
+  if (df && *df->ckpt >= 0) {
+    ckpt = *df->ckpt != 0;  // the decision the captured work was planned with
+  } else if (grad && ctx->checkpoint_mode != 0) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
       const size_t need = (size_t)npf_est * vbytes;
@@ -537,6 +589,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       if (need > have) ckpt = false;
     }
   }
+  if (df) *df->ckpt = ckpt ? 1 : 0;
   void *dphi = ckpt ? nullptr : ctx->phi.get(vbytes);
   unsigned char *dck = ckpt ? (unsigned char *)ctx->ckpt.get((size_t)npf_est * vbytes) : nullptr;
   // forward pass j writes checkpoint j (or the single in-place buffer)
@@ -953,9 +1006,10 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const size_t off_mal = (off_cnt + cnt_bytes + 255) & ~size_t(255);
   const size_t off_mab = (off_mal + mal_bytes + 255) & ~size_t(255);
   const size_t total = off_mab + mab_bytes;
-  unsigned char *h = (unsigned char *)ctx->hparams.get(total);
-  // the previous call may still read the pinned staging buffer through its async copy
-  HIPCHK(hipStreamSynchronize(st));
+  unsigned char *h = (unsigned char *)(df ? df->hstage : &ctx->hparams)->get(total);
+  // the previous call may still read the pinned staging buffer through its async copy (a
+  // deferred instance owns its staging until the call's synchronisation)
+  if (!df) HIPCHK(hipStreamSynchronize(st));
   std::memcpy(h, sps.data(), sp_bytes);
   if (job_bytes) std::memcpy(h + off_jobs, jobs.data(), job_bytes);
   if (jobm_bytes) std::memcpy(h + off_jobm, jobs_m.data(), jobm_bytes);
@@ -963,17 +1017,28 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   if (mal_bytes) std::memcpy(h + off_mal, ma_lut.data(), mal_bytes);
   if (mab_bytes) std::memcpy(h + off_mab, ma_bf.data(), mab_bytes);
   unsigned char *d = (unsigned char *)ctx->params.get(total);
-  HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
+  uint64_t *fp = df ? df->fp : nullptr;
+  fnv_v(fp, d);
+  fnv_v(fp, h);
+  fnv_v(fp, total);
+  fnv_v(fp, jobs.size());
+  fnv_v(fp, jobs_m.size());
+  fnv_v(fp, lut_len);
+  if (dev) HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, st));
   void *dluts = nullptr;
   if (!jobs.empty()) {
     dluts = ctx->luts.get(jobs.size() * (size_t)lut_len * esz);
-    HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobs), (int)jobs.size(), lut_len, prob->dvals, dluts, st));
+    if (dev)
+      HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobs), (int)jobs.size(), lut_len, prob->dvals, dluts, st));
   }
   void *dluts_m = nullptr;
   if (!jobs_m.empty()) {
     dluts_m = ctx->luts2.get(jobs_m.size() * (size_t)lut_mix * esz);
-    HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobm), (int)jobs_m.size(), lut_mix, xm->xvals, dluts_m, st));
+    if (dev)
+      HIPCHK(launch_luts(prec, (const LutJob *)(d + off_jobm), (int)jobs_m.size(), lut_mix, xm->xvals, dluts_m, st));
   }
+  fnv_v(fp, dluts);
+  fnv_v(fp, dluts_m);
   // ---------------- passes
   for (size_t i = 0; i < passes.size(); i++) {
     PassArgs<R> &a = passes[i];
@@ -983,6 +1048,12 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       a.luts = d + off_mal + (size_t)ma_block[i] * nsets * RNq * sizeof(std::complex<R>);
       a.vals = d + off_mab + (size_t)ma_block[i] * nsets * 33 * sizeof(cd);
     }
+    fnv(fp, &a, sizeof(a));
+    fnv_v(fp, nvs[i]);
+    fnv_v(fp, sxs[i]);
+    fnv_v(fp, shapes[i]);
+    fnv_v(fp, mixlut[i]);
+    if (!dev) continue;
     const uint32_t fl = a.flags;
     double by = 0;
     if (fl & (PF_LOAD_PHI | PF_LOAD_PSI0)) by += (double)N * esz;
@@ -1005,13 +1076,18 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   }
   // ---------------- reductions
   double *dres = (double *)ctx->results.get((size_t)nsets * nout * sizeof(double));
-  {
+  if (dev) {
     KTimer kt(ctx, st, QAOA_KC_OTHER, (double)part_elems * 8.0, 0.0);
     HIPCHK(launch_finalize(dpart, (const int *)(d + off_cnt), maxc, nsets, nwg, nout, dres, st));
     kt.done();
   }
-  double *hres = (double *)ctx->hresults.get((size_t)nsets * nout * sizeof(double));
-  HIPCHK(hipMemcpyAsync(hres, dres, (size_t)nsets * nout * sizeof(double), hipMemcpyDeviceToHost, st));
+  double *hres = (double *)(df ? df->rstage : &ctx->hresults)->get((size_t)nsets * nout * sizeof(double));
+  fnv_v(fp, dres);
+  fnv_v(fp, hres);
+  fnv_v(fp, dpart);
+  fnv_v(fp, nout);
+  fnv_v(fp, maxc);
+  if (dev) HIPCHK(hipMemcpyAsync(hres, dres, (size_t)nsets * nout * sizeof(double), hipMemcpyDeviceToHost, st));
   if (d_state_out) {
     // nsets == 1 here: final state(x) = sigma_p * phi(x ^ F), F = all bits when an odd
     // number of rounds used the tau = -cot form
@@ -1021,8 +1097,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     HIPCHK(launch_scale_copy(prec, fwd_out(npf - 1), d_state_out, N, sig_p[0].real(), sig_p[0].imag(),
                              flip, st));
   }
-  HIPCHK(hipStreamSynchronize(st));
-  profile_collect(ctx);
+  auto read_out = [=]() {
   for (int s = 0; s < nsets; s++) {
     const double *r = hres + (size_t)s * nout;
     const double E = r[om.E()], Nr = r[om.Nr()];
@@ -1041,11 +1116,20 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
       }
     }
   }
+  };
+  if (df) {
+    df->finish->push_back(read_out);
+    return;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  profile_collect(ctx);
+  read_out();
 }
 
 // Whole-state path: items of n <= SMALL_MAX_N, one workgroup each.
 void run_small(const std::vector<SmallItem> &items_in, int precision, const double *angles, int nsets,
-               int p, int grad, double *hout, qaoa_ctx *ctx, hipStream_t st) {
+               int p, int grad, double *hout, qaoa_ctx *ctx, hipStream_t st,
+               std::vector<std::function<void()>> *finish = nullptr, bool launch = true, uint64_t *fp = nullptr) {
   // items whose state fits the register-resident kernel go first, grouped by (n, table width);
   // the rest run in the LDS kernel
   std::vector<SmallItem> items;
@@ -1077,6 +1161,7 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
   // start, so items and angles stay in mapped host memory and no copy precedes the launch (the
   // previous call's kernels have finished: every call synchronises its stream before returning).
   const int stage = p <= 1024 ? 1 : 0;
+  if (!stage && finish) throw fail(QAOA_ERR_UNSUPPORTED, "deferred whole-state launches need p <= 1024");
   unsigned char *d;
   if (stage) {
     ctx->small_params.get(total);
@@ -1100,6 +1185,13 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
   double *dres = (double *)ctx->small_out.d;
   const SmallItem *ditems = (const SmallItem *)d;
   const double *dang = (const double *)(d + off_a);
+  fnv_v(fp, d);
+  fnv_v(fp, dres);
+  fnv_v(fp, total);
+  fnv_v(fp, max_lut);
+  for (auto &g : groups) fnv_v(fp, g);
+  fnv_v(fp, items.size());
+  fnv_v(fp, nwhole);
   // algorithmic work per item: the table read once; FP32 flops of the method per amplitude:
   // 6 per qubit rotation and 6 per phase multiply in each layer, and with the gradient the
   // same again on the state and on the adjoint vector plus 4 per qubit and 4 per layer for
@@ -1114,6 +1206,7 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
     }
   };
   for (auto &g : groups) {
+    if (!launch) break;
     double by, fl;
     work(std::get<2>(g), std::get<3>(g), by, fl);
     KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
@@ -1121,7 +1214,7 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
                         max_lut, dang, p, grad, dres, st, stage));
     kt.done();
   }
-  if (items.size() > nwhole) {
+  if (items.size() > nwhole && launch) {
     double by, fl;
     work(nwhole, items.size() - nwhole, by, fl);
     KTimer kt(ctx, st, QAOA_KC_SMALL, by, fl);
@@ -1129,8 +1222,14 @@ void run_small(const std::vector<SmallItem> &items_in, int precision, const doub
                         grad, dres, st, stage));
     kt.done();
   }
+  const void *src = ctx->small_out.h;
+  const size_t rbytes = (size_t)nrow * rowlen * sizeof(double);
+  if (finish) {
+    finish->push_back([=]() { std::memcpy(hout, src, rbytes); });
+    return;
+  }
   HIPCHK(hipStreamSynchronize(st));
-  std::memcpy(hout, ctx->small_out.h, (size_t)nrow * rowlen * sizeof(double));
+  std::memcpy(hout, src, rbytes);
   profile_collect(ctx);
 }
 
@@ -1347,6 +1446,7 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
     // free device memory allows
     if (const char *e = std::getenv("QAOA_GRAD_CHECKPOINT")) c->checkpoint_mode = std::atoi(e) ? 1 : 0;
     if (const char *e = std::getenv("QAOA_XPROD_TILES")) c->xprod_tiles = std::atoi(e) ? 1 : 0;
+    if (const char *e = std::getenv("QAOA_BATCH_GRAPH")) c->batch_graphs = std::atoi(e) ? 1 : 0;
     c->scratch = scratch_address(hip_device);
     *out = c.release();
   });
@@ -2214,28 +2314,6 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
   const int g2p = (int)set_len(mixers[0], p);
   check_angles(p, angles, (size_t)n_sets * g2p);
   DeviceGuard g(ctx->device);
-  // whole-state items first (one launch), then the larger problems one by one
-  std::vector<SmallItem> items;
-  std::vector<int> small_probs;
-  for (int i = 0; i < n_probs; i++) {
-    if (mixers[i]->kind == 0 && small_path(probs[i], precision)) {
-      if (probs[i]->max_value + 1 > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
-      for (int s = 0; s < n_sets; s++)
-        items.push_back(small_item(probs[i], s, (int)small_probs.size() * n_sets + s));
-      small_probs.push_back(i);
-    }
-  }
-  if (!items.empty()) {
-    std::vector<double> hout((size_t)small_probs.size() * n_sets * (1 + g2p));
-    run_small(items, precision, angles, n_sets, p, grad, hout.data(), ctx, st);
-    for (size_t j = 0; j < small_probs.size(); j++)
-      for (int s = 0; s < n_sets; s++) {
-        const double *r = hout.data() + ((size_t)j * n_sets + s) * (1 + g2p);
-        int i = small_probs[j];
-        out_expect[(size_t)i * n_sets + s] = r[0];
-        if (grad) std::memcpy(out_grad + ((size_t)i * n_sets + s) * g2p, r + 1, g2p * sizeof(double));
-      }
-  }
   // Grover-mixer problems: every (problem, set) pair in one launch
   std::vector<GroverItem> gitems;
   std::vector<int> gprobs;
@@ -2257,13 +2335,133 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
         if (grad) std::memcpy(out_grad + ((size_t)i * n_sets + s) * g2p, r + 1, g2p * sizeof(double));
       }
   }
+  // problems on other paths (eigenbasis mixers, X products): one evaluation each
   for (int i = 0; i < n_probs; i++) {
-    if (mixers[i]->kind == 0 && small_path(probs[i], precision)) continue;
-    if (mixers[i]->kind == 2) continue;
+    if (mixers[i]->kind == 0 || mixers[i]->kind == 2) continue;
     evaluate(probs[i], mixers[i], p, angles, n_sets, nullptr, precision, grad,
              out_expect + (size_t)i * n_sets, grad ? out_grad + (size_t)i * n_sets * g2p : nullptr,
              nullptr, st);
   }
+  // transverse-field problems: the whole-state pairs in one launch, then every larger problem's
+  // tile passes, all enqueued back to back and read after one synchronisation; from the second
+  // call with the same problems, mixers, p, sets and precision on, the device work is a HIP
+  // graph captured once and replayed (its parameters are re-staged in the same pinned buffers)
+  std::vector<SmallItem> items;
+  std::vector<int> small_probs, tile_probs;
+  for (int i = 0; i < n_probs; i++) {
+    if (mixers[i]->kind != 0) continue;
+    if (small_path(probs[i], precision)) {
+      if (probs[i]->max_value + 1 > MAX_LUT) throw fail(QAOA_ERR_UNSUPPORTED, "largest cost value exceeds the LUT limit");
+      for (int s = 0; s < n_sets; s++)
+        items.push_back(small_item(probs[i], s, (int)small_probs.size() * n_sets + s));
+      small_probs.push_back(i);
+    } else {
+      tile_probs.push_back(i);
+    }
+  }
+  if (items.empty() && tile_probs.empty()) return;
+  while (ctx->bstage.size() < tile_probs.size()) {
+    ctx->bstage.push_back(std::make_unique<HostBuf>());
+    ctx->brstage.push_back(std::make_unique<HostBuf>());
+  }
+  std::vector<double> hout((size_t)small_probs.size() * n_sets * (1 + g2p));
+  std::vector<std::function<void()>> fin;
+  // the graph entry of this call's key
+  std::vector<uint64_t> key = {(uint64_t)precision, (uint64_t)grad, (uint64_t)p, (uint64_t)n_sets};
+  for (int i = 0; i < n_probs; i++)
+    if (mixers[i]->kind == 0) {
+      key.push_back(probs[i]->id);
+      key.push_back(mixers[i]->id);
+    }
+  qaoa_ctx::BGraph *G = nullptr;
+  for (auto &g : ctx->bgraphs)
+    if (g.key == key) G = &g;
+  if (!G) {
+    if (ctx->bgraphs.size() >= 64) {  // bounded cache: drop the oldest entry
+      if (ctx->bgraphs.front().exec) (void)hipGraphExecDestroy(ctx->bgraphs.front().exec);
+      ctx->bgraphs.erase(ctx->bgraphs.begin());
+    }
+    ctx->bgraphs.push_back(qaoa_ctx::BGraph{});
+    G = &ctx->bgraphs.back();
+    G->key = key;
+    G->ckpt.assign(tile_probs.size(), -1);
+  }
+  // enqueue (launch) or only stage (replay) the work of every instance on stream s
+  auto stage_all = [&](bool launch, hipStream_t s, uint64_t *fp) {
+    fin.clear();
+    if (!items.empty()) run_small(items, precision, angles, n_sets, p, grad, hout.data(), ctx, s, &fin, launch, fp);
+    for (size_t j = 0; j < tile_probs.size(); j++) {
+      const int i = tile_probs[j];
+      XDefer df{ctx->bstage[j].get(), ctx->brstage[j].get(), launch, &G->ckpt[j], &fin, fp};
+      qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
+      double *oe = out_expect + (size_t)i * n_sets, *og = grad ? out_grad + (size_t)i * n_sets * g2p : nullptr;
+      if (precision == QAOA_FP32)
+        run_x_path<float>(pr, p, angles, n_sets, nullptr, grad, oe, og, nullptr, s, nullptr, &df);
+      else
+        run_x_path<double>(pr, p, angles, n_sets, nullptr, grad, oe, og, nullptr, s, nullptr, &df);
+    }
+  };
+  const bool graphs = ctx->batch_graphs && !ctx->profiling && p <= 1024;
+  bool done = false;
+  if (graphs && G->exec) {
+    // replay: re-stage the parameters; the captured work must be what this call would enqueue
+    uint64_t fp = 1469598103934665603ull;
+    stage_all(false, st ? st : ctx->gstream, &fp);
+    if (fp == G->fp) {
+      hipStream_t gs = st ? st : ctx->gstream;
+      HIPCHK(hipGraphLaunch(G->exec, gs));
+      HIPCHK(hipStreamSynchronize(gs));
+      done = true;
+    } else {
+      (void)hipGraphExecDestroy(G->exec);  // planned differently (e.g. another reverse-sweep
+      G->exec = nullptr;                    // scalar form): run eagerly, capture again later
+      G->calls = 0;
+    }
+  } else if (graphs && G->calls >= 1) {
+    // capture: every buffer was sized by the earlier call with this key
+    if (!st && !ctx->gstream) HIPCHK(hipStreamCreate(&ctx->gstream));
+    hipStream_t gs = st ? st : ctx->gstream;
+    if (!st) HIPCHK(hipDeviceSynchronize());  // the capture stream does not order with the null stream
+    uint64_t fp = 1469598103934665603ull;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      try {
+        stage_all(true, gs, &fp);
+      } catch (...) {
+        ok = false;
+      }
+      ok = (hipStreamEndCapture(gs, &graph) == hipSuccess) && ok && graph;
+      ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+    (void)hipGetLastError();
+    if (ok) {
+      G->exec = exec;
+      G->fp = fp;
+      HIPCHK(hipGraphLaunch(G->exec, gs));
+      HIPCHK(hipStreamSynchronize(gs));
+      done = true;
+    } else {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      G->calls = -(1 << 30);  // not capturable: this key stays eager
+    }
+  }
+  if (!done) {
+    stage_all(true, st, nullptr);
+    HIPCHK(hipStreamSynchronize(st));
+    G->calls++;
+  }
+  profile_collect(ctx);
+  for (auto &f : fin) f();
+  for (size_t j = 0; j < small_probs.size(); j++)
+    for (int s = 0; s < n_sets; s++) {
+      const double *r = hout.data() + ((size_t)j * n_sets + s) * (1 + g2p);
+      int i = small_probs[j];
+      out_expect[(size_t)i * n_sets + s] = r[0];
+      if (grad) std::memcpy(out_grad + ((size_t)i * n_sets + s) * g2p, r + 1, g2p * sizeof(double));
+    }
 }
 
 // Pair i: probs[i] with mixers[i] at angle set i. Whole-state and Grover pairs of every problem
