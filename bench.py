@@ -497,6 +497,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fwd-only", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed tile-pass plan rule instead of the library's measured plan choice")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the QAOA state of this workload is evaluated on a single "
@@ -522,6 +524,8 @@ def main():
     log(f"copy roof: {roof_copy['GBps']:.0f} GB/s")
     R = Runner(q, W)
     h = R.ctx.handle
+    if not args.no_autotune:
+        R.ctx.set_autotune(True)   # plans measured on first use (in the warm-up), then fixed
     log(f"workload {W.name}: {W.description}")
 
     # ---- FP32 state (timed, with per-kernel events)
@@ -637,6 +641,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic", "config": cfg,
         "roofline": roof, "path": path, "copy_roof": roof_copy, "fp64": fp64,
+        "plans": R.ctx.plans().splitlines()[1:],
         "event_timed_region": event_timing,
         "speedup_vs_fp64": (evals32 / fp64["value"]) if fp64 else None, "forward_only": fwd,
         "error": err, "cpu_baseline": cpu, "kernels": prof,

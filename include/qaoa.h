@@ -67,8 +67,37 @@ typedef struct qaoa_mixer qaoa_mixer;     /* H_M: transverse field, eigenbasis m
  * QAOA_GRAD_CHECKPOINT = "0" never keep the forward passes' outputs for the gradient's
  * reverse sweep (undo the state in place), "1" always keep them; unset: keep them when they
  * fit in half the free device memory. QAOA_XPROD_TILES = "0" runs X-product and per-qubit
- * mixers on separate Walsh-Hadamard and diagonal kernels instead of the tile passes. */
+ * mixers on separate Walsh-Hadamard and diagonal kernels instead of the tile passes.
+ * QAOA_AUTOTUNE = "1" turns the plan tuner on (qaoa_ctx_set_autotune). */
 int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
+
+/* Plan tuner of the tile-pass evaluations (every problem above the whole-state size: the
+ * transverse-field mixer and the X-product mixers). A plan fixes choices that leave the
+ * result exact up to rounding: the reverse sweep reading the forward passes' outputs or
+ * undoing the state in place, the tile cover (narrow 64-byte runs where they save a tile;
+ * which tile takes them), which tile rotates the low qubits, the tile order of the first
+ * round, and the XCD-aware workgroup order. Off (enable = 0, the default): a fixed rule.
+ * On: the first evaluation of each (n, precision, gradient or not, mixer, whether the
+ * checkpoints fit in memory) times the alternatives one at a time on the caller's stream
+ * (min(p, 2) layers per trial, about 20 trials) and keeps the fastest; every later
+ * evaluation of that key, single or batched, any number of angle sets, uses it. Different
+ * plans round differently (FP32: within the 1e-5 bound), so a run that must repeat another
+ * bit for bit saves the plans (qaoa_plans_save) and loads them (qaoa_plans_load).
+ * INVALID_ARG for ctx == NULL. */
+int qaoa_ctx_set_autotune(qaoa_ctx *ctx, int enable);
+
+/* The context's chosen plans as text, one line per key:
+ *   "n precision grad mixer ckpt_fits : narrow narrow_top lowbits down xcd ckpt"
+ * after a header line "qaoa-plans 1". buf may be NULL; *needed (if not NULL) receives the
+ * length including the terminating NUL; at most len bytes are written (always terminated
+ * when len > 0). INVALID_ARG for ctx == NULL. */
+int qaoa_plans_text(const qaoa_ctx *ctx, char *buf, size_t len, size_t *needed);
+
+/* Write the plans to a file (qaoa_plans_text's format; written to path.tmp and renamed), or
+ * add the plans of such a file to the context (a line for a key already present replaces
+ * it). INVALID_ARG for NULL arguments or a malformed file; HIP is not involved. */
+int qaoa_plans_save(const qaoa_ctx *ctx, const char *path);
+int qaoa_plans_load(qaoa_ctx *ctx, const char *path);
 
 /* Destroy a context and free its scratch. Problems and mixers created on it must be
  * destroyed first: while any is alive the call returns QAOA_ERR_INVALID_ARG and destroys

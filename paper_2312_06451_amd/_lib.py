@@ -30,7 +30,8 @@ EXPORTED = [
     "qaoa_basinhopping", "qaoa_find_angles", "qaoa_find_angles_random", "qaoa_find_angles_multi",
     "qaoa_expect_pairs", "qaoa_expect_grad_pairs", "qaoa_mixer_x_orders", "qaoa_mixer_x_terms",
     "qaoa_mixer_x_multiangle", "qaoa_mixer_info", "qaoa_stream_copy",
-    "qaoa_expect_grad_pairs_noalloc",
+    "qaoa_expect_grad_pairs_noalloc", "qaoa_ctx_set_autotune", "qaoa_plans_text", "qaoa_plans_save",
+    "qaoa_plans_load",
 ]
 KERNEL_CLASSES = {"fwd_pass": 0, "rev_pass": 1, "small": 2, "dense": 3, "other": 4, "grover": 5,
                   "count_states": 6, "xmix": 7}
@@ -106,6 +107,10 @@ def lib() -> ctypes.CDLL:
     L.qaoa_profile_enable.argtypes = [c_void_p, c_int]
     L.qaoa_profile_read.argtypes = [c_void_p, c_int, P(c_int64), P(c_double), P(c_double), P(c_double)]
     L.qaoa_stream_copy.argtypes = [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.qaoa_ctx_set_autotune.argtypes = [c_void_p, c_int]
+    L.qaoa_plans_text.argtypes = [c_void_p, ctypes.c_char_p, c_size_t, P(c_size_t)]
+    L.qaoa_plans_save.argtypes = [c_void_p, ctypes.c_char_p]
+    L.qaoa_plans_load.argtypes = [c_void_p, ctypes.c_char_p]
     opts_p = P(qaoa_angle_opts)
     L.qaoa_angle_opts_default.argtypes = [opts_p]
     L.qaoa_minimize.argtypes = [c_void_p, c_void_p, c_int, c_int, P(c_double), P(c_double), P(c_int), opts_p,
@@ -441,6 +446,26 @@ def qaoa_profile_read(ctx: int, kernel_class: int) -> dict:
 
 def qaoa_stream_copy(ctx: int, src: int, dst: int, nbytes: int, stream: int = 0) -> None:
     check(lib().qaoa_stream_copy(ctx, src, dst, nbytes, stream), "qaoa_stream_copy")
+
+
+def qaoa_ctx_set_autotune(ctx: int, enable: bool = True) -> None:
+    check(lib().qaoa_ctx_set_autotune(ctx, 1 if enable else 0), "qaoa_ctx_set_autotune")
+
+
+def qaoa_plans_text(ctx: int) -> str:
+    need = c_size_t()
+    check(lib().qaoa_plans_text(ctx, None, 0, ctypes.byref(need)), "qaoa_plans_text")
+    buf = ctypes.create_string_buffer(need.value)
+    check(lib().qaoa_plans_text(ctx, buf, need.value, None), "qaoa_plans_text")
+    return buf.value.decode()
+
+
+def qaoa_plans_save(ctx: int, path: str) -> None:
+    check(lib().qaoa_plans_save(ctx, os.fsencode(path)), "qaoa_plans_save")
+
+
+def qaoa_plans_load(ctx: int, path: str) -> None:
+    check(lib().qaoa_plans_load(ctx, os.fsencode(path)), "qaoa_plans_load")
 
 
 # ---------------------------------------------------------------- angle finding

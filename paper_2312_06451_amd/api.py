@@ -32,6 +32,20 @@ class Context:
         self.device = device
         self._children = weakref.WeakSet()
 
+    def set_autotune(self, enable: bool = True):
+        """Turn the tile-pass plan tuner on or off (``qaoa_ctx_set_autotune``)."""
+        _lib.qaoa_ctx_set_autotune(self.handle, enable)
+
+    def plans(self) -> str:
+        """The chosen tile-pass plans as text (``qaoa_plans_text``)."""
+        return _lib.qaoa_plans_text(self.handle)
+
+    def save_plans(self, path: str):
+        _lib.qaoa_plans_save(self.handle, path)
+
+    def load_plans(self, path: str):
+        _lib.qaoa_plans_load(self.handle, path)
+
     def close(self):
         """Destroy the context; problems and mixers still open on it are closed first."""
         if self.handle:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <array>
 #include <complex>
@@ -177,11 +178,26 @@ struct KTotals {
   double ms = 0, bytes = 0, flops = 0;
 };
 
+// Choices of the tile-pass plan that leave the results exact up to rounding: the run-time
+// tuner (plan_for) searches them, the defaults are the fixed rule.
+struct PlanOpts {
+  uint8_t narrow = 1;      // strided tiles take runs down to 64 B when that saves a tile
+  uint8_t narrow_top = 1;  // with uneven widths, the top tile takes the narrowest runs
+  uint8_t lowbits = 1;     // the register-group rules of make_tiles
+  uint8_t down = 0;        // the first round visits the tiles from the top one down
+  uint8_t xcd = 1;         // XCD-aware workgroup order (consecutive tiles on one XCD)
+  int8_t ckpt = -1;        // reverse sweep: -1 the context's memory rule, 0 in place, 1 checkpoints
+};
+
 struct qaoa_ctx {
   int device = 0;
   int64_t live = 0;          // problems and mixers created on this context and not yet destroyed
   int checkpoint_mode = -1;  // -1: when memory allows, 0: never, 1: always
   int xprod_tiles = 1;       // X-product mixers on Hadamard tile passes when they apply
+  // tile-pass plans: QAOA_AUTOTUNE / qaoa_ctx_set_autotune; chosen plans per (n, precision,
+  // gradient, mixer, checkpoints fit), measured or loaded from a file
+  int autotune = 0;
+  std::map<std::array<int, 5>, PlanOpts> plans;
   DevBuf phi, lam, ckpt, partials, params, luts, luts2, results, cnt, items, gitems, gamps;
   HostBuf hparams, hresults;
   MappedBuf small_out;  // results of the whole-state kernels
@@ -376,16 +392,32 @@ struct TileGeo {
   uint32_t rot;  // tile bits rotated by this tile
 };
 
-std::vector<TileGeo> make_tiles(int n, int T, int cmin) {
+// Tile cover of n address bits: tile 0 holds bits [0, T); each further tile holds c contiguous
+// low bits and T - c bits above the previous tile's. Fewest tiles first, runs of at least 2^cmin
+// amplitudes (widest-first, as wide as allowed); when runs down to 2^cnarrow save a tile, the
+// strided bits are spread as evenly as possible over the tiles instead.
+std::vector<TileGeo> make_tiles(int n, int T, int cmin, int cnarrow, const PlanOpts &o) {
   std::vector<TileGeo> t;
   t.push_back({T, T, (1u << T) - 1});
+  auto ntiles = [&](int c) { return n <= T ? 1 : 1 + (n - T + (T - c) - 1) / (T - c); };
+  std::vector<int> widths;
+  if (o.narrow && ntiles(cnarrow) < ntiles(cmin)) {
+    const int ns = ntiles(cnarrow) - 1, S = n - T;
+    widths.assign(ns, S / ns);
+    for (int i = 0; i < S % ns; i++) widths[o.narrow_top ? ns - 1 - i : i]++;
+  } else {
+    for (int next = T; next < n;) {
+      widths.push_back(std::min(n - next, T - cmin));
+      next += widths.back();
+    }
+  }
   int next = T;
-  while (next < n) {
-    int width = std::min(n - next, T - cmin);
+  for (int width : widths) {
     int c = T - width;
     t.push_back({c, next, ((1u << T) - 1) & ~((1u << c) - 1)});
     next += width;
   }
+  if (!o.lowbits) return t;
   // Balance the rotation work between passes. The lowest T - 8 address bits (the L register
   // group) are contiguous bits of every tile, so any tile may rotate them. With three or more
   // tiles, the middle tile of a layer runs as a single-block pass (memory-bound, with spare
@@ -408,16 +440,33 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin) {
   return t;
 }
 
+// Whether option `which` of PlanOpts changes the plan of n bits at all (the tuner skips the
+// others).
+bool plan_knob_applies(int which, int n, int T, int cmin, int cnarrow, const PlanOpts &o) {
+  PlanOpts a = o, b = o;
+  switch (which) {
+    case 0: a.narrow = 1; b.narrow = 0; break;
+    case 1: a.narrow_top = 1; b.narrow_top = 0; break;
+    case 2: a.lowbits = 1; b.lowbits = 0; break;
+    default: return false;
+  }
+  auto ta = make_tiles(n, T, cmin, cnarrow, a), tb = make_tiles(n, T, cmin, cnarrow, b);
+  if (ta.size() != tb.size()) return true;
+  for (size_t i = 0; i < ta.size(); i++)
+    if (ta[i].c != tb[i].c || ta[i].h0 != tb[i].h0 || ta[i].rot != tb[i].rot) return true;
+  return false;
+}
+
 // One forward pass: [rotate tile bits for layer pre] [phase of layer ph] [rotate for layer post]
 struct FwdPass {
   int tile;
   int pre = -1, ph = -1, post = -1;
 };
 
-std::vector<FwdPass> make_forward(int K, int p) {
+std::vector<FwdPass> make_forward(int K, int p, bool down = false) {
   std::vector<std::pair<int, int>> seq;  // (tile, layer): layers alternate tile order
   for (int k = 0; k < p; k++)
-    for (int i = 0; i < K; i++) seq.push_back({(k % 2 == 0) ? i : K - 1 - i, k});
+    for (int i = 0; i < K; i++) seq.push_back({((k % 2 == 0) != down) ? i : K - 1 - i, k});
   std::vector<FwdPass> out;
   out.push_back(FwdPass{seq[0].first, -1, 0, 0});
   size_t i = 1;
@@ -522,22 +571,51 @@ inline void fnv_v(uint64_t *h, const T &v) {
   fnv(h, &v, sizeof(T));
 }
 
+// Checkpointed reverse sweep: the forward passes' outputs (need bytes) are kept when they and
+// one more vector fit in half of the free device memory (the context's own checkpoint buffer
+// counts as free), or always when the context says so and they fit at all.
+bool ckpt_fits(qaoa_ctx *ctx, size_t need, size_t vbytes) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const size_t have = fr + ctx->ckpt.cap;
+  if (need > have) return false;
+  return ctx->checkpoint_mode == 1 || need + vbytes <= have / 2;
+}
+
 template <typename R>
 void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
                 int grad, double *out_expect, double *out_grad, void *d_state_out, hipStream_t st,
-                const qaoa_mixer *xm = nullptr, const XDefer *df = nullptr) {
+                const qaoa_mixer *xm = nullptr, const XDefer *df = nullptr, const PlanOpts *force = nullptr);
+
+// Plan options of one evaluation shape: the context's tuned choice for (n, precision, gradient,
+// mixer, whether checkpoints fit), measured on first use when the context tunes, else the
+// fixed rule. The angle-set count is not part of the key, so a batched call and a single
+// evaluation of the same problem follow the same plan and give bit-identical results.
+template <typename R>
+PlanOpts plan_for(qaoa_problem *prob, int p, const double *angles, int nsets, int grad, const qaoa_mixer *xm,
+                  hipStream_t st, bool may_tune);
+
+template <typename R>
+void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
+                int grad, double *out_expect, double *out_grad, void *d_state_out, hipStream_t st,
+                const qaoa_mixer *xm, const XDefer *df, const PlanOpts *force) {
   const bool dev = !df || df->launch;  // enqueue device work
   qaoa_ctx *ctx = prob->ctx;
   const int prec = sizeof(R) == 4 ? QAOA_FP32 : QAOA_FP64;
   const int T = prec == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
   const int cmin = prec == QAOA_FP32 ? MIN_CONTIG_F32 : MIN_CONTIG_F64;
+  const int cnarrow = prec == QAOA_FP32 ? MIN_CONTIG_NARROW_F32 : MIN_CONTIG_NARROW_F64;
   const int n = prob->n;
-  const std::vector<TileGeo> tiles = make_tiles(n, T, cmin);
+  const PlanOpts po = force ? *force : plan_for<R>(prob, p, angles, nsets, grad, xm, st, !df);
+  const std::vector<TileGeo> tiles = make_tiles(n, T, cmin, cnarrow, po);
   const int K = (int)tiles.size();
   const int L = xm ? 2 * p : p;  // layers of the pass plan
   const bool ma = xm && xm->kind == 4;      // per-qubit angles
   const int SL = ma ? p * (n + 1) : 2 * p;  // angles per set
-  const std::vector<FwdPass> fwd = make_forward(K, L);
+  const std::vector<FwdPass> fwd = make_forward(K, L, po.down != 0);
   const uint32_t nwg = 1u << (n - T);
   const uint64_t N = 1ull << n;
   const size_t esz = 2 * sizeof(R);
@@ -580,14 +658,8 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   bool ckpt = false;
   if (df && *df->ckpt >= 0) {
     ckpt = *df->ckpt != 0;  // the decision the captured work was planned with
-  } else if (grad && ctx->checkpoint_mode != 0) {
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-      const size_t need = (size_t)npf_est * vbytes;
-      const size_t have = fr + ctx->ckpt.cap;
-      ckpt = ctx->checkpoint_mode == 1 || need + vbytes <= have / 2;
-      if (need > have) ckpt = false;
-    }
+  } else if (grad && ctx->checkpoint_mode != 0 && po.ckpt != 0) {
+    ckpt = ckpt_fits(ctx, (size_t)npf_est * vbytes, vbytes);
   }
   if (df) *df->ckpt = ckpt ? 1 : 0;
   void *dphi = ckpt ? nullptr : ctx->phi.get(vbytes);
@@ -746,7 +818,7 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     a.c = tiles[tile].c;
     a.h0 = tiles[tile].h0;
     a.nwg = nwg;
-    a.xcd_remap = nwg >= 8 ? 1 : 0;
+    a.xcd_remap = (nwg >= 8 && po.xcd) ? 1 : 0;
     a.nsets = nsets;
     a.vstride = N;
     a.phi = dphi;
@@ -1359,6 +1431,103 @@ void evaluate_grover(qaoa_problem *prob, int p, const double *angles, int nsets,
   }
 }
 
+// The tuner. Candidate plans differ in one option at a time (coordinate descent from the fixed
+// rule over the options that change this shape's plan: checkpointed or in-place reverse sweep,
+// narrow-run cover, which tile takes the narrowest runs, the register-group rules, the tile
+// order of the first round, the XCD-aware workgroup order). Each candidate runs the caller's
+// evaluation shape on its first min(p, 2) layers (the per-pass cost does not depend on p) on
+// the caller's stream: one run to settle allocations, then the faster of two timed runs; a
+// change is kept when it is at least 1 % faster.
+template <typename R>
+PlanOpts plan_for(qaoa_problem *prob, int p, const double *angles, int nsets, int grad, const qaoa_mixer *xm,
+                  hipStream_t st, bool may_tune) {
+  qaoa_ctx *ctx = prob->ctx;
+  const int prec = sizeof(R) == 4 ? QAOA_FP32 : QAOA_FP64;
+  const int T = prec == QAOA_FP32 ? TILE_BITS_F32 : TILE_BITS_F64;
+  const int cmin = prec == QAOA_FP32 ? MIN_CONTIG_F32 : MIN_CONTIG_F64;
+  const int cnarrow = prec == QAOA_FP32 ? MIN_CONTIG_NARROW_F32 : MIN_CONTIG_NARROW_F64;
+  const int n = prob->n;
+  const PlanOpts def;
+  const int L = xm ? 2 * p : p;
+  const int K = (int)make_tiles(n, T, cmin, cnarrow, def).size();
+  const size_t vbytes = (size_t)nsets * ((size_t)1 << n) * 2 * sizeof(R);
+  const bool fits = grad && ctx->checkpoint_mode != 0 && ckpt_fits(ctx, (size_t)(1 + L * (K - 1)) * vbytes, vbytes);
+  const int mixcode = xm ? 1 + 16 * xm->kind + xm->xd.mode : 0;
+  const std::array<int, 5> key = {n, prec, grad ? 1 : 0, mixcode, fits ? 1 : 0};
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) return it->second;
+  if (!ctx->autotune || !may_tune) return def;
+
+  const bool ma = xm && xm->kind == 4;
+  const int pt = std::min(p, 2);
+  const int SL = ma ? p * (n + 1) : 2 * p, SLt = ma ? pt * (n + 1) : 2 * pt;
+  const int nb = ma ? n : 1;  // beta angles per layer
+  std::vector<double> at((size_t)nsets * SLt);
+  for (int s = 0; s < nsets; s++) {
+    const double *src = angles + (size_t)s * SL;
+    double *dst = at.data() + (size_t)s * SLt;
+    std::memcpy(dst, src, sizeof(double) * pt * nb);
+    std::memcpy(dst + pt * nb, src + p * nb, sizeof(double) * pt);
+  }
+  std::vector<double> e(nsets), g(grad ? (size_t)nsets * SLt : 0);
+  auto run = [&](const PlanOpts &o) {
+    run_x_path<R>(prob, pt, at.data(), nsets, nullptr, grad, e.data(), grad ? g.data() : nullptr, nullptr, st, xm,
+                  nullptr, &o);
+  };
+  auto timed = [&](const PlanOpts &o) {
+    run(o);
+    double best = 1e300;
+    for (int r = 0; r < 2; r++) {
+      const auto t0 = std::chrono::steady_clock::now();
+      run(o);  // synchronises the stream before it returns its results
+      best = std::min(best, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    }
+    return best;
+  };
+  // the trials are not part of any measured call: kernel timing is off while they run
+  struct ProfOff {
+    qaoa_ctx *c;
+    bool was;
+    ~ProfOff() { c->profiling = was; }
+  } prof_off{ctx, ctx->profiling};
+  ctx->profiling = false;
+  PlanOpts best = def;
+  if (!fits) best.ckpt = 0;
+  double tbest = timed(best);
+  auto consider = [&](PlanOpts o) {
+    const double t = timed(o);
+    if (t < 0.99 * tbest) {
+      best = o;
+      tbest = t;
+    }
+  };
+  if (fits) {
+    PlanOpts o = best;
+    o.ckpt = 0;
+    consider(o);
+  }
+  for (int which = 0; which < 3; which++)
+    if (plan_knob_applies(which, n, T, cmin, cnarrow, best)) {
+      PlanOpts o = best;
+      if (which == 0) o.narrow ^= 1;
+      if (which == 1) o.narrow_top ^= 1;
+      if (which == 2) o.lowbits ^= 1;
+      consider(o);
+    }
+  if (K >= 2) {
+    PlanOpts o = best;
+    o.down ^= 1;
+    consider(o);
+  }
+  if (n - T >= 3) {
+    PlanOpts o = best;
+    o.xcd ^= 1;
+    consider(o);
+  }
+  ctx->plans[key] = best;
+  return best;
+}
+
 void evaluate_x(qaoa_problem *prob, int p, const double *angles, int nsets, const void *d_psi0,
                 int precision, int grad, double *out_expect, double *out_grad, void *d_state,
                 hipStream_t st) {
@@ -1447,8 +1616,99 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out) {
     if (const char *e = std::getenv("QAOA_GRAD_CHECKPOINT")) c->checkpoint_mode = std::atoi(e) ? 1 : 0;
     if (const char *e = std::getenv("QAOA_XPROD_TILES")) c->xprod_tiles = std::atoi(e) ? 1 : 0;
     if (const char *e = std::getenv("QAOA_BATCH_GRAPH")) c->batch_graphs = std::atoi(e) ? 1 : 0;
+    if (const char *e = std::getenv("QAOA_AUTOTUNE")) c->autotune = std::atoi(e) ? 1 : 0;
     c->scratch = scratch_address(hip_device);
     *out = c.release();
+  });
+}
+
+int qaoa_ctx_set_autotune(qaoa_ctx *ctx, int enable) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr, "ctx is NULL");
+    ctx->autotune = enable != 0;
+  });
+}
+
+static std::string plans_text(const qaoa_ctx *ctx) {
+  std::string out = "qaoa-plans 1\n";
+  char line[160];
+  for (const auto &kv : ctx->plans) {
+    const auto &k = kv.first;
+    const PlanOpts &o = kv.second;
+    std::snprintf(line, sizeof(line), "%d %d %d %d %d : %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], o.narrow,
+                  o.narrow_top, o.lowbits, o.down, o.xcd, o.ckpt);
+    out += line;
+  }
+  return out;
+}
+
+int qaoa_plans_text(const qaoa_ctx *ctx, char *buf, size_t len, size_t *needed) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr, "ctx is NULL");
+    const std::string t = plans_text(ctx);
+    if (needed) *needed = t.size() + 1;
+    if (buf && len > 0) {
+      const size_t m = std::min(len - 1, t.size());
+      std::memcpy(buf, t.data(), m);
+      buf[m] = 0;
+    }
+  });
+}
+
+int qaoa_plans_save(const qaoa_ctx *ctx, const char *path) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr && path != nullptr, "ctx or path is NULL");
+    const std::string t = plans_text(ctx), tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    REQUIRE(f != nullptr, "cannot open the plan file for writing");
+    const bool ok = std::fwrite(t.data(), 1, t.size(), f) == t.size();
+    const bool closed = std::fclose(f) == 0;
+    REQUIRE(ok && closed, "writing the plan file failed");
+    REQUIRE(std::rename(tmp.c_str(), path) == 0, "renaming the plan file failed");
+  });
+}
+
+int qaoa_plans_load(qaoa_ctx *ctx, const char *path) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr && path != nullptr, "ctx or path is NULL");
+    FILE *f = std::fopen(path, "r");
+    REQUIRE(f != nullptr, "cannot open the plan file");
+    std::map<std::array<int, 5>, PlanOpts> got;
+    char line[256];
+    bool header = false, bad = false;
+    while (std::fgets(line, sizeof(line), f)) {
+      if (!header) {
+        header = std::strncmp(line, "qaoa-plans 1", 12) == 0;
+        if (!header) bad = true;
+        if (bad) break;
+        continue;
+      }
+      std::array<int, 5> k{};
+      int v[6];
+      if (std::sscanf(line, "%d %d %d %d %d : %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &v[0], &v[1],
+                      &v[2], &v[3], &v[4], &v[5]) != 11) {
+        bad = true;
+        break;
+      }
+      bool ok = k[0] >= 1 && k[0] <= 33 && (k[1] == 0 || k[1] == 1) && (k[2] == 0 || k[2] == 1) &&
+                (k[4] == 0 || k[4] == 1) && v[5] >= -1 && v[5] <= 1;
+      for (int i = 0; i < 5; i++) ok = ok && (v[i] == 0 || v[i] == 1);
+      if (!ok) {
+        bad = true;
+        break;
+      }
+      PlanOpts o;
+      o.narrow = (uint8_t)v[0];
+      o.narrow_top = (uint8_t)v[1];
+      o.lowbits = (uint8_t)v[2];
+      o.down = (uint8_t)v[3];
+      o.xcd = (uint8_t)v[4];
+      o.ckpt = (int8_t)v[5];
+      got[k] = o;
+    }
+    std::fclose(f);
+    REQUIRE(header && !bad, "malformed plan file");
+    for (const auto &kv : got) ctx->plans[kv.first] = kv.second;
   });
 }
 
@@ -2385,6 +2645,13 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
     G = &ctx->bgraphs.back();
     G->key = key;
     G->ckpt.assign(tile_probs.size(), -1);
+  }
+  // each instance's plan (tuned here on first use when the context tunes: the staging below
+  // may be captured, and a capture cannot time anything)
+  for (int i : tile_probs) {
+    qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
+    if (precision == QAOA_FP32) (void)plan_for<float>(pr, p, angles, n_sets, grad, nullptr, st, true);
+    else (void)plan_for<double>(pr, p, angles, n_sets, grad, nullptr, st, true);
   }
   // enqueue (launch) or only stage (replay) the work of every instance on stream s
   auto stage_all = [&](bool launch, hipStream_t s, uint64_t *fp) {

@@ -15,6 +15,10 @@ constexpr int PASS_THREADS = 256;
 // Shortest run of contiguous amplitudes a strided tile keeps together (256 B either way).
 constexpr int MIN_CONTIG_F32 = 5;
 constexpr int MIN_CONTIG_F64 = 4;
+// Shortest run a strided tile may take when that saves a whole tile of the cover (64 B either
+// way: n = 30..33 in FP32 and 29..32 in FP64 then need three tiles instead of four).
+constexpr int MIN_CONTIG_NARROW_F32 = 3;
+constexpr int MIN_CONTIG_NARROW_F64 = 2;
 // Whole-state (one workgroup per item) kernel: both vectors resident in LDS.
 constexpr int SMALL_MAX_N_F32 = 13;
 constexpr int SMALL_MAX_N_F64 = 12;

@@ -1,0 +1,177 @@
+"""Tile-pass plans: each option of a plan (reverse sweep in place or from checkpoints, tile
+cover, low-qubit placement, first-round tile order, workgroup order) gives the oracle's
+results; the tuner's choice is shared by single and batched evaluations (bit-identical) and a
+saved plan file reproduces a run bit for bit in a new context. The narrow-run covers (three
+tiles instead of four: n = 30..33 in FP32, 29..32 in FP64) are checked at full size against
+the cycle light cone, which holds at any size."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: (1e-5, 1e-5), 1: (1e-12, 1e-11)}   # precision -> (<C> rel, grad inf-rel)
+OPTS = ("narrow", "narrow_top", "lowbits", "down", "xcd", "ckpt")
+DEFAULT = dict(narrow=1, narrow_top=1, lowbits=1, down=0, xcd=1, ckpt=-1)
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2312_06451_amd as q
+    return q
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _gerr(g, ref):
+    return float(np.max(np.abs(np.asarray(g) - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _plan_file(path, n, opts):
+    """A plan file that gives every key of n (both precisions, with and without gradient,
+    checkpoints fitting or not) the options `opts` (transverse-field mixer)."""
+    o = dict(DEFAULT, **opts)
+    vals = " ".join(str(o[k]) for k in OPTS)
+    with open(path, "w") as f:
+        f.write("qaoa-plans 1\n")
+        for prec in (0, 1):
+            for grad in (0, 1):
+                for fits in (0, 1):
+                    f.write(f"{n} {prec} {grad} 0 {fits} : {vals}\n")
+
+
+def _cycle(n):
+    u = np.arange(n, dtype=np.int32)
+    v = (u + 1) % n
+    return workloads.Graph(n, np.minimum(u, v).astype(np.int32), np.maximum(u, v).astype(np.int32),
+                           np.ones(n, dtype=np.int32))
+
+
+@pytest.fixture(scope="module")
+def reg22():
+    g = workloads.random_regular_graph(22, 3, 2222)
+    a = workloads.random_angles(3, 1, 2223)[0]
+    E, Nr, G = oracle.grad(22, oracle.graph_table(g), a)
+    return g, a, E / Nr, G / Nr
+
+
+@pytest.mark.parametrize("opts", [{}, {"lowbits": 0}, {"down": 1}, {"xcd": 0}, {"ckpt": 0},
+                                  {"down": 1, "lowbits": 0, "xcd": 0, "ckpt": 0}])
+def test_plan_options_match_oracle(q, tmp_path, reg22, opts):
+    """n = 22, p = 3 (three tiles in both precisions): every option against the FP64 oracle,
+    forward and fwd+grad, after loading the plan from a file."""
+    g, a, E, G = reg22
+    path = str(tmp_path / "plans.txt")
+    _plan_file(path, 22, opts)
+    ctx = q.Context(0)
+    ctx.load_plans(path)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, 22)
+    for prec in (0, 1):
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        e1 = q.expect(P, M, a, precision=prec)
+        print("plan", opts, "prec", prec, "E err", _rel(e, E), "grad err", _gerr(gr, G), flush=True)
+        assert _rel(e, E) < TOL[prec][0] and _rel(e1, E) < TOL[prec][0]
+        assert _gerr(gr, G) < TOL[prec][1]
+    text = ctx.plans()
+    assert text.splitlines()[0] == "qaoa-plans 1" and len(text.splitlines()) == 9
+    P.close(); M.close(); ctx.close()
+
+
+def test_tuner_shared_by_single_and_batched(q, tmp_path, reg22):
+    """With the tuner on, the first evaluation measures the plan of its key; a batched call over
+    several angle sets follows the same plan (bit-identical to single evaluations), and a new
+    context that loads the saved plans reproduces both bit for bit."""
+    g, a, E, G = reg22
+    sets = np.vstack([a, workloads.random_angles(3, 2, 2224)])
+    ctx = q.Context(0)
+    ctx.set_autotune(True)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, 22)
+    e0, g0 = q.expect_grad(P, M, a, precision=0)
+    lines = ctx.plans().splitlines()
+    print("tuned plans:", lines, flush=True)
+    assert len(lines) == 2 and lines[1].startswith("22 0 1 0 ")
+    assert _rel(e0, E) < TOL[0][0] and _gerr(g0, G) < TOL[0][1]
+    eb, gb = q.expect_grad_batched([P], [M], sets, precision=0)
+    assert eb[0, 0] == e0 and np.array_equal(gb[0, 0], g0)
+    singles = [q.expect_grad(P, M, s, precision=0) for s in sets]
+    for i, (es, gs) in enumerate(singles):
+        assert eb[0, i] == es and np.array_equal(gb[0, i], gs)
+    path = str(tmp_path / "tuned.txt")
+    ctx.save_plans(path)
+    ctx2 = q.Context(0)
+    ctx2.load_plans(path)
+    assert ctx2.plans() == ctx.plans()
+    P2, M2 = q.Problem.from_graph(ctx2, g), q.Mixer.x(ctx2, 22)
+    e2, g2 = q.expect_grad(P2, M2, a, precision=0)
+    assert e2 == e0 and np.array_equal(g2, g0)
+    for c, PP, MM in ((ctx, P, M), (ctx2, P2, M2)):
+        PP.close(); MM.close(); c.close()
+
+
+def test_plan_file_rejects_malformed(q, tmp_path):
+    ctx = q.Context(0)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("qaoa-plans 1\n22 0 1 0 1 : 1 1 1 0 1\n")   # one option missing
+    with pytest.raises(q.QAOAError):
+        ctx.load_plans(str(bad))
+    bad.write_text("plans\n")
+    with pytest.raises(q.QAOAError):
+        ctx.load_plans(str(bad))
+    assert ctx.plans() == "qaoa-plans 1\n"
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,prec", [(30, 0), (29, 1)])
+def test_narrow_cover_light_cone(q, tmp_path, n, prec):
+    """The first sizes whose fewest-tile cover takes narrow runs (FP32 n = 30: 13 + 9 + 8 bits
+    with 64- and 128-byte runs; FP64 n = 29: 12 + 9 + 8 bits), fwd+grad on the cycle C_n at
+    p = 3 against the light cone (dense evolution of the 8-vertex path, no oracle), with the
+    narrow cover and with the four-tile cover loaded from a plan file."""
+    from tests import pins
+    p = 3
+    g = _cycle(n)
+    a = workloads.random_angles(p, 1, 4130 + n)[0]
+    ev, eg = pins.cycle_edge(p, a)
+    res = {}
+    for narrow in (1, 0):
+        ctx = q.Context(0)
+        path = str(tmp_path / f"plans{narrow}.txt")
+        _plan_file(path, n, {"narrow": narrow})
+        ctx.load_plans(path)
+        P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        print(f"n={n} prec={prec} narrow={narrow}: E err {_rel(e, n * ev):.2e} grad err "
+              f"{np.max(np.abs(gr - n * eg)) / (n * np.max(np.abs(eg))):.2e}", flush=True)
+        assert _rel(e, n * ev) < TOL[prec][0]
+        assert np.max(np.abs(gr - n * eg)) < max(TOL[prec][1], 1e-9) * n * np.max(np.abs(eg))
+        res[narrow] = (e, gr)
+        P.close(); M.close(); ctx.close()
+    assert _rel(res[1][0], res[0][0]) < TOL[prec][0]
+
+
+def test_n32_cycle_light_cone_p8(q):
+    """n = 32 (three tiles with narrow runs, reverse sweep in place) at p = 8 on the cycle C_32
+    against the light cone (path of 18 vertices, block-exponential mixer, no oracle): <C> and
+    three gradient entries, both precisions."""
+    from tests import pins
+    n, p = 32, 8
+    g = _cycle(n)
+    a = workloads.random_angles(p, 1, 4832)[0]
+    comps = [0, p - 1, p]
+    ev, eg = pins.cycle_edge_blocks(p, a, components=comps)
+    ctx = q.Context(0)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+    for prec in (0, 1):
+        e, gr = q.expect_grad(P, M, a, precision=prec)
+        print(f"n=32 p=8 prec={prec}: E err {_rel(e, n * ev):.2e}", flush=True)
+        assert _rel(e, n * ev) < TOL[prec][0]
+        scale = n * np.nanmax(np.abs(eg))
+        for i in comps:
+            assert abs(gr[i] - n * eg[i]) < max(TOL[prec][1], 1e-9) * scale
+    P.close(); M.close(); ctx.close()
