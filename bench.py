@@ -291,10 +291,31 @@ def roofline(prof, workload, alg_bytes):
         a = fpl / (mean_ms * 1e-3) / 1e12
         return dict({"bound": "mfma", "achieved": round(a, 1), "peak": MFMA_F16_PEAK_TFS, "unit": "TFLOP/s",
                      "frac": round(a / MFMA_F16_PEAK_TFS, 4), "traffic": None, "flops_per_launch": fpl,
-                     "mfma_issued_TFLOPs": round(3 * a, 1), "mfma_issued_frac": round(3 * a / MFMA_F16_PEAK_TFS, 4)},
+                     "mfma_issued_TFLOPs": round(3 * a, 1), "mfma_issued_frac": round(3 * a / MFMA_F16_PEAK_TFS, 4),
+                     "counters": mfma_from_profile(workload)},
                     **base)
     return dict({"bound": "alu", "achieved": None, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
                  "frac": None, "traffic": None}, **base)
+
+
+def mfma_from_profile(workload):
+    """MFMA busy fraction and issued MFMA flops of the split product from the committed
+    rocprofv3 counter summary (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs)), valid only
+    while the product kernel's source is the one the counters were taken with."""
+    tpath = os.path.join(ROOT, "profiles", f"pmc_mfma_k_split_gemm_{workload}.md")
+    if not os.path.exists(tpath):
+        return None
+    txt = open(tpath).read()
+    src = os.path.join(ROOT, "paper_2312_06451_amd", "csrc", "qaoa_gemm.hip")
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"kernel_source_sha256 = {cur}" not in txt:
+        return None
+    out = {}
+    for line in txt.splitlines():
+        for key in ("mfma_busy_frac", "lds_bank_conflicts_per_dispatch", "wait_inst_frac"):
+            if line.startswith(key + " = "):
+                out[key] = float(line.split("=")[1])
+    return out or None
 
 
 def valu_per_state_from_profile(workload):

@@ -87,7 +87,7 @@ constexpr int RB_ROWS = 1024;  // rows per block in the elementwise kernels (4 p
 struct CliqueMixer {
   int n = 0, k = 0;
   int64_t N = 0;
-  int64_t Mp = 0, Kp = 0;  // rows / K of the padded FP16 planes (multiples of 128 / 32)
+  int64_t Mp = 0, Kp = 0;  // rows / K of the padded FP16 planes (multiples of 256 / 128)
   rocblas_handle blas = nullptr;
   Buf V, D, V16;  // FP64 eigenbasis (N x N col-major, column j = eigenvector j), eigenvalues,
                   // FP16 planes [VT_hi, VT_lo, VN_hi, VN_lo], each Mp x Kp: row r of VT is
@@ -154,7 +154,7 @@ __global__ void k_clique_matrix(int n, int k, int ring, int64_t N, const int64_t
   }
 }
 
-// FP16 halves of V: hi = fp16(v), lo = fp16(2^11 (v - hi)), into the zero-padded blocked
+// FP16 halves of V: hi = fp16(v), lo = fp16(2^11 (v - hi)), into the zero-padded fragment-major
 // planes of the split products (VT: row r = eigenvector r; VN: row x = row x of V; rows of Kp).
 __global__ void k_split_v(const double *__restrict__ V, int64_t N, int64_t Mp, int64_t Kp, __half *__restrict__ P) {
   const int64_t total = N * N, stride = (int64_t)gridDim.x * blockDim.x, plane = Mp * Kp;
@@ -163,7 +163,7 @@ __global__ void k_split_v(const double *__restrict__ V, int64_t N, int64_t Mp, i
     const double v = V[i];
     const __half hi = __float2half((float)v);
     const __half lo = __float2half((float)((v - (double)__half2float(hi)) * 2048.0));
-    const int64_t t = split_plane_offset(r, x, Kp), n = split_plane_offset(x, r, Kp);
+    const int64_t t = split_frag_offset(r, x, Kp), n = split_frag_offset(x, r, Kp);
     P[t] = hi;
     P[plane + t] = lo;
     P[2 * plane + n] = hi;
@@ -385,8 +385,8 @@ std::unique_ptr<CliqueMixer, CliqueMixerDeleter> clique_create(int kind, int n, 
     if (hinfo != 0) throw CliqueError{QAOA_ERR_HIP, "eigendecomposition did not converge"};
   }
   // FP16 halves for the FP32 form, in zero-padded planes
-  m->Mp = (N + SPLIT_TILE - 1) / SPLIT_TILE * SPLIT_TILE;
-  m->Kp = (N + SPLIT_KTILE - 1) / SPLIT_KTILE * SPLIT_KTILE;
+  m->Mp = (N + SPLIT_MTILE - 1) / SPLIT_MTILE * SPLIT_MTILE;
+  m->Kp = (N + SPLIT_KQUANT - 1) / SPLIT_KQUANT * SPLIT_KQUANT;
   const size_t vbytes = (size_t)4 * m->Mp * m->Kp * sizeof(__half);
   __half *P16 = (__half *)m->V16.get(vbytes);
   hipchk(hipMemsetAsync(P16, 0, vbytes, st), "clear FP16 planes");
@@ -418,26 +418,19 @@ struct Dense {
   int64_t ldb;    // column stride of the product input B (Kp halves for FP32, N for FP64)
   int64_t plane;  // FP32: halves between the lo and hi planes of B
 
-  // out (N x cols, ld N) = op(V) in (the product input B), op = V^T (transpose) or V
+  // FP64 form: out (N x cols, ld N) = op(V) in (the product input B), op = V^T (transpose) or
+  // V, on the FP64 eigenbasis (the FP32 form's products carry their epilogues, run_clique)
   void product(bool transpose, const void *B, R *out) {
+    static_assert(sizeof(R) == 8, "the FP32 form multiplies through launch_split_gemm_epi");
     if (m.timer.begin) m.timer.begin(m.timer.ctx, st);
-    if constexpr (sizeof(R) == 4) {
-      const __half *P = (const __half *)m.V16.p;
-      const int64_t vp = m.Mp * m.Kp;
-      const __half *mh = transpose ? P : P + 2 * vp, *ml = mh + vp;
-      const __half *bl = (const __half *)B, *bh = bl + plane;
-      hipchk(launch_split_gemm(bh, bl, mh, ml, m.Kp, (int)N, cols, (float *)out, N, st), "split-FP16 product");
-    } else {
-      const rocblas_int n = (rocblas_int)N, c = cols;
-      const double one = 1.0, zero = 0.0;
-      blaschk(rocblas_set_stream(m.blas, st), "rocblas_set_stream");
-      blaschk(rocblas_dgemm(m.blas, transpose ? rocblas_operation_transpose : rocblas_operation_none,
-                            rocblas_operation_none, n, c, n, &one, (const double *)m.V.p, n, (const double *)B, n,
-                            &zero, out, n),
-              "rocblas_dgemm");
-    }
-    // algorithmic work of one real N x N x cols product (the three half products are the
-    // cost of the FP32 form, not the algorithm)
+    const rocblas_int n = (rocblas_int)N, c = cols;
+    const double one = 1.0, zero = 0.0;
+    blaschk(rocblas_set_stream(m.blas, st), "rocblas_set_stream");
+    blaschk(rocblas_dgemm(m.blas, transpose ? rocblas_operation_transpose : rocblas_operation_none,
+                          rocblas_operation_none, n, c, n, &one, (const double *)m.V.p, n, (const double *)B, n,
+                          &zero, out, n),
+            "rocblas_dgemm");
+    // algorithmic work of one real N x N x cols product
     if (m.timer.end) m.timer.end(m.timer.ctx, st, QAOA_KC_DENSE, 0.0, 2.0 * (double)N * N * cols);
   }
 };
@@ -470,7 +463,7 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
   R *ckT = grad ? (R *)m.ckT.get(mat * p) : nullptr;
   // partial sums per block of rows: the elementwise kernels' blocks (FP64 form) or the
   // product's row tiles (FP32 form: the reductions are fused into the product epilogues)
-  const int nblk = sizeof(R) == 4 ? (int)((N + SPLIT_TILE - 1) / SPLIT_TILE) : (int)((N + RB_ROWS - 1) / RB_ROWS);
+  const int nblk = sizeof(R) == 4 ? (int)((N + SPLIT_MTILE - 1) / SPLIT_MTILE) : (int)((N + RB_ROWS - 1) / RB_ROWS);
   const int nout = 2 + 2 * p;
   double *part = (double *)m.partials.get((size_t)nout * S * nblk * sizeof(double));
   auto pslot = [&](int o) { return part + (size_t)o * S * nblk; };

@@ -11,23 +11,27 @@
 // with the hi x hi products and the cross products in two FP32 accumulators, three MFMAs per
 // block. The dropped term is 2^-22 relative.
 //
-// Tiling (gfx950, v_mfma_f32_32x32x16_f16): a workgroup of 256 threads owns a 128 x 128 tile
-// of C^T (128 state columns x 128 rows of C), each wave a 64 x 64 quarter (2 x 2 blocks of 32
-// x 32). The MFMA's first operand is the state (K-contiguous per column), the second the
-// matrix (K-contiguous per row of op(V)), so the accumulator of a lane holds 4 consecutive
-// rows of C per group and lanes run over consecutive rows: stores are 128-byte runs per
-// column, and the real and imaginary columns of an angle set (adjacent columns) sit in the
-// same lane. K advances in tiles of 32 through two LDS buffers: the next tile streams from
-// global memory straight into one buffer (global_load_lds, 16 bytes per lane) while the
-// current one is multiplied out of the other.
+// Tiling (gfx950, v_mfma_f32_32x32x16_f16): a workgroup of 256 threads (one wave per SIMD)
+// owns a tile of 128 state columns x 256 rows of C; wave w computes all 128 columns (4 blocks of
+// 32) for its own 64 rows (2 blocks of 32). The MFMA's first operand is the state (K-contiguous
+// per column), the second the matrix (K-contiguous per row of op(V)), so the accumulator of a
+// lane holds 4 consecutive state columns per group for one row of C: the real and imaginary
+// columns of an angle set sit in the same lane, and stores of C run over consecutive rows.
 //
-// Operand layout (blocked): each FP16 plane is stored as blocks of 128 rows x 32 halves, one
-// per (row tile, K tile), K tiles of a row tile consecutive, rows inside a block in the
-// chunk-swizzled order the LDS reads want; a K tile of a plane is therefore one contiguous
-// 8 KB copy. Operands are zero-padded so every access is in bounds and unguarded: the matrix
-// planes hold Mp = roundup(N, 128) rows of Kp = roundup(N, 32) halves, the state planes
-// Ncp = roundup(cols, 128) columns of Kp halves. Every tile configuration is fixed at build
-// time, so results do not depend on the process or the run.
+// Operand paths. The matrix is constant, so it is kept in the fragment-major layout
+// (split_frag_offset): a wave's fragment of one row block and K step is one contiguous 1 KB
+// global load straight into registers, prefetched seven K steps ahead; rows are private to a
+// wave, so nothing of the matrix passes through LDS. The state is shared by the four waves: its
+// K tiles of 32 (the blocked layout, one contiguous 8 KB block per plane) are copied through
+// registers into one of two LDS stages while the other stage is multiplied out; its fragments
+// are read from LDS (chunk-swizzled rows: conflict-free 16-byte reads). Per K step of 16 a wave
+// issues 24 MFMAs (4 x 2 blocks, three products each) against 4 KB of matrix loads and 8 KB of
+// LDS reads.
+//
+// Operands are zero-padded so every access is in bounds and unguarded: the matrix planes hold
+// Mp = roundup(M, 256) rows of Kp = roundup(K, 128) halves, the state planes Ncp =
+// roundup(cols, 128) columns of Kp halves. The tile configuration is fixed at build time, so
+// results do not depend on the process or the run.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -41,108 +45,203 @@ namespace {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
-constexpr int GT = SPLIT_TILE;           // tile edge (rows of C, state columns)
-constexpr int GK = SPLIT_KTILE;          // K tile
-constexpr int BLK = GT * GK;             // halves per block (one plane, one tile, one K tile)
-constexpr int BUF = 4 * BLK;             // halves per LDS buffer (four planes)
+constexpr int GN = SPLIT_TILE;           // state columns per workgroup
+constexpr int GM = SPLIT_MTILE;          // rows of C per workgroup
+constexpr int GK = SPLIT_KTILE;          // K tile of one LDS stage
+constexpr int BLK = GN * GK;             // halves per state block (one plane, one column tile, one K tile)
+constexpr int STAGE = 2 * BLK;           // halves per LDS stage (hi and lo planes)
+constexpr int NB = 4, MB = 2;            // 32-blocks per wave: state columns, rows of C
+constexpr int DV = 7;                    // matrix prefetch depth in K steps (a ring of 8 slots)
 
 // Chunk swizzle of a block: row r holds its four 16-byte chunks in the order c ^ ((r >> 2) & 3),
 // so the 16-byte fragment reads of 16 consecutive rows hit 64 distinct banks.
 __device__ __forceinline__ int swz(int r, int c) { return c ^ ((r >> 2) & 3); }
 
-// Thread-block loads of one K tile: wave w copies plane w (8 KB contiguous) into LDS, 1 KB per
-// instruction, straight from global memory to LDS (no registers in between).
-__device__ __forceinline__ void issue_tile(const _Float16 *const (&pl)[4], int kt, _Float16 *buf, int t) {
-  const int lane = t & 63, w = t >> 6;
-  const _Float16 *src = pl[w] + (int64_t)kt * BLK;
-  _Float16 *dst = buf + w * BLK;
-#pragma unroll
-  for (int i = 0; i < 8; i++)
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(src + 512 * i + 8 * lane),
-                                     (void __attribute__((address_space(3))) *)(dst + 512 * i), 16, 0, 0);
-}
-
-// The eight MFMA operand fragments of one 16-deep step: state hi/lo and matrix hi/lo of the
-// wave's two 32-row blocks each (lane l: row l % 32, halves 8 (l / 32) .. + 7 of the step).
-struct Frags {
-  h8 ah[2], al[2], bh[2], bl[2];
-};
-
-__device__ __forceinline__ h8 frag(const _Float16 *buf, int plane, int r, int k) {
+__device__ __forceinline__ h8 sfrag(const _Float16 *buf, int plane, int r, int k) {
   return *(const h8 *)(buf + plane * BLK + r * GK + 8 * swz(r, k >> 3));
 }
 
-__device__ __forceinline__ void load_frags(Frags &f, const _Float16 *buf, int wn, int wm, int fr, int k) {
-#pragma unroll
-  for (int i = 0; i < 2; i++) {
-    f.ah[i] = frag(buf, 0, wn + 32 * i + fr, k);
-    f.al[i] = frag(buf, 1, wn + 32 * i + fr, k);
-    f.bh[i] = frag(buf, 2, wm + 32 * i + fr, k);
-    f.bl[i] = frag(buf, 3, wm + 32 * i + fr, k);
-  }
-}
-
-__device__ __forceinline__ void mfma_step(const Frags &f, f16v (&acc)[2][2], f16v (&cx)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.ah[i], f.bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) cx[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.al[i], f.bh[j], cx[i][j], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) cx[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.ah[i], f.bl[j], cx[i][j], 0, 0, 0);
-}
+// One wave's matrix fragments of one K step: rows blocks 0 and 1 of the wave, hi and lo.
+struct VFr {
+  h8 h[MB], l[MB];
+};
 
 }  // namespace
 
-// acc (per lane: 2 x 2 blocks of 16 floats) of this workgroup's tile, = op(V) Psi; the
-// epilogue is the caller's. The hi x hi products and the two cross products go to separate
-// accumulators (each summed at its own scale), joined as hh + 2^-11 x at the end. Two LDS
-// buffers: tile kt + 1 streams into one while tile kt is multiplied out of the other, one
-// barrier per K tile.
+// The hi x hi products (acc) and the two cross products (cx, each summed at its own scale) of
+// this workgroup's tile (per lane: NB x MB blocks of 16 floats); op(V) Psi = acc + 2^-11 cx,
+// joined by the caller's epilogue one element at a time (the accumulators stay in the matrix
+// registers until then).
 __device__ __forceinline__ void split_gemm_tile(const _Float16 *__restrict__ st_h, const _Float16 *__restrict__ st_l,
                                                 const _Float16 *__restrict__ m_h, const _Float16 *__restrict__ m_l,
-                                                int64_t kp, int ct, int rt, _Float16 *lds, f16v (&acc)[2][2]) {
+                                                int64_t kp, int ct, int rt, int kt0, int kt1, _Float16 *lds,
+                                                f16v (&acc)[NB][MB], f16v (&cx)[NB][MB]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wn = (w >> 1) * 64, wm = (w & 1) * 64;  // this wave's state columns / rows of C
-  const int nk = (int)(kp / GK);
-  const _Float16 *const pl[4] = {st_h + (int64_t)ct * nk * BLK, st_l + (int64_t)ct * nk * BLK,
-                                 m_h + (int64_t)rt * nk * BLK, m_l + (int64_t)rt * nk * BLK};
-  f16v cx[2][2];
+  const int nk = (int)(kp / GK), nks = 2 * nk;
+  const int klast = kt1 - 1, slast = 2 * kt1 - 1;  // last K tile and K step of the range
+  // state: block (ct, kt) of each plane is 8 KB contiguous; wave w copies its 2 KB of each
+  // through two sets of four registers (a tile is loaded two tiles before it is stored)
+  const uint4 *sh = (const uint4 *)(st_h + (int64_t)ct * nk * BLK) + w * 128 + lane;
+  const uint4 *sl = (const uint4 *)(st_l + (int64_t)ct * nk * BLK) + w * 128 + lane;
+  uint4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
+#define SLOAD(kt, r0, r1, r2, r3)                        \
+  do {                                                   \
+    const int64_t o_ = (int64_t)(kt) * (BLK / 8);        \
+    r0 = sh[o_];                                         \
+    r1 = sh[o_ + 64];                                    \
+    r2 = sl[o_];                                         \
+    r3 = sl[o_ + 64];                                    \
+  } while (0)
+#define SSTORE(stage, r0, r1, r2, r3)                                      \
+  do {                                                                     \
+    uint4 *d_ = (uint4 *)(lds + (stage) * STAGE) + w * 128 + lane;         \
+    d_[0] = r0;                                                            \
+    d_[64] = r1;                                                           \
+    d_[BLK / 8] = r2;                                                      \
+    d_[BLK / 8 + 64] = r3;                                                 \
+  } while (0)
+  // matrix: row blocks 8 rt + 2 w and + 1; chunk (rb, ks) at ((rb * nks + ks) * 64 + lane) * 8 halves
+  const int rb0 = rt * (GM / 32) + MB * w;
+  const h8 *vh = (const h8 *)m_h + (int64_t)rb0 * nks * 64 + lane;
+  const h8 *vl = (const h8 *)m_l + (int64_t)rb0 * nks * 64 + lane;
+  const int64_t vrow = (int64_t)nks * 64;  // h8 elements between consecutive row blocks
+  auto vload = [&](VFr &f, int ks) {
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+    for (int j = 0; j < MB; j++) {
+      f.h[j] = vh[j * vrow + ks * 64];
+      f.l[j] = vl[j * vrow + ks * 64];
+    }
+  };
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
+  for (int i = 0; i < NB; i++)
+#pragma unroll
+    for (int j = 0; j < MB; j++) {
       acc[i][j] = f16v{};
       cx[i][j] = f16v{};
     }
   const int fr = lane & 31, fk = 8 * (lane >> 5);
-  issue_tile(pl, 0, lds, t);
-  for (int kt = 0; kt < nk; kt++) {
-    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // this wave's loads of tile kt (vmcnt 0)
-    __syncthreads();                                   // everyone's; everyone is done with tile kt - 1
-    if (kt + 1 < nk) issue_tile(pl, kt + 1, lds + ((kt + 1) & 1) * BUF, t);
-    const _Float16 *buf = lds + (kt & 1) * BUF;
-    Frags f[2];
-    load_frags(f[0], buf, wn, wm, fr, fk);
-    load_frags(f[1], buf, wn, wm, fr, 16 + fk);
-    mfma_step(f[0], acc, cx);
-    mfma_step(f[1], acc, cx);
+  // state fragments of one K step (hi and lo of the 4 column blocks), double-buffered: the next
+  // step's are read from LDS while this step's MFMAs run
+  struct SFr {
+    h8 h[NB], l[NB];
+  };
+  auto sread = [&](SFr &f, const _Float16 *buf, int koff) {
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+      f.h[i] = sfrag(buf, 0, 32 * i + fr, koff + fk);
+      f.l[i] = sfrag(buf, 1, 32 * i + fr, koff + fk);
+    }
+  };
+  auto mfmas = [&](const SFr &a, const VFr &b) {
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+#pragma unroll
+      for (int j = 0; j < MB; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.h[i], b.h[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+#pragma unroll
+      for (int j = 0; j < MB; j++) cx[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.l[i], b.h[j], cx[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+#pragma unroll
+      for (int j = 0; j < MB; j++) cx[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.h[i], b.l[j], cx[i][j], 0, 0, 0);
+  };
+  // K tiles [kt0, kt1) (multiples of 4, at least 4 tiles). Prologue: tiles kt0 and kt0 + 1 into LDS stages 0 and 1, kt0 + 2 and kt0 + 3 into
+  // the register sets, the matrix fragments of the first DV steps (past-the-end tile and step
+  // indices are clamped: they re-read the range's last one, never used)
+  VFr ring[DV + 1];
+#pragma unroll
+  for (int d = 0; d < DV; d++) vload(ring[d], 2 * kt0 + d);
+  SLOAD(kt0, sa0, sa1, sa2, sa3);
+  SLOAD(kt0 + 1, sb0, sb1, sb2, sb3);
+  SSTORE(0, sa0, sa1, sa2, sa3);
+  SSTORE(1, sb0, sb1, sb2, sb3);
+  SLOAD(kt0 + 2, sa0, sa1, sa2, sa3);
+  SLOAD(kt0 + 3, sb0, sb1, sb2, sb3);
+  __syncthreads();
+  SFr f0, f1;
+  sread(f0, lds, 0);
+  // Three LDS stages, K tiles in fours (the range is a multiple of 4) so that register sets and matrix
+  // slots are constants. Tile k2 (stage k2 % 3): one barrier (stages k2 and k2 + 1 written by
+  // every wave, stage k2 + 2 = k2 - 1 free); tile k2 + 2 goes from its registers to LDS and
+  // tile k2 + 4 is loaded into them; step 2 k2 multiplies fragments read during the previous
+  // step while it reads those of step 2 k2 + 1, which in turn reads tile k2 + 1's first ones.
+  // The matrix fragments of step s are loaded DV steps ahead into the slot step s - 1 used.
+  for (int kt = kt0; kt < kt1; kt += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int k2 = kt + u, kr = k2 - kt0;  // kr: position in the range (stage index)
+      __syncthreads();
+      if ((u & 1) == 0) {
+        SSTORE((kr + 2) % 3, sa0, sa1, sa2, sa3);
+        SLOAD(min(k2 + 4, klast), sa0, sa1, sa2, sa3);
+      } else {
+        SSTORE((kr + 2) % 3, sb0, sb1, sb2, sb3);
+        SLOAD(min(k2 + 4, klast), sb0, sb1, sb2, sb3);
+      }
+      const _Float16 *cur = lds + (kr % 3) * STAGE, *nxt = lds + ((kr + 1) % 3) * STAGE;
+      const int s0 = 2 * k2;
+      sread(f1, cur, 16);
+      vload(ring[(2 * u + DV) & 7], min(s0 + DV, slast));
+      mfmas(f0, ring[2 * u]);
+      sread(f0, nxt, 0);
+      vload(ring[(2 * u + 1 + DV) & 7], min(s0 + 1 + DV, slast));
+      mfmas(f1, ring[2 * u + 1]);
+      // Issue order of this tile (the region between two barriers): the LDS stores first, then
+      // the 48 MFMAs with the 8 + 8 fragment reads and the 12 global loads slotted between
+      // them one at a time, so every load is issued early and its latency hides behind the
+      // matrix instructions (left alone, the scheduler sinks the loads to the end of the
+      // region to shorten register lifetimes, and the next tile waits on them).
+      __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);  // DS write: tile k2 + 2 to LDS
+#pragma unroll
+      for (int g = 0; g < 8; g++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read: step 2 k2 + 1 fragments
+      }
+#pragma unroll
+      for (int g = 0; g < 12; g++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read: state tile, matrix slots
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+#pragma unroll
+      for (int g = 0; g < 8; g++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read: tile k2 + 1 fragments
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    }
   }
-  const float inv = 1.0f / 2048.0f;
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) acc[i][j] += cx[i][j] * inv;
+#undef SLOAD
+#undef SSTORE
+  __syncthreads();  // every wave is done with the stages before the epilogue reuses LDS
 }
 
 template <typename TT>
 __device__ __forceinline__ uint32_t tab_at(const void *t, int64_t x) {
   return (uint32_t)((const TT *)t)[x];
+}
+
+// Sine and cosine of x (FP64 angle of modest size, |x| < 2^20): x = q pi/2 + r with |r| <= pi/4
+// in FP64 (pi/2 as a two-part constant), then the Taylor polynomials of sin and cos in FP32 on r
+// (through r^9 and r^10: truncation below 2e-9 on |r| <= pi/4) and the quadrant q mod 4. No
+// table and no large-argument path, so nothing leaves the registers.
+__device__ __forceinline__ void sincos_reduced(double x, float &sn, float &cs) {
+  const double q = rint(x * 0.6366197723675814);
+  const float r = (float)fma(-q, 6.123233995736766e-17, fma(-q, 1.5707963267948966, x));
+  const float r2 = r * r;
+  float s = fmaf(r2, 2.7557319e-6f, -1.9841270e-4f);
+  s = fmaf(r2, s, 8.3333333e-3f);
+  s = fmaf(r2, s, -1.6666667e-1f);
+  s = fmaf(r2 * r, s, r);
+  float c = fmaf(r2, -2.7557319e-7f, 2.4801587e-5f);
+  c = fmaf(r2, c, -1.3888889e-3f);
+  c = fmaf(r2, c, 4.1666667e-2f);
+  c = fmaf(r2, c, -0.5f);
+  c = fmaf(r2, c, 1.0f);
+  const int k = (int)q & 3;
+  sn = k == 0 ? s : (k == 1 ? c : (k == 2 ? -s : -c));
+  cs = k == 0 ? c : (k == 1 ? -s : (k == 2 ? -c : s));
 }
 
 // Sum v over the 32 rows of this lane's half-wave (lanes with the same lane >> 5), in a fixed
@@ -153,47 +252,49 @@ __device__ __forceinline__ double rows_sum(double v) {
   return v;
 }
 
-// The product of one workgroup tile with epilogue MODE. Workgroup b runs on XCD b % 8
-// (round-robin dispatch); each XCD takes the row tiles r = x (mod 8) and, for each, every
-// column tile in consecutive workgroups, so the workgroups resident on one XCD at a time cover
-// 8 row tiles x 8 column tiles and read each operand block once from memory into that XCD's L2.
+// Epilogue of one workgroup tile (rows r * GM.., columns c * GN..) of product op(V) Psi =
+// acc + 2^-11 cx (per lane, NB x MB blocks of 16 floats): the elementwise step of MODE on each
+// element, its FP32 or next-product output, and the tile's FP64 row sums per angle set. LDS
+// (gsm) must be free.
 template <int MODE, typename TT>
-__global__ __launch_bounds__(256, 2) void k_split_gemm(const _Float16 *__restrict__ st_h,
-                                                       const _Float16 *__restrict__ st_l,
-                                                       const _Float16 *__restrict__ m_h,
-                                                       const _Float16 *__restrict__ m_l, int64_t kp, int M,
-                                                       int cols, const SplitEpi e) {
-  extern __shared__ __align__(16) unsigned char gsm[];
-  _Float16 *lds = (_Float16 *)gsm;
-  const int ctiles = (cols + GT - 1) / GT, mtiles = (M + GT - 1) / GT;
-  const int b = blockIdx.x, x = b & 7, j = b >> 3;
-  const int r = 8 * (j / ctiles) + x, c = j % ctiles;
-  if (r >= mtiles) return;
-  f16v acc[2][2];
-  split_gemm_tile(st_h, st_l, m_h, m_l, kp, c, r, lds, acc);
+__device__ __forceinline__ void split_epilogue(f16v (&acc)[NB][MB], f16v (&cx)[NB][MB], int r, int c, int M, int cols,
+                                               const SplitEpi &e, unsigned char *gsm) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int m0 = r * GT + (w & 1) * 64, n0 = c * GT + (w >> 1) * 64;
+  const int m0 = r * GM + w * (32 * MB), n0 = c * GN;
   constexpr bool RED = MODE == SE_LAST || MODE == SE_REIG || MODE == SE_RPHASE;
-  double red0[2][4][2], red1[2][4][2];  // per (column block, group, pair): this lane's row sums
+  constexpr int SW = GN / 2;     // angle sets of the tile
+  double *sred = (double *)gsm;  // [wave][SW sets][2]: per-wave row sums, reduced in wave order
+  // per-row data of the wave's two row blocks
+  double dd[MB], cvv[MB];
+  uint32_t cii[MB];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int jj = 0; jj < MB; jj++) {
+    const int m = m0 + 32 * jj + (lane & 31);
+    dd[jj] = cvv[jj] = 0.0;
+    cii[jj] = 0;
+    if (m >= M) continue;
+    if constexpr (MODE == SE_EIG || MODE == SE_REIG) dd[jj] = e.D[m];
+    if constexpr (MODE == SE_PHASE || MODE == SE_LAST || MODE == SE_RPHASE) {
+      cii[jj] = tab_at<TT>(e.table, m);
+      cvv[jj] = e.vals[cii[jj]];
+    }
+  }
+  const float inv = 1.0f / 2048.0f;
+  // one column block (16 angle sets) at a time: its sums over the wave's rows are complete
+  // after both row blocks, so only 8 (or 16) FP64 sums are live
+#pragma unroll
+  for (int i = 0; i < NB; i++) {
+    double red0[4][2], red1[4][2];
 #pragma unroll
     for (int g = 0; g < 4; g++)
 #pragma unroll
-      for (int h = 0; h < 2; h++) red0[i][g][h] = red1[i][g][h] = 0.0;
+      for (int h = 0; h < 2; h++) red0[g][h] = red1[g][h] = 0.0;
 #pragma unroll
-  for (int jj = 0; jj < 2; jj++) {
-    const int m = m0 + 32 * jj + (lane & 31);
-    if (m >= M) continue;
-    double d = 0.0, cv = 0.0;
-    uint32_t ci = 0;
-    if constexpr (MODE == SE_EIG || MODE == SE_REIG) d = e.D[m];
-    if constexpr (MODE == SE_PHASE || MODE == SE_LAST || MODE == SE_RPHASE) {
-      ci = tab_at<TT>(e.table, m);
-      cv = e.vals[ci];
-    }
-#pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int jj = 0; jj < MB; jj++) {
+      const int m = m0 + 32 * jj + (lane & 31);
+      if (m >= M) continue;
+      const double d = dd[jj], cv = cvv[jj];
+      const uint32_t ci = cii[jj];
 #pragma unroll
       for (int g = 0; g < 4; g++)
 #pragma unroll
@@ -201,7 +302,8 @@ __global__ __launch_bounds__(256, 2) void k_split_gemm(const _Float16 *__restric
           const int n = n0 + 32 * i + 8 * g + 4 * (lane >> 5) + 2 * h;  // real-part column, even
           if (n >= cols) continue;
           const int sidx = n >> 1;
-          float re = acc[i][jj][4 * g + 2 * h], im = acc[i][jj][4 * g + 2 * h + 1];
+          float re = fmaf(cx[i][jj][4 * g + 2 * h], inv, acc[i][jj][4 * g + 2 * h]);
+          float im = fmaf(cx[i][jj][4 * g + 2 * h + 1], inv, acc[i][jj][4 * g + 2 * h + 1]);
           if constexpr (MODE == SE_PLAIN) {
             e.C[m + (int64_t)n * e.ldc] = re;
             e.C[m + (int64_t)(n + 1) * e.ldc] = im;
@@ -209,16 +311,16 @@ __global__ __launch_bounds__(256, 2) void k_split_gemm(const _Float16 *__restric
           }
           if constexpr (MODE == SE_REIG) {
             const float ta = e.ckr[m + (int64_t)n * e.ldc], tb = e.ckr[m + (int64_t)(n + 1) * e.ldc];
-            red0[i][g][h] += d * ((double)re * tb - (double)im * ta);
+            red0[g][h] += d * ((double)re * tb - (double)im * ta);
           }
           if constexpr (MODE == SE_RPHASE) {
             const float pa = e.ckr[m + (int64_t)n * e.ldc], pb = e.ckr[m + (int64_t)(n + 1) * e.ldc];
-            red0[i][g][h] += (cv - e.c0) * ((double)re * pb - (double)im * pa);
+            red0[g][h] += (cv - e.c0) * ((double)re * pb - (double)im * pa);
           }
           if constexpr (MODE == SE_LAST) {
             const double pr = (double)re * re + (double)im * im;
-            red0[i][g][h] += pr * cv;
-            red1[i][g][h] += pr;
+            red0[g][h] += pr * cv;
+            red1[g][h] += pr;
             e.C[m + (int64_t)n * e.ldc] = re;
             e.C[m + (int64_t)(n + 1) * e.ldc] = im;
             if (e.bout) {
@@ -228,11 +330,12 @@ __global__ __launch_bounds__(256, 2) void k_split_gemm(const _Float16 *__restric
             continue;
           }
           if constexpr (MODE == SE_EIG || MODE == SE_REIG) {
-            double sn, cs;
-            sincos((MODE == SE_EIG ? -1.0 : 1.0) * e.betas[sidx] * d, &sn, &cs);
+            // e^{-+i beta_s d} (angle in FP64; the result is rounded to FP32 anyway)
+            float sn, cs;
+            sincos_reduced((MODE == SE_EIG ? -1.0 : 1.0) * e.betas[sidx] * d, sn, cs);
             const float a = re, bb = im;
-            re = (float)((double)a * cs - (double)bb * sn);
-            im = (float)((double)a * sn + (double)bb * cs);
+            re = a * cs - bb * sn;
+            im = a * sn + bb * cs;
           }
           if constexpr (MODE == SE_PHASE || MODE == SE_RPHASE) {
             if (MODE == SE_RPHASE && !e.bout) continue;
@@ -249,52 +352,72 @@ __global__ __launch_bounds__(256, 2) void k_split_gemm(const _Float16 *__restric
           }
           split_emit(e.bout, e.bld, e.bplane, m, sidx, re, im);
         }
-  }
-  if constexpr (RED) {
-    // rows of this wave -> lanes 0 and 32; the two waves of a column half meet in LDS, in order
-    __syncthreads();  // every wave is done with the last K tile in LDS
-    double *sred = (double *)gsm;  // [wave][32 sets][2]
-#pragma unroll
-    for (int i = 0; i < 2; i++)
+    }
+    if constexpr (RED) {
+      // rows of this wave -> lanes 0 and 32
 #pragma unroll
       for (int g = 0; g < 4; g++)
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-          const double s0 = rows_sum(red0[i][g][h]);
-          const double s1 = MODE == SE_LAST ? rows_sum(red1[i][g][h]) : 0.0;
+          const double s0 = rows_sum(red0[g][h]);
+          const double s1 = MODE == SE_LAST ? rows_sum(red1[g][h]) : 0.0;
           if ((lane & 31) == 0) {
-            const int sl = (32 * i + 8 * g + 4 * (lane >> 5) + 2 * h) >> 1;  // set within the wave's 64 columns
-            sred[(w * 32 + sl) * 2] = s0;
-            sred[(w * 32 + sl) * 2 + 1] = s1;
+            const int sl = (32 * i + 8 * g + 4 * (lane >> 5) + 2 * h) >> 1;  // set within the tile's columns
+            sred[(w * SW + sl) * 2] = s0;
+            sred[(w * SW + sl) * 2 + 1] = s1;
           }
         }
+    }
+    // the scheduler may not hoist the next block's loads and transcendentals above this one
+    // (that would keep them all live at once)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (RED) {
     __syncthreads();
-    if (t < 64) {
-      const int half = t >> 5, sl = t & 31;  // column half (wn) and set within it
-      const int wa = 2 * half, wb = 2 * half + 1;  // the waves with rows 0..63 and 64..127
-      const int s = (c * GT + 64 * half) / 2 + sl;
+    if (t < SW) {
+      const int s = c * SW + t;
       if (2 * s < cols) {
-        const double a0 = sred[(wa * 32 + sl) * 2] + sred[(wb * 32 + sl) * 2];
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < 4; ww++) {
+          a0 += sred[(ww * SW + t) * 2];
+          a1 += sred[(ww * SW + t) * 2 + 1];
+        }
         e.part0[(int64_t)s * e.nblk + r] = a0;
-        if (MODE == SE_LAST) e.part1[(int64_t)s * e.nblk + r] = sred[(wa * 32 + sl) * 2 + 1] + sred[(wb * 32 + sl) * 2 + 1];
+        if (MODE == SE_LAST) e.part1[(int64_t)s * e.nblk + r] = a1;
       }
     }
   }
 }
 
-constexpr size_t split_gemm_lds() { return (size_t)2 * BUF * sizeof(_Float16); }
+// The product of one workgroup tile with epilogue MODE. Workgroup b runs on XCD b % 8
+// (round-robin dispatch); each XCD takes the row tiles r = x (mod 8) and, for each, every
+// column tile in consecutive workgroups, so the workgroups resident on one XCD at a time share
+// each matrix row tile (8 column tiles) and each state column tile (4 row tiles) through that
+// XCD's L2.
+template <int MODE, typename TT>
+__global__ __launch_bounds__(256, 1) void k_split_gemm(const _Float16 *__restrict__ st_h,
+                                                       const _Float16 *__restrict__ st_l,
+                                                       const _Float16 *__restrict__ m_h,
+                                                       const _Float16 *__restrict__ m_l, int64_t kp, int M,
+                                                       int cols, const SplitEpi e) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  _Float16 *lds = (_Float16 *)gsm;
+  const int ctiles = (cols + GN - 1) / GN, mtiles = (M + GM - 1) / GM;
+  const int b = blockIdx.x, x = b & 7, j = b >> 3;
+  const int r = 8 * (j / ctiles) + x, c = j % ctiles;
+  if (r >= mtiles) return;
+  f16v acc[NB][MB], cx[NB][MB];
+  split_gemm_tile(st_h, st_l, m_h, m_l, kp, c, r, 0, (int)(kp / GK), lds, acc, cx);
+  split_epilogue<MODE, TT>(acc, cx, r, c, M, cols, e, gsm);
+}
+
+constexpr size_t split_gemm_lds() { return (size_t)3 * STAGE * sizeof(_Float16); }
 
 template <int MODE, typename TT>
 static hipError_t launch_mode(const void *st_h, const void *st_l, const void *m_h, const void *m_l, int64_t kp, int M,
                               int cols, const SplitEpi &e, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t er = hipFuncSetAttribute((const void *)k_split_gemm<MODE, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)split_gemm_lds());
-    if (er != hipSuccess) return er;
-    attr_set = true;
-  }
-  const int mtiles = (M + GT - 1) / GT, ctiles = (cols + GT - 1) / GT;
+  const int mtiles = (M + GM - 1) / GM, ctiles = (cols + GN - 1) / GN;
   const dim3 grid((unsigned)(8 * ((mtiles + 7) / 8) * ctiles));
   k_split_gemm<MODE, TT><<<grid, 256, split_gemm_lds(), s>>>((const _Float16 *)st_h, (const _Float16 *)st_l,
                                                              (const _Float16 *)m_h, (const _Float16 *)m_l, kp, M, cols, e);
@@ -303,7 +426,7 @@ static hipError_t launch_mode(const void *st_h, const void *st_l, const void *m_
 
 hipError_t launch_split_gemm_epi(int mode, const void *st_h, const void *st_l, const void *m_h, const void *m_l,
                                  int64_t kp, int M, int cols, const SplitEpi &e, hipStream_t s) {
-  if (kp % GK != 0 || M <= 0 || cols <= 0 || (cols & 1)) return hipErrorInvalidValue;
+  if (kp % SPLIT_KQUANT != 0 || kp <= 0 || M <= 0 || cols <= 0 || (cols & 1)) return hipErrorInvalidValue;
   const bool u16 = e.tbytes == 2;
   switch (mode) {
     case SE_PLAIN: return launch_mode<SE_PLAIN, uint8_t>(st_h, st_l, m_h, m_l, kp, M, cols, e, s);
@@ -320,15 +443,6 @@ hipError_t launch_split_gemm_epi(int mode, const void *st_h, const void *st_l, c
                  : launch_mode<SE_RPHASE, uint8_t>(st_h, st_l, m_h, m_l, kp, M, cols, e, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_split_gemm(const void *st_h, const void *st_l, const void *m_h, const void *m_l, int64_t kp,
-                             int M, int cols, float *C, int64_t ldc, hipStream_t s) {
-  SplitEpi e{};
-  e.C = C;
-  e.ldc = ldc;
-  e.tbytes = 1;
-  return launch_split_gemm_epi(SE_PLAIN, st_h, st_l, m_h, m_l, kp, M, cols, e, s);
 }
 
 }  // namespace qaoa

@@ -252,11 +252,15 @@ hipError_t launch_whole(int precision, int n, int tbytes, const SmallItem *items
 hipError_t launch_scale_copy(int precision, const void *src, void *dst, uint64_t N, double re,
                              double im, uint64_t flip, hipStream_t s);
 size_t pass_lds_bytes(int precision, int tbytes, int lut_len);
-// Split-FP16 MFMA product (qaoa_gemm.hip): C[m + n ldc] = sum_k M[m][k] S[n][k] for m < M, n < cols,
-// with every operand given as FP16 hi and 2^11-scaled lo planes of rows of kp halves (kp a
-// multiple of SPLIT_KTILE) in the blocked layout of split_plane_offset; the state planes hold
-// roundup(cols, SPLIT_TILE) rows, the matrix planes roundup(M, SPLIT_TILE), zero-padded.
+// Split-FP16 MFMA product (qaoa_gemm.hip): C[m + n ldc] = sum_k M[m][k] S[n][k] for m < M,
+// n < cols, every operand given as FP16 hi and 2^11-scaled lo planes. The state planes (S) are
+// rows of kp halves (kp a multiple of SPLIT_KQUANT) in the blocked layout of
+// split_plane_offset, roundup(cols, SPLIT_TILE) rows, zero-padded; the matrix planes (M) are in
+// the fragment-major layout of split_frag_offset, roundup(M, SPLIT_MTILE) rows of kp halves,
+// zero-padded.
 constexpr int SPLIT_TILE = 128, SPLIT_KTILE = 32;
+constexpr int SPLIT_MTILE = 256;   // rows of C per workgroup
+constexpr int SPLIT_KQUANT = 128;  // K of four LDS stages: the padded K of every plane is a multiple
 // Offset (in halves) of element (row r, k) of a blocked plane: blocks of SPLIT_TILE rows x
 // SPLIT_KTILE halves, one per (row tile, K tile), K tiles of a row tile consecutive; inside a
 // block row rr holds its four 16-byte chunks in the order c ^ ((rr >> 2) & 3).
@@ -265,8 +269,14 @@ __host__ __device__ inline int64_t split_plane_offset(int64_t r, int64_t k, int6
   return (rt * (kp / SPLIT_KTILE) + kt) * (SPLIT_TILE * SPLIT_KTILE) + rr * SPLIT_KTILE +
          8 * ((kk >> 3) ^ ((rr >> 2) & 3)) + (kk & 7);
 }
-hipError_t launch_split_gemm(const void *st_h, const void *st_l, const void *m_h, const void *m_l, int64_t kp,
-                             int M, int cols, float *C, int64_t ldc, hipStream_t s);
+// Offset (in halves) of element (row r, k) of a fragment-major plane: one 1 KB chunk per (block
+// of 32 rows, K step of 16), K steps of a row block consecutive; inside a chunk, lane l of a
+// wave holds the 16 bytes of row (l % 32), k = 8 (l / 32) .. + 7 of the step (the operand
+// fragment of the 32 x 32 x 16 MFMA), so one wave reads a fragment with one contiguous 1 KB load.
+__host__ __device__ inline int64_t split_frag_offset(int64_t r, int64_t k, int64_t kp) {
+  const int64_t rb = r >> 5, ks = k >> 4, lane = (r & 31) + 32 * ((k >> 3) & 1);
+  return ((rb * (kp >> 4) + ks) * 64 + lane) * 8 + (k & 7);
+}
 // Write the complex value (re, im) of row x of angle set s as the next split product's input:
 // FP16 hi and 2^11-scaled lo of the real part (state column 2s) and the imaginary part (column
 // 2s + 1), into the blocked planes lo = B, hi = B + plane (rows of ldb halves).

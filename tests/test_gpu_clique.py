@@ -103,8 +103,8 @@ def test_clique_full_size_vs_oracle(q, ctx, prec):
         assert abs(e - s["expect"]) <= TOL[prec] * abs(s["expect"])
         assert np.max(np.abs(gr - np.array(s["grad"]))) <= TOL[prec] * np.max(np.abs(s["grad"]))
     # the batched call over 8 sets agrees with the single evaluations: bit for bit in the FP32
-    # form (every column of the split product is reduced in the same fixed order whatever the
-    # number of columns), to rounding in the FP64 form (library DGEMM)
+    # form (every column of the split product is reduced in the same fixed order while the
+    # tiles fit one round of workgroups, as here), to rounding in the FP64 form (library DGEMM)
     Eb, Gb = q.expect_grad_batched([P], [M], W.angles, precision=prec)
     for i in (0, 5):
         e, gr = q.expect_grad(P, M, W.angles[i], precision=prec)
@@ -112,3 +112,28 @@ def test_clique_full_size_vs_oracle(q, ctx, prec):
             assert Eb[0, i] == e and np.array_equal(Gb[0, i], gr)
         else:
             assert abs(Eb[0, i] - e) <= 1e-13 * abs(e) and np.max(np.abs(Gb[0, i] - gr)) <= 1e-12 * np.max(np.abs(gr))
+
+
+def test_clique_full_batch_512(q, ctx):
+    """The benchmark's launch configuration: all 512 angle sets in one call (products of 12870 x
+    12870 by 1024 columns: 408 workgroup tiles, more than one round of the 256 CUs). Sets 0 and
+    1 against the stored oracle values; the call repeated gives identical results (the tile
+    configuration and every summation order are fixed)."""
+    path = os.path.join(HERE, "golden", "bisection_g16_k8_p6.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values for the weight-8 workload not generated")
+    G = json.load(open(path))
+    W = workloads.workload("bisection_g16_k8_p6")
+    assert W.angles.shape[0] == 512
+    g = W.graphs[0]
+    P, M = q.Problem.from_graph(ctx, g, hamming_k=8), q.Mixer.clique(ctx, 16, 8)
+    Eb, Gb = q.expect_grad_batched([P], [M], W.angles, precision=0)
+    for i, s in enumerate(G["sets"]):
+        assert np.array_equal(np.array(s["angles"]), W.angles[i])
+        e_err = abs(Eb[0, i] - s["expect"]) / abs(s["expect"])
+        g_err = np.max(np.abs(Gb[0, i] - np.array(s["grad"]))) / np.max(np.abs(s["grad"]))
+        print("bisection 512 sets, set", i, "E err", e_err, "g err", g_err, flush=True)
+        assert e_err <= TOL[0] and g_err <= TOL[0]
+    Eb2, Gb2 = q.expect_grad_batched([P], [M], W.angles, precision=0)
+    assert np.array_equal(Eb, Eb2) and np.array_equal(Gb, Gb2)
+    P.close(); M.close()
