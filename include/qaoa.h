@@ -76,7 +76,8 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
  * result exact up to rounding: the reverse sweep reading the forward passes' outputs or
  * undoing the state in place, the tile cover (narrow 64-byte runs where they save a tile;
  * which tile takes them), which tile rotates the low qubits, the tile order of the first
- * round, and the XCD-aware workgroup order. Off (enable = 0, the default): a fixed rule.
+ * round, which strided tile takes the round boundaries (three tiles), and the XCD-aware
+ * workgroup order. Off (enable = 0, the default): a fixed rule.
  * On: the first evaluation of each (n, precision, gradient or not, mixer, whether the
  * checkpoints fit in memory) times the alternatives one at a time on the caller's stream
  * (min(p, 2) layers per trial, about 20 trials) and keeps the fastest; every later
@@ -87,8 +88,9 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
 int qaoa_ctx_set_autotune(qaoa_ctx *ctx, int enable);
 
 /* The context's chosen plans as text, one line per key:
- *   "n precision grad mixer ckpt_fits : narrow narrow_top lowbits down xcd ckpt"
- * after a header line "qaoa-plans 1". buf may be NULL; *needed (if not NULL) receives the
+ *   "n precision grad mixer ckpt_fits : narrow narrow_top lowbits down xcd ckpt swap"
+ * after a header line "qaoa-plans 2" (files with the header "qaoa-plans 1" and no swap field
+ * still load, with swap 0). buf may be NULL; *needed (if not NULL) receives the
  * length including the terminating NUL; at most len bytes are written (always terminated
  * when len > 0). INVALID_ARG for ctx == NULL. */
 int qaoa_plans_text(const qaoa_ctx *ctx, char *buf, size_t len, size_t *needed);

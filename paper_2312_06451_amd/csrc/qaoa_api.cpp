@@ -184,6 +184,8 @@ struct PlanOpts {
   uint8_t narrow = 1;      // strided tiles take runs down to 64 B when that saves a tile
   uint8_t narrow_top = 1;  // with uneven widths, the top tile takes the narrowest runs
   uint8_t lowbits = 1;     // the register-group rules of make_tiles
+  uint8_t swap = 0;        // three tiles: the top tile in the middle of a round (single-block
+                           // passes) instead of at its end (the round-boundary passes)
   uint8_t down = 0;        // the first round visits the tiles from the top one down
   uint8_t xcd = 1;         // XCD-aware workgroup order (consecutive tiles on one XCD)
   int8_t ckpt = -1;        // reverse sweep: -1 the context's memory rule, 0 in place, 1 checkpoints
@@ -209,10 +211,10 @@ struct qaoa_ctx {
   std::vector<std::unique_ptr<HostBuf>> bstage, brstage;
   struct BGraph {
     std::vector<uint64_t> key;
-    std::vector<int> ckpt;        // per instance: reverse-sweep mode the work was planned with
-    uint64_t fp = 0;              // fingerprint of the captured work
-    int calls = 0;                // eager calls with this key so far
-    hipGraphExec_t exec = nullptr;
+    std::vector<int> ckpt;                // per instance: reverse-sweep mode the work was planned with
+    std::vector<uint64_t> fps;            // per unit of work: fingerprint of the captured work
+    std::vector<hipGraphExec_t> execs;    // per unit of work: its graph
+    int calls = 0;                        // eager calls with this key so far
   };
   std::vector<BGraph> bgraphs;
   hipStream_t gstream = nullptr;  // capture stream when the caller passes the null stream
@@ -228,7 +230,8 @@ struct qaoa_ctx {
   KTotals totals[QAOA_KC_COUNT];
   ~qaoa_ctx() {
     for (auto &g : bgraphs)
-      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      for (auto ex : g.execs)
+        if (ex) (void)hipGraphExecDestroy(ex);
     if (gstream) (void)hipStreamDestroy(gstream);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto &p : pending) {
@@ -417,6 +420,9 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin, int cnarrow, const PlanO
     t.push_back({c, next, ((1u << T) - 1) & ~((1u << c) - 1)});
     next += width;
   }
+  // Rounds visit the tiles in vector order (alternating direction), so the middle tile runs as
+  // a single-block pass and the first and last share the round boundaries (two-block passes).
+  if (o.swap && t.size() == 3) std::swap(t[1], t[2]);
   if (!o.lowbits) return t;
   // Balance the rotation work between passes. The lowest T - 8 address bits (the L register
   // group) are contiguous bits of every tile, so any tile may rotate them. With three or more
@@ -448,6 +454,7 @@ bool plan_knob_applies(int which, int n, int T, int cmin, int cnarrow, const Pla
     case 0: a.narrow = 1; b.narrow = 0; break;
     case 1: a.narrow_top = 1; b.narrow_top = 0; break;
     case 2: a.lowbits = 1; b.lowbits = 0; break;
+    case 3: a.swap = 1; b.swap = 0; break;
     default: return false;
   }
   auto ta = make_tiles(n, T, cmin, cnarrow, a), tb = make_tiles(n, T, cmin, cnarrow, b);
@@ -1506,12 +1513,13 @@ PlanOpts plan_for(qaoa_problem *prob, int p, const double *angles, int nsets, in
     o.ckpt = 0;
     consider(o);
   }
-  for (int which = 0; which < 3; which++)
+  for (int which = 0; which < 4; which++)
     if (plan_knob_applies(which, n, T, cmin, cnarrow, best)) {
       PlanOpts o = best;
       if (which == 0) o.narrow ^= 1;
       if (which == 1) o.narrow_top ^= 1;
       if (which == 2) o.lowbits ^= 1;
+      if (which == 3) o.swap ^= 1;
       consider(o);
     }
   if (K >= 2) {
@@ -1630,13 +1638,13 @@ int qaoa_ctx_set_autotune(qaoa_ctx *ctx, int enable) {
 }
 
 static std::string plans_text(const qaoa_ctx *ctx) {
-  std::string out = "qaoa-plans 1\n";
+  std::string out = "qaoa-plans 2\n";
   char line[160];
   for (const auto &kv : ctx->plans) {
     const auto &k = kv.first;
     const PlanOpts &o = kv.second;
-    std::snprintf(line, sizeof(line), "%d %d %d %d %d : %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], o.narrow,
-                  o.narrow_top, o.lowbits, o.down, o.xcd, o.ckpt);
+    std::snprintf(line, sizeof(line), "%d %d %d %d %d : %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], o.narrow,
+                  o.narrow_top, o.lowbits, o.down, o.xcd, o.ckpt, o.swap);
     out += line;
   }
   return out;
@@ -1676,22 +1684,27 @@ int qaoa_plans_load(qaoa_ctx *ctx, const char *path) {
     std::map<std::array<int, 5>, PlanOpts> got;
     char line[256];
     bool header = false, bad = false;
+    int version = 0;
     while (std::fgets(line, sizeof(line), f)) {
       if (!header) {
-        header = std::strncmp(line, "qaoa-plans 1", 12) == 0;
+        // version 1 files (written before the swap option) load with swap = 0
+        if (std::strncmp(line, "qaoa-plans 1", 12) == 0) version = 1;
+        if (std::strncmp(line, "qaoa-plans 2", 12) == 0) version = 2;
+        header = version != 0;
         if (!header) bad = true;
         if (bad) break;
         continue;
       }
       std::array<int, 5> k{};
-      int v[6];
-      if (std::sscanf(line, "%d %d %d %d %d : %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &v[0], &v[1],
-                      &v[2], &v[3], &v[4], &v[5]) != 11) {
+      int v[7] = {0, 0, 0, 0, 0, 0, 0};
+      const int want = version == 1 ? 11 : 12;
+      if (std::sscanf(line, "%d %d %d %d %d : %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &v[0], &v[1],
+                      &v[2], &v[3], &v[4], &v[5], &v[6]) != want) {
         bad = true;
         break;
       }
       bool ok = k[0] >= 1 && k[0] <= 33 && (k[1] == 0 || k[1] == 1) && (k[2] == 0 || k[2] == 1) &&
-                (k[4] == 0 || k[4] == 1) && v[5] >= -1 && v[5] <= 1;
+                (k[4] == 0 || k[4] == 1) && v[5] >= -1 && v[5] <= 1 && (v[6] == 0 || v[6] == 1);
       for (int i = 0; i < 5; i++) ok = ok && (v[i] == 0 || v[i] == 1);
       if (!ok) {
         bad = true;
@@ -1704,6 +1717,7 @@ int qaoa_plans_load(qaoa_ctx *ctx, const char *path) {
       o.down = (uint8_t)v[3];
       o.xcd = (uint8_t)v[4];
       o.ckpt = (int8_t)v[5];
+      o.swap = (uint8_t)v[6];
       got[k] = o;
     }
     std::fclose(f);
@@ -2638,7 +2652,8 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
     if (g.key == key) G = &g;
   if (!G) {
     if (ctx->bgraphs.size() >= 64) {  // bounded cache: drop the oldest entry
-      if (ctx->bgraphs.front().exec) (void)hipGraphExecDestroy(ctx->bgraphs.front().exec);
+      for (auto ex : ctx->bgraphs.front().execs)
+        if (ex) (void)hipGraphExecDestroy(ex);
       ctx->bgraphs.erase(ctx->bgraphs.begin());
     }
     ctx->bgraphs.push_back(qaoa_ctx::BGraph{});
@@ -2646,77 +2661,96 @@ static void batched(const qaoa_problem *const *probs, const qaoa_mixer *const *m
     G->key = key;
     G->ckpt.assign(tile_probs.size(), -1);
   }
-  // each instance's plan (tuned here on first use when the context tunes: the staging below
-  // may be captured, and a capture cannot time anything)
-  for (int i : tile_probs) {
-    qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
-    if (precision == QAOA_FP32) (void)plan_for<float>(pr, p, angles, n_sets, grad, nullptr, st, true);
-    else (void)plan_for<double>(pr, p, angles, n_sets, grad, nullptr, st, true);
-  }
-  // enqueue (launch) or only stage (replay) the work of every instance on stream s
-  auto stage_all = [&](bool launch, hipStream_t s, uint64_t *fp) {
-    fin.clear();
-    if (!items.empty()) run_small(items, precision, angles, n_sets, p, grad, hout.data(), ctx, s, &fin, launch, fp);
-    for (size_t j = 0; j < tile_probs.size(); j++) {
-      const int i = tile_probs[j];
-      XDefer df{ctx->bstage[j].get(), ctx->brstage[j].get(), launch, &G->ckpt[j], &fin, fp};
-      qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
-      double *oe = out_expect + (size_t)i * n_sets, *og = grad ? out_grad + (size_t)i * n_sets * g2p : nullptr;
-      if (precision == QAOA_FP32)
-        run_x_path<float>(pr, p, angles, n_sets, nullptr, grad, oe, og, nullptr, s, nullptr, &df);
-      else
-        run_x_path<double>(pr, p, angles, n_sets, nullptr, grad, oe, og, nullptr, s, nullptr, &df);
+  // Units of device work: the whole-state pairs (one launch), then each tile-path instance.
+  // Staging a unit (its host planning and parameter upload) overlaps the device work of the
+  // units before it, eagerly and as graphs alike: one graph per unit.
+  const int u0 = items.empty() ? 0 : 1, nunits = u0 + (int)tile_probs.size();
+  auto stage_unit = [&](int u, bool launch, hipStream_t s, uint64_t *fp) {
+    if (u < u0) {
+      run_small(items, precision, angles, n_sets, p, grad, hout.data(), ctx, s, &fin, launch, fp);
+      return;
     }
+    const int jj = u - u0, i = tile_probs[jj];
+    XDefer df{ctx->bstage[jj].get(), ctx->brstage[jj].get(), launch, &G->ckpt[jj], &fin, fp};
+    qaoa_problem *pr = const_cast<qaoa_problem *>(probs[i]);
+    double *oe = out_expect + (size_t)i * n_sets, *og = grad ? out_grad + (size_t)i * n_sets * g2p : nullptr;
+    if (precision == QAOA_FP32)
+      run_x_path<float>(pr, p, angles, n_sets, nullptr, grad, oe, og, nullptr, s, nullptr, &df);
+    else
+      run_x_path<double>(pr, p, angles, n_sets, nullptr, grad, oe, og, nullptr, s, nullptr, &df);
   };
+  auto drop_graphs = [&]() {
+    for (auto ex : G->execs)
+      if (ex) (void)hipGraphExecDestroy(ex);
+    G->execs.clear();
+    G->fps.clear();
+  };
+  const uint64_t fnv0 = 1469598103934665603ull;
   const bool graphs = ctx->batch_graphs && !ctx->profiling && p <= 1024;
-  bool done = false;
-  if (graphs && G->exec) {
-    // replay: re-stage the parameters; the captured work must be what this call would enqueue
-    uint64_t fp = 1469598103934665603ull;
-    stage_all(false, st ? st : ctx->gstream, &fp);
-    if (fp == G->fp) {
-      hipStream_t gs = st ? st : ctx->gstream;
-      HIPCHK(hipGraphLaunch(G->exec, gs));
-      HIPCHK(hipStreamSynchronize(gs));
-      done = true;
-    } else {
-      (void)hipGraphExecDestroy(G->exec);  // planned differently (e.g. another reverse-sweep
-      G->exec = nullptr;                    // scalar form): run eagerly, capture again later
+  if (graphs && (!st && !ctx->gstream)) HIPCHK(hipStreamCreate(&ctx->gstream));
+  hipStream_t gs = st ? st : ctx->gstream;
+  if (graphs && (int)G->execs.size() == nunits) {
+    // replay: re-stage each unit's parameters (the captured work must be what this call
+    // would enqueue) and launch its graph; a unit planned differently (e.g. another reverse-
+    // sweep scalar form) and the ones after it run eagerly, and the key is captured again
+    int u = 0;
+    for (; u < nunits; u++) {
+      const size_t nfin = fin.size();
+      uint64_t fp = fnv0;
+      stage_unit(u, false, gs, &fp);
+      if (fp != G->fps[u]) {
+        fin.resize(nfin);
+        break;
+      }
+      HIPCHK(hipGraphLaunch(G->execs[u], gs));
+    }
+    if (u < nunits) {
+      for (; u < nunits; u++) stage_unit(u, true, gs, nullptr);
+      drop_graphs();
       G->calls = 0;
     }
+    HIPCHK(hipStreamSynchronize(gs));
   } else if (graphs && G->calls >= 1) {
-    // capture: every buffer was sized by the earlier call with this key
-    if (!st && !ctx->gstream) HIPCHK(hipStreamCreate(&ctx->gstream));
-    hipStream_t gs = st ? st : ctx->gstream;
+    // capture unit by unit (every buffer was sized by the earlier call with this key); each
+    // unit's graph is launched as soon as it is instantiated
+    drop_graphs();
     if (!st) HIPCHK(hipDeviceSynchronize());  // the capture stream does not order with the null stream
-    uint64_t fp = 1469598103934665603ull;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-      try {
-        stage_all(true, gs, &fp);
-      } catch (...) {
-        ok = false;
+    int u = 0;
+    for (; u < nunits; u++) {
+      uint64_t fp = fnv0;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      const size_t nfin = fin.size();
+      bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        try {
+          stage_unit(u, true, gs, &fp);
+        } catch (...) {
+          ok = false;
+        }
+        ok = (hipStreamEndCapture(gs, &graph) == hipSuccess) && ok && graph;
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
       }
-      ok = (hipStreamEndCapture(gs, &graph) == hipSuccess) && ok && graph;
-      ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      if (!ok) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        fin.resize(nfin);
+        break;
+      }
+      G->execs.push_back(exec);
+      G->fps.push_back(fp);
+      HIPCHK(hipGraphLaunch(exec, gs));
     }
-    (void)hipGetLastError();
-    if (ok) {
-      G->exec = exec;
-      G->fp = fp;
-      HIPCHK(hipGraphLaunch(G->exec, gs));
-      HIPCHK(hipStreamSynchronize(gs));
-      done = true;
-    } else {
-      if (exec) (void)hipGraphExecDestroy(exec);
-      G->calls = -(1 << 30);  // not capturable: this key stays eager
+    if (u < nunits) {
+      // not capturable: the rest runs eagerly and this key stays eager
+      for (; u < nunits; u++) stage_unit(u, true, gs, nullptr);
+      drop_graphs();
+      G->calls = -(1 << 30);
     }
-  }
-  if (!done) {
-    stage_all(true, st, nullptr);
+    HIPCHK(hipStreamSynchronize(gs));
+  } else {
+    for (int u = 0; u < nunits; u++) stage_unit(u, true, st, nullptr);
     HIPCHK(hipStreamSynchronize(st));
     G->calls++;
   }

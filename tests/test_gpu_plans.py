@@ -1,5 +1,6 @@
 """Tile-pass plans: each option of a plan (reverse sweep in place or from checkpoints, tile
-cover, low-qubit placement, first-round tile order, workgroup order) gives the oracle's
+cover, low-qubit placement, first-round tile order, which tile takes the round boundaries,
+workgroup order) gives the oracle's
 results; the tuner's choice is shared by single and batched evaluations (bit-identical) and a
 saved plan file reproduces a run bit for bit in a new context. The narrow-run covers (three
 tiles instead of four: n = 30..33 in FP32, 29..32 in FP64) are checked at full size against
@@ -15,8 +16,8 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 TOL = {0: (1e-5, 1e-5), 1: (1e-12, 1e-11)}   # precision -> (<C> rel, grad inf-rel)
-OPTS = ("narrow", "narrow_top", "lowbits", "down", "xcd", "ckpt")
-DEFAULT = dict(narrow=1, narrow_top=1, lowbits=1, down=0, xcd=1, ckpt=-1)
+OPTS = ("narrow", "narrow_top", "lowbits", "down", "xcd", "ckpt", "swap")
+DEFAULT = dict(narrow=1, narrow_top=1, lowbits=1, down=0, xcd=1, ckpt=-1, swap=0)
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +40,7 @@ def _plan_file(path, n, opts):
     o = dict(DEFAULT, **opts)
     vals = " ".join(str(o[k]) for k in OPTS)
     with open(path, "w") as f:
-        f.write("qaoa-plans 1\n")
+        f.write("qaoa-plans 2\n")
         for prec in (0, 1):
             for grad in (0, 1):
                 for fits in (0, 1):
@@ -61,8 +62,8 @@ def reg22():
     return g, a, E / Nr, G / Nr
 
 
-@pytest.mark.parametrize("opts", [{}, {"lowbits": 0}, {"down": 1}, {"xcd": 0}, {"ckpt": 0},
-                                  {"down": 1, "lowbits": 0, "xcd": 0, "ckpt": 0}])
+@pytest.mark.parametrize("opts", [{}, {"lowbits": 0}, {"down": 1}, {"xcd": 0}, {"ckpt": 0}, {"swap": 1},
+                                  {"swap": 1, "ckpt": 0}, {"down": 1, "lowbits": 0, "xcd": 0, "ckpt": 0}])
 def test_plan_options_match_oracle(q, tmp_path, reg22, opts):
     """n = 22, p = 3 (three tiles in both precisions): every option against the FP64 oracle,
     forward and fwd+grad, after loading the plan from a file."""
@@ -79,7 +80,7 @@ def test_plan_options_match_oracle(q, tmp_path, reg22, opts):
         assert _rel(e, E) < TOL[prec][0] and _rel(e1, E) < TOL[prec][0]
         assert _gerr(gr, G) < TOL[prec][1]
     text = ctx.plans()
-    assert text.splitlines()[0] == "qaoa-plans 1" and len(text.splitlines()) == 9
+    assert text.splitlines()[0] == "qaoa-plans 2" and len(text.splitlines()) == 9
     P.close(); M.close(); ctx.close()
 
 
@@ -117,13 +118,18 @@ def test_tuner_shared_by_single_and_batched(q, tmp_path, reg22):
 def test_plan_file_rejects_malformed(q, tmp_path):
     ctx = q.Context(0)
     bad = tmp_path / "bad.txt"
-    bad.write_text("qaoa-plans 1\n22 0 1 0 1 : 1 1 1 0 1\n")   # one option missing
+    bad.write_text("qaoa-plans 2\n22 0 1 0 1 : 1 1 1 0 1 -1\n")   # one option missing
     with pytest.raises(q.QAOAError):
         ctx.load_plans(str(bad))
     bad.write_text("plans\n")
     with pytest.raises(q.QAOAError):
         ctx.load_plans(str(bad))
-    assert ctx.plans() == "qaoa-plans 1\n"
+    assert ctx.plans() == "qaoa-plans 2\n"
+    # a version-1 file (no swap field) loads with swap = 0
+    old = tmp_path / "v1.txt"
+    old.write_text("qaoa-plans 1\n22 0 1 0 1 : 1 1 1 1 1 -1\n")
+    ctx.load_plans(str(old))
+    assert ctx.plans().splitlines()[1] == "22 0 1 0 1 : 1 1 1 1 1 -1 0"
     ctx.close()
 
 
