@@ -80,8 +80,10 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
  * workgroup order. Off (enable = 0, the default): a fixed rule.
  * On: the first evaluation of each (n, precision, gradient or not, mixer, whether the
  * checkpoints fit in memory) times the alternatives one at a time on the caller's stream
- * (min(p, 2) layers per trial, about 20 trials) and keeps the fastest; every later
- * evaluation of that key, single or batched, any number of angle sets, uses it. Different
+ * (min(p, 4) layers per trial, by the summed kernel durations; a change is kept when it is
+ * at least 2 % faster) and keeps the fastest. Every later evaluation of that key, single or
+ * batched, any number of angle sets, uses the choice; a batched call itself does not tune
+ * (an instance whose key has no choice yet follows the fixed rule). Different
  * plans round differently (FP32: within the 1e-5 bound), so a run that must repeat another
  * bit for bit saves the plans (qaoa_plans_save) and loads them (qaoa_plans_load).
  * INVALID_ARG for ctx == NULL. */

@@ -115,6 +115,30 @@ def test_tuner_shared_by_single_and_batched(q, tmp_path, reg22):
         PP.close(); MM.close(); c.close()
 
 
+def test_batched_call_does_not_tune(q, reg22):
+    """A batched call never tunes: with no plan for its key it follows the fixed rule (bit for
+    bit the same as a context that does not tune) and records nothing; a later single
+    evaluation tunes the key, and batched calls follow that choice from then on."""
+    g, a, E, G = reg22
+    sets = np.vstack([a, workloads.random_angles(3, 3, 2225)])
+    ctx, ref = q.Context(0), q.Context(0)
+    ctx.set_autotune(True)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, 22)
+    Pr, Mr = q.Problem.from_graph(ref, g), q.Mixer.x(ref, 22)
+    eb, gb = q.expect_grad_batched([P], [M], sets, precision=0)
+    er, gr = q.expect_grad_batched([Pr], [Mr], sets, precision=0)
+    assert ctx.plans() == "qaoa-plans 2\n"
+    assert np.array_equal(eb, er) and np.array_equal(gb, gr)
+    assert _rel(eb[0, 0], E) < TOL[0][0] and _gerr(gb[0, 0], G) < TOL[0][1]
+    e0, g0 = q.expect_grad(P, M, a, precision=0)
+    lines = ctx.plans().splitlines()
+    assert len(lines) == 2 and lines[1].startswith("22 0 1 0 ")
+    eb2, gb2 = q.expect_grad_batched([P], [M], sets, precision=0)
+    assert eb2[0, 0] == e0 and np.array_equal(gb2[0, 0], g0)
+    for c, PP, MM in ((ctx, P, M), (ref, Pr, Mr)):
+        PP.close(); MM.close(); c.close()
+
+
 def test_plan_file_rejects_malformed(q, tmp_path):
     ctx = q.Context(0)
     bad = tmp_path / "bad.txt"
