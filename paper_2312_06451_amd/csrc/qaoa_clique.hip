@@ -94,6 +94,7 @@ struct CliqueMixer {
                   // eigenvector r (the V^T product), row x of VN is row x of V (the V product)
   Buf X, Y, B, B16, ckP, ckT, partials, params, luts, results, hres_dev;  // B: FP64 form's product input,
                                                                           // B16: FP32 form's (FP16 planes)
+  Buf ws;               // the split-FP16 product's workspace (its XCD-balanced schedule)
   size_t b_zeroed = 0;  // bytes of B16 cleared since its allocation (its padding must stay zero)
   std::vector<double> hres;
   CliqueTimer timer;
@@ -513,6 +514,8 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
     int cur = 0;
     const __half *P16 = (const __half *)m.V16.p;
     const int64_t vp = m.Mp * m.Kp;
+    const size_t wsb = split_gemm_ws_bytes((int)N, cols, m.Kp);
+    float *dws = wsb ? (float *)m.ws.get(wsb) : nullptr;
     auto product = [&](bool transpose, int mode, SplitEpi e) {
       const __half *mh = transpose ? P16 : P16 + 2 * vp, *ml = mh + vp;
       const _Float16 *bl = Bset[cur], *bh = bl + plane;
@@ -526,6 +529,7 @@ void run_clique(CliqueMixer &m, const CliqueEval &ev, int p, const double *angle
       e.c0 = ev.c0;
       e.lut_len = ev.lut_len;
       e.nblk = nblk;
+      e.ws = dws;
       if (m.timer.begin) m.timer.begin(m.timer.ctx, st);
       hipchk(launch_split_gemm_epi(mode, bh, bl, mh, ml, m.Kp, (int)N, cols, e, st), "split-FP16 product");
       if (m.timer.end) m.timer.end(m.timer.ctx, st, QAOA_KC_DENSE, 0.0, 2.0 * (double)N * N * cols);

@@ -255,8 +255,8 @@ __device__ __forceinline__ double rows_sum(double v) {
 // Epilogue of one workgroup tile (rows r * GM.., columns c * GN..) of product op(V) Psi =
 // acc + 2^-11 cx (per lane, NB x MB blocks of 16 floats): the elementwise step of MODE on each
 // element, its FP32 or next-product output, and the tile's FP64 row sums per angle set. LDS
-// (gsm) must be free.
-template <int MODE, typename TT>
+// (gsm) must be free. Column blocks [IB, IE) only (each block's angle sets are complete in it).
+template <int MODE, typename TT, int IB = 0, int IE = NB>
 __device__ __forceinline__ void split_epilogue(f16v (&acc)[NB][MB], f16v (&cx)[NB][MB], int r, int c, int M, int cols,
                                                const SplitEpi &e, unsigned char *gsm) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -283,7 +283,7 @@ __device__ __forceinline__ void split_epilogue(f16v (&acc)[NB][MB], f16v (&cx)[N
   // one column block (16 angle sets) at a time: its sums over the wave's rows are complete
   // after both row blocks, so only 8 (or 16) FP64 sums are live
 #pragma unroll
-  for (int i = 0; i < NB; i++) {
+  for (int i = IB; i < IE; i++) {
     double red0[4][2], red1[4][2];
 #pragma unroll
     for (int g = 0; g < 4; g++)
@@ -374,7 +374,7 @@ __device__ __forceinline__ void split_epilogue(f16v (&acc)[NB][MB], f16v (&cx)[N
   }
   if constexpr (RED) {
     __syncthreads();
-    if (t < SW) {
+    if (t >= 16 * IB && t < 16 * IE) {
       const int s = c * SW + t;
       if (2 * s < cols) {
         double a0 = 0.0, a1 = 0.0;
@@ -412,16 +412,160 @@ __global__ __launch_bounds__(256, 1) void k_split_gemm(const _Float16 *__restric
   split_epilogue<MODE, TT>(acc, cx, r, c, M, cols, e, gsm);
 }
 
+// ---- XCD-balanced schedule
+//
+// With one 256-row x 128-column tile per CU at a time, a product of more tiles than CUs runs in
+// rounds, and the last round is partly empty (M = 12870 rows, 1024 columns: 51 x 8 tiles on 256
+// CUs take two full rounds for 1.59 rounds of work). The balanced schedule keeps 32 workgroups
+// per XCD at a time and splits the work evenly over the XCDs along K: a super-tile is RPS =
+// 32 / ctiles row tiles
+// times every column tile, processed by the 32 workgroups of one XCD in step (so each matrix
+// row tile is shared by the column tiles and each state tile by the row tiles through that
+// XCD's L2, as in the plain schedule); the S super-tiles x NQ K quads (4 K tiles each) are cut
+// into 8 equal ranges, one per XCD. A super-tile cut by a range boundary is computed in two K
+// pieces on two XCDs; each piece stores its partial sums to the workspace, and a second
+// kernel adds the two (head piece first) and runs the epilogue. The cuts depend only on the
+// product's shape, so results do not depend on the process or the run.
+struct BalShape {
+  int mtiles, ctiles, rps, S, nq;
+};
+
+__host__ __device__ inline bool bal_shape(int M, int cols, int64_t kp, BalShape &b) {
+  b.mtiles = (M + GM - 1) / GM;
+  b.ctiles = (cols + GN - 1) / GN;
+  b.nq = (int)(kp / (4 * GK));
+  if (b.ctiles > 32) return false;
+  b.rps = 32 / b.ctiles;
+  b.S = (b.mtiles + b.rps - 1) / b.rps;
+  return b.S > 8 && b.S % 8 != 0;
+}
+
+// First K quad (global index super-tile * nq + quad) of XCD x's range; x = 0..8.
+__host__ __device__ inline int64_t bal_cut(const BalShape &b, int x) { return (int64_t)x * b.S * b.nq / 8; }
+
+constexpr int BAL_SLOT = NB * MB * 16 * 256;  // floats of one tile's partial sums
+
+// Partial-sum slot of the piece of cut xb (1..7) that ends at the cut (part 0) or starts there
+// (part 1), for workgroup j of its XCD.
+__device__ __forceinline__ float *bal_slot(float *ws, int xb, int part, int j) {
+  return ws + ((int64_t)((xb - 1) * 2 + part) * 32 + j) * BAL_SLOT;
+}
+
+// Pieces an XCD's range can touch: at most ceil(S / 8) + 1 super-tiles.
+__host__ __device__ inline int bal_pmax(const BalShape &b) { return (b.S + 7) / 8 + 1; }
+
+// Workgroup b: XCD x = b % 8 (round-robin dispatch), piece pi = (b / 8) / 32 of that XCD's
+// range, tile j = (b / 8) % 32 of the super-tile. The workgroups of piece pi + 1 are queued
+// behind those of piece pi on the XCD, so its 32 CUs move from piece to piece together.
+template <int MODE, typename TT>
+__global__ __launch_bounds__(256, 1) void k_split_gemm_bal(const _Float16 *__restrict__ st_h,
+                                                           const _Float16 *__restrict__ st_l,
+                                                           const _Float16 *__restrict__ m_h,
+                                                           const _Float16 *__restrict__ m_l, int64_t kp, int M,
+                                                           int cols, const SplitEpi e) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  _Float16 *lds = (_Float16 *)gsm;
+  BalShape bs;
+  (void)bal_shape(M, cols, kp, bs);
+  const int b = blockIdx.x, x = b & 7, pi = (b >> 3) >> 5, j = (b >> 3) & 31;
+  const int rho = j / bs.ctiles, c = j % bs.ctiles;
+  if (rho >= bs.rps) return;
+  const int64_t g0 = bal_cut(bs, x), g1 = bal_cut(bs, x + 1);
+  const int64_t gs = pi == 0 ? g0 : (g0 / bs.nq + pi) * bs.nq;
+  if (gs >= g1) return;
+  const int64_t ge = (gs / bs.nq + 1) * bs.nq < g1 ? (gs / bs.nq + 1) * bs.nq : g1;
+  const int q0 = (int)(gs % bs.nq), q1 = q0 + (int)(ge - gs);
+  const int r = (int)(gs / bs.nq) * bs.rps + rho;
+  if (r >= bs.mtiles) return;
+  f16v acc[NB][MB], cx[NB][MB];
+  split_gemm_tile(st_h, st_l, m_h, m_l, kp, c, r, 4 * q0, 4 * q1, lds, acc, cx);
+  if (q0 == 0 && q1 == bs.nq) {
+    split_epilogue<MODE, TT>(acc, cx, r, c, M, cols, e, gsm);
+    return;
+  }
+  // a piece of a cut super-tile: its partial sums, element-major (coalesced per element)
+  const int t = threadIdx.x;
+  const float inv = 1.0f / 2048.0f;
+  float *slot = q0 == 0 ? bal_slot(e.ws, x + 1, 0, j) : bal_slot(e.ws, x, 1, j);
+#pragma unroll
+  for (int i = 0; i < NB; i++)
+#pragma unroll
+    for (int jj = 0; jj < MB; jj++)
+#pragma unroll
+      for (int v = 0; v < 16; v++)
+        slot[(int64_t)((i * MB + jj) * 16 + v) * 256 + t] = fmaf(cx[i][jj][v], inv, acc[i][jj][v]);
+}
+
+// Second kernel of the balanced schedule: the tiles of the super-tiles cut at XCD boundaries,
+// head piece + tail piece, then the epilogue; one workgroup per tile and column block of 32
+// (workgroup 4 (32 (xb - 1) + j) + i: cut xb, tile j, block i), so that the work spreads over
+// every CU with few registers per thread.
+template <int MODE, typename TT, int I>
+__device__ __forceinline__ void split_fix_block(const float *p0, const float *p1, int r, int c, int M, int cols,
+                                                const SplitEpi &e, unsigned char *gsm) {
+  const int t = threadIdx.x;
+  f16v acc[NB][MB], cx[NB][MB];
+#pragma unroll
+  for (int jj = 0; jj < MB; jj++) {
+    cx[I][jj] = f16v{};
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      const int64_t o = (int64_t)((I * MB + jj) * 16 + v) * 256 + t;
+      acc[I][jj][v] = p0[o] + p1[o];
+    }
+  }
+  split_epilogue<MODE, TT, I, I + 1>(acc, cx, r, c, M, cols, e, gsm);
+}
+
+template <int MODE, typename TT>
+__global__ __launch_bounds__(256) void k_split_gemm_fix(int64_t kp, int M, int cols, const SplitEpi e) {
+  __shared__ double sred[4 * (GN / 2) * 2];
+  BalShape bs;
+  (void)bal_shape(M, cols, kp, bs);
+  const int i = blockIdx.x & 3, j = (blockIdx.x >> 2) & 31, xb = 1 + (int)(blockIdx.x >> 7);
+  const int64_t gc = bal_cut(bs, xb);
+  if (gc % bs.nq == 0) return;  // this cut falls between super-tiles
+  const int rho = j / bs.ctiles, c = j % bs.ctiles;
+  if (rho >= bs.rps) return;
+  const int r = (int)(gc / bs.nq) * bs.rps + rho;
+  if (r >= bs.mtiles) return;
+  const float *p0 = bal_slot(e.ws, xb, 0, j), *p1 = bal_slot(e.ws, xb, 1, j);
+  unsigned char *gsm = (unsigned char *)sred;
+  switch (i) {
+    case 0: split_fix_block<MODE, TT, 0>(p0, p1, r, c, M, cols, e, gsm); break;
+    case 1: split_fix_block<MODE, TT, 1>(p0, p1, r, c, M, cols, e, gsm); break;
+    case 2: split_fix_block<MODE, TT, 2>(p0, p1, r, c, M, cols, e, gsm); break;
+    default: split_fix_block<MODE, TT, 3>(p0, p1, r, c, M, cols, e, gsm); break;
+  }
+}
+
 constexpr size_t split_gemm_lds() { return (size_t)3 * STAGE * sizeof(_Float16); }
 
 template <int MODE, typename TT>
 static hipError_t launch_mode(const void *st_h, const void *st_l, const void *m_h, const void *m_l, int64_t kp, int M,
                               int cols, const SplitEpi &e, hipStream_t s) {
+  BalShape bs;
+  if (bal_shape(M, cols, kp, bs)) {
+    if (!e.ws) return hipErrorInvalidValue;
+    k_split_gemm_bal<MODE, TT><<<8 * 32 * bal_pmax(bs), 256, split_gemm_lds(), s>>>((const _Float16 *)st_h, (const _Float16 *)st_l,
+                                                                  (const _Float16 *)m_h, (const _Float16 *)m_l, kp, M,
+                                                                  cols, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_split_gemm_fix<MODE, TT><<<7 * 32 * NB, 256, 0, s>>>(kp, M, cols, e);
+    return hipGetLastError();
+  }
   const int mtiles = (M + GM - 1) / GM, ctiles = (cols + GN - 1) / GN;
   const dim3 grid((unsigned)(8 * ((mtiles + 7) / 8) * ctiles));
   k_split_gemm<MODE, TT><<<grid, 256, split_gemm_lds(), s>>>((const _Float16 *)st_h, (const _Float16 *)st_l,
                                                              (const _Float16 *)m_h, (const _Float16 *)m_l, kp, M, cols, e);
   return hipGetLastError();
+}
+
+size_t split_gemm_ws_bytes(int M, int cols, int64_t kp) {
+  BalShape bs;
+  if (M <= 0 || cols <= 0 || kp <= 0 || !bal_shape(M, cols, kp, bs)) return 0;
+  return (size_t)7 * 2 * 32 * BAL_SLOT * sizeof(float);
 }
 
 hipError_t launch_split_gemm_epi(int mode, const void *st_h, const void *st_l, const void *m_h, const void *m_l,

@@ -317,9 +317,13 @@ struct SplitEpi {
   int lut_len;
   double *part0, *part1;     // partial sums [s * nblk + row tile]
   int nblk;
+  float *ws;                 // split_gemm_ws_bytes of workspace when that is nonzero
 };
 hipError_t launch_split_gemm_epi(int mode, const void *st_h, const void *st_l, const void *m_h, const void *m_l,
                                  int64_t kp, int M, int cols, const SplitEpi &e, hipStream_t s);
+// Workspace (bytes) of one product of M rows, cols columns and padded depth kp: nonzero when the
+// product runs the XCD-balanced schedule, whose K-split tiles keep their partial sums there.
+size_t split_gemm_ws_bytes(int M, int cols, int64_t kp);
 // dst <- src, bytes a multiple of 16, both 16-byte aligned (the HBM copy roof).
 hipError_t launch_stream_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 // Grover path (qaoa_grover.hip)
