@@ -235,7 +235,7 @@ KERNEL_NAMES = {"xmix": "k_pass<float,13,1|3|4,uint8,1..4> (tile passes with Y r
                 "fwd_pass": "k_pass<float,13,1,uint8,0> (tile pass, one vector)",
                 "rev_pass": "k_pass<float,13,2|3|4,uint8,0> (tile pass, state and adjoint vector)",
                 "small": "k_whole / k_small<float> (whole state in one workgroup)",
-                "dense": "k_split_gemm<mode> (hand-written split-FP16 MFMA eigenbasis product, fused epilogue)"}
+                "dense": "k_split_gemm_bal<mode> + k_split_gemm_fix<mode> (hand-written split-FP16 MFMA eigenbasis product, XCD-balanced K-split schedule, fused epilogue)"}
 
 
 def algorithmic_bytes(R, steps):
