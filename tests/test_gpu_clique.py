@@ -1,8 +1,9 @@
 """GPU parity of the constrained path: clique mixer on the Hamming-weight-k subspace,
 eigenbasis products (FP16-split MFMA products in the FP32 form, DGEMM in the FP64 form).
 
-Tolerances: FP32 form <C> 1e-5 relative and gradient 1e-5 of max|g|; FP64 form 1e-12 for
-both (the eigendecomposition carries ~1e-13 relative error per eigenpair, which the 2p to
+Tolerances: FP32 form <C> 1e-5 relative and gradient 1e-5 of max|g| (at N = 12870 over many
+random sets: 1e-5 of the batch's gradient scale, 5e-5 of a set's own, see the balanced-schedule
+test); FP64 form 1e-12 for both (the eigendecomposition carries ~1e-13 relative error per eigenpair, which the 2p to
 4p products of an evaluation compound; measured at N = 12870: 1e-16 in <C>, 7e-13 in the
 gradient)."""
 import json
@@ -148,3 +149,44 @@ def test_clique_full_batch_512(q, ctx):
     # different K orders): they agree to 2 TOL
     assert e_dev <= 2 * TOL[0] and g_dev <= 2 * TOL[0]
     P.close(); M.close()
+
+
+@pytest.fixture(scope="module")
+def bisection(q, ctx):
+    W = workloads.workload("bisection_g16_k8_p6")
+    P, M = q.Problem.from_graph(ctx, W.graphs[0], hamming_k=8), q.Mixer.clique(ctx, 16, 8)
+    yield P, M
+    P.close(); M.close()
+
+
+@pytest.mark.parametrize("nsets", [320, 650])
+def test_clique_balanced_schedule_shapes(q, bisection, nsets):
+    """Other shapes of the XCD-balanced product schedule at N = 12870: 320 sets (5 column
+    tiles, super-tiles of 6 row tiles: 9 super-tiles, one more than the XCDs) and 650 sets (11
+    column tiles, 2 row tiles per super-tile, 26 super-tiles, up to 5 pieces per XCD). Every set
+    of the call, and of the same sets in calls of 100 (one round of tiles: the plain schedule),
+    against the FP64 form (DGEMM on the FP64 eigenbasis, 1e-12): <C> to 1e-6 relative; the
+    gradient to 1e-5 of the batch's gradient scale (the largest |g| over its sets) and to 5e-5
+    of each set's own largest |g|. The FP32 form's gradient error comes from the FP32
+    accumulation of the products over N = 12870 terms (about 2e-6 relative per element and
+    product, over 4p = 24 products) and is absolute rather than relative per set: measured, at
+    most 3.5e-6 of the batch scale, and up to 2.6e-5 of a set's own scale for sets whose
+    gradient is small (both schedules alike). The call repeated gives identical results."""
+    P, M = bisection
+    a = workloads.random_angles(6, nsets, 4400 + nsets)
+    E, G = q.expect_grad_batched([P], [M], a, precision=0)
+    chunks = [q.expect_grad_batched([P], [M], a[h:h + 100], precision=0) for h in range(0, nsets, 100)]
+    Ec = np.concatenate([e[0] for e, _ in chunks])
+    Gc = np.concatenate([g_[0] for _, g_ in chunks])
+    E64, G64 = q.expect_grad_batched([P], [M], a, precision=1)
+    E64, G64 = E64[0], G64[0]
+    own = np.max(np.abs(G64), axis=1)
+    for name, e, g_ in (("balanced", E[0], G[0]), ("calls of 100", Ec, Gc)):
+        e_err = np.max(np.abs(e - E64) / np.abs(E64))
+        g_abs = np.max(np.abs(g_ - G64), axis=1)
+        print(f"{nsets} sets, {name}: E {e_err:.2e}, grad {g_abs.max() / own.max():.2e} of the batch scale, "
+              f"{np.max(g_abs / own):.2e} of a set's own", flush=True)
+        assert e_err <= 1e-6
+        assert g_abs.max() <= 1e-5 * own.max() and np.all(g_abs <= 5e-5 * own)
+    E2, G2 = q.expect_grad_batched([P], [M], a, precision=0)
+    assert np.array_equal(E, E2) and np.array_equal(G, G2)
