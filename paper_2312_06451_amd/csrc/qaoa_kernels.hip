@@ -163,25 +163,35 @@ __global__ void k_luts(const LutJob *__restrict__ jobs, int lut_len, const doubl
 // ============================================================== reductions
 
 // out[q][o] = sum over contributions c < cnt[o] and tiles b < nwg of
-// partials[((o * maxc + c) * nsets + q) * nwg + b], in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials,
-                                                  const int *__restrict__ cnt, int maxc,
-                                                  int nsets, int64_t nwg, int nout,
-                                                  double *__restrict__ out) {
-  __shared__ double red[256];
-  const int o = blockIdx.x, q = blockIdx.y;
-  double s = 0.0;
+// partials[((o * maxc + c) * nsets + q) * nwg + b], in a fixed order (deterministic): 1024
+// threads, each with four interleaved running sums (four loads in flight per thread), then a
+// fixed tree over the threads.
+constexpr int FIN_THREADS = 1024;
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restrict__ partials,
+                                                          const int *__restrict__ cnt, int maxc,
+                                                          int nsets, int64_t nwg, int nout,
+                                                          double *__restrict__ out) {
+  __shared__ double red[FIN_THREADS];
+  const int o = blockIdx.x, q = blockIdx.y, t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int c = 0; c < cnt[o]; c++) {
     const double *src = partials + (((int64_t)o * maxc + c) * nsets + q) * nwg;
-    for (int64_t k = threadIdx.x; k < nwg; k += 256) s += src[k];
+    int64_t k = t;
+    for (; k + 3 * FIN_THREADS < nwg; k += 4 * FIN_THREADS) {
+      s0 += src[k];
+      s1 += src[k + FIN_THREADS];
+      s2 += src[k + 2 * FIN_THREADS];
+      s3 += src[k + 3 * FIN_THREADS];
+    }
+    for (; k < nwg; k += FIN_THREADS) s0 += src[k];
   }
-  red[threadIdx.x] = s;
+  red[t] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+  for (int h = FIN_THREADS / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[(int64_t)q * nout + o] = red[0];
+  if (t == 0) out[(int64_t)q * nout + o] = red[0];
 }
 
 // dst[i] = (re + i im) * src[i ^ flip]
@@ -910,7 +920,7 @@ hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shap
 hipError_t launch_finalize(const double *partials, const int *cnt, int maxc, int nsets,
                            int64_t nwg, int nout, double *out, hipStream_t s) {
   if (nout <= 0 || nsets <= 0) return hipSuccess;
-  k_finalize<<<dim3(nout, nsets), 256, 0, s>>>(partials, cnt, maxc, nsets, nwg, nout, out);
+  k_finalize<<<dim3(nout, nsets), FIN_THREADS, 0, s>>>(partials, cnt, maxc, nsets, nwg, nout, out);
   return hipGetLastError();
 }
 
