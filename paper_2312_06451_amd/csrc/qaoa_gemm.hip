@@ -418,11 +418,10 @@ __global__ __launch_bounds__(256, 1) void k_split_gemm(const _Float16 *__restric
 // rounds, and the last round is partly empty (M = 12870 rows, 1024 columns: 51 x 8 tiles on 256
 // CUs take two full rounds for 1.59 rounds of work). The balanced schedule keeps 32 workgroups
 // per XCD at a time and splits the work evenly over the XCDs along K: a super-tile is RPS =
-// 32 / ctiles row tiles
-// times every column tile, processed by the 32 workgroups of one XCD in step (so each matrix
-// row tile is shared by the column tiles and each state tile by the row tiles through that
-// XCD's L2, as in the plain schedule); the S super-tiles x NQ K quads (4 K tiles each) are cut
-// into 8 equal ranges, one per XCD. A super-tile cut by a range boundary is computed in two K
+// 32 / ctiles row tiles times every column tile, processed by the 32 workgroups of one XCD in
+// step (so each matrix row tile is shared by the column tiles and each state tile by the row
+// tiles through that XCD's L2, as in the plain schedule); the S super-tiles x NQ K quads (4 K
+// tiles each) are cut into 8 equal ranges, one per XCD. A super-tile cut by a range boundary is computed in two K
 // pieces on two XCDs; each piece stores its partial sums to the workspace, and a second
 // kernel adds the two (head piece first) and runs the epilogue. The cuts depend only on the
 // product's shape, so results do not depend on the process or the run.
