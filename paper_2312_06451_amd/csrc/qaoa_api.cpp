@@ -182,7 +182,8 @@ struct KTotals {
 // tuner (plan_for) searches them, the defaults are the fixed rule.
 struct PlanOpts {
   uint8_t narrow = 1;      // strided tiles take runs down to 64 B when that saves a tile
-  uint8_t narrow_top = 1;  // with uneven widths, the top tile takes the narrowest runs
+  uint8_t narrow_top = 1;  // with uneven widths (narrow covers; two strided tiles one bit
+                           // apart), the top tile takes the narrowest runs
   uint8_t lowbits = 1;     // the register-group rules of make_tiles
   uint8_t swap = 0;        // three tiles: the top tile in the middle of a round (single-block
                            // passes) instead of at its end (the round-boundary passes)
@@ -413,6 +414,11 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin, int cnarrow, const PlanO
       widths.push_back(std::min(n - next, T - cmin));
       next += widths.back();
     }
+    // Two strided tiles one bit apart: the top tile takes the extra strided bit (option
+    // narrow_top), so the middle tile, which runs the single-block passes, gets runs twice as
+    // long (FP32 n = 28: 8 + 7 -> 7 + 8 strided bits, one evaluation 32.15 -> 31.78 ms). Moving
+    // more bits does not pay (n = 24, 8 + 3 -> 3 + 8: 4 % slower).
+    if (o.narrow_top && widths.size() == 2 && widths[0] == widths[1] + 1) std::swap(widths[0], widths[1]);
   }
   int next = T;
   for (int width : widths) {

@@ -205,3 +205,30 @@ def test_n32_cycle_light_cone_p8(q):
         for i in comps:
             assert abs(gr[i] - n * eg[i]) < max(TOL[prec][1], 1e-9) * scale
     P.close(); M.close(); ctx.close()
+
+
+@pytest.mark.parametrize("narrow_top", [1, 0])
+def test_n28_cover_options_vs_golden(q, tmp_path, narrow_top):
+    """n = 28, FP32 and FP64, in the benchmark's configuration (random 3-regular graph, p = 8,
+    checkpointed reverse sweep): the cover with the extra strided bit in the top tile
+    (narrow_top = 1, the fixed rule: B = [0,6) + [13,20), C = [0,5) + [20,28) in FP32) and in
+    the middle tile (narrow_top = 0) against the stored oracle values."""
+    import json
+    here = os.path.dirname(os.path.abspath(__file__))
+    G = json.load(open(os.path.join(here, "golden", "maxcut3reg_n28_p8.json")))
+    W = workloads.workload("maxcut3reg_n28_p8")
+    g = W.graphs[0]
+    s = G["sets"][0]
+    assert np.array_equal(np.array(s["angles"]), W.angles[0])
+    path = str(tmp_path / "plans.txt")
+    _plan_file(path, 28, {"narrow_top": narrow_top})
+    ctx = q.Context(0)
+    ctx.load_plans(path)
+    P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, 28)
+    for prec in (0, 1):
+        e, gr = q.expect_grad(P, M, W.angles[0], precision=prec)
+        print(f"n28 narrow_top={narrow_top} prec={prec}: E err {_rel(e, s['expect']):.2e} "
+              f"grad err {_gerr(gr, np.array(s['grad'])):.2e}", flush=True)
+        assert _rel(e, s["expect"]) < TOL[prec][0]
+        assert _gerr(gr, np.array(s["grad"])) < TOL[prec][1]
+    P.close(); M.close(); ctx.close()
