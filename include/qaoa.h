@@ -276,7 +276,11 @@ int qaoa_state(const qaoa_problem *prob, const qaoa_mixer *mix, int p, const dou
  * Every (problem, set) pair whose state fits one workgroup (n <= 13 for QAOA_FP32, n <= 12
  * for QAOA_FP64, transverse-field mixer) runs in one launch, one workgroup per pair; each
  * larger problem runs as one sequence of tile passes (or eigenbasis products) that covers
- * all n_sets angle sets per launch. Problems may differ in n and in mixer. */
+ * all n_sets angle sets per launch. Problems may differ in n and in mixer. A call repeats bit
+ * for bit; its results equal single evaluations' bit for bit except in the QAOA_FP32 form of
+ * the eigenbasis mixers when a product needs more than one round of the GPU's workgroups
+ * (about 320 sets at C(16,8) states): such products split part of their sums along K over
+ * two XCDs and round differently, within the same error bound. */
 int qaoa_expect_batched(const qaoa_problem *const *probs, const qaoa_mixer *const *mixers,
                         int n_probs, int n_sets, int p, const double *angles, int precision,
                         double *out_expect, void *stream);
