@@ -75,8 +75,8 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
  * transverse-field mixer and the X-product mixers). A plan fixes choices that leave the
  * result exact up to rounding: the reverse sweep reading the forward passes' outputs or
  * undoing the state in place, the tile cover (narrow 64-byte runs where they save a tile;
- * which strided tile takes the narrowest runs, also between two strided tiles one bit
- * apart), which tile rotates the low qubits, the tile order of the first
+ * which strided tile takes the narrowest runs, also the odd bit of two evenly split strided
+ * tiles), which tile rotates the low qubits, the tile order of the first
  * round, which strided tile takes the round boundaries (three tiles), and the XCD-aware
  * workgroup order. Off (enable = 0, the default): a fixed rule.
  * On: the first evaluation of each (n, precision, gradient or not, mixer, whether the

@@ -182,8 +182,8 @@ struct KTotals {
 // tuner (plan_for) searches them, the defaults are the fixed rule.
 struct PlanOpts {
   uint8_t narrow = 1;      // strided tiles take runs down to 64 B when that saves a tile
-  uint8_t narrow_top = 1;  // with uneven widths (narrow covers; two strided tiles one bit
-                           // apart), the top tile takes the narrowest runs
+  uint8_t narrow_top = 1;  // with uneven widths (narrow covers; the odd bit of two evenly
+                           // split strided tiles), the top tile takes the narrowest runs
   uint8_t lowbits = 1;     // the register-group rules of make_tiles
   uint8_t swap = 0;        // three tiles: the top tile in the middle of a round (single-block
                            // passes) instead of at its end (the round-boundary passes)
@@ -398,8 +398,9 @@ struct TileGeo {
 
 // Tile cover of n address bits: tile 0 holds bits [0, T); each further tile holds c contiguous
 // low bits and T - c bits above the previous tile's. Fewest tiles first, runs of at least 2^cmin
-// amplitudes (widest-first, as wide as allowed); when runs down to 2^cnarrow save a tile, the
-// strided bits are spread as evenly as possible over the tiles instead.
+// amplitudes (widest-first, as wide as allowed; two strided tiles share their bits evenly);
+// when runs down to 2^cnarrow save a tile, the strided bits are spread as evenly as possible
+// over the tiles instead.
 std::vector<TileGeo> make_tiles(int n, int T, int cmin, int cnarrow, const PlanOpts &o) {
   std::vector<TileGeo> t;
   t.push_back({T, T, (1u << T) - 1});
@@ -414,11 +415,14 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin, int cnarrow, const PlanO
       widths.push_back(std::min(n - next, T - cmin));
       next += widths.back();
     }
-    // Two strided tiles one bit apart: the top tile takes the extra strided bit (option
-    // narrow_top), so the middle tile, which runs the single-block passes, gets runs twice as
-    // long (FP32 n = 28: 8 + 7 -> 7 + 8 strided bits, one evaluation 32.15 -> 31.78 ms). Moving
-    // more bits does not pay (n = 24, 8 + 3 -> 3 + 8: 4 % slower).
-    if (o.narrow_top && widths.size() == 2 && widths[0] == widths[1] + 1) std::swap(widths[0], widths[1]);
+    // Two strided tiles split the strided bits evenly, the odd bit to the top tile (option
+    // narrow_top) or to the middle one: measured (X mixer, fwd+grad, FP32) faster than
+    // widest-first for n = 22..27 by 0.5-4.7 %, and at n = 28 (7 + 8 against 8 + 7 bits) by 1 %.
+    if (widths.size() == 2) {
+      const int S = widths[0] + widths[1];
+      widths[0] = o.narrow_top ? S / 2 : (S + 1) / 2;
+      widths[1] = S - widths[0];
+    }
   }
   int next = T;
   for (int width : widths) {
