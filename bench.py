@@ -218,7 +218,8 @@ def traffic_from_profile(workload, cls):
     txt = open(tpath).read()
     csrc = os.path.join(ROOT, "paper_2312_06451_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("qaoa_tile.h", "qaoa_kernels.hip", "qaoa_xpass.hip"):  # the pass kernel and its launchers
+    # the pass kernel and its launchers
+    for f in ("qaoa_tile.h", "qaoa_kernels.hip", "qaoa_xpass.hip", "qaoa_swz_f32.hip", "qaoa_swz_f64.hip"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     if f"kernel_source_sha256 = {h.hexdigest()}" not in txt:
         return None

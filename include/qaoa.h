@@ -77,8 +77,12 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
  * undoing the state in place, the tile cover (narrow 64-byte runs where they save a tile;
  * which strided tile takes the narrowest runs, also the odd bit of two evenly split strided
  * tiles), which tile rotates the low qubits, the tile order of the first
- * round, which strided tile takes the round boundaries (three tiles), and the XCD-aware
- * workgroup order. Off (enable = 0, the default): a fixed rule.
+ * round, which strided tile takes the round boundaries (three tiles), the XCD-aware
+ * workgroup order, and, on narrow covers of the transverse-field mixer, the state layout in
+ * device memory (natural, or the top ten index bits XOR-folded into ten middle ones; never
+ * visible to the caller: an evaluation with a caller's initial state or final-state output
+ * runs the natural layout; the layout changes no arithmetic, so its results are identical
+ * bit for bit). Off (enable = 0, the default): a fixed rule.
  * On: the first evaluation of each (n, precision, gradient or not, mixer, whether the
  * checkpoints fit in memory) times the alternatives one at a time on the caller's stream
  * (min(p, 4) layers per trial, by the summed kernel durations; a change is kept when it is
@@ -91,9 +95,10 @@ int qaoa_ctx_create(int hip_device, qaoa_ctx **out);
 int qaoa_ctx_set_autotune(qaoa_ctx *ctx, int enable);
 
 /* The context's chosen plans as text, one line per key:
- *   "n precision grad mixer ckpt_fits : narrow narrow_top lowbits down xcd ckpt swap"
- * after a header line "qaoa-plans 2" (files with the header "qaoa-plans 1" and no swap field
- * still load, with swap 0). buf may be NULL; *needed (if not NULL) receives the
+ *   "n precision grad mixer ckpt_fits : narrow narrow_top lowbits down xcd ckpt swap swz"
+ * after a header line "qaoa-plans 3" (files with the header "qaoa-plans 1" and no swap field
+ * still load, with swap 0; files with "qaoa-plans 1" or "qaoa-plans 2" and no swz field load
+ * with swz 1, the fixed rule's layout). buf may be NULL; *needed (if not NULL) receives the
  * length including the terminating NUL; at most len bytes are written (always terminated
  * when len > 0). INVALID_ARG for ctx == NULL. */
 int qaoa_plans_text(const qaoa_ctx *ctx, char *buf, size_t len, size_t *needed);

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa.so")
-SOURCES = ["qaoa_kernels.hip", "qaoa_xpass.hip", "qaoa_clique.hip", "qaoa_grover.hip", "qaoa_xmix.hip",
+SOURCES = ["qaoa_kernels.hip", "qaoa_xpass.hip", "qaoa_swz_f32.hip", "qaoa_swz_f64.hip", "qaoa_clique.hip",
+           "qaoa_grover.hip", "qaoa_xmix.hip",
            "qaoa_gemm.hip", "qaoa_api.cpp", "qaoa_angles.cpp"]
 HOST_ONLY = {"qaoa_angles.cpp"}  # plain C++ above the C ABI: no device code
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -190,7 +190,15 @@ struct PlanOpts {
   uint8_t down = 0;        // the first round visits the tiles from the top one down
   uint8_t xcd = 1;         // XCD-aware workgroup order (consecutive tiles on one XCD)
   int8_t ckpt = -1;        // reverse sweep: -1 the context's memory rule, 0 in place, 1 checkpoints
+  uint8_t swz = 1;         // narrow covers: the swizzled state layout, cached accesses for the
+                           // tiles with runs under 128 bytes
 };
+
+// Element shift of the swizzled layout's target bits (bits [S, S + 10) of the element index,
+// byte address bits [9, 19)), measured best over shifts 3..12 for the top tile of the n = 32
+// narrow cover.
+inline int swz_shift(int prec) { return prec == QAOA_FP32 ? 6 : 5; }
+
 
 struct qaoa_ctx {
   int device = 0;
@@ -456,6 +464,15 @@ std::vector<TileGeo> make_tiles(int n, int T, int cmin, int cnarrow, const PlanO
   return t;
 }
 
+// Whether the cover of n bits under options o uses runs narrower than 2^cmin amplitudes, and
+// the swizzled layout applies to it.
+bool swz_applies(int n, int T, int cmin, int cnarrow, int prec, const PlanOpts &o) {
+  if (n - 10 < swz_shift(prec) + 10) return false;
+  for (const TileGeo &g : make_tiles(n, T, cmin, cnarrow, o))
+    if (g.c < cmin) return true;
+  return false;
+}
+
 // Whether option `which` of PlanOpts changes the plan of n bits at all (the tuner skips the
 // others).
 bool plan_knob_applies(int which, int n, int T, int cmin, int cnarrow, const PlanOpts &o) {
@@ -629,6 +646,16 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
   const PlanOpts po = force ? *force : plan_for<R>(prob, p, angles, nsets, grad, xm, st, !df);
   const std::vector<TileGeo> tiles = make_tiles(n, T, cmin, cnarrow, po);
   const int K = (int)tiles.size();
+  // the swizzled layout on narrow covers of the transverse-field mixer (each of their tiles
+  // rotates bits of all three register groups, the one stage set built for that layout); not
+  // when the initial state comes from the caller or the final vector goes to the caller (both
+  // in natural order)
+  bool swz = po.swz && swz_applies(n, T, cmin, cnarrow, prec, po) && !d_psi0 && !d_state_out && !xm;
+  for (const TileGeo &g : tiles) {
+    const uint32_t H = ((1u << T) - 1) & ~((1u << 8) - 1), M = ((1u << 8) - 1) & ~((1u << (T - 8)) - 1),
+                   Lg = (1u << (T - 8)) - 1;
+    swz = swz && (g.rot & H) && (g.rot & M) && (g.rot & Lg);
+  }
   const int L = xm ? 2 * p : p;  // layers of the pass plan
   const bool ma = xm && xm->kind == 4;      // per-qubit angles
   const int SL = ma ? p * (n + 1) : 2 * p;  // angles per set
@@ -851,6 +878,13 @@ void run_x_path(qaoa_problem *prob, int p, const double *angles, int nsets, cons
     a.lam_c0 = (R)prob->mean;
     a.partials = dpart;
     for (int s = 0; s < NSLOT; s++) a.slot_off[s] = -1;
+    if (swz) {
+      a.swz = swz_shift(prec);
+      a.swz_src = n - 10;
+      a.swz_add = tiles[tile].h0 + (T - tiles[tile].c) <= a.swz_src ? 1 : 0;
+      // runs under a 128-byte line: the two workgroups that share each line meet in L2
+      a.cached = ((size_t)1 << tiles[tile].c) * esz < 128 ? 1 : 0;
+    }
     return a;
   };
 
@@ -1559,6 +1593,11 @@ PlanOpts plan_for(qaoa_problem *prob, int p, const double *angles, int nsets, in
     o.xcd ^= 1;
     consider(o);
   }
+  if (!xm && swz_applies(n, T, cmin, cnarrow, prec, best)) {
+    PlanOpts o = best;
+    o.swz ^= 1;
+    consider(o);
+  }
   ctx->plans[key] = best;
   return best;
 }
@@ -1665,13 +1704,13 @@ int qaoa_ctx_set_autotune(qaoa_ctx *ctx, int enable) {
 }
 
 static std::string plans_text(const qaoa_ctx *ctx) {
-  std::string out = "qaoa-plans 2\n";
+  std::string out = "qaoa-plans 3\n";
   char line[160];
   for (const auto &kv : ctx->plans) {
     const auto &k = kv.first;
     const PlanOpts &o = kv.second;
-    std::snprintf(line, sizeof(line), "%d %d %d %d %d : %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], o.narrow,
-                  o.narrow_top, o.lowbits, o.down, o.xcd, o.ckpt, o.swap);
+    std::snprintf(line, sizeof(line), "%d %d %d %d %d : %d %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4],
+                  o.narrow, o.narrow_top, o.lowbits, o.down, o.xcd, o.ckpt, o.swap, o.swz);
     out += line;
   }
   return out;
@@ -1714,24 +1753,27 @@ int qaoa_plans_load(qaoa_ctx *ctx, const char *path) {
     int version = 0;
     while (std::fgets(line, sizeof(line), f)) {
       if (!header) {
-        // version 1 files (written before the swap option) load with swap = 0
+        // version 1 files (written before the swap option) load with swap = 0, versions 1 and
+        // 2 (before the layout option) with swz = 1
         if (std::strncmp(line, "qaoa-plans 1", 12) == 0) version = 1;
         if (std::strncmp(line, "qaoa-plans 2", 12) == 0) version = 2;
+        if (std::strncmp(line, "qaoa-plans 3", 12) == 0) version = 3;
         header = version != 0;
         if (!header) bad = true;
         if (bad) break;
         continue;
       }
       std::array<int, 5> k{};
-      int v[7] = {0, 0, 0, 0, 0, 0, 0};
-      const int want = version == 1 ? 11 : 12;
-      if (std::sscanf(line, "%d %d %d %d %d : %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &v[0], &v[1],
-                      &v[2], &v[3], &v[4], &v[5], &v[6]) != want) {
+      int v[8] = {0, 0, 0, 0, 0, 0, 0, 1};
+      const int want = version == 1 ? 11 : (version == 2 ? 12 : 13);
+      if (std::sscanf(line, "%d %d %d %d %d : %d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &v[0],
+                      &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]) != want) {
         bad = true;
         break;
       }
       bool ok = k[0] >= 1 && k[0] <= 33 && (k[1] == 0 || k[1] == 1) && (k[2] == 0 || k[2] == 1) &&
-                (k[4] == 0 || k[4] == 1) && v[5] >= -1 && v[5] <= 1 && (v[6] == 0 || v[6] == 1);
+                (k[4] == 0 || k[4] == 1) && v[5] >= -1 && v[5] <= 1 && (v[6] == 0 || v[6] == 1) &&
+                (v[7] == 0 || v[7] == 1);
       for (int i = 0; i < 5; i++) ok = ok && (v[i] == 0 || v[i] == 1);
       if (!ok) {
         bad = true;
@@ -1745,6 +1787,7 @@ int qaoa_plans_load(qaoa_ctx *ctx, const char *path) {
       o.xcd = (uint8_t)v[4];
       o.ckpt = (int8_t)v[5];
       o.swap = (uint8_t)v[6];
+      o.swz = (uint8_t)v[7];
       got[k] = o;
     }
     std::fclose(f);

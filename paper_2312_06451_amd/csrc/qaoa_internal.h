@@ -115,6 +115,12 @@ struct PassArgs {
   // index (16).
   int64_t ma_total, ma_slot, ma_stride;
   int8_t ma_src[32];
+  // State layout: swz == 0 stores element x of a vector at x; swz > 0 at
+  // x ^ (((x >> swz_src) & 1023) << swz) (the top ten index bits folded into ten middle ones;
+  // requires swz + 10 <= swz_src). The caller's initial state is always read in natural order.
+  int swz, swz_src;
+  int swz_add;  // 1: the tile's own address bits all lie below swz_src (uniform swizzle value)
+  int cached;   // state loads and stores through the caches instead of non-temporal
 };
 
 // LUT construction job: luts[i][c] = scale_i * exp(sign_i * i * gamma_i * vals[c]),
@@ -180,6 +186,12 @@ hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape
                            hipStream_t s);
 hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
                            hipStream_t s);
+// The same passes in the swizzled layout (a.swz > 0; qaoa_swz_f32.hip, qaoa_swz_f64.hip): stage
+// set 7 only, no caller initial state; the access form follows a.cached and a.swz_add.
+hipError_t launch_pass_swz_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes,
+                               hipStream_t s);
+hipError_t launch_pass_swz_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
+                               hipStream_t s);
 // The same passes with Y rotations and no X-pair terms (X-product mixers, qaoa_xpass.hip):
 // kinds 1 (shapes 0, 1, 2, 3), 3 (shape 1), 2 and 4 (shapes 0, 1, 3); mixd (kinds 1, 2, 4, shape 1):
 // 0 = the middle's diagonal is the cost's, XD_POPCOUNT / XD_TERMS = the mixer's, indexed by the

@@ -873,28 +873,12 @@ size_t pass_lds_bytes(int precision, int tbytes, int lut_len) {
                         : lds_for<double, TILE_BITS_F64>(tbytes, lut_len);
 }
 
-// Shapes: 0 = part 1 only; 1 = both parts with the kind's middle steps (forward: phase;
-// reverse: gamma gradient and inverse phase; fused: <C> and lam); 2 = part 2 only after the
-// phase (first forward pass); 3 = part 1 then a reduction (forward: <C>; reverse: gamma
-// gradient).
-template <typename R, int T, int KIND, typename TT, int SX>
-static hipError_t launch_shape(const PassArgs<R> &a, int shape, hipStream_t s) {
-  if constexpr (KIND == 3) return launch_pass_t<R, T, KIND, SX, SX, 1, TT>(a, s);
-  else {
-    if (shape == 0) return launch_pass_t<R, T, KIND, SX, 0, 0, TT>(a, s);
-    if (shape == 3) return launch_pass_t<R, T, KIND, SX, 0, 3, TT>(a, s);
-    if constexpr (KIND == 1)
-      if (shape == 2) return launch_pass_t<R, T, KIND, 0, SX, 2, TT>(a, s);
-    return launch_pass_t<R, T, KIND, SX, SX, 1, TT>(a, s);
-  }
-}
-
 template <typename R, int T, int KIND, typename TT>
 static hipError_t launch_sx(const PassArgs<R> &a, int sx, int shape, hipStream_t s) {
-  if (sx == 7) return launch_shape<R, T, KIND, TT, 7>(a, shape, s);
-  if (sx == 5) return launch_shape<R, T, KIND, TT, 5>(a, shape, s);
-  if (sx == 3) return launch_shape<R, T, KIND, TT, 3>(a, shape, s);
-  return launch_shape<R, T, KIND, TT, 1>(a, shape, s);
+  if (sx == 7) return launch_shape<R, T, KIND, TT, 7, 0>(a, shape, s);
+  if (sx == 5) return launch_shape<R, T, KIND, TT, 5, 0>(a, shape, s);
+  if (sx == 3) return launch_shape<R, T, KIND, TT, 3, 0>(a, shape, s);
+  return launch_shape<R, T, KIND, TT, 1, 0>(a, shape, s);
 }
 
 template <typename R, int T, typename TT>
@@ -905,14 +889,17 @@ static hipError_t launch_kind(const PassArgs<R> &a, int kind, int sx, int shape,
   return launch_sx<R, T, 3, TT>(a, sx, shape, s);
 }
 
+// The swizzled layout's passes (a.swz > 0) live in their own translation units.
 hipError_t launch_pass_f32(const PassArgs<float> &a, int kind, int sx, int shape, int tbytes,
                            hipStream_t s) {
+  if (a.swz) return launch_pass_swz_f32(a, kind, sx, shape, tbytes, s);
   return tbytes == 1 ? launch_kind<float, TILE_BITS_F32, uint8_t>(a, kind, sx, shape, s)
                      : launch_kind<float, TILE_BITS_F32, uint16_t>(a, kind, sx, shape, s);
 }
 
 hipError_t launch_pass_f64(const PassArgs<double> &a, int kind, int sx, int shape, int tbytes,
                            hipStream_t s) {
+  if (a.swz) return launch_pass_swz_f64(a, kind, sx, shape, tbytes, s);
   return tbytes == 1 ? launch_kind<double, TILE_BITS_F64, uint8_t>(a, kind, sx, shape, s)
                      : launch_kind<double, TILE_BITS_F64, uint16_t>(a, kind, sx, shape, s);
 }

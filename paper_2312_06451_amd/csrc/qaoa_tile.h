@@ -526,7 +526,7 @@ constexpr int after_stages() {
 // with no X-pair terms; OP 1 indexes the middle's diagonal by the cost table, OP 2 by the
 // Hamming weight of the state index, OP 3 by its parities against a set of masks, OP 4 is the
 // per-qubit multi-angle diagonal (OP 2 to 4: the mixer's diagonal; no table is read).
-template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT, int OP = 0>
+template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT, int OP = 0, int LAY = 0>
 __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void k_pass(const PassArgs<R> a) {
   using G = TileCfg<T>;
   using T2 = typename Cplx<R>::T2;
@@ -581,6 +581,63 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
     __builtin_nontemporal_store(v, (gV2 *)((gbyte *)uniform64(vb + jb) + tbyte));
   };
   const uint64_t vs = ((uint64_t)q * a.vstride + base) * sizeof(T2);
+  // LAY 1..3: the swizzled layout, element x at x ^ (((x >> a.swz_src) & 1023) << a.swz).
+  // A tile whose strided bits are the top ones has 2^10 rows a large power of two apart, which
+  // in the natural layout share their low address bits and so their L2 channel and DRAM bank;
+  // folding the top bits into middle ones spreads them. The map is linear over XOR, so element
+  // base | off(t) | off(j) sits at sw(base) ^ sw(off(t)) ^ sw(off(j)): a uniform part (scalar
+  // base) and a per-thread part below 2^32 bytes, combined with one XOR per access (LAY 1:
+  // non-temporal accesses, LAY 2: cached ones).
+  const uint64_t vq = (uint64_t)q * a.vstride * sizeof(T2);
+  auto swzf = [](uint64_t x, uint32_t sh, uint32_t src) -> uint64_t { return x ^ (((x >> src) & 1023ull) << sh); };
+  auto tswf = [&]() -> uint32_t { return (uint32_t)(swzf(off(t), a.swz, a.swz_src) * sizeof(T2)); };
+  auto atz = [&](uint64_t v0, uint32_t ts, int j) -> gV2 * {
+    const uint64_t u = swzf(base | off((uint32_t)j << G::TB), a.swz, a.swz_src) * sizeof(T2);
+    return (gV2 *)((gbyte *)uniform64(v0 + (u & ~0xffffffffull)) + ((uint32_t)u ^ ts));
+  };
+  auto ldz = [&](uint64_t v0, uint32_t ts, int j, auto nt) -> T2 {
+    V2 v;
+    if constexpr (decltype(nt)::value) v = __builtin_nontemporal_load(atz(v0, ts, j));
+    else v = *atz(v0, ts, j);
+    return T2{v.x, v.y};
+  };
+  // stores: offsets recomputed from fresh copies of the geometry, as in st
+  auto stz = [&](uint64_t v0, uint32_t ts, int j, const T2 &x, auto nt) {
+    const uint32_t cs = fresh_s((uint32_t)a.c), hs = fresh_s((uint32_t)a.h0);
+    const uint32_t ss = fresh_s((uint32_t)a.swz), sr = fresh_s((uint32_t)a.swz_src);
+    const uint64_t e = (uint64_t)j << G::TB;
+    const uint64_t u = swzf(base | (e & ((1ull << cs) - 1)) | ((e >> cs) << hs), ss, sr) * sizeof(T2);
+    gV2 *ptr = (gV2 *)((gbyte *)uniform64(v0 + (u & ~0xffffffffull)) + ((uint32_t)u ^ ts));
+    V2 v;
+    v.x = x.x;
+    v.y = x.y;
+    if constexpr (decltype(nt)::value) __builtin_nontemporal_store(v, ptr);
+    else *ptr = v;
+  };
+  // LAY 3, add form (non-temporal): when the tile's own address bits all lie below the
+  // source bits, the swizzle value K is uniform per workgroup and splits into its part on the
+  // thread bits' positions and the rest, so that the address is a uniform part plus a
+  // per-thread part, as in the natural layout (no per-access XOR).
+  const uint64_t Kw = ((base >> a.swz_src) & 1023ull) << a.swz;
+  auto tsaf = [&]() -> uint32_t { return (uint32_t)((off(t) ^ (Kw & off(255u))) * sizeof(T2)); };
+  auto lda = [&](uint64_t v0, uint32_t ts, int j) -> T2 {
+    const uint64_t u = ((base | off((uint32_t)j << G::TB)) ^ (Kw & ~off(255u))) * sizeof(T2);
+    V2 v = __builtin_nontemporal_load((gV2 *)((gbyte *)uniform64(v0 + u) + ts));
+    return T2{v.x, v.y};
+  };
+  auto sta = [&](uint64_t v0, uint32_t ts, int j, const T2 &x) {
+    const uint32_t cs = fresh_s((uint32_t)a.c), hs = fresh_s((uint32_t)a.h0);
+    const uint32_t ss = fresh_s((uint32_t)a.swz), sr = fresh_s((uint32_t)a.swz_src);
+    auto dep = [&](uint64_t e) -> uint64_t { return (e & ((1ull << cs) - 1)) | ((e >> cs) << hs); };
+    const uint64_t K = ((base >> sr) & 1023ull) << ss;
+    const uint64_t u = ((base | dep((uint64_t)j << G::TB)) ^ (K & ~dep(255u))) * sizeof(T2);
+    V2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, (gV2 *)((gbyte *)uniform64(v0 + u) + ts));
+  };
+  // One access form per instantiation (forms chosen at run time would be merged by the
+  // compiler into one load sequence with 64-bit per-lane addresses and no cache hint).
 
   T2 phi[RN];
   T2 lam[NV == 2 ? RN : 1];
@@ -600,8 +657,21 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   {
     const uint64_t src = (f & PF_LOAD_PSI0) ? (uint64_t)a.psi0 + base * sizeof(T2) : (uint64_t)a.phi + vs;
     if (f & (PF_LOAD_PHI | PF_LOAD_PSI0)) {
+      if constexpr (LAY == 0) {
 #pragma unroll
-      for (int j = 0; j < RN; j++) phi[j] = ld(src, j);
+        for (int j = 0; j < RN; j++) phi[j] = ld(src, j);
+      } else {
+        const uint64_t v0 = (uint64_t)a.phi + vq;
+        if constexpr (LAY == 3) {
+          const uint32_t ts = tsaf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) phi[j] = lda(v0, ts, j);
+        } else {
+          const uint32_t ts = tswf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) phi[j] = ldz(v0, ts, j, std::integral_constant<bool, LAY == 1>{});
+        }
+      }
       if (f & PF_LOAD_SCALE) {
         const T2 k{sp.out_re, sp.out_im};
 #pragma unroll
@@ -614,9 +684,22 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   }
   if constexpr (NV == 2) {
     if (KIND == 2 || KIND == 4) {
-      const uint64_t src = (uint64_t)a.lam + vs;
+      if constexpr (LAY == 0) {
+        const uint64_t src = (uint64_t)a.lam + vs;
 #pragma unroll
-      for (int j = 0; j < RN; j++) lam[j] = ld(src, j);
+        for (int j = 0; j < RN; j++) lam[j] = ld(src, j);
+      } else {
+        const uint64_t v0 = (uint64_t)a.lam + vq;
+        if constexpr (LAY == 3) {
+          const uint32_t ts = tsaf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) lam[j] = lda(v0, ts, j);
+        } else {
+          const uint32_t ts = tswf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) lam[j] = ldz(v0, ts, j, std::integral_constant<bool, LAY == 1>{});
+        }
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < RN; j++) lam[j] = T2{(R)0, (R)0};
@@ -748,17 +831,43 @@ __global__ __launch_bounds__(256, (pass_half_xchg<KIND, S1, S2>() ? 3 : 2)) void
   if constexpr (KIND == 1 || KIND == 2) {
     if (f & PF_STORE_PHI) {
       xchg1p<R, T, CE, AH, HALF>(lds, phi, t);
-      const uint64_t dst = (uint64_t)a.phi_out + vs;
+      if constexpr (LAY == 0) {
+        const uint64_t dst = (uint64_t)a.phi_out + vs;
 #pragma unroll
-      for (int j = 0; j < RN; j++) st(dst, j, phi[j]);
+        for (int j = 0; j < RN; j++) st(dst, j, phi[j]);
+      } else {
+        const uint64_t v0 = (uint64_t)a.phi_out + vq;
+        if constexpr (LAY == 3) {
+          const uint32_t ts = tsaf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) sta(v0, ts, j, phi[j]);
+        } else {
+          const uint32_t ts = tswf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) stz(v0, ts, j, phi[j], std::integral_constant<bool, LAY == 1>{});
+        }
+      }
     }
   }
   if constexpr (KIND != 1) {
     if (f & PF_STORE_LAM) {
       xchg1p<R, T, CE, AH, HALF>(lds, lam, t);
-      const uint64_t dl = (uint64_t)a.lam + vs;
+      if constexpr (LAY == 0) {
+        const uint64_t dl = (uint64_t)a.lam + vs;
 #pragma unroll
-      for (int j = 0; j < RN; j++) st(dl, j, lam[j]);
+        for (int j = 0; j < RN; j++) st(dl, j, lam[j]);
+      } else {
+        const uint64_t v0 = (uint64_t)a.lam + vq;
+        if constexpr (LAY == 3) {
+          const uint32_t ts = tsaf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) sta(v0, ts, j, lam[j]);
+        } else {
+          const uint32_t ts = tswf();
+#pragma unroll
+          for (int j = 0; j < RN; j++) stz(v0, ts, j, lam[j], std::integral_constant<bool, LAY == 1>{});
+        }
+      }
     }
   }
   // ---- workgroup reduction of the partial sums (fixed order: deterministic)
@@ -794,19 +903,35 @@ static size_t lds_for(int tbytes, int lut_len, bool half = false) {
   return st + tb + (size_t)lut_len * 3 * sizeof(R);
 }
 
-template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT, int OP = 0>
+template <typename R, int T, int KIND, int S1, int S2, int SHAPE, typename TT, int OP = 0, int LAY = 0>
 static hipError_t launch_pass_t(const PassArgs<R> &a, hipStream_t s) {
   size_t lds = lds_for<R, T>((int)sizeof(TT), a.lut_len, pass_half_xchg<KIND, S1, S2>());
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_pass<R, T, KIND, S1, S2, SHAPE, TT, OP>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_pass<R, T, KIND, S1, S2, SHAPE, TT, OP, LAY>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid(a.nwg, a.nsets);
-  hipLaunchKernelGGL((k_pass<R, T, KIND, S1, S2, SHAPE, TT, OP>), grid, dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_pass<R, T, KIND, S1, S2, SHAPE, TT, OP, LAY>), grid, dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+// Shapes: 0 = part 1 only; 1 = both parts with the kind's middle steps (forward: phase;
+// reverse: gamma gradient and inverse phase; fused: <C> and lam); 2 = part 2 only after the
+// phase (first forward pass); 3 = part 1 then a reduction (forward: <C>; reverse: gamma
+// gradient).
+template <typename R, int T, int KIND, typename TT, int SX, int LAY>
+static hipError_t launch_shape(const PassArgs<R> &a, int shape, hipStream_t s) {
+  if constexpr (KIND == 3) return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 0, LAY>(a, s);
+  else {
+    if (shape == 0) return launch_pass_t<R, T, KIND, SX, 0, 0, TT, 0, LAY>(a, s);
+    if (shape == 3) return launch_pass_t<R, T, KIND, SX, 0, 3, TT, 0, LAY>(a, s);
+    if constexpr (KIND == 1)
+      if (shape == 2) return launch_pass_t<R, T, KIND, 0, SX, 2, TT, 0, LAY>(a, s);
+    return launch_pass_t<R, T, KIND, SX, SX, 1, TT, 0, LAY>(a, s);
+  }
 }
 
 }  // namespace qaoa

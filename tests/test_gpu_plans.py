@@ -16,8 +16,8 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 TOL = {0: (1e-5, 1e-5), 1: (1e-12, 1e-11)}   # precision -> (<C> rel, grad inf-rel)
-OPTS = ("narrow", "narrow_top", "lowbits", "down", "xcd", "ckpt", "swap")
-DEFAULT = dict(narrow=1, narrow_top=1, lowbits=1, down=0, xcd=1, ckpt=-1, swap=0)
+OPTS = ("narrow", "narrow_top", "lowbits", "down", "xcd", "ckpt", "swap", "swz")
+DEFAULT = dict(narrow=1, narrow_top=1, lowbits=1, down=0, xcd=1, ckpt=-1, swap=0, swz=1)
 
 
 @pytest.fixture(scope="module")
@@ -40,7 +40,7 @@ def _plan_file(path, n, opts):
     o = dict(DEFAULT, **opts)
     vals = " ".join(str(o[k]) for k in OPTS)
     with open(path, "w") as f:
-        f.write("qaoa-plans 2\n")
+        f.write("qaoa-plans 3\n")
         for prec in (0, 1):
             for grad in (0, 1):
                 for fits in (0, 1):
@@ -80,7 +80,7 @@ def test_plan_options_match_oracle(q, tmp_path, reg22, opts):
         assert _rel(e, E) < TOL[prec][0] and _rel(e1, E) < TOL[prec][0]
         assert _gerr(gr, G) < TOL[prec][1]
     text = ctx.plans()
-    assert text.splitlines()[0] == "qaoa-plans 2" and len(text.splitlines()) == 9
+    assert text.splitlines()[0] == "qaoa-plans 3" and len(text.splitlines()) == 9
     P.close(); M.close(); ctx.close()
 
 
@@ -127,7 +127,7 @@ def test_batched_call_does_not_tune(q, reg22):
     Pr, Mr = q.Problem.from_graph(ref, g), q.Mixer.x(ref, 22)
     eb, gb = q.expect_grad_batched([P], [M], sets, precision=0)
     er, gr = q.expect_grad_batched([Pr], [Mr], sets, precision=0)
-    assert ctx.plans() == "qaoa-plans 2\n"
+    assert ctx.plans() == "qaoa-plans 3\n"
     assert np.array_equal(eb, er) and np.array_equal(gb, gr)
     assert _rel(eb[0, 0], E) < TOL[0][0] and _gerr(gb[0, 0], G) < TOL[0][1]
     e0, g0 = q.expect_grad(P, M, a, precision=0)
@@ -142,18 +142,25 @@ def test_batched_call_does_not_tune(q, reg22):
 def test_plan_file_rejects_malformed(q, tmp_path):
     ctx = q.Context(0)
     bad = tmp_path / "bad.txt"
-    bad.write_text("qaoa-plans 2\n22 0 1 0 1 : 1 1 1 0 1 -1\n")   # one option missing
+    bad.write_text("qaoa-plans 3\n22 0 1 0 1 : 1 1 1 0 1 -1 0\n")   # one option missing
+    with pytest.raises(q.QAOAError):
+        ctx.load_plans(str(bad))
+    bad.write_text("qaoa-plans 3\n22 0 1 0 1 : 1 1 1 0 1 -1 0 2\n")   # layout option out of range
     with pytest.raises(q.QAOAError):
         ctx.load_plans(str(bad))
     bad.write_text("plans\n")
     with pytest.raises(q.QAOAError):
         ctx.load_plans(str(bad))
-    assert ctx.plans() == "qaoa-plans 2\n"
-    # a version-1 file (no swap field) loads with swap = 0
+    assert ctx.plans() == "qaoa-plans 3\n"
+    # a version-1 file (no swap field) loads with swap = 0, versions 1 and 2 (no layout field)
+    # with swz = 1
     old = tmp_path / "v1.txt"
     old.write_text("qaoa-plans 1\n22 0 1 0 1 : 1 1 1 1 1 -1\n")
     ctx.load_plans(str(old))
-    assert ctx.plans().splitlines()[1] == "22 0 1 0 1 : 1 1 1 1 1 -1 0"
+    assert ctx.plans().splitlines()[1] == "22 0 1 0 1 : 1 1 1 1 1 -1 0 1"
+    old.write_text("qaoa-plans 2\n23 0 1 0 1 : 1 1 1 1 1 -1 1\n")
+    ctx.load_plans(str(old))
+    assert ctx.plans().splitlines()[2] == "23 0 1 0 1 : 1 1 1 1 1 -1 1 1"
     ctx.close()
 
 
@@ -162,27 +169,70 @@ def test_narrow_cover_light_cone(q, tmp_path, n, prec):
     """The first sizes whose fewest-tile cover takes narrow runs (FP32 n = 30: 13 + 9 + 8 bits
     with 64- and 128-byte runs; FP64 n = 29: 12 + 9 + 8 bits), fwd+grad on the cycle C_n at
     p = 3 against the light cone (dense evolution of the 8-vertex path, no oracle), with the
-    narrow cover and with the four-tile cover loaded from a plan file."""
+    narrow cover in the swizzled layout (the fixed rule) and in the natural one, and with the
+    four-tile cover, loaded from plan files. The layout changes addresses only: the two narrow
+    runs agree bit for bit."""
     from tests import pins
     p = 3
     g = _cycle(n)
     a = workloads.random_angles(p, 1, 4130 + n)[0]
     ev, eg = pins.cycle_edge(p, a)
     res = {}
-    for narrow in (1, 0):
+    for narrow, swz in ((1, 1), (1, 0), (0, 1)):
         ctx = q.Context(0)
-        path = str(tmp_path / f"plans{narrow}.txt")
-        _plan_file(path, n, {"narrow": narrow})
+        path = str(tmp_path / f"plans{narrow}{swz}.txt")
+        _plan_file(path, n, {"narrow": narrow, "swz": swz})
         ctx.load_plans(path)
         P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
         e, gr = q.expect_grad(P, M, a, precision=prec)
-        print(f"n={n} prec={prec} narrow={narrow}: E err {_rel(e, n * ev):.2e} grad err "
+        print(f"n={n} prec={prec} narrow={narrow} swz={swz}: E err {_rel(e, n * ev):.2e} grad err "
               f"{np.max(np.abs(gr - n * eg)) / (n * np.max(np.abs(eg))):.2e}", flush=True)
         assert _rel(e, n * ev) < TOL[prec][0]
         assert np.max(np.abs(gr - n * eg)) < max(TOL[prec][1], 1e-9) * n * np.max(np.abs(eg))
-        res[narrow] = (e, gr)
+        res[narrow, swz] = (e, gr)
         P.close(); M.close(); ctx.close()
-    assert _rel(res[1][0], res[0][0]) < TOL[prec][0]
+    assert res[1, 1][0] == res[1, 0][0] and np.array_equal(res[1, 1][1], res[1, 0][1])
+    assert _rel(res[1, 1][0], res[0, 1][0]) < TOL[prec][0]
+
+
+@pytest.mark.parametrize("n,prec", [(30, 0), (29, 1)])
+def test_swizzled_layout_bit_identical(q, tmp_path, n, prec):
+    """The swizzled state layout of the narrow covers (the top ten index bits folded into ten
+    middle ones; per tile the add form, the XOR form, or the XOR form with cached accesses for
+    runs under 128 bytes) against the natural layout, on a random 3-regular (n even) or
+    4-regular (n odd) graph at p = 2: <C> and the gradient bit for bit, with the reverse sweep
+    from checkpoints and in place, and <C> alone. A wrong address anywhere in the swizzled
+    passes (a lost or doubled element, an element read from the wrong place) changes the
+    results. A caller's initial state (natural order) runs the natural layout under either
+    plan."""
+    import torch
+    p = 2
+    g = workloads.random_regular_graph(n, 3 if n % 2 == 0 else 4, 7300 + n)
+    a = workloads.random_angles(p, 1, 7301 + n)[0]
+    gen = torch.Generator(device="cuda").manual_seed(7302 + n)
+    dt = torch.complex64 if prec == 0 else torch.complex128
+    psi0 = torch.randn(1 << n, dtype=dt, device="cuda", generator=gen)
+    res = {}
+    for swz in (1, 0):
+        for ckpt in (-1, 0):
+            ctx = q.Context(0)
+            path = str(tmp_path / f"plans{swz}{ckpt}.txt")
+            _plan_file(path, n, {"swz": swz, "ckpt": ckpt})
+            ctx.load_plans(path)
+            P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+            res[swz, ckpt] = (q.expect_grad(P, M, a, precision=prec), q.expect(P, M, a, precision=prec),
+                              q.expect_grad(P, M, a, psi0=psi0, precision=prec))
+            P.close(); M.close(); ctx.close()
+    del psi0
+    torch.cuda.empty_cache()
+    for ckpt in (-1, 0):
+        (e1, g1), x1, (f1, h1) = res[1, ckpt]
+        (e0, g0), x0, (f0, h0) = res[0, ckpt]
+        print(f"n={n} prec={prec} ckpt={ckpt}: E {e1!r} / {e0!r}, expect {x1!r} / {x0!r}", flush=True)
+        assert e1 == e0 and np.array_equal(g1, g0) and x1 == x0
+        assert f1 == f0 and np.array_equal(h1, h0)
+    # the two reverse sweeps agree to rounding
+    assert _rel(res[1, -1][0][0], res[1, 0][0][0]) < TOL[prec][0]
 
 
 def test_n32_cycle_light_cone_p8(q):
