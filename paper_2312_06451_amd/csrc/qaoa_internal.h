@@ -117,7 +117,8 @@ struct PassArgs {
   int8_t ma_src[32];
   // State layout: swz == 0 stores element x of a vector at x; swz > 0 at
   // x ^ (((x >> swz_src) & 1023) << swz) (the top ten index bits folded into ten middle ones;
-  // requires swz + 10 <= swz_src). The caller's initial state is always read in natural order.
+  // requires swz + 10 <= swz_src). Passes that read the caller's initial state (natural order)
+  // run swz == 0.
   int swz, swz_src;
   int swz_add;  // 1: the tile's own address bits all lie below swz_src (uniform swizzle value)
   int cached;   // state loads and stores through the caches instead of non-temporal

@@ -195,8 +195,8 @@ def test_narrow_cover_light_cone(q, tmp_path, n, prec):
     assert _rel(res[1, 1][0], res[0, 1][0]) < TOL[prec][0]
 
 
-@pytest.mark.parametrize("n,prec", [(30, 0), (29, 1)])
-def test_swizzled_layout_bit_identical(q, tmp_path, n, prec):
+@pytest.mark.parametrize("n,prec,weighted", [(30, 0, False), (29, 1, False), (30, 0, True)])
+def test_swizzled_layout_bit_identical(q, tmp_path, n, prec, weighted):
     """The swizzled state layout of the narrow covers (the top ten index bits folded into ten
     middle ones; per tile the add form, the XOR form, or the XOR form with cached accesses for
     runs under 128 bytes) against the natural layout, on a random 3-regular (n even) or
@@ -204,10 +204,13 @@ def test_swizzled_layout_bit_identical(q, tmp_path, n, prec):
     from checkpoints and in place, and <C> alone. A wrong address anywhere in the swizzled
     passes (a lost or doubled element, an element read from the wrong place) changes the
     results. A caller's initial state (natural order) runs the natural layout under either
-    plan."""
+    plan. The weighted case (G(n, 1/2), weights U{1..4}) takes 16-bit tables."""
     import torch
     p = 2
-    g = workloads.random_regular_graph(n, 3 if n % 2 == 0 else 4, 7300 + n)
+    if weighted:
+        g = workloads.erdos_renyi(n, 7300 + n, 0.5, (1, 4))
+    else:
+        g = workloads.random_regular_graph(n, 3 if n % 2 == 0 else 4, 7300 + n)
     a = workloads.random_angles(p, 1, 7301 + n)[0]
     gen = torch.Generator(device="cuda").manual_seed(7302 + n)
     dt = torch.complex64 if prec == 0 else torch.complex128
@@ -220,6 +223,7 @@ def test_swizzled_layout_bit_identical(q, tmp_path, n, prec):
             _plan_file(path, n, {"swz": swz, "ckpt": ckpt})
             ctx.load_plans(path)
             P, M = q.Problem.from_graph(ctx, g), q.Mixer.x(ctx, n)
+            assert (P.max_value > 255) == weighted
             res[swz, ckpt] = (q.expect_grad(P, M, a, precision=prec), q.expect(P, M, a, precision=prec),
                               q.expect_grad(P, M, a, psi0=psi0, precision=prec))
             P.close(); M.close(); ctx.close()
