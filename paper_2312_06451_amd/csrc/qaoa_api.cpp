@@ -199,7 +199,6 @@ struct PlanOpts {
 // narrow cover.
 inline int swz_shift(int prec) { return prec == QAOA_FP32 ? 6 : 5; }
 
-
 struct qaoa_ctx {
   int device = 0;
   int64_t live = 0;          // problems and mixers created on this context and not yet destroyed
